@@ -1,0 +1,121 @@
+"""Seeded synthetic inputs shaped like the paper's workloads.
+
+Positions and strengths only: nothing in this module computes any part of the
+FFT-PIM method, so both the GPU path's tests and the CPU oracle can draw their
+inputs from it.  The paper's tetrahedral meshes are not available; these
+stand in with the shapes it describes (quasi-uniform volume points with a near
+grid of about one node per point, Table "near-zone"; a closed surface in a
+2D-periodic cell for the Helmholtz case).
+
+Every generator uses numpy's default_rng(seed).
+"""
+import numpy as np
+
+
+def uniform_cube(n, seed, L=(1.0, 1.0, 1.0)):
+    """n points uniform in [0, Lx) x [0, Ly) x [0, Lz)."""
+    rng = np.random.default_rng(seed)
+    return rng.random((n, 3)) * np.asarray(L, dtype=float)
+
+
+def plus_minus_charges(n, seed):
+    """n/2 charges +1 and n/2 charges -1 in random order (a neutral set)."""
+    rng = np.random.default_rng(seed)
+    q = np.where(np.arange(n) < n // 2, 1.0, -1.0)
+    if n % 2:
+        q[-1] = 0.0
+    rng.shuffle(q)
+    return q
+
+
+def gaussian_neutral(nrhs, n, seed, dtype=np.float64):
+    """nrhs real N(0,1) vectors with the mean removed from each (neutral)."""
+    rng = np.random.default_rng(seed)
+    q = rng.standard_normal((nrhs, n))
+    q -= q.mean(axis=1, keepdims=True)
+    return q.astype(dtype)
+
+
+def gaussian_complex(nrhs, n, seed, dtype=np.complex64):
+    """nrhs complex vectors with real and imaginary parts N(0,1)."""
+    rng = np.random.default_rng(seed)
+    q = rng.standard_normal((nrhs, n)) + 1j * rng.standard_normal((nrhs, n))
+    return q.astype(dtype)
+
+
+def _real_sph_harm(l, m, theta, phi):
+    """Real spherical harmonic of degree l, order m (theta polar angle)."""
+    from scipy.special import sph_harm_y
+    y = sph_harm_y(l, abs(m), theta, phi)
+    if m > 0:
+        return np.sqrt(2.0) * y.real
+    if m < 0:
+        return np.sqrt(2.0) * y.imag
+    return y.real
+
+
+def smooth_closed_surface(n, seed, center=(0.5, 0.5, 0.25), semi_axes=(0.35, 0.35, 0.17),
+                          lmax=4, amp=0.1, clip=0.3):
+    """n points, area-uniform, on a random smooth star-shaped closed surface.
+
+    The radial profile is 1 + sum_{l=1..lmax} sum_m a_lm Y_lm(theta, phi) with
+    a_lm ~ N(0, amp/l^2), clipped to |delta r| <= clip, scaled by semi_axes
+    and shifted to center.  Points are drawn uniformly in area by rejection
+    against the surface's area element.
+    """
+    rng = np.random.default_rng(seed)
+    coef = [(l, m, rng.normal(0.0, amp / l ** 2)) for l in range(1, lmax + 1)
+            for m in range(-l, l + 1)]
+    c = np.asarray(center, float)
+    ax = np.asarray(semi_axes, float)
+
+    def surface(theta, phi):
+        dr = np.zeros_like(theta)
+        for l, m, a in coef:
+            dr += a * _real_sph_harm(l, m, theta, phi)
+        rr = 1.0 + np.clip(dr, -clip, clip)
+        d = np.stack([np.sin(theta) * np.cos(phi), np.sin(theta) * np.sin(phi), np.cos(theta)], -1)
+        return c + ax * (rr[..., None] * d)
+
+    def area_density(theta, phi, eps=1e-6):
+        # |dX/dtheta x dX/dphi| / sin(theta): density w.r.t. the uniform sphere measure
+        xt = (surface(theta + eps, phi) - surface(theta - eps, phi)) / (2 * eps)
+        xp = (surface(theta, phi + eps) - surface(theta, phi - eps)) / (2 * eps)
+        return np.linalg.norm(np.cross(xt, xp), axis=-1) / np.maximum(np.sin(theta), 1e-300)
+
+    # bound the density on a fine probe grid
+    tt, pp = np.meshgrid(np.linspace(0.01, np.pi - 0.01, 200), np.linspace(0, 2 * np.pi, 400), indexing="ij")
+    dmax = 1.2 * area_density(tt, pp).max()
+    out = []
+    have = 0
+    while have < n:
+        m = 2 * (n - have) + 1024
+        u = rng.random(m)
+        theta = np.arccos(1 - 2 * u)
+        phi = 2 * np.pi * rng.random(m)
+        keep = rng.random(m) * dmax < area_density(theta, phi)
+        pts = surface(theta[keep], phi[keep])
+        out.append(pts)
+        have += pts.shape[0]
+    return np.concatenate(out)[:n]
+
+
+# ---------------------------------------------------------------------------
+# the workloads (seed = workload number)
+# ---------------------------------------------------------------------------
+
+def coulomb_cube_1k():
+    """3D-periodic static Coulomb, unit cube, 1000 uniform points, +-1 charges."""
+    return uniform_cube(1000, 1), plus_minus_charges(1000, 1)
+
+
+def helmholtz_surface_100k(n=100_000):
+    """2D-periodic Helmholtz with phase shift: points on a closed surface in a
+    1 x 1 x 0.5 wavelength cell; complex64 N(0,1) strengths."""
+    return smooth_closed_surface(n, 2), gaussian_complex(1, n, 2)[0]
+
+
+def coulomb_cube_1m_batched(n=1_000_000, nrhs=64):
+    """3D-periodic static Coulomb, 1M uniform points, 64 neutral Gaussian
+    right-hand sides (float32)."""
+    return uniform_cube(n, 3), gaussian_neutral(nrhs, n, 3, np.float32)

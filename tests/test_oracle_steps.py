@@ -1,0 +1,133 @@
+"""Pins of the step-by-step FFT-PIM oracle (Sec. 3) against definitions that
+do not go through its own pipeline: polynomial reproduction of the Lagrange
+weights, the direct (non-FFT) grid sum, the direct near-zone pair sum when
+every image pair is corrected, convergence of the far zone to the direct far
+sum, and the conjugate-transpose identity."""
+import numpy as np
+import pytest
+
+from oracle import pgf as P
+from oracle import steps as S
+from oracle.psp import psp_forward
+
+
+@pytest.mark.parametrize("q", [1, 2, 3, 4, 5, 7])
+def test_lagrange_weights_reproduce_polynomials(q):
+    rng = np.random.default_rng(q)
+    x = rng.uniform(0.0, 1.0, 50)
+    h, origin, n = 0.1, -0.1 * 0.5 * (q - 1), 40
+    s, w = S.lagrange_stencil(x, origin, h, q, n)
+    nodes = origin + (s[:, None] + np.arange(q + 1)[None, :]) * h
+    for p in range(q + 1):
+        np.testing.assert_allclose(np.sum(w * (nodes - x[:, None]) ** p, axis=1), 1.0 if p == 0 else 0.0,
+                                   atol=1e-12)
+    # the point sits in the central cell of its stencil
+    t = (x - origin) / h - s
+    assert np.all(t >= 0.5 * (q - 1) - 1e-12) and np.all(t < 0.5 * (q + 1) + 1e-12)
+
+
+def _small(lat, n=8, q=2, rc=3, nf=8, qf=3, N=40, seed=0):
+    rng = np.random.default_rng(seed)
+    src = rng.random((N, 3)) * lat.L
+    if lat.dims < 3:
+        src[:, 2] = rng.random(N) * 0.5
+    return S.FFTPIM(lat, S.Params(n, q, rc, nf, qf, 1), src), rng
+
+
+def test_fft_convolution_equals_direct_grid_sum():
+    lat = P.Lattice(3, [1, 1, 1], k0=2.0, kt=[0.5, 0.2, -0.3])
+    m, rng = _small(lat)
+    n = m.prm.near_n
+    Q = rng.standard_normal((1, m.Ng)) + 1j * rng.standard_normal((1, m.Ng))
+    V = m._near_conv(Q)[0]
+    idx = np.stack(np.meshgrid(*[np.arange(n[c]) for c in range(3)], indexing="ij"), -1).reshape(-1, 3)
+    T = m.near_table
+    for a in rng.choice(m.Ng, 6, replace=False):
+        e = idx[a][None, :] - idx + (n - 1)
+        direct = np.sum(T[e[:, 0], e[:, 1], e[:, 2]] * Q[0])
+        assert V[a] == pytest.approx(direct, rel=1e-12)
+
+
+@pytest.mark.parametrize("dims", [1, 2, 3])
+def test_full_correction_gives_direct_near_sum(dims):
+    # with r_c covering every (m, n, i) triple the grid cancels and the near
+    # zone is exactly sum_{n, |i|<=i_d} phi_i G0(r_m - r_n - R_i), self image dropped
+    # 1D: neutral static (the oracle has no small-distance 1D Helmholtz form)
+    k = 3.0 if dims > 1 else 0.0
+    lat = P.Lattice(dims, [1, 1, 1], k0=k, kt=[0.4, -0.7, 0.2][:dims] if dims > 1 else [0.0])
+    n, q = 8, 2
+    nint = n - q
+    m, rng = _small(lat, n=n, q=q, rc=2 * nint + 2, N=30, seed=dims)
+    qv = (rng.standard_normal(30) + 1j * rng.standard_normal(30))[None, :]
+    rows = np.arange(30)
+    got = (m.near_grid_part(qv, rows) + m.near_corr_part(qv, rows))[0]
+    d = m.obs[:, None, :] - m.src[None, :, :]
+    G = P.g_near(d, lat, 1)
+    np.fill_diagonal(G, 0.0)
+    # images of a source acting on itself (i != 0)
+    rngs = [range(-1, 2) if c < dims else range(0, 1) for c in range(3)]
+    s_img = 0.0
+    for ix in rngs[0]:
+        for iy in rngs[1]:
+            for iz in rngs[2]:
+                if ix == iy == iz == 0:
+                    continue
+                R = np.array([ix, iy, iz]) * lat.L
+                s_img += np.exp(-1j * lat.kt @ R) * P.g0(-R, lat.k0)
+    want = G @ qv[0] + s_img * qv[0]
+    np.testing.assert_allclose(got, want, rtol=1e-11, atol=1e-12 * np.abs(want).max())
+
+
+def test_far_zone_converges_to_direct_far_sum():
+    lat = P.Lattice(3, [1, 1, 1])
+    rng = np.random.default_rng(5)
+    src = rng.random((25, 3))
+    q = rng.standard_normal(25)
+    q -= q.mean()
+    d = src[:, None, :] - src[None, :, :]
+    Gf = np.empty((25, 25), dtype=complex)
+    off = ~np.eye(25, dtype=bool)
+    Gf[off] = P.g_far(d[off], lat, 1)
+    s_img = sum(P.g0(-np.array([ix, iy, iz], float), 0.0) for ix in (-1, 0, 1) for iy in (-1, 0, 1)
+                for iz in (-1, 0, 1) if (ix, iy, iz) != (0, 0, 0))
+    np.fill_diagonal(Gf, P.pgf_self(lat) - s_img)
+    want = Gf @ q
+    errs = []
+    for nf, qf in [(8, 3), (10, 5), (14, 7)]:
+        m = S.FFTPIM(lat, S.Params(8, 2, 2, nf, qf, 1), src)
+        got = m.far_part(q[None, :].astype(complex), np.arange(25))[0]
+        errs.append(np.linalg.norm(got - want) / np.linalg.norm(want))
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] < 1e-4
+
+
+@pytest.mark.parametrize("case", ["npsp3", "helm2", "phase3"])
+def test_adjoint_is_conjugate_transpose(case):
+    k = 2 * np.pi
+    lat = {"npsp3": P.Lattice(3, [1, 1, 1]),
+           "helm2": P.Lattice(2, [1, 1], k0=k, kt=[0.3 * k, 0.1 * k]),
+           "phase3": P.Lattice(3, [1, 1, 1], k0=0.0, kt=[0.5, 0.3, 0.2])}[case]
+    m, rng = _small(lat, N=35, seed=7)
+    qv = rng.standard_normal(35) + 1j * rng.standard_normal(35)
+    vv = rng.standard_normal(35) + 1j * rng.standard_normal(35)
+    Aq = m.apply(qv)
+    AHv = m.adjoint(vv)
+    lhs = np.vdot(vv, Aq)
+    rhs = np.vdot(AHv, qv)
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_method_accuracy_against_direct_pair_sum():
+    lat = P.Lattice(3, [1, 1, 1])
+    rng = np.random.default_rng(9)
+    src = rng.random((120, 3))
+    q = rng.standard_normal(120)
+    q -= q.mean()
+    ref = psp_forward(lat, src, q, workers=1)
+    errs = []
+    for rc in (4, 6):   # r_c >= q keeps the zeroed singular table entry off uncorrected pairs
+        m = S.FFTPIM(lat, S.Params(12, 4, rc, 12, 5, 1), src)
+        u = m.apply(q)
+        errs.append(np.linalg.norm(u - ref) / np.linalg.norm(ref))
+    assert errs[1] < errs[0] < 1e-3
+    assert errs[1] < 1e-4
