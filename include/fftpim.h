@@ -1,0 +1,194 @@
+/*
+ * fftpim.h - C ABI of the MI355X FFT-PIM apply.
+ *
+ * The FFT periodic interpolation method (Ai & Lomakin) evaluates the periodic
+ * scalar potential of Sec. 2, Eq. (1),
+ *
+ *     u(r_m) = sum_n G^p(r_m - r_n) q_n ,
+ *
+ * with G^p the 1D/2D/3D periodic Green's function of Eq. (2) built from
+ * G0(r) = exp(-j k0 |r|) / (4 pi |r|) and image phases exp(-j k_t . R_i).
+ * The sum is split into a near zone and a far zone (Sec. 3.1, Eq. (4)-(5)):
+ *   far zone  (Sec. 3.2): projection onto a sparse source grid, a dense grid
+ *             sum with the far-image kernel (Eq. (8)), interpolation from the
+ *             shifted observer grid;
+ *   near zone (Sec. 3.3): projection onto one dense grid, a zero-padded FFT
+ *             convolution with the tabulated near-image kernel, interpolation,
+ *             and the error correction of Eq. (er) over close source/observer
+ *             pairs and their close images.
+ *
+ * Conventions shared by every entry point:
+ *   - All pointers named *_dev are device pointers (hipMalloc'ed or torch CUDA
+ *     tensors); host pointers are named otherwise.
+ *   - Positions are double [n][3] (x, y, z interleaved), in the zeroth cell:
+ *     0 <= x_c < L_c on every periodic axis c.
+ *   - Amplitudes/potentials are right-hand-side major: q[r][n], r < nrhs.
+ *     Element type: double / float (FFTPIM_REAL) or interleaved complex
+ *     (re, im) double / float (FFTPIM_COMPLEX), per the plan's precision.
+ *   - Nothing is copied back to the host by an apply: work is enqueued on the
+ *     given stream and the call returns.  Errors found on the device (e.g. a
+ *     non-neutral right-hand side of a static no-phase problem) are latched
+ *     and reported by fftpim_last_status.
+ *   - Every function returns an fftpim_status (0 = success); no exception or
+ *     longjmp crosses the ABI.
+ *   - Applies on one plan share its workspace: enqueue them on one stream, or
+ *     use one plan per stream.
+ */
+#ifndef FFTPIM_H
+#define FFTPIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fftpim_plan_s* fftpim_plan_t;
+typedef void* fftpim_stream_t; /* a hipStream_t; NULL = the null stream */
+
+typedef enum {
+  FFTPIM_OK = 0,
+  FFTPIM_ERR_INVALID_ARG = 1,  /* null pointer, bad size or parameter */
+  FFTPIM_ERR_OUT_OF_CELL = 2,  /* a point outside [0, L) on a periodic axis,
+                                  or outside the given box elsewhere */
+  FFTPIM_ERR_NOT_NEUTRAL = 3,  /* static no-phase problem with sum(q) != 0 */
+  FFTPIM_ERR_WOOD_ANOMALY = 4, /* a Floquet wavenumber vanishes (Sec. 2) */
+  FFTPIM_ERR_UNSUPPORTED = 5,  /* a combination this build does not handle */
+  FFTPIM_ERR_NO_MEMORY = 6,    /* device or host allocation failed */
+  FFTPIM_ERR_DEVICE = 7,       /* a HIP runtime call failed */
+  FFTPIM_ERR_UNIMPLEMENTED = 8
+} fftpim_status;
+
+enum { FFTPIM_F64 = 0, FFTPIM_F32 = 1 };          /* precision of the bulk path */
+enum { FFTPIM_REAL = 0, FFTPIM_COMPLEX = 1 };     /* element type of q and u */
+enum { FFTPIM_SELF_IMAGES = 0, FFTPIM_SELF_EXCLUDE = 1 };
+enum { FFTPIM_ORDER_USER = 0, FFTPIM_ORDER_PLAN = 1 };
+enum { FFTPIM_PART_NEAR_GRID = 1, FFTPIM_PART_NEAR_CORR = 2, FFTPIM_PART_FAR = 4,
+       FFTPIM_PART_ALL = 7 };
+
+/* The problem of Sec. 2: periodicity, periods, free-space wavenumber k0
+ * (0 = static) and phase-shift wavenumbers k_x0, k_y0, k_z0.  This build
+ * takes real k0 and real phase shifts. */
+typedef struct {
+  int periodic_dims;   /* 1: x; 2: x, y; 3: x, y, z */
+  double L[3];         /* periods (entries beyond periodic_dims ignored) */
+  double k0;           /* free-space wavenumber */
+  double kt[3];        /* phase-shift wavenumbers (beyond periodic_dims ignored) */
+  int has_box;         /* 1: use box_lo/box_hi on the non-periodic axes, */
+  double box_lo[3];    /* else the bounding box of the points (target region */
+  double box_hi[3];    /* D of Sec. 3.2) */
+} fftpim_problem_t;
+
+/* Method parameters (Sec. 3.2-3.3).  Grid sizes count the interpolation halo:
+ * a grid of n nodes and order q spans n - q cells on a periodic axis of the
+ * near grid and n - q - 1 cells otherwise.  Orders are Lagrange degrees
+ * (q + 1 nodes per axis). */
+typedef struct {
+  int near_n[3];     /* near grid nodes per axis (2*near_n must be a power of 2) */
+  int near_order;    /* near projection/interpolation degree */
+  int corr_radius;   /* error-correction radius in near-grid boxes (Chebyshev) */
+  int far_n[3];      /* far grid nodes per axis */
+  int far_order;     /* far projection/interpolation degree */
+  int n_images;      /* i_d of Eq. (4): near-zone images per periodic axis */
+  int precision;     /* FFTPIM_F64 or FFTPIM_F32 (correction stays FP64) */
+  int value_type;    /* FFTPIM_REAL (static no-phase only) or FFTPIM_COMPLEX */
+  int self_mode;     /* FFTPIM_SELF_IMAGES or FFTPIM_SELF_EXCLUDE */
+  int order_io;      /* FFTPIM_ORDER_USER: q/u indexed like the input points;
+                        FFTPIM_ORDER_PLAN: indexed in the plan's sorted order */
+  int nrhs_max;      /* largest nrhs a single apply may pass */
+} fftpim_params_t;
+
+typedef struct {
+  int64_t n_src, n_obs;
+  int near_n[3], near_fft[3], near_cells[3];
+  double near_h[3], domain_lo[3], domain_hi[3];
+  int far_n[3], far_cells[3];
+  double far_h[3];
+  int64_t corr_nnz;           /* stored correction entries */
+  int64_t device_bytes;       /* device memory held by the plan */
+  int nplanes_max;            /* complex grid planes for nrhs_max */
+  double plan_seconds;        /* wall time of fftpim_plan */
+} fftpim_info_t;
+
+/* Fill *params with defaults for the problem (order 4 near, order 7 far,
+ * i_d = 1, F64, complex values, images kept, user order, nrhs_max 1). */
+int fftpim_default_params(const fftpim_problem_t* problem, fftpim_params_t* params);
+
+/* Build a plan (Sec. 3.2 and 3.3 preprocessing: grids, interpolation
+ * stencils, the far-zone kernel table of Eq. (8) from the series of
+ * Eq. (pgf)/(lgf), the FFT of the zero-padded near-zone table, and the
+ * error-correction operator of Eq. (er)).
+ *   src_xyz_dev: device double [n_src][3]; copied, may be freed afterwards.
+ *   obs_xyz_dev: must be NULL (observers coincide with sources, Sec. 2);
+ *                separate observer sets return FFTPIM_ERR_UNIMPLEMENTED.
+ *   stream:      stream for the plan's device work; the call synchronizes it.
+ * On success *plan owns all device memory it needs; free with fftpim_destroy.
+ * Errors: INVALID_ARG, OUT_OF_CELL, WOOD_ANOMALY, UNSUPPORTED, NO_MEMORY,
+ * DEVICE. */
+int fftpim_plan(fftpim_plan_t* plan, const fftpim_problem_t* problem,
+                const fftpim_params_t* params, int64_t n_src, const double* src_xyz_dev,
+                int64_t n_obs, const double* obs_xyz_dev, fftpim_stream_t stream);
+
+/* u = A q (Eq. (1) through Eq. (5)): q_dev [nrhs][n_src], u_dev [nrhs][n_obs]
+ * (overwritten).  1 <= nrhs <= nrhs_max.  For a static no-phase problem
+ * every right-hand side must be neutral (Eq. (neutral)); a violation is
+ * latched for fftpim_last_status. */
+int fftpim_apply(fftpim_plan_t plan, const void* q_dev, void* u_dev, int nrhs,
+                 fftpim_stream_t stream);
+
+/* w = A^H v, the exact conjugate transpose of the discrete operator applied
+ * by fftpim_apply: v_dev [nrhs][n_obs], w_dev [nrhs][n_src] (overwritten).
+ * For a static no-phase problem only the zero-mean part of w is defined;
+ * this call returns w with its mean removed per right-hand side. */
+int fftpim_apply_adjoint(fftpim_plan_t plan, const void* v_dev, void* w_dev, int nrhs,
+                         fftpim_stream_t stream);
+
+/* Apply only some parts of the operator (FFTPIM_PART_* mask) - forward
+ * (adjoint = 0) or conjugate transpose (adjoint = 1).  PART_ALL equals
+ * fftpim_apply / fftpim_apply_adjoint except that no mean is removed and no
+ * neutrality check is made.  Used to check the stages one at a time. */
+int fftpim_apply_parts(fftpim_plan_t plan, int parts, int adjoint, const void* q_dev,
+                       void* u_dev, int nrhs, fftpim_stream_t stream);
+
+/* perm_dev (device int32 [n]) receives, for each plan-order position, the
+ * index of that point in the caller's order.  which: 0 sources, 1 observers. */
+int fftpim_get_permutation(fftpim_plan_t plan, int which, int32_t* perm_dev);
+
+/* Sizes and parameters of a plan. */
+int fftpim_plan_info(fftpim_plan_t plan, fftpim_info_t* info);
+
+/* Synchronizes the plan's last stream and returns the first device-detected
+ * error of the applies since the previous call (then clears it). */
+int fftpim_last_status(fftpim_plan_t plan);
+
+/* Frees the plan and every device buffer it owns. NULL is accepted. */
+int fftpim_destroy(fftpim_plan_t plan);
+
+/* Per-stage device timing with HIP events recorded on the apply stream.
+ * enable = 1: start recording (accumulators reset); every later apply records
+ * an event pair around each stage.  enable = 0: stop recording.  On return
+ * (either way) ms_out[FFTPIM_NSTAGES] and calls_out[FFTPIM_NSTAGES] (host
+ * arrays, may be NULL) hold the summed milliseconds and the number of timed
+ * launches per stage since recording started; the call synchronizes. */
+enum { FFTPIM_STAGE_PACK = 0, FFTPIM_STAGE_NEAR_SPREAD = 1, FFTPIM_STAGE_NEAR_FFT = 2,
+       FFTPIM_STAGE_NEAR_INTERP = 3, FFTPIM_STAGE_NEAR_CORR = 4, FFTPIM_STAGE_FAR = 5,
+       FFTPIM_STAGE_UNPACK = 6, FFTPIM_NSTAGES = 7 };
+int fftpim_stage_times(fftpim_plan_t plan, int enable, double* ms_out, int64_t* calls_out);
+
+/* Static description of a status code. */
+const char* fftpim_error_string(int status);
+
+/* The periodic Green's function of Sec. 2 as the library's host evaluator
+ * computes it for the far-zone table (Eq. (pgf) / Eq. (lgf) with the
+ * neutral-static gauge of zero cell mean in 3D), at n host points
+ * r_xyz [n][3]; out [n][2] receives (re, im).  Points must not be lattice
+ * vectors.  Exposed so the evaluator can be checked on its own. */
+int fftpim_eval_pgf(const fftpim_problem_t* problem, int64_t n, const double* r_xyz,
+                    double* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FFTPIM_H */

@@ -67,11 +67,15 @@ class Params:
 
 def domain_bounds(lat, pts):
     """Target region D (Sec. 3.2): the cell [0, L) on periodic axes, the
-    bounding box of the points on the others."""
+    bounding box of the points on the others (a zero extent is widened to
+    [lo, lo + 1], the reading for a flat or single-point set)."""
     lo = pts.min(axis=0).astype(float)
     hi = pts.max(axis=0).astype(float)
-    for c in range(lat.dims):
-        lo[c], hi[c] = 0.0, lat.L[c]
+    for c in range(3):
+        if c < lat.dims:
+            lo[c], hi[c] = 0.0, lat.L[c]
+        elif not hi[c] > lo[c]:
+            hi[c] = lo[c] + 1.0
     return lo, hi
 
 

@@ -1,0 +1,862 @@
+// C ABI of the FFT-PIM apply: plan construction (Sec. 3.2-3.3 preprocessing)
+// and the apply / conjugate-transpose orchestration.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "kernels.h"
+
+using namespace fftpim;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr int kMaxNearOrder = 8;
+constexpr int kMaxFarOrder = 9;
+constexpr int kMaxCorrRadius = 40;
+constexpr size_t kLdsBudget = 64 * 1024;
+
+#define HIPCHK(expr)                                  \
+  do {                                                \
+    hipError_t e_ = (expr);                           \
+    if (e_ != hipSuccess) {                           \
+      if (e_ == hipErrorOutOfMemory) return FFTPIM_ERR_NO_MEMORY; \
+      return FFTPIM_ERR_DEVICE;                       \
+    }                                                 \
+  } while (0)
+
+#define CHK(expr)               \
+  do {                          \
+    int s_ = (expr);            \
+    if (s_ != FFTPIM_OK) return s_; \
+  } while (0)
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+int ilog2(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+template <typename T>
+int dalloc(fftpim_plan_s* p, T** out, size_t count) {
+  void* ptr = nullptr;
+  size_t bytes = std::max<size_t>(count * sizeof(T), 16);
+  if (hipMalloc(&ptr, bytes) != hipSuccess) return FFTPIM_ERR_NO_MEMORY;
+  p->allocations.push_back(ptr);
+  p->device_bytes += static_cast<int64_t>(bytes);
+  *out = static_cast<T*>(ptr);
+  return FFTPIM_OK;
+}
+
+void dfree(fftpim_plan_s* p, void* ptr) {
+  if (!ptr) return;
+  auto it = std::find(p->allocations.begin(), p->allocations.end(), ptr);
+  if (it != p->allocations.end()) {
+    p->allocations.erase(it);
+    hipFree(ptr);
+  }
+}
+
+template <typename T>
+int upload(fftpim_plan_s* p, T** out, const std::vector<T>& host) {
+  CHK(dalloc(p, out, host.size()));
+  if (!host.empty()) HIPCHK(hipMemcpy(*out, host.data(), host.size() * sizeof(T), hipMemcpyHostToDevice));
+  return FFTPIM_OK;
+}
+
+size_t cbytes(const fftpim_plan_s* p) { return p->prm.precision == FFTPIM_F32 ? 8 : 16; }
+
+// Stencil start and offset for one coordinate on a grid (Sec. 3.2, Eq. (grid),
+// with the halo reading): t = (x - origin)/h, s = floor(t - (q-1)/2) clamped
+// to [0, n-1-q], u = t - s.
+void stencil(double x, double origin, double h, int q, int n, int32_t& s, double& u) {
+  double t = (x - origin) / h;
+  double sf = std::floor(t - 0.5 * (q - 1));
+  int si = static_cast<int>(sf);
+  si = std::max(0, std::min(n - 1 - q, si));
+  s = si;
+  u = t - si;
+}
+
+// Stable counting sort of keys in [0, nkeys): order[] lists indices by key,
+// start[k] = first position of key k (start[nkeys] = count).
+void counting_sort(const std::vector<int64_t>& key, int64_t nkeys, std::vector<int32_t>& order,
+                   std::vector<int32_t>& start) {
+  start.assign(nkeys + 1, 0);
+  for (int64_t k : key) start[k + 1]++;
+  for (int64_t k = 0; k < nkeys; ++k) start[k + 1] += start[k];
+  std::vector<int32_t> fill(start.begin(), start.end() - 1);
+  order.resize(key.size());
+  for (size_t i = 0; i < key.size(); ++i) order[fill[key[i]]++] = static_cast<int32_t>(i);
+}
+
+int planes_for(const fftpim_plan_s* p, int nrhs) {
+  return p->prm.value_type == FFTPIM_REAL ? (nrhs + 1) / 2 : nrhs;
+}
+
+// ---------------------------------------------------------------------------
+// FFT pass descriptors for the pruned, zero-padded convolution (Step 2)
+// ---------------------------------------------------------------------------
+
+int lines_per_block(int M, size_t esize, int64_t cap) {
+  int T = 1;
+  while (static_cast<size_t>(T) * 2 * M * esize <= kLdsBudget && T * 2 <= cap) T *= 2;
+  return T;
+}
+
+FftPassDesc pass_desc(int M, int n_in, int n_out, bool contig, int64_t nouter, int64_t ncols, int64_t in_line,
+                      int64_t in_outer, int64_t out_line, int64_t out_outer, size_t esize) {
+  FftPassDesc d{};
+  d.M = M;
+  d.logM = ilog2(M);
+  d.n_in = n_in;
+  d.n_out = n_out;
+  d.contig = contig ? 1 : 0;
+  d.nouter = nouter;
+  d.ncols = contig ? 1 : ncols;
+  d.in_line = in_line;
+  d.in_col = 1;
+  d.in_outer = in_outer;
+  d.out_line = out_line;
+  d.out_col = 1;
+  d.out_outer = out_outer;
+  d.T = contig ? lines_per_block(M, esize, 1 << 20) : lines_per_block(M, esize, ncols);
+  d.spec_line = 0;
+  d.spec_col = 0;
+  return d;
+}
+
+template <typename R>
+void near_convolution(fftpim_plan_s* p, int P, bool adjoint, hipStream_t st) {
+  const int nx = p->ng.n[0], ny = p->ng.n[1], nz = p->ng.n[2];
+  const int Mx = p->M[0], My = p->M[1], Mz = p->M[2];
+  const size_t es = sizeof(cplx<R>);
+  // z: grid0 [P*nx*ny][nz] -> bufA [P*nx*ny][Mz]
+  FftPassDesc dz = pass_desc(Mz, nz, Mz, true, static_cast<int64_t>(P) * nx * ny, 1, 1, nz, 1, Mz, es);
+  launch_fft_pass<R>(0, p->grid0, p->bufA, dz, p->twiddle[2], nullptr, false, st);
+  // y: bufA [P*nx][ny][Mz] -> bufB [P*nx][My][Mz]
+  FftPassDesc dy = pass_desc(My, ny, My, false, static_cast<int64_t>(P) * nx, Mz, Mz,
+                             static_cast<int64_t>(ny) * Mz, Mz, static_cast<int64_t>(My) * Mz, es);
+  launch_fft_pass<R>(0, p->bufA, p->bufB, dy, p->twiddle[1], nullptr, false, st);
+  // x: in place on bufB [P][nx][My*Mz], fused spectrum multiply
+  const int64_t cols = static_cast<int64_t>(My) * Mz;
+  FftPassDesc dx = pass_desc(Mx, nx, nx, false, P, cols, cols, nx * cols, cols, nx * cols, es);
+  dx.spec_line = cols;
+  dx.spec_col = 1;
+  launch_fft_pass<R>(2, p->bufB, p->bufB, dx, p->twiddle[0], p->near_hat, adjoint, st);
+  // inverse y: bufB [P*nx][My][Mz] -> bufA [P*nx][ny][Mz]
+  FftPassDesc iy = pass_desc(My, My, ny, false, static_cast<int64_t>(P) * nx, Mz, Mz,
+                             static_cast<int64_t>(My) * Mz, Mz, static_cast<int64_t>(ny) * Mz, es);
+  launch_fft_pass<R>(1, p->bufB, p->bufA, iy, p->twiddle[1], nullptr, false, st);
+  // inverse z: bufA [P*nx*ny][Mz] -> grid0 [P*nx*ny][nz]
+  FftPassDesc iz = pass_desc(Mz, Mz, nz, true, static_cast<int64_t>(P) * nx * ny, 1, 1, Mz, 1, nz, es);
+  launch_fft_pass<R>(1, p->bufA, p->grid0, iz, p->twiddle[2], nullptr, false, st);
+}
+
+GridArgs grid_args(const GridGeom& g) {
+  GridArgs a{};
+  for (int c = 0; c < 3; ++c) {
+    a.n[c] = g.n[c];
+    a.nint[c] = g.nint[c];
+    a.nb[c] = g.nint[c] + 1;
+  }
+  return a;
+}
+
+FarArgs far_args(const fftpim_plan_s* p) {
+  FarArgs f{};
+  for (int c = 0; c < 3; ++c) {
+    f.nf[c] = p->fg.n[c];
+    f.nint[c] = p->fg.nint[c];
+    f.nb[c] = p->fg.nint[c] + 1;
+  }
+  f.Ngf = static_cast<int64_t>(f.nf[0]) * f.nf[1] * f.nf[2];
+  f.nboxes = static_cast<int64_t>(f.nb[0]) * f.nb[1] * f.nb[2];
+  return f;
+}
+
+// Event pair around one stage when timing is on (pool grows on demand; the
+// pairs are resolved by fftpim_stage_times).
+struct StageTimer {
+  fftpim_plan_s* p;
+  hipStream_t st;
+  int stage;
+  size_t start = 0;
+  bool on = false;
+  StageTimer(fftpim_plan_s* p_, hipStream_t st_, int stage_) : p(p_), st(st_), stage(stage_) {
+    if (!p->timing) return;
+    while (p->ev_pool.size() < p->ev_used + 2) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return;
+      p->ev_pool.push_back(e);
+    }
+    start = p->ev_used;
+    p->ev_used += 2;
+    on = hipEventRecord(p->ev_pool[start], st) == hipSuccess;
+  }
+  ~StageTimer() {
+    if (!on) return;
+    if (hipEventRecord(p->ev_pool[start + 1], st) == hipSuccess) p->ev_pairs.emplace_back(stage, start);
+  }
+};
+
+void resolve_timers(fftpim_plan_s* p) {
+  for (auto& pr : p->ev_pairs) {
+    float ms = 0.f;
+    if (hipEventSynchronize(p->ev_pool[pr.second + 1]) == hipSuccess &&
+        hipEventElapsedTime(&ms, p->ev_pool[pr.second], p->ev_pool[pr.second + 1]) == hipSuccess) {
+      p->stage_ms[pr.first] += ms;
+      p->stage_calls[pr.first] += 1;
+    }
+  }
+  p->ev_pairs.clear();
+  p->ev_used = 0;
+}
+
+template <typename R>
+int run_apply(fftpim_plan_s* p, int parts, bool adjoint, const void* in, void* out, int nrhs, hipStream_t st,
+              bool finalize) {
+  const int64_t N = p->N;
+  const int P = planes_for(p, nrhs);
+  const bool real_io = p->prm.value_type == FFTPIM_REAL;
+  const bool use_perm = p->prm.order_io == FFTPIM_ORDER_USER;
+  p->last_stream = st;
+  if (p->timing && p->ev_used > 4096) resolve_timers(p);
+  {
+    StageTimer t(p, st, FFTPIM_STAGE_PACK);
+    launch_pack<R>(in, p->q_int, p->perm, N, nrhs, P, real_io, use_perm, st);
+    if (finalize && !adjoint && p->lat.npsp()) {
+      launch_plane_sums<R>(p->q_int, N, P, p->sums, st);
+      launch_check_neutral(p->sums, P, p->prm.precision == FFTPIM_F32 ? 1e-5 : 1e-10, p->status_dev, st);
+    }
+  }
+  const GridArgs ga = grid_args(p->ng);
+  if (parts & FFTPIM_PART_NEAR_GRID) {
+    // Steps 1-3 of Sec. 3.3 (the same grid serves sources and observers)
+    {
+      StageTimer t(p, st, FFTPIM_STAGE_NEAR_SPREAD);
+      CHK(launch_spread_near<R>(p->ng.q, ga, p->box_start, p->near_u, N, p->q_int, P, p->grid0, st));
+    }
+    {
+      StageTimer t(p, st, FFTPIM_STAGE_NEAR_FFT);
+      near_convolution<R>(p, P, adjoint, st);
+    }
+    StageTimer t(p, st, FFTPIM_STAGE_NEAR_INTERP);
+    CHK(launch_interp<R>(p->ng.q, ga, p->near_s, p->near_u, N, p->grid0, P, p->u_int, false, st));
+  } else {
+    HIPCHK(hipMemsetAsync(p->u_int, 0, static_cast<size_t>(N) * P * sizeof(cplx<R>), st));
+  }
+  if (parts & FFTPIM_PART_NEAR_CORR) {
+    // Step 4 of Sec. 3.3
+    const void* v = (adjoint && p->helmholtz) ? p->val_adj : p->val;
+    StageTimer t(p, st, FFTPIM_STAGE_NEAR_CORR);
+    launch_corr_spmv<R>(p->complex_kernel, p->rowptr, p->col, v, N, p->q_int, P, p->u_int, st);
+  }
+  if (parts & FFTPIM_PART_FAR) {
+    // Steps 1-3 of Sec. 3.2; the adjoint projects with the observer-grid
+    // weights, applies K^H and interpolates from the source grid
+    const FarArgs fa = far_args(p);
+    const int qf = p->fg.q;
+    const int32_t* fbs = adjoint ? p->fbox_start_o : p->fbox_start_s;
+    const int32_t* fpm = adjoint ? p->fperm_o : p->fperm_s;
+    const double* fu_in = adjoint ? p->fo_u : p->fs_u;
+    const int32_t* fs_out = adjoint ? p->fs_s : p->fo_s;
+    const double* fu_out = adjoint ? p->fs_u : p->fo_u;
+    StageTimer t(p, st, FFTPIM_STAGE_FAR);
+    CHK(launch_far_moments<R>(qf, fa, fbs, fpm, fu_in, N, p->q_int, P, p->far_mom, st));
+    CHK(launch_far_gather<R>(qf, fa, p->far_mom, P, p->far_q, st));
+    launch_far_apply<R>(fa, p->far_table, p->far_q, p->far_u, P, adjoint, st);
+    CHK(launch_interp<R>(qf, grid_args(p->fg), fs_out, fu_out, N, p->far_u, P, p->u_int, true, st));
+  }
+  const double* mean = nullptr;
+  if (finalize && adjoint && p->lat.npsp()) {
+    // only the zero-mean part of A^H v is defined for the neutral static case
+    launch_plane_sums<R>(p->u_int, N, P, p->sums, st);
+    launch_mean_from_sums(p->sums, P, N, p->sums + 4 * p->nplanes_max, st);
+    mean = p->sums + 4 * p->nplanes_max;
+  }
+  {
+    StageTimer t(p, st, FFTPIM_STAGE_UNPACK);
+    launch_unpack<R>(p->u_int, out, p->perm, N, nrhs, P, real_io, use_perm, mean, st);
+  }
+  if (hipPeekAtLastError() != hipSuccess) return FFTPIM_ERR_DEVICE;
+  return FFTPIM_OK;
+}
+
+int apply_common(fftpim_plan_t plan, int parts, int adjoint, const void* in, void* out, int nrhs,
+                 fftpim_stream_t stream, bool finalize) {
+  if (!plan || !in || !out) return FFTPIM_ERR_INVALID_ARG;
+  if (nrhs < 1 || nrhs > plan->prm.nrhs_max) return FFTPIM_ERR_INVALID_ARG;
+  if (parts < 0 || parts > FFTPIM_PART_ALL) return FFTPIM_ERR_INVALID_ARG;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (plan->prm.precision == FFTPIM_F32)
+    return run_apply<float>(plan, parts, adjoint != 0, in, out, nrhs, st, finalize);
+  return run_apply<double>(plan, parts, adjoint != 0, in, out, nrhs, st, finalize);
+}
+
+// ---------------------------------------------------------------------------
+// plan construction
+// ---------------------------------------------------------------------------
+
+int validate(const fftpim_problem_t* pr, const fftpim_params_t* pm) {
+  if (pr->periodic_dims < 1 || pr->periodic_dims > 3) return FFTPIM_ERR_INVALID_ARG;
+  for (int c = 0; c < pr->periodic_dims; ++c)
+    if (!(pr->L[c] > 0.0) || !std::isfinite(pr->L[c])) return FFTPIM_ERR_INVALID_ARG;
+  if (!std::isfinite(pr->k0) || pr->k0 < 0.0) return FFTPIM_ERR_INVALID_ARG;
+  for (int c = 0; c < 3; ++c)
+    if (!std::isfinite(pr->kt[c])) return FFTPIM_ERR_INVALID_ARG;
+  if (pm->near_order < 1 || pm->near_order > kMaxNearOrder) return FFTPIM_ERR_INVALID_ARG;
+  if (pm->far_order < 1 || pm->far_order > kMaxFarOrder) return FFTPIM_ERR_INVALID_ARG;
+  for (int c = 0; c < 3; ++c) {
+    if (pm->near_n[c] < pm->near_order + 2 || !is_pow2(2 * pm->near_n[c]) || pm->near_n[c] > 2048)
+      return FFTPIM_ERR_INVALID_ARG;
+    if (pm->far_n[c] < pm->far_order + 2 || pm->far_n[c] > 512) return FFTPIM_ERR_INVALID_ARG;
+  }
+  if (pm->corr_radius < pm->near_order || pm->corr_radius > kMaxCorrRadius) return FFTPIM_ERR_INVALID_ARG;
+  if (pm->n_images < 0 || pm->n_images > 2) return FFTPIM_ERR_INVALID_ARG;
+  if (pm->precision != FFTPIM_F64 && pm->precision != FFTPIM_F32) return FFTPIM_ERR_INVALID_ARG;
+  if (pm->value_type != FFTPIM_REAL && pm->value_type != FFTPIM_COMPLEX) return FFTPIM_ERR_INVALID_ARG;
+  if (pm->self_mode != FFTPIM_SELF_IMAGES && pm->self_mode != FFTPIM_SELF_EXCLUDE) return FFTPIM_ERR_INVALID_ARG;
+  if (pm->order_io != FFTPIM_ORDER_USER && pm->order_io != FFTPIM_ORDER_PLAN) return FFTPIM_ERR_INVALID_ARG;
+  if (pm->nrhs_max < 1 || pm->nrhs_max > 4096) return FFTPIM_ERR_INVALID_ARG;
+  return FFTPIM_OK;
+}
+
+template <typename R>
+std::vector<cplx<R>> twiddles(int M) {
+  std::vector<cplx<R>> t(std::max(1, M / 2));
+  for (int k = 0; k < M / 2; ++k) {
+    double a = 2.0 * kPi * k / M;
+    t[k] = cmake<R>(static_cast<R>(std::cos(a)), static_cast<R>(-std::sin(a)));
+  }
+  return t;
+}
+
+template <typename R>
+int build_tables(fftpim_plan_s* p, hipStream_t st) {
+  // twiddles per axis (working precision)
+  for (int c = 0; c < 3; ++c) {
+    cplx<R>* tw = nullptr;
+    CHK(upload(p, &tw, twiddles<R>(p->M[c])));
+    p->twiddle[c] = tw;
+  }
+  // near-zone table G^p_near at node offsets, zero padded, FFT in FP64
+  const int dims = p->lat.dims;
+  const int id = p->prm.n_images;
+  std::vector<int> img;
+  std::vector<double> ph;
+  int lim[3];
+  for (int c = 0; c < 3; ++c) lim[c] = c < dims ? id : 0;
+  for (int ix = -lim[0]; ix <= lim[0]; ++ix)
+    for (int iy = -lim[1]; iy <= lim[1]; ++iy)
+      for (int iz = -lim[2]; iz <= lim[2]; ++iz) {
+        img.push_back(ix);
+        img.push_back(iy);
+        img.push_back(iz);
+        double a = p->lat.kt[0] * ix * p->lat.L[0] + p->lat.kt[1] * iy * p->lat.L[1] + p->lat.kt[2] * iz * p->lat.L[2];
+        ph.push_back(std::cos(a));
+        ph.push_back(-std::sin(a));
+      }
+  int* dimg = nullptr;
+  double* dph = nullptr;
+  CHK(upload(p, &dimg, img));
+  CHK(upload(p, &dph, ph));
+  NearTableArgs na{};
+  for (int c = 0; c < 3; ++c) {
+    na.M[c] = p->M[c];
+    na.n[c] = p->ng.n[c];
+    na.nint[c] = p->ng.nint[c];
+    na.h[c] = p->ng.h[c];
+  }
+  na.k0 = p->lat.k0;
+  na.nimg = static_cast<int>(img.size() / 3);
+  na.img = dimg;
+  na.phase = dph;
+  const int64_t total = static_cast<int64_t>(p->M[0]) * p->M[1] * p->M[2];
+  cplx<double>* T = nullptr;
+  CHK(dalloc(p, &T, total));
+  launch_near_table(T, na, st);
+  cplx<double>* tw64[3];
+  for (int c = 0; c < 3; ++c) CHK(upload(p, &tw64[c], twiddles<double>(p->M[c])));
+  {
+    const int Mx = p->M[0], My = p->M[1], Mz = p->M[2];
+    const size_t es = sizeof(cplx<double>);
+    FftPassDesc dz = pass_desc(Mz, Mz, Mz, true, static_cast<int64_t>(Mx) * My, 1, 1, Mz, 1, Mz, es);
+    launch_fft_pass<double>(0, T, T, dz, tw64[2], nullptr, false, st);
+    FftPassDesc dy = pass_desc(My, My, My, false, Mx, Mz, Mz, static_cast<int64_t>(My) * Mz, Mz,
+                               static_cast<int64_t>(My) * Mz, es);
+    launch_fft_pass<double>(0, T, T, dy, tw64[1], nullptr, false, st);
+    const int64_t cols = static_cast<int64_t>(My) * Mz;
+    FftPassDesc dx = pass_desc(Mx, Mx, Mx, false, 1, cols, cols, Mx * cols, cols, Mx * cols, es);
+    launch_fft_pass<double>(0, T, T, dx, tw64[0], nullptr, false, st);
+  }
+  cplx<R>* hat = nullptr;
+  CHK(dalloc(p, &hat, total));
+  launch_scale_convert<R>(T, hat, total, 1.0 / static_cast<double>(total), st);
+  p->near_hat = hat;
+  HIPCHK(hipStreamSynchronize(st));
+  dfree(p, T);
+  for (int c = 0; c < 3; ++c) dfree(p, tw64[c]);
+  dfree(p, dimg);
+  dfree(p, dph);
+
+  // far-zone table G^p_far at the offsets between observer and source grids
+  std::vector<cd> ft;
+  int nf[3] = {p->fg.n[0], p->fg.n[1], p->fg.n[2]};
+  far_table(p->lat, id, nf, p->fg.h, ft);
+  std::vector<cplx<R>> ftr(ft.size());
+  for (size_t i = 0; i < ft.size(); ++i) {
+    if (!std::isfinite(ft[i].real()) || !std::isfinite(ft[i].imag())) return FFTPIM_ERR_UNSUPPORTED;
+    ftr[i] = cmake<R>(static_cast<R>(ft[i].real()), static_cast<R>(ft[i].imag()));
+  }
+  cplx<R>* dft = nullptr;
+  CHK(upload(p, &dft, ftr));
+  p->far_table = dft;
+  return FFTPIM_OK;
+}
+
+int build_correction(fftpim_plan_s* p, const std::vector<int32_t>& s_host, const double* pos3_dev,
+                     hipStream_t st) {
+  const int q = p->ng.q, rc = p->prm.corr_radius, id = p->prm.n_images;
+  const int dims = p->lat.dims;
+  const int A = 2 * id + 1;
+  CorrArgs ca{};
+  for (int c = 0; c < 3; ++c) {
+    ca.nb[c] = p->nb[c];
+    ca.nint[c] = p->ng.nint[c];
+    ca.per[c] = c < dims ? 1 : 0;
+    ca.L[c] = p->lat.L[c];
+  }
+  ca.rc = rc;
+  ca.id = id;
+  ca.R = rc + q;
+  ca.W = 2 * ca.R + 1;
+  ca.N = p->N;
+  ca.k0 = p->lat.k0;
+  ca.nimg_axis = A;
+  // image phases indexed by (gx, gy, gz), image g - id on periodic axes
+  std::vector<double> ph(2 * A * A * A, 0.0);
+  for (int gx = 0; gx < A; ++gx)
+    for (int gy = 0; gy < A; ++gy)
+      for (int gz = 0; gz < A; ++gz) {
+        int im[3] = {gx - id * ca.per[0], gy - id * ca.per[1], gz - id * ca.per[2]};
+        double a = 0.0;
+        for (int c = 0; c < 3; ++c) a += p->lat.kt[c] * im[c] * p->lat.L[c];
+        int k = (gx * A + gy) * A + gz;
+        ph[2 * k] = std::cos(a);
+        ph[2 * k + 1] = -std::sin(a);
+      }
+  double* dph = nullptr;
+  CHK(upload(p, &dph, ph));
+  ca.phase = dph;
+  // per-axis candidate source boxes for every observer box
+  int32_t* doff[3];
+  int32_t* dent[3];
+  for (int c = 0; c < 3; ++c) {
+    const int nint = p->ng.nint[c];
+    std::vector<int32_t> off(nint + 2, 0), ent;
+    for (int S = 0; S <= nint; ++S) {
+      off[S] = static_cast<int32_t>(ent.size());
+      for (int b = 0; b <= nint; ++b) {
+        int mask = 0;
+        if (ca.per[c]) {
+          for (int i = -id; i <= id; ++i)
+            if (std::abs(S - b - i * nint) <= rc) mask |= 1 << (i + id);
+        } else if (std::abs(S - b) <= rc) {
+          mask = 1;
+        }
+        if (mask) ent.push_back(b | (mask << 16));
+      }
+    }
+    off[nint + 1] = static_cast<int32_t>(ent.size());
+    CHK(upload(p, &doff[c], off));
+    CHK(upload(p, &dent[c], ent));
+    ca.loff[c] = doff[c];
+    ca.lent[c] = dent[c];
+  }
+  // G0 at node offsets [-R, R]^3 (0 at the origin)
+  const int W = ca.W, Rr = ca.R;
+  std::vector<cplx<double>> g0t(static_cast<size_t>(W) * W * W);
+  for (int ex = -Rr; ex <= Rr; ++ex)
+    for (int ey = -Rr; ey <= Rr; ++ey)
+      for (int ez = -Rr; ez <= Rr; ++ez) {
+        size_t k = (static_cast<size_t>(ex + Rr) * W + (ey + Rr)) * W + (ez + Rr);
+        if (ex == 0 && ey == 0 && ez == 0) {
+          g0t[k] = cmake<double>(0.0, 0.0);
+          continue;
+        }
+        double dx = ex * p->ng.h[0], dy = ey * p->ng.h[1], dz = ez * p->ng.h[2];
+        cd g = g0(std::sqrt(dx * dx + dy * dy + dz * dz), p->lat.k0);
+        g0t[k] = cmake<double>(g.real(), g.imag());
+      }
+  cplx<double>* dg0 = nullptr;
+  CHK(upload(p, &dg0, g0t));
+  // count, scan, fill
+  int64_t* dcount = nullptr;
+  CHK(dalloc(p, &dcount, p->N));
+  CHK(launch_corr_count(ca, p->near_s, p->box_start, dcount, st));
+  std::vector<int64_t> rowptr(p->N + 1, 0);
+  HIPCHK(hipMemcpyAsync(rowptr.data() + 1, dcount, p->N * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (int64_t m = 0; m < p->N; ++m) rowptr[m + 1] += rowptr[m];
+  p->nnz = rowptr[p->N];
+  CHK(upload(p, &p->rowptr, rowptr));
+  CHK(dalloc(p, &p->col, p->nnz));
+  const bool cv = p->complex_kernel;
+  const size_t vb = cv ? 16 : 8;
+  {
+    unsigned char* v = nullptr;
+    CHK(dalloc(p, &v, p->nnz * vb));
+    p->val = v;
+    if (p->helmholtz) {
+      unsigned char* va = nullptr;
+      CHK(dalloc(p, &va, p->nnz * vb));
+      p->val_adj = va;
+    }
+  }
+  CHK(launch_corr_fill(q, cv, p->helmholtz, ca, p->near_s, p->near_u, pos3_dev, p->box_start, dg0, p->rowptr,
+                       p->col, p->val, p->val_adj, st));
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipGetLastError());
+  dfree(p, dcount);
+  dfree(p, dg0);
+  dfree(p, dph);
+  for (int c = 0; c < 3; ++c) {
+    dfree(p, doff[c]);
+    dfree(p, dent[c]);
+  }
+  (void)s_host;
+  return FFTPIM_OK;
+}
+
+int build_plan(fftpim_plan_s* p, int64_t N, const double* src_dev, hipStream_t st) {
+  const fftpim_problem_t& pr = p->problem;
+  const fftpim_params_t& pm = p->prm;
+  const int dims = pr.periodic_dims;
+  // positions to host
+  std::vector<double> xyz(static_cast<size_t>(N) * 3);
+  HIPCHK(hipMemcpyAsync(xyz.data(), src_dev, xyz.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  // target region D (Sec. 3.2): the cell on periodic axes; the given box or
+  // the bounding box elsewhere
+  double lo[3], hi[3];
+  for (int c = 0; c < 3; ++c) {
+    double mn = INFINITY, mx = -INFINITY;
+    for (int64_t i = 0; i < N; ++i) {
+      double v = xyz[3 * i + c];
+      if (!std::isfinite(v)) return FFTPIM_ERR_INVALID_ARG;
+      mn = std::min(mn, v);
+      mx = std::max(mx, v);
+    }
+    if (c < dims) {
+      if (mn < 0.0 || mx >= pr.L[c]) return FFTPIM_ERR_OUT_OF_CELL;
+      lo[c] = 0.0;
+      hi[c] = pr.L[c];
+    } else if (pr.has_box) {
+      if (mn < pr.box_lo[c] || mx > pr.box_hi[c] || !(pr.box_hi[c] > pr.box_lo[c])) return FFTPIM_ERR_OUT_OF_CELL;
+      lo[c] = pr.box_lo[c];
+      hi[c] = pr.box_hi[c];
+    } else {
+      lo[c] = mn;
+      hi[c] = mx > mn ? mx : mn + 1.0;
+    }
+  }
+  // near grid (Sec. 3.3): n - q cells on periodic axes, n - q - 1 otherwise
+  GridGeom& g = p->ng;
+  g.q = pm.near_order;
+  for (int c = 0; c < 3; ++c) {
+    g.n[c] = pm.near_n[c];
+    g.nint[c] = c < dims ? g.n[c] - g.q : g.n[c] - g.q - 1;
+    if (g.nint[c] < 1) return FFTPIM_ERR_INVALID_ARG;
+    g.h[c] = (hi[c] - lo[c]) / g.nint[c];
+    g.origin[c] = lo[c] - 0.5 * (g.q - 1) * g.h[c];
+    g.lo[c] = lo[c];
+    p->M[c] = 2 * g.n[c];
+    p->nb[c] = g.nint[c] + 1;
+  }
+  // far grids (Sec. 3.2, Eq. (grid)): n - q - 1 cells on every axis
+  GridGeom& f = p->fg;
+  f.q = pm.far_order;
+  for (int c = 0; c < 3; ++c) {
+    f.n[c] = pm.far_n[c];
+    f.nint[c] = f.n[c] - f.q - 1;
+    if (f.nint[c] < 1) return FFTPIM_ERR_INVALID_ARG;
+    f.h[c] = (hi[c] - lo[c]) / f.nint[c];
+    f.origin[c] = lo[c] - 0.5 * (f.q - 1) * f.h[c];
+    f.lo[c] = lo[c];
+    p->fnb[c] = f.nint[c] + 1;
+  }
+  // near stencils and the box sort
+  std::vector<int32_t> s(3 * N);
+  std::vector<double> u(3 * N);
+  std::vector<int64_t> key(N);
+  for (int64_t i = 0; i < N; ++i) {
+    for (int c = 0; c < 3; ++c) stencil(xyz[3 * i + c], g.origin[c], g.h[c], g.q, g.n[c], s[3 * i + c], u[3 * i + c]);
+    key[i] = (static_cast<int64_t>(s[3 * i]) * p->nb[1] + s[3 * i + 1]) * p->nb[2] + s[3 * i + 2];
+  }
+  const int64_t nboxes = static_cast<int64_t>(p->nb[0]) * p->nb[1] * p->nb[2];
+  std::vector<int32_t> order, start;
+  counting_sort(key, nboxes, order, start);
+  std::vector<int32_t> s_sorted(3 * N), fs_s(3 * N), fo_s(3 * N);
+  std::vector<double> u_sorted(3 * N), pos_sorted(3 * N), fs_u(3 * N), fo_u(3 * N);
+  std::vector<int64_t> fkey_s(N), fkey_o(N);
+  for (int64_t j = 0; j < N; ++j) {
+    const int64_t i = order[j];
+    for (int c = 0; c < 3; ++c) {
+      s_sorted[c * N + j] = s[3 * i + c];
+      u_sorted[c * N + j] = u[3 * i + c];
+      pos_sorted[c * N + j] = xyz[3 * i + c];
+      stencil(xyz[3 * i + c], f.origin[c], f.h[c], f.q, f.n[c], fs_s[c * N + j], fs_u[c * N + j]);
+      stencil(xyz[3 * i + c], f.origin[c] - 0.5 * f.h[c], f.h[c], f.q, f.n[c], fo_s[c * N + j], fo_u[c * N + j]);
+    }
+    fkey_s[j] = (static_cast<int64_t>(fs_s[j]) * p->fnb[1] + fs_s[N + j]) * p->fnb[2] + fs_s[2 * N + j];
+    fkey_o[j] = (static_cast<int64_t>(fo_s[j]) * p->fnb[1] + fo_s[N + j]) * p->fnb[2] + fo_s[2 * N + j];
+  }
+  const int64_t fboxes = static_cast<int64_t>(p->fnb[0]) * p->fnb[1] * p->fnb[2];
+  std::vector<int32_t> forder_s, fstart_s, forder_o, fstart_o;
+  counting_sort(fkey_s, fboxes, forder_s, fstart_s);
+  counting_sort(fkey_o, fboxes, forder_o, fstart_o);
+
+  CHK(upload(p, &p->perm, order));
+  CHK(upload(p, &p->near_s, s_sorted));
+  CHK(upload(p, &p->near_u, u_sorted));
+  CHK(upload(p, &p->box_start, start));
+  CHK(upload(p, &p->fs_s, fs_s));
+  CHK(upload(p, &p->fs_u, fs_u));
+  CHK(upload(p, &p->fo_s, fo_s));
+  CHK(upload(p, &p->fo_u, fo_u));
+  CHK(upload(p, &p->fperm_s, forder_s));
+  CHK(upload(p, &p->fbox_start_s, fstart_s));
+  CHK(upload(p, &p->fperm_o, forder_o));
+  CHK(upload(p, &p->fbox_start_o, fstart_o));
+  double* dpos = nullptr;
+  CHK(upload(p, &dpos, pos_sorted));
+
+  if (pm.precision == FFTPIM_F32)
+    CHK(build_tables<float>(p, st));
+  else
+    CHK(build_tables<double>(p, st));
+  CHK(build_correction(p, s_sorted, dpos, st));
+  dfree(p, dpos);
+
+  // workspace
+  const int P = planes_for(p, pm.nrhs_max);
+  p->nplanes_max = P;
+  const size_t es = cbytes(p);
+  const int64_t n3 = static_cast<int64_t>(g.n[0]) * g.n[1] * g.n[2];
+  unsigned char* b = nullptr;
+  CHK(dalloc(p, &b, static_cast<size_t>(N) * P * es));
+  p->q_int = b;
+  CHK(dalloc(p, &b, static_cast<size_t>(N) * P * es));
+  p->u_int = b;
+  CHK(dalloc(p, &b, static_cast<size_t>(n3) * P * es));
+  p->grid0 = b;
+  CHK(dalloc(p, &b, static_cast<size_t>(g.n[0]) * g.n[1] * p->M[2] * P * es));
+  p->bufA = b;
+  CHK(dalloc(p, &b, static_cast<size_t>(g.n[0]) * p->M[1] * p->M[2] * P * es));
+  p->bufB = b;
+  const int K1 = f.q + 1;
+  CHK(dalloc(p, &b, static_cast<size_t>(fboxes) * K1 * K1 * K1 * P * es));
+  p->far_mom = b;
+  const int64_t Ngf = static_cast<int64_t>(f.n[0]) * f.n[1] * f.n[2];
+  CHK(dalloc(p, &b, static_cast<size_t>(Ngf) * P * es));
+  p->far_q = b;
+  CHK(dalloc(p, &b, static_cast<size_t>(Ngf) * P * es));
+  p->far_u = b;
+  CHK(dalloc(p, &p->sums, static_cast<size_t>(6) * P));
+  CHK(dalloc(p, &p->status_dev, 1));
+  HIPCHK(hipMemsetAsync(p->status_dev, 0, sizeof(int), st));
+  HIPCHK(hipStreamSynchronize(st));
+  return FFTPIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fftpim_default_params(const fftpim_problem_t* problem, fftpim_params_t* params) {
+  if (!problem || !params) return FFTPIM_ERR_INVALID_ARG;
+  fftpim_params_t p{};
+  for (int c = 0; c < 3; ++c) {
+    p.near_n[c] = 16;
+    p.far_n[c] = 16;
+  }
+  p.near_order = 4;
+  p.corr_radius = 6;
+  p.far_order = 7;
+  p.n_images = 1;
+  p.precision = FFTPIM_F64;
+  p.value_type = FFTPIM_COMPLEX;
+  p.self_mode = FFTPIM_SELF_IMAGES;
+  p.order_io = FFTPIM_ORDER_USER;
+  p.nrhs_max = 1;
+  *params = p;
+  return FFTPIM_OK;
+}
+
+int fftpim_plan(fftpim_plan_t* plan, const fftpim_problem_t* problem, const fftpim_params_t* params,
+                int64_t n_src, const double* src_xyz_dev, int64_t n_obs, const double* obs_xyz_dev,
+                fftpim_stream_t stream) {
+  if (!plan || !problem || !params || !src_xyz_dev) return FFTPIM_ERR_INVALID_ARG;
+  *plan = nullptr;
+  if (n_src < 1 || n_src > (int64_t{1} << 30)) return FFTPIM_ERR_INVALID_ARG;
+  if (obs_xyz_dev != nullptr) return FFTPIM_ERR_UNIMPLEMENTED;
+  if (n_obs != n_src && n_obs != 0) return FFTPIM_ERR_INVALID_ARG;
+  CHK(validate(problem, params));
+  Lattice lat{};
+  lat.dims = problem->periodic_dims;
+  for (int c = 0; c < 3; ++c) {
+    lat.L[c] = c < lat.dims ? problem->L[c] : 1.0;
+    lat.kt[c] = c < lat.dims ? problem->kt[c] : 0.0;
+  }
+  lat.k0 = problem->k0;
+  if (params->value_type == FFTPIM_REAL && !lat.npsp()) return FFTPIM_ERR_INVALID_ARG;
+  if (params->self_mode == FFTPIM_SELF_EXCLUDE) return FFTPIM_ERR_UNIMPLEMENTED;
+  if (check_supported(lat)) return FFTPIM_ERR_UNSUPPORTED;
+  if (wood_anomaly(lat)) return FFTPIM_ERR_WOOD_ANOMALY;
+  auto t0 = std::chrono::steady_clock::now();
+  fftpim_plan_s* p = new (std::nothrow) fftpim_plan_s();
+  if (!p) return FFTPIM_ERR_NO_MEMORY;
+  p->lat = lat;
+  p->problem = *problem;
+  p->prm = *params;
+  p->N = n_src;
+  p->complex_kernel = !lat.npsp();
+  p->helmholtz = lat.k0 != 0.0;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int s = build_plan(p, n_src, src_xyz_dev, st);
+  if (s != FFTPIM_OK) {
+    fftpim_destroy(p);
+    return s;
+  }
+  p->plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  p->last_stream = st;
+  if (std::getenv("FFTPIM_LOG")) {
+    std::fprintf(stderr, "fftpim plan: N=%lld near %dx%dx%d q=%d rc=%d far %dx%dx%d q=%d nnz=%lld bytes=%lld %.3fs\n",
+                 static_cast<long long>(p->N), p->ng.n[0], p->ng.n[1], p->ng.n[2], p->ng.q, p->prm.corr_radius,
+                 p->fg.n[0], p->fg.n[1], p->fg.n[2], p->fg.q, static_cast<long long>(p->nnz),
+                 static_cast<long long>(p->device_bytes), p->plan_seconds);
+  }
+  *plan = p;
+  return FFTPIM_OK;
+}
+
+int fftpim_apply(fftpim_plan_t plan, const void* q_dev, void* u_dev, int nrhs, fftpim_stream_t stream) {
+  return apply_common(plan, FFTPIM_PART_ALL, 0, q_dev, u_dev, nrhs, stream, true);
+}
+
+int fftpim_apply_adjoint(fftpim_plan_t plan, const void* v_dev, void* w_dev, int nrhs, fftpim_stream_t stream) {
+  return apply_common(plan, FFTPIM_PART_ALL, 1, v_dev, w_dev, nrhs, stream, true);
+}
+
+int fftpim_apply_parts(fftpim_plan_t plan, int parts, int adjoint, const void* q_dev, void* u_dev, int nrhs,
+                       fftpim_stream_t stream) {
+  return apply_common(plan, parts, adjoint, q_dev, u_dev, nrhs, stream, false);
+}
+
+int fftpim_get_permutation(fftpim_plan_t plan, int which, int32_t* perm_dev) {
+  if (!plan || !perm_dev || (which != 0 && which != 1)) return FFTPIM_ERR_INVALID_ARG;
+  HIPCHK(hipMemcpy(perm_dev, plan->perm, plan->N * sizeof(int32_t), hipMemcpyDeviceToDevice));
+  return FFTPIM_OK;
+}
+
+int fftpim_plan_info(fftpim_plan_t plan, fftpim_info_t* info) {
+  if (!plan || !info) return FFTPIM_ERR_INVALID_ARG;
+  fftpim_info_t r{};
+  r.n_src = plan->N;
+  r.n_obs = plan->N;
+  for (int c = 0; c < 3; ++c) {
+    r.near_n[c] = plan->ng.n[c];
+    r.near_fft[c] = plan->M[c];
+    r.near_cells[c] = plan->ng.nint[c];
+    r.near_h[c] = plan->ng.h[c];
+    r.domain_lo[c] = plan->ng.lo[c];
+    r.domain_hi[c] = plan->ng.lo[c] + plan->ng.h[c] * plan->ng.nint[c];
+    r.far_n[c] = plan->fg.n[c];
+    r.far_cells[c] = plan->fg.nint[c];
+    r.far_h[c] = plan->fg.h[c];
+  }
+  r.corr_nnz = plan->nnz;
+  r.device_bytes = plan->device_bytes;
+  r.nplanes_max = plan->nplanes_max;
+  r.plan_seconds = plan->plan_seconds;
+  *info = r;
+  return FFTPIM_OK;
+}
+
+int fftpim_last_status(fftpim_plan_t plan) {
+  if (!plan) return FFTPIM_ERR_INVALID_ARG;
+  HIPCHK(hipStreamSynchronize(plan->last_stream));
+  int v = 0;
+  HIPCHK(hipMemcpy(&v, plan->status_dev, sizeof(int), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemset(plan->status_dev, 0, sizeof(int)));
+  return v;
+}
+
+int fftpim_stage_times(fftpim_plan_t plan, int enable, double* ms_out, int64_t* calls_out) {
+  if (!plan) return FFTPIM_ERR_INVALID_ARG;
+  resolve_timers(plan);
+  if (ms_out)
+    for (int s = 0; s < FFTPIM_NSTAGES; ++s) ms_out[s] = plan->stage_ms[s];
+  if (calls_out)
+    for (int s = 0; s < FFTPIM_NSTAGES; ++s) calls_out[s] = plan->stage_calls[s];
+  if (enable) {
+    for (int s = 0; s < FFTPIM_NSTAGES; ++s) {
+      plan->stage_ms[s] = 0.0;
+      plan->stage_calls[s] = 0;
+    }
+  }
+  plan->timing = enable != 0;
+  return FFTPIM_OK;
+}
+
+int fftpim_destroy(fftpim_plan_t plan) {
+  if (!plan) return FFTPIM_OK;
+  for (hipEvent_t e : plan->ev_pool) hipEventDestroy(e);
+  plan->ev_pool.clear();
+  for (void* ptr : plan->allocations) hipFree(ptr);
+  plan->allocations.clear();
+  delete plan;
+  return FFTPIM_OK;
+}
+
+const char* fftpim_error_string(int status) {
+  switch (status) {
+    case FFTPIM_OK: return "success";
+    case FFTPIM_ERR_INVALID_ARG: return "invalid argument";
+    case FFTPIM_ERR_OUT_OF_CELL: return "a point lies outside the zeroth cell or the given box";
+    case FFTPIM_ERR_NOT_NEUTRAL: return "static no-phase problem with a non-neutral right-hand side";
+    case FFTPIM_ERR_WOOD_ANOMALY: return "a Floquet wavenumber vanishes (Rayleigh-Wood anomaly)";
+    case FFTPIM_ERR_UNSUPPORTED: return "problem class not supported by this build";
+    case FFTPIM_ERR_NO_MEMORY: return "out of memory";
+    case FFTPIM_ERR_DEVICE: return "HIP runtime error";
+    case FFTPIM_ERR_UNIMPLEMENTED: return "not implemented";
+    default: return "unknown status";
+  }
+}
+
+int fftpim_eval_pgf(const fftpim_problem_t* problem, int64_t n, const double* r_xyz, double* out) {
+  if (!problem || !r_xyz || !out || n < 0) return FFTPIM_ERR_INVALID_ARG;
+  if (problem->periodic_dims < 1 || problem->periodic_dims > 3) return FFTPIM_ERR_INVALID_ARG;
+  Lattice lat{};
+  lat.dims = problem->periodic_dims;
+  for (int c = 0; c < 3; ++c) {
+    lat.L[c] = c < lat.dims ? problem->L[c] : 1.0;
+    lat.kt[c] = c < lat.dims ? problem->kt[c] : 0.0;
+  }
+  lat.k0 = problem->k0;
+  if (check_supported(lat)) return FFTPIM_ERR_UNSUPPORTED;
+  for (int64_t i = 0; i < n; ++i) {
+    cd v = pgf(lat, r_xyz + 3 * i);
+    out[2 * i] = v.real();
+    out[2 * i + 1] = v.imag();
+  }
+  return FFTPIM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,198 @@
+// Shared definitions of the FFT-PIM library: complex helpers, grid geometry and
+// the plan object.  Device code targets gfx950 (CDNA4, 64-wide wavefronts).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/fftpim.h"
+#include "pgf_host.h"
+
+namespace fftpim {
+
+template <typename R>
+struct cplx {
+  R x, y;
+};
+
+template <typename R>
+__host__ __device__ inline cplx<R> cmake(R a, R b) {
+  cplx<R> c;
+  c.x = a;
+  c.y = b;
+  return c;
+}
+template <typename R>
+__host__ __device__ inline cplx<R> cadd(cplx<R> a, cplx<R> b) {
+  return cmake<R>(a.x + b.x, a.y + b.y);
+}
+template <typename R>
+__host__ __device__ inline cplx<R> csub(cplx<R> a, cplx<R> b) {
+  return cmake<R>(a.x - b.x, a.y - b.y);
+}
+template <typename R>
+__host__ __device__ inline cplx<R> cmul(cplx<R> a, cplx<R> b) {
+  return cmake<R>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename R>
+__host__ __device__ inline cplx<R> cconj(cplx<R> a) {
+  return cmake<R>(a.x, -a.y);
+}
+template <typename R>
+__host__ __device__ inline cplx<R> cscale(cplx<R> a, R s) {
+  return cmake<R>(a.x * s, a.y * s);
+}
+
+// Geometry of one uniform grid with an interpolation halo (Sec. 3.2, Eq. (grid)):
+// node l on axis c sits at origin[c] + l h[c]; a point uses the q+1 nodes
+// s..s+q.  Cells (boxes) are indexed by s in [0, nint].
+struct GridGeom {
+  int n[3];        // nodes per axis
+  int nint[3];     // cells per axis
+  int q;           // Lagrange degree
+  double h[3];     // spacing
+  double origin[3];
+  double lo[3];    // start of the target region
+};
+
+// Lagrange basis value l_k(u) on the nodes 0..Q at position u.
+template <int Q, typename R>
+__host__ __device__ inline R lagrange_basis(int k, R u) {
+  // c_k = 1 / prod_{j != k} (k - j) = (-1)^{Q-k} / (k! (Q-k)!)
+  R num = R(1);
+  R den = R(1);
+#pragma unroll
+  for (int j = 0; j <= Q; ++j) {
+    if (j != k) {
+      num *= (u - R(j));
+      den *= R(k - j);
+    }
+  }
+  return num / den;
+}
+
+// All Q+1 basis values at u.
+template <int Q, typename R>
+__host__ __device__ inline void lagrange_all(R u, R* w) {
+  R left[Q + 1], right[Q + 1];
+  left[0] = R(1);
+#pragma unroll
+  for (int k = 1; k <= Q; ++k) left[k] = left[k - 1] * (u - R(k - 1));
+  right[Q] = R(1);
+#pragma unroll
+  for (int k = Q - 1; k >= 0; --k) right[k] = right[k + 1] * (u - R(k + 1));
+  R fact = R(1);
+  R inv_fact[Q + 1];
+  inv_fact[0] = R(1);
+#pragma unroll
+  for (int k = 1; k <= Q; ++k) {
+    fact *= R(k);
+    inv_fact[k] = R(1) / fact;
+  }
+#pragma unroll
+  for (int k = 0; k <= Q; ++k) {
+    R c = inv_fact[k] * inv_fact[Q - k];
+    if ((Q - k) & 1) c = -c;
+    w[k] = c * left[k] * right[k];
+  }
+}
+
+// 1 / prod_{j != k} (k - j) and prod_{j != k} (u - j): the two factors of the
+// Lagrange basis value l_k(u) on the nodes 0..Q.
+template <int Q>
+__host__ __device__ inline double basis_den_inv(int k) {
+  double d = 1.0;
+#pragma unroll
+  for (int j = 0; j <= Q; ++j)
+    if (j != k) d *= static_cast<double>(k - j);
+  return 1.0 / d;
+}
+
+template <int Q>
+__host__ __device__ inline double basis_num(int k, double u) {
+  double num = 1.0;
+#pragma unroll
+  for (int j = 0; j <= Q; ++j)
+    if (j != k) num *= (u - static_cast<double>(j));
+  return num;
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace fftpim
+
+struct fftpim_plan_s {
+  fftpim::Lattice lat;
+  fftpim_problem_t problem;
+  fftpim_params_t prm;
+  int64_t N = 0;
+  bool complex_kernel = true;  // G0 or the phases are complex
+  bool helmholtz = false;      // k0 != 0 (correction values not Hermitian)
+
+  // near grid
+  fftpim::GridGeom ng;
+  int M[3];        // FFT sizes (2 n)
+  int nb[3];       // boxes per axis (nint + 1)
+  // far grids (source grid origin; the observer grid is shifted by -h/2)
+  fftpim::GridGeom fg;
+  int fnb[3];
+
+  // sorted geometry (device)
+  int32_t* perm = nullptr;        // plan position -> caller index
+  int32_t* near_s = nullptr;      // [3][N] stencil starts (= near boxes)
+  double* near_u = nullptr;       // [3][N] position within the stencil
+  int32_t* box_start = nullptr;   // [nb^3 + 1] first point of each box
+  int32_t* fs_s = nullptr;        // far source-grid stencils [3][N]
+  double* fs_u = nullptr;
+  int32_t* fo_s = nullptr;        // far observer-grid stencils [3][N]
+  double* fo_u = nullptr;
+  int32_t* fperm_s = nullptr;     // points ordered by far source box
+  int32_t* fbox_start_s = nullptr;
+  int32_t* fperm_o = nullptr;     // points ordered by far observer box
+  int32_t* fbox_start_o = nullptr;
+
+  // tables
+  void* near_hat = nullptr;       // [Mx][My][Mz] complex R, scaled by 1/(Mx My Mz)
+  void* twiddle[3] = {nullptr, nullptr, nullptr};  // per axis, M/2 complex R
+  void* far_table = nullptr;      // [(2nf-1)^3] complex R
+  double self_value[2] = {0.0, 0.0};
+
+  // correction (FP64 values)
+  int64_t* rowptr = nullptr;
+  int32_t* col = nullptr;
+  void* val = nullptr;            // double or complex double
+  void* val_adj = nullptr;        // Helmholtz only: values of C^H on the same pattern
+  int64_t nnz = 0;
+
+  // workspace
+  int nplanes_max = 0;
+  void* q_int = nullptr;          // [N][planes] complex R (plan order)
+  void* u_int = nullptr;          // [N][planes] complex R
+  void* grid0 = nullptr;          // [planes][n^3]
+  void* bufA = nullptr;           // [planes][nx][ny][Mz]
+  void* bufB = nullptr;           // [planes][nx][My][Mz]
+  void* far_mom = nullptr;        // [far boxes][(qf+1)^3][planes]
+  void* far_q = nullptr;          // [planes][Ngf]
+  void* far_u = nullptr;          // [planes][Ngf]
+  double* sums = nullptr;         // [2][planes] neutrality / mean sums
+  int* status_dev = nullptr;      // latched device-detected error
+
+  // stage timing (fftpim_stage_times)
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<int, size_t>> ev_pairs;  // (stage, index of the start event)
+  double stage_ms[8] = {0};
+  int64_t stage_calls[8] = {0};
+
+  std::vector<void*> allocations;
+  int64_t device_bytes = 0;
+  double plan_seconds = 0.0;
+  hipStream_t last_stream = nullptr;
+};

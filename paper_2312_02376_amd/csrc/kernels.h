@@ -1,0 +1,105 @@
+// Kernel argument structs and launcher declarations shared by the kernel
+// translation units and the plan/apply orchestration.
+#pragma once
+
+#include "common.h"
+
+namespace fftpim {
+
+// Geometry of one grid as the kernels see it.
+struct GridArgs {
+  int n[3];     // nodes per axis
+  int nint[3];  // cells per axis (box index range 0..nint)
+  int nb[3];    // boxes per axis (nint + 1)
+};
+
+// One batched 1D FFT pass.  The data is viewed as outer x line x column; the
+// transform runs along the line.  contig = 1: lines are contiguous (in_line
+// = 1) and a block takes T consecutive outer indices; contig = 0: a block takes
+// one outer index and T consecutive columns (coalesced across the block).
+struct FftPassDesc {
+  int M, logM;         // transform length (power of 2)
+  int n_in, n_out;     // nonzero inputs / outputs kept along the line
+  int T;               // lines per block
+  int contig;
+  int64_t ncols, nouter;
+  int64_t in_line, in_col, in_outer;
+  int64_t out_line, out_col, out_outer;
+  int64_t spec_line, spec_col;  // spectrum strides (fused pass only)
+};
+
+struct NearTableArgs {
+  int M[3], n[3], nint[3];
+  double h[3];
+  double k0;
+  int nimg;
+  const int* img;        // device [nimg][3] image offsets
+  const double* phase;   // device [nimg][2] image phases
+};
+
+struct CorrArgs {
+  int nb[3], nint[3], per[3];
+  int rc, id;
+  int R, W;            // g0 table covers offsets [-R, R]^3, W = 2R + 1
+  int64_t N;
+  double L[3];
+  double k0;
+  int nimg_axis;       // 2 id + 1
+  const double* phase;    // device image phases (re, im), index (gx * A + gy) * A + gz, image g - id
+  // per-axis candidate source boxes of an observer box S: entries
+  // lent[c][loff[c][S] .. loff[c][S+1]) = b | (mask << 16), bit g of mask
+  // marking image g - id (g = 0 only on non-periodic axes) as close
+  const int32_t* loff[3];
+  const int32_t* lent[3];
+};
+
+struct FarArgs {
+  int nf[3], nint[3], nb[3];
+  int64_t Ngf;
+  int64_t nboxes;
+};
+
+template <typename R>
+void launch_pack(const void* qu, void* qint, const int32_t* perm, int64_t N, int nrhs, int P, bool real_in,
+                 bool use_perm, hipStream_t st);
+template <typename R>
+void launch_unpack(const void* uint, void* uu, const int32_t* perm, int64_t N, int nrhs, int P,
+                   bool real_out, bool use_perm, const double* mean, hipStream_t st);
+template <typename R>
+void launch_plane_sums(const void* v, int64_t N, int P, double* out, hipStream_t st);
+void launch_check_neutral(const double* sums, int P, double tol, int* status, hipStream_t st);
+void launch_mean_from_sums(const double* sums, int P, int64_t N, double* mean, hipStream_t st);
+template <typename R>
+int launch_spread_near(int q, const GridArgs& g, const int32_t* box_start, const double* u3, int64_t N,
+                       const void* qint, int P, void* grid, hipStream_t st);
+template <typename R>
+int launch_interp(int q, const GridArgs& g, const int32_t* s3, const double* u3, int64_t N, const void* grid,
+                  int P, void* uint, bool acc, hipStream_t st);
+template <typename R>
+void launch_fft_pass(int mode, const void* in, void* out, const FftPassDesc& d, const void* tw,
+                     const void* spec, bool conj_spec, hipStream_t st);
+void launch_near_table(void* T, const NearTableArgs& a, hipStream_t st);
+template <typename R>
+void launch_scale_convert(const void* in, void* out, int64_t n, double s, hipStream_t st);
+
+// correction
+int launch_corr_count(const CorrArgs& a, const int32_t* s3, const int32_t* box_start, int64_t* rowcount,
+                      hipStream_t st);
+int launch_corr_fill(int q, bool cplx_vals, bool adj, const CorrArgs& a, const int32_t* s3, const double* u3,
+                     const double* pos3, const int32_t* box_start, const void* g0tab, const int64_t* rowptr,
+                     int32_t* col, void* val, void* val_adj, hipStream_t st);
+template <typename R>
+void launch_corr_spmv(bool cplx_vals, const int64_t* rowptr, const int32_t* col, const void* val, int64_t N,
+                      const void* qint, int P, void* uint, hipStream_t st);
+
+// far zone
+template <typename R>
+int launch_far_moments(int qf, const FarArgs& f, const int32_t* fbox_start, const int32_t* fperm,
+                       const double* u3, int64_t N, const void* qint, int P, void* mom, hipStream_t st);
+template <typename R>
+int launch_far_gather(int qf, const FarArgs& f, const void* mom, int P, void* grid, hipStream_t st);
+template <typename R>
+void launch_far_apply(const FarArgs& f, const void* table, const void* in, void* out, int P, bool adjoint,
+                      hipStream_t st);
+
+}  // namespace fftpim

@@ -1,0 +1,307 @@
+// Near-zone error correction, Sec. 3.3 Step 4, Eq. (er), with only the close
+// images kept (end of Sec. 3.3).
+//
+// For an observer m and a source n, the image i (|i_c| <= i_d on periodic
+// axes) is close when the Chebyshev distance between m's near-grid box and
+// the image box s_n + i * nint is at most r_c.  The stored entry is
+//     C[m, n] = sum_{close i} phi_i X_i(m, n),
+//     X_i(m, n) = G0(r_m - r_n - R_i) - G_grid,i(m, n)      (G0 term dropped
+//                                                            for n = m, i = 0)
+//     G_grid,i(m, n) = sum_a sum_b w_a(r_m) w_b(r_n) G0tab((a - b - i nint) h)
+// and the double sum over the two (q+1)^3 stencils is evaluated through the
+// 1D weight correlations C_c(d) = sum_{a - b = d} w_a w_b, d in [-q, q]:
+//     G_grid,i = sum_{d in [-q, q]^3} Cx(dx) Cy(dy) Cz(dz) G0tab(Delta + d),
+// Delta = s_m - s_n - i nint.  Values are FP64.  For a Helmholtz kernel a
+// second array on the same (symmetric) pattern holds the conjugate transpose:
+// entry (n, m) of C^H equals sum_{close i} phi_i conj(X_i(n, m)).
+#include "kernels.h"
+
+namespace fftpim {
+
+// Per-axis candidate source boxes of an observer box: entries (b | mask << 16)
+// where bit (i + id) of mask marks image i_c as close.
+__device__ inline void axis_range(const int32_t* __restrict__ off, int S, int& lo, int& hi) {
+  lo = off[S];
+  hi = off[S + 1];
+}
+
+__global__ void k_corr_count(CorrArgs a, const int32_t* __restrict__ s3, const int32_t* __restrict__ box_start,
+                             int64_t* __restrict__ rowcount) {
+  const int32_t *loff0 = a.loff[0], *loff1 = a.loff[1], *loff2 = a.loff[2];
+  const int32_t *lent0 = a.lent[0], *lent1 = a.lent[1], *lent2 = a.lent[2];
+  int64_t m = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (m >= a.N) return;
+  int x0, x1, y0, y1, z0, z1;
+  axis_range(loff0, s3[m], x0, x1);
+  axis_range(loff1, s3[a.N + m], y0, y1);
+  axis_range(loff2, s3[2 * a.N + m], z0, z1);
+  int64_t cnt = 0;
+  for (int ix = x0; ix < x1; ++ix) {
+    int bx = lent0[ix] & 0xffff;
+    for (int iy = y0; iy < y1; ++iy) {
+      int by = lent1[iy] & 0xffff;
+      for (int iz = z0; iz < z1; ++iz) {
+        int bz = lent2[iz] & 0xffff;
+        int64_t b = (static_cast<int64_t>(bx) * a.nb[1] + by) * a.nb[2] + bz;
+        cnt += box_start[b + 1] - box_start[b];
+      }
+    }
+  }
+  rowcount[m] = cnt;
+}
+
+template <int Q, bool CPLX, bool ADJ>
+__global__ void __launch_bounds__(64) k_corr_fill(
+    CorrArgs a, const int32_t* __restrict__ s3, const double* __restrict__ u3, const double* __restrict__ pos3,
+    const int32_t* __restrict__ box_start, const cplx<double>* __restrict__ g0tab,
+    const int64_t* __restrict__ rowptr, int32_t* __restrict__ col, void* __restrict__ val_v,
+    void* __restrict__ vadj_v) {
+  const int32_t *loff0 = a.loff[0], *loff1 = a.loff[1], *loff2 = a.loff[2];
+  const int32_t *lent0 = a.lent[0], *lent1 = a.lent[1], *lent2 = a.lent[2];
+  int64_t m = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (m >= a.N) return;
+  const int64_t N = a.N;
+  const int S[3] = {s3[m], s3[N + m], s3[2 * N + m]};
+  double wm[3][Q + 1];
+  for (int c = 0; c < 3; ++c) lagrange_all<Q, double>(u3[c * N + m], wm[c]);
+  const double rm[3] = {pos3[m], pos3[N + m], pos3[2 * N + m]};
+  int lo[3], hi[3];
+  axis_range(loff0, S[0], lo[0], hi[0]);
+  axis_range(loff1, S[1], lo[1], hi[1]);
+  axis_range(loff2, S[2], lo[2], hi[2]);
+  const int A = a.nimg_axis;
+  const int W = a.W, R = a.R;
+  int64_t j = rowptr[m];
+  double* valr = static_cast<double*>(val_v);
+  cplx<double>* valc = static_cast<cplx<double>*>(val_v);
+  cplx<double>* vadj = static_cast<cplx<double>*>(vadj_v);
+  for (int ix = lo[0]; ix < hi[0]; ++ix) {
+    const int bx = lent0[ix] & 0xffff, mx = lent0[ix] >> 16;
+    for (int iy = lo[1]; iy < hi[1]; ++iy) {
+      const int by = lent1[iy] & 0xffff, my = lent1[iy] >> 16;
+      for (int iz = lo[2]; iz < hi[2]; ++iz) {
+        const int bz = lent2[iz] & 0xffff, mz = lent2[iz] >> 16;
+        const int64_t b = (static_cast<int64_t>(bx) * a.nb[1] + by) * a.nb[2] + bz;
+        const int n0 = box_start[b], n1 = box_start[b + 1];
+        for (int n = n0; n < n1; ++n) {
+          double wn[3][Q + 1];
+          for (int c = 0; c < 3; ++c) lagrange_all<Q, double>(u3[c * N + n], wn[c]);
+          double C[3][2 * Q + 1];
+          for (int c = 0; c < 3; ++c)
+            for (int d = -Q; d <= Q; ++d) {
+              double s = 0.0;
+              for (int aa = max(0, d); aa <= min(Q, Q + d); ++aa) s += wm[c][aa] * wn[c][aa - d];
+              C[c][d + Q] = s;
+            }
+          const double rn[3] = {pos3[n], pos3[N + n], pos3[2 * N + n]};
+          double fr = 0.0, fi = 0.0, ar = 0.0, ai = 0.0;
+          for (int gx = 0; gx < A; ++gx) {
+            if (!((mx >> gx) & 1)) continue;
+            const int imx = gx - a.id * a.per[0];
+            for (int gy = 0; gy < A; ++gy) {
+              if (!((my >> gy) & 1)) continue;
+              const int imy = gy - a.id * a.per[1];
+              for (int gz = 0; gz < A; ++gz) {
+                if (!((mz >> gz) & 1)) continue;
+                const int imz = gz - a.id * a.per[2];
+                const int D[3] = {S[0] - bx - imx * a.nint[0], S[1] - by - imy * a.nint[1],
+                                  S[2] - bz - imz * a.nint[2]};
+                // exact part
+                double er = 0.0, ei = 0.0;
+                if (!(n == m && imx == 0 && imy == 0 && imz == 0)) {
+                  double dx = rm[0] - rn[0] - imx * a.L[0];
+                  double dy = rm[1] - rn[1] - imy * a.L[1];
+                  double dz = rm[2] - rn[2] - imz * a.L[2];
+                  double r = sqrt(dx * dx + dy * dy + dz * dz);
+                  double inv = 1.0 / (4.0 * M_PI * r);
+                  if (CPLX) {
+                    double s, c;
+                    sincos(a.k0 * r, &s, &c);
+                    er = c * inv;
+                    ei = -s * inv;
+                  } else {
+                    er = inv;
+                  }
+                }
+                // grid part
+                double gr = 0.0, gi = 0.0;
+                for (int dx = -Q; dx <= Q; ++dx) {
+                  const double cx = C[0][dx + Q];
+                  const int64_t rowx = static_cast<int64_t>(D[0] + dx + R) * W;
+                  for (int dy = -Q; dy <= Q; ++dy) {
+                    const double cxy = cx * C[1][dy + Q];
+                    const cplx<double>* g = g0tab + (rowx + D[1] + dy + R) * W + (D[2] + R);
+                    double sr = 0.0, si = 0.0;
+#pragma unroll
+                    for (int dz = -Q; dz <= Q; ++dz) {
+                      const cplx<double> t = g[dz];
+                      sr += C[2][dz + Q] * t.x;
+                      if (CPLX) si += C[2][dz + Q] * t.y;
+                    }
+                    gr += cxy * sr;
+                    gi += cxy * si;
+                  }
+                }
+                const double xr = er - gr, xi = ei - gi;
+                if (CPLX) {
+                  const int pidx = (gx * A + gy) * A + gz;
+                  const double pr = a.phase[2 * pidx], pi = a.phase[2 * pidx + 1];
+                  fr += pr * xr - pi * xi;
+                  fi += pr * xi + pi * xr;
+                  if (ADJ) {
+                    ar += pr * xr + pi * xi;
+                    ai += pi * xr - pr * xi;
+                  }
+                } else {
+                  fr += xr;
+                }
+              }
+            }
+          }
+          col[j] = n;
+          if (CPLX) {
+            valc[j] = cmake<double>(fr, fi);
+            if (ADJ) vadj[j] = cmake<double>(ar, ai);
+          } else {
+            valr[j] = fr;
+          }
+          ++j;
+        }
+      }
+    }
+  }
+}
+
+// One wavefront per row; lanes stride over the row; wave-level reduction.
+template <typename R, bool CPLX, int PB>
+__global__ void __launch_bounds__(256) k_corr_spmv(const int64_t* __restrict__ rowptr,
+                                                   const int32_t* __restrict__ col,
+                                                   const void* __restrict__ val_v, int64_t N,
+                                                   const cplx<R>* __restrict__ qint, int P,
+                                                   cplx<R>* __restrict__ uint) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (row >= N) return;
+  const int p0 = blockIdx.y * PB;
+  double ar[PB], ai[PB];
+#pragma unroll
+  for (int pp = 0; pp < PB; ++pp) ar[pp] = ai[pp] = 0.0;
+  const int64_t j1 = rowptr[row + 1];
+  for (int64_t j = rowptr[row] + lane; j < j1; j += 64) {
+    const int n = col[j];
+    double vr, vi = 0.0;
+    if (CPLX) {
+      cplx<double> v = static_cast<const cplx<double>*>(val_v)[j];
+      vr = v.x;
+      vi = v.y;
+    } else {
+      vr = static_cast<const double*>(val_v)[j];
+    }
+#pragma unroll
+    for (int pp = 0; pp < PB; ++pp) {
+      if (p0 + pp < P) {
+        cplx<R> q = qint[static_cast<int64_t>(n) * P + p0 + pp];
+        const double qr = static_cast<double>(q.x), qi = static_cast<double>(q.y);
+        ar[pp] += vr * qr - vi * qi;
+        ai[pp] += vr * qi + vi * qr;
+      }
+    }
+  }
+#pragma unroll
+  for (int pp = 0; pp < PB; ++pp) {
+    for (int off = 32; off > 0; off >>= 1) {
+      ar[pp] += __shfl_down(ar[pp], off, 64);
+      ai[pp] += __shfl_down(ai[pp], off, 64);
+    }
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int pp = 0; pp < PB; ++pp) {
+      if (p0 + pp < P) {
+        cplx<R>* o = uint + row * P + p0 + pp;
+        cplx<R> u = *o;
+        u.x = static_cast<R>(static_cast<double>(u.x) + ar[pp]);
+        u.y = static_cast<R>(static_cast<double>(u.y) + ai[pp]);
+        *o = u;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+int launch_corr_count(const CorrArgs& a, const int32_t* s3, const int32_t* box_start, int64_t* rowcount,
+                      hipStream_t st) {
+  unsigned nb = static_cast<unsigned>((a.N + 255) / 256);
+  hipLaunchKernelGGL(k_corr_count, dim3(nb), dim3(256), 0, st, a, s3, box_start, rowcount);
+  return FFTPIM_OK;
+}
+
+template <int Q>
+static void fill_q(bool cplx_vals, bool adj, const CorrArgs& a, const int32_t* s3, const double* u3,
+                   const double* pos3, const int32_t* box_start, const void* g0tab, const int64_t* rowptr,
+                   int32_t* col, void* val, void* val_adj, hipStream_t st) {
+  unsigned nb = static_cast<unsigned>((a.N + 63) / 64);
+  const cplx<double>* g = static_cast<const cplx<double>*>(g0tab);
+#define FFTPIM_FILL(C, J)                                                                                  \
+  hipLaunchKernelGGL((k_corr_fill<Q, C, J>), dim3(nb), dim3(64), 0, st, a, s3, u3, pos3, box_start, g,     \
+                     rowptr, col, val, val_adj)
+  if (!cplx_vals)
+    FFTPIM_FILL(false, false);
+  else if (adj)
+    FFTPIM_FILL(true, true);
+  else
+    FFTPIM_FILL(true, false);
+#undef FFTPIM_FILL
+}
+
+int launch_corr_fill(int q, bool cplx_vals, bool adj, const CorrArgs& a, const int32_t* s3, const double* u3,
+                     const double* pos3, const int32_t* box_start, const void* g0tab, const int64_t* rowptr,
+                     int32_t* col, void* val, void* val_adj, hipStream_t st) {
+  switch (q) {
+    case 1: fill_q<1>(cplx_vals, adj, a, s3, u3, pos3, box_start, g0tab, rowptr, col, val, val_adj, st); break;
+    case 2: fill_q<2>(cplx_vals, adj, a, s3, u3, pos3, box_start, g0tab, rowptr, col, val, val_adj, st); break;
+    case 3: fill_q<3>(cplx_vals, adj, a, s3, u3, pos3, box_start, g0tab, rowptr, col, val, val_adj, st); break;
+    case 4: fill_q<4>(cplx_vals, adj, a, s3, u3, pos3, box_start, g0tab, rowptr, col, val, val_adj, st); break;
+    case 5: fill_q<5>(cplx_vals, adj, a, s3, u3, pos3, box_start, g0tab, rowptr, col, val, val_adj, st); break;
+    case 6: fill_q<6>(cplx_vals, adj, a, s3, u3, pos3, box_start, g0tab, rowptr, col, val, val_adj, st); break;
+    case 7: fill_q<7>(cplx_vals, adj, a, s3, u3, pos3, box_start, g0tab, rowptr, col, val, val_adj, st); break;
+    case 8: fill_q<8>(cplx_vals, adj, a, s3, u3, pos3, box_start, g0tab, rowptr, col, val, val_adj, st); break;
+    default: return FFTPIM_ERR_UNSUPPORTED;
+  }
+  return FFTPIM_OK;
+}
+
+template <typename R>
+void launch_corr_spmv(bool cplx_vals, const int64_t* rowptr, const int32_t* col, const void* val, int64_t N,
+                      const void* qint, int P, void* uint, hipStream_t st) {
+  const cplx<R>* q = static_cast<const cplx<R>*>(qint);
+  cplx<R>* u = static_cast<cplx<R>*>(uint);
+  unsigned nb = static_cast<unsigned>((N + 3) / 4);
+#define FFTPIM_SPMV(PBV)                                                                                   \
+  do {                                                                                                     \
+    dim3 gr(nb, (P + PBV - 1) / PBV);                                                                      \
+    if (cplx_vals)                                                                                         \
+      hipLaunchKernelGGL((k_corr_spmv<R, true, PBV>), gr, dim3(256), 0, st, rowptr, col, val, N, q, P, u); \
+    else                                                                                                   \
+      hipLaunchKernelGGL((k_corr_spmv<R, false, PBV>), gr, dim3(256), 0, st, rowptr, col, val, N, q, P, u); \
+  } while (0)
+  if (P >= 8)
+    FFTPIM_SPMV(8);
+  else if (P >= 4)
+    FFTPIM_SPMV(4);
+  else if (P >= 2)
+    FFTPIM_SPMV(2);
+  else
+    FFTPIM_SPMV(1);
+#undef FFTPIM_SPMV
+}
+
+template void launch_corr_spmv<double>(bool, const int64_t*, const int32_t*, const void*, int64_t, const void*,
+                                       int, void*, hipStream_t);
+template void launch_corr_spmv<float>(bool, const int64_t*, const int32_t*, const void*, int64_t, const void*,
+                                      int, void*, hipStream_t);
+
+}  // namespace fftpim

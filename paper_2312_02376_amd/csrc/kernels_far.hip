@@ -1,0 +1,229 @@
+// Far zone, Sec. 3.2.
+//   Step 1 (Eq. (projection)): projection onto the sparse source grid, done
+//     atomic-free in two stages: every far box sums the weighted amplitudes
+//     of its points into its own (qf+1)^3 stencil patch ("moments"), then
+//     every grid node gathers the patches that cover it.
+//   Step 2 (Eq. (8)): the dense grid sum u_g[m'] = sum_n' K[m', n'] q_g[n'].
+//     K is shift invariant, K[m', n'] = G^p_far((m' - n') h - h/2), so its
+//     tiles are generated from the (2 nf - 1)^3 offset table instead of being
+//     stored (the table stays in L2).  The conjugate transpose uses
+//     conj(K[n', m']) from the same table.
+//   Step 3 (Eq. (interpolation)): the generic grid-to-point interpolation.
+#include "kernels.h"
+
+namespace fftpim {
+
+template <typename R, int QF, int PB>
+__global__ void k_far_moments(FarArgs f, const int32_t* __restrict__ fbox_start, const int32_t* __restrict__ fperm,
+                              const double* __restrict__ u3, int64_t N, const cplx<R>* __restrict__ qint, int P,
+                              cplx<R>* __restrict__ mom) {
+  constexpr int K1 = QF + 1;
+  constexpr int K = K1 * K1 * K1;
+  const int k = threadIdx.x;
+  if (k >= K) return;
+  const int64_t b = blockIdx.x;
+  const int p0 = blockIdx.y * PB;
+  const int kx = k / (K1 * K1), ky = (k / K1) % K1, kz = k % K1;
+  const double c = basis_den_inv<QF>(kx) * basis_den_inv<QF>(ky) * basis_den_inv<QF>(kz);
+  double ar[PB], ai[PB];
+#pragma unroll
+  for (int pp = 0; pp < PB; ++pp) ar[pp] = ai[pp] = 0.0;
+  const int j0 = fbox_start[b], j1 = fbox_start[b + 1];
+  for (int j = j0; j < j1; ++j) {
+    const int n = fperm[j];
+    const double w = c * basis_num<QF>(kx, u3[n]) * basis_num<QF>(ky, u3[N + n]) * basis_num<QF>(kz, u3[2 * N + n]);
+#pragma unroll
+    for (int pp = 0; pp < PB; ++pp) {
+      if (p0 + pp < P) {
+        cplx<R> q = qint[static_cast<int64_t>(n) * P + p0 + pp];
+        ar[pp] += w * static_cast<double>(q.x);
+        ai[pp] += w * static_cast<double>(q.y);
+      }
+    }
+  }
+#pragma unroll
+  for (int pp = 0; pp < PB; ++pp)
+    if (p0 + pp < P)
+      mom[(b * K + k) * P + p0 + pp] = cmake<R>(static_cast<R>(ar[pp]), static_cast<R>(ai[pp]));
+}
+
+template <typename R, int QF>
+__global__ void k_far_gather(FarArgs f, const cplx<R>* __restrict__ mom, int P, cplx<R>* __restrict__ grid) {
+  constexpr int K1 = QF + 1;
+  constexpr int K = K1 * K1 * K1;
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= f.Ngf * P) return;
+  const int p = static_cast<int>(idx / f.Ngf);
+  const int64_t g = idx - static_cast<int64_t>(p) * f.Ngf;
+  const int gz = static_cast<int>(g % f.nf[2]);
+  const int gy = static_cast<int>((g / f.nf[2]) % f.nf[1]);
+  const int gx = static_cast<int>(g / (static_cast<int64_t>(f.nf[1]) * f.nf[2]));
+  double ar = 0.0, ai = 0.0;
+  for (int bx = max(0, gx - QF); bx <= min(gx, f.nint[0]); ++bx)
+    for (int by = max(0, gy - QF); by <= min(gy, f.nint[1]); ++by)
+      for (int bz = max(0, gz - QF); bz <= min(gz, f.nint[2]); ++bz) {
+        const int64_t b = (static_cast<int64_t>(bx) * f.nb[1] + by) * f.nb[2] + bz;
+        const int k = ((gx - bx) * K1 + (gy - by)) * K1 + (gz - bz);
+        cplx<R> v = mom[(b * K + k) * P + p];
+        ar += static_cast<double>(v.x);
+        ai += static_cast<double>(v.y);
+      }
+  grid[static_cast<int64_t>(p) * f.Ngf + g] = cmake<R>(static_cast<R>(ar), static_cast<R>(ai));
+}
+
+// out[p][i] = sum_j K(i, j) in[p][j] with K(i, j) = table[base(i) - off(j)]
+// (forward) or conj(table[base(j) - off(i)]) (conjugate transpose), where
+// base(i) = ((ix + nfx - 1) sy + iy + nfy - 1) sz + iz + nfz - 1 and
+// off(j) = (jx sy + jy) sz + jz index the (2 nf - 1)^3 offset table.
+template <typename R, int PB>
+__global__ void __launch_bounds__(256) k_far_apply(FarArgs f, const cplx<R>* __restrict__ table,
+                                                   const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out,
+                                                   int P, int adjoint) {
+  __shared__ cplx<R> sh[PB][256];
+  __shared__ int64_t shi[256];
+  const int64_t sy = 2 * f.nf[1] - 1, sz = 2 * f.nf[2] - 1;
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int p0 = blockIdx.y * PB;
+  const bool active = i < f.Ngf;
+  int64_t base_i = 0, off_i = 0;
+  if (active) {
+    const int iz = static_cast<int>(i % f.nf[2]);
+    const int iy = static_cast<int>((i / f.nf[2]) % f.nf[1]);
+    const int ix = static_cast<int>(i / (static_cast<int64_t>(f.nf[1]) * f.nf[2]));
+    base_i = ((ix + f.nf[0] - 1) * sy + iy + f.nf[1] - 1) * sz + iz + f.nf[2] - 1;
+    off_i = (ix * sy + iy) * sz + iz;
+  }
+  R ar[PB], ai[PB];
+#pragma unroll
+  for (int pp = 0; pp < PB; ++pp) ar[pp] = ai[pp] = R(0);
+  for (int64_t jc = 0; jc < f.Ngf; jc += 256) {
+    const int64_t j = jc + threadIdx.x;
+    if (j < f.Ngf) {
+      const int jz = static_cast<int>(j % f.nf[2]);
+      const int jy = static_cast<int>((j / f.nf[2]) % f.nf[1]);
+      const int jx = static_cast<int>(j / (static_cast<int64_t>(f.nf[1]) * f.nf[2]));
+      shi[threadIdx.x] = adjoint ? ((jx + f.nf[0] - 1) * sy + jy + f.nf[1] - 1) * sz + jz + f.nf[2] - 1
+                                 : (jx * sy + jy) * sz + jz;
+#pragma unroll
+      for (int pp = 0; pp < PB; ++pp)
+        sh[pp][threadIdx.x] = (p0 + pp < P) ? in[static_cast<int64_t>(p0 + pp) * f.Ngf + j] : cmake<R>(R(0), R(0));
+    }
+    __syncthreads();
+    const int cnt = static_cast<int>(min<int64_t>(256, f.Ngf - jc));
+    if (active) {
+      for (int jj = 0; jj < cnt; ++jj) {
+        const int64_t t = adjoint ? (shi[jj] - off_i) : (base_i - shi[jj]);
+        cplx<R> kv = table[t];
+        if (adjoint) kv.y = -kv.y;
+#pragma unroll
+        for (int pp = 0; pp < PB; ++pp) {
+          const cplx<R> x = sh[pp][jj];
+          ar[pp] += kv.x * x.x - kv.y * x.y;
+          ai[pp] += kv.x * x.y + kv.y * x.x;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (active) {
+#pragma unroll
+    for (int pp = 0; pp < PB; ++pp)
+      if (p0 + pp < P) out[static_cast<int64_t>(p0 + pp) * f.Ngf + i] = cmake<R>(ar[pp], ai[pp]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+template <typename R, int QF>
+static void moments_q(const FarArgs& f, const int32_t* fbox_start, const int32_t* fperm, const double* u3,
+                      int64_t N, const void* qint, int P, void* mom, hipStream_t st) {
+  constexpr int K = (QF + 1) * (QF + 1) * (QF + 1);
+  const int bs = ((K + 63) / 64) * 64;
+#define FFTPIM_MOM(PBV)                                                                                     \
+  do {                                                                                                      \
+    dim3 gr(static_cast<unsigned>(f.nboxes), (P + PBV - 1) / PBV);                                          \
+    hipLaunchKernelGGL((k_far_moments<R, QF, PBV>), gr, dim3(bs), 0, st, f, fbox_start, fperm, u3, N,       \
+                       static_cast<const cplx<R>*>(qint), P, static_cast<cplx<R>*>(mom));                   \
+  } while (0)
+  if (P >= 4)
+    FFTPIM_MOM(4);
+  else if (P >= 2)
+    FFTPIM_MOM(2);
+  else
+    FFTPIM_MOM(1);
+#undef FFTPIM_MOM
+}
+
+template <typename R>
+int launch_far_moments(int qf, const FarArgs& f, const int32_t* fbox_start, const int32_t* fperm,
+                       const double* u3, int64_t N, const void* qint, int P, void* mom, hipStream_t st) {
+  switch (qf) {
+    case 1: moments_q<R, 1>(f, fbox_start, fperm, u3, N, qint, P, mom, st); break;
+    case 2: moments_q<R, 2>(f, fbox_start, fperm, u3, N, qint, P, mom, st); break;
+    case 3: moments_q<R, 3>(f, fbox_start, fperm, u3, N, qint, P, mom, st); break;
+    case 4: moments_q<R, 4>(f, fbox_start, fperm, u3, N, qint, P, mom, st); break;
+    case 5: moments_q<R, 5>(f, fbox_start, fperm, u3, N, qint, P, mom, st); break;
+    case 6: moments_q<R, 6>(f, fbox_start, fperm, u3, N, qint, P, mom, st); break;
+    case 7: moments_q<R, 7>(f, fbox_start, fperm, u3, N, qint, P, mom, st); break;
+    case 8: moments_q<R, 8>(f, fbox_start, fperm, u3, N, qint, P, mom, st); break;
+    case 9: moments_q<R, 9>(f, fbox_start, fperm, u3, N, qint, P, mom, st); break;
+    default: return FFTPIM_ERR_UNSUPPORTED;
+  }
+  return FFTPIM_OK;
+}
+
+template <typename R, int QF>
+static void gather_q(const FarArgs& f, const void* mom, int P, void* grid, hipStream_t st) {
+  const int64_t total = f.Ngf * P;
+  hipLaunchKernelGGL((k_far_gather<R, QF>), dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0, st, f,
+                     static_cast<const cplx<R>*>(mom), P, static_cast<cplx<R>*>(grid));
+}
+
+template <typename R>
+int launch_far_gather(int qf, const FarArgs& f, const void* mom, int P, void* grid, hipStream_t st) {
+  switch (qf) {
+    case 1: gather_q<R, 1>(f, mom, P, grid, st); break;
+    case 2: gather_q<R, 2>(f, mom, P, grid, st); break;
+    case 3: gather_q<R, 3>(f, mom, P, grid, st); break;
+    case 4: gather_q<R, 4>(f, mom, P, grid, st); break;
+    case 5: gather_q<R, 5>(f, mom, P, grid, st); break;
+    case 6: gather_q<R, 6>(f, mom, P, grid, st); break;
+    case 7: gather_q<R, 7>(f, mom, P, grid, st); break;
+    case 8: gather_q<R, 8>(f, mom, P, grid, st); break;
+    case 9: gather_q<R, 9>(f, mom, P, grid, st); break;
+    default: return FFTPIM_ERR_UNSUPPORTED;
+  }
+  return FFTPIM_OK;
+}
+
+template <typename R>
+void launch_far_apply(const FarArgs& f, const void* table, const void* in, void* out, int P, bool adjoint,
+                      hipStream_t st) {
+  const unsigned nb = static_cast<unsigned>((f.Ngf + 255) / 256);
+#define FFTPIM_FARAPPLY(PBV)                                                                               \
+  do {                                                                                                     \
+    dim3 gr(nb, (P + PBV - 1) / PBV);                                                                      \
+    hipLaunchKernelGGL((k_far_apply<R, PBV>), gr, dim3(256), 0, st, f, static_cast<const cplx<R>*>(table), \
+                       static_cast<const cplx<R>*>(in), static_cast<cplx<R>*>(out), P, adjoint ? 1 : 0);   \
+  } while (0)
+  if (P >= 4)
+    FFTPIM_FARAPPLY(4);
+  else if (P >= 2)
+    FFTPIM_FARAPPLY(2);
+  else
+    FFTPIM_FARAPPLY(1);
+#undef FFTPIM_FARAPPLY
+}
+
+#define FFTPIM_INST_FAR(R)                                                                                 \
+  template int launch_far_moments<R>(int, const FarArgs&, const int32_t*, const int32_t*, const double*,   \
+                                     int64_t, const void*, int, void*, hipStream_t);                       \
+  template int launch_far_gather<R>(int, const FarArgs&, const void*, int, void*, hipStream_t);            \
+  template void launch_far_apply<R>(const FarArgs&, const void*, const void*, void*, int, bool, hipStream_t);
+
+FFTPIM_INST_FAR(double)
+FFTPIM_INST_FAR(float)
+
+}  // namespace fftpim

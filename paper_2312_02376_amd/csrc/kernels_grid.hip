@@ -1,0 +1,553 @@
+// Near-zone grid kernels (Sec. 3.3, Steps 1-3) and shared helpers:
+//   * pack / unpack between the caller's [nrhs][N] arrays and the plan-order,
+//     point-major complex "planes" used inside (two real right-hand sides
+//     share one complex plane when the kernel is real);
+//   * projection onto the near grid (Step 1) as an atomic-free gather: every
+//     grid node sums the contributions of the points in the (q+1)^3 boxes
+//     whose stencils cover it;
+//   * zero-padded FFT passes (Step 2) with radix-2 transforms in LDS; the
+//     x-axis pass fuses forward transform, multiplication by the kernel
+//     spectrum and inverse transform;
+//   * interpolation back to the points (Step 3);
+//   * the near-zone kernel table G^p_near at grid offsets (plan time).
+#include "kernels.h"
+
+namespace fftpim {
+
+// ---------------------------------------------------------------------------
+// pack / unpack
+// ---------------------------------------------------------------------------
+
+template <typename R, bool REAL_IN>
+__global__ void k_pack(const void* __restrict__ qu, cplx<R>* __restrict__ qint,
+                       const int32_t* __restrict__ perm, int64_t N, int nrhs, int P, int use_perm) {
+  int64_t tid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (tid >= N * P) return;
+  int p = static_cast<int>(tid / N);
+  int64_t m = tid - static_cast<int64_t>(p) * N;
+  int64_t src = use_perm ? perm[m] : m;
+  cplx<R> v;
+  if (REAL_IN) {
+    const R* q = static_cast<const R*>(qu);
+    int r0 = 2 * p, r1 = 2 * p + 1;
+    v.x = r0 < nrhs ? q[static_cast<int64_t>(r0) * N + src] : R(0);
+    v.y = r1 < nrhs ? q[static_cast<int64_t>(r1) * N + src] : R(0);
+  } else {
+    const cplx<R>* q = static_cast<const cplx<R>*>(qu);
+    v = q[static_cast<int64_t>(p) * N + src];
+  }
+  qint[m * P + p] = v;
+}
+
+template <typename R, bool REAL_OUT>
+__global__ void k_unpack(const cplx<R>* __restrict__ uint, void* __restrict__ uu,
+                         const int32_t* __restrict__ perm, int64_t N, int nrhs, int P, int use_perm,
+                         const double* __restrict__ mean) {
+  int64_t tid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (tid >= N * P) return;
+  int p = static_cast<int>(tid / N);
+  int64_t m = tid - static_cast<int64_t>(p) * N;
+  int64_t dst = use_perm ? perm[m] : m;
+  cplx<R> v = uint[m * P + p];
+  if (mean) {
+    v.x -= static_cast<R>(mean[2 * p]);
+    v.y -= static_cast<R>(mean[2 * p + 1]);
+  }
+  if (REAL_OUT) {
+    R* u = static_cast<R*>(uu);
+    int r0 = 2 * p, r1 = 2 * p + 1;
+    if (r0 < nrhs) u[static_cast<int64_t>(r0) * N + dst] = v.x;
+    if (r1 < nrhs) u[static_cast<int64_t>(r1) * N + dst] = v.y;
+  } else {
+    cplx<R>* u = static_cast<cplx<R>*>(uu);
+    u[static_cast<int64_t>(p) * N + dst] = v;
+  }
+}
+
+// Per-plane sums over points, deterministic (one block per plane):
+// out[4p + 0/1] = sum of re/im, out[4p + 2/3] = sum of |re| / |im|.
+template <typename R>
+__global__ void k_plane_sums(const cplx<R>* __restrict__ v, int64_t N, int P, double* __restrict__ out) {
+  __shared__ double sh[4][256];
+  int p = blockIdx.x;
+  double a = 0, b = 0, c = 0, d = 0;
+  for (int64_t m = threadIdx.x; m < N; m += blockDim.x) {
+    cplx<R> t = v[m * P + p];
+    a += t.x;
+    b += t.y;
+    c += fabs(static_cast<double>(t.x));
+    d += fabs(static_cast<double>(t.y));
+  }
+  sh[0][threadIdx.x] = a;
+  sh[1][threadIdx.x] = b;
+  sh[2][threadIdx.x] = c;
+  sh[3][threadIdx.x] = d;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s)
+      for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) out[4 * p + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// Neutrality (Eq. (neutral)) per real right-hand side; latches the status.
+__global__ void k_check_neutral(const double* __restrict__ sums, int P, double tol, int* status) {
+  for (int p = threadIdx.x; p < P; p += blockDim.x) {
+    bool bad = fabs(sums[4 * p + 0]) > tol * fmax(sums[4 * p + 2], 1e-300) ||
+               fabs(sums[4 * p + 1]) > tol * fmax(sums[4 * p + 3], 1e-300);
+    if (bad) atomicCAS(status, 0, static_cast<int>(FFTPIM_ERR_NOT_NEUTRAL));
+  }
+}
+
+__global__ void k_mean_from_sums(const double* __restrict__ sums, int P, double invN, double* mean) {
+  for (int p = threadIdx.x; p < P; p += blockDim.x) {
+    mean[2 * p] = sums[4 * p] * invN;
+    mean[2 * p + 1] = sums[4 * p + 1] * invN;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Step 1: projection onto the near grid (gather form)
+// ---------------------------------------------------------------------------
+
+template <typename R, int Q, int PB>
+__global__ void __launch_bounds__(256) k_spread_near(
+    GridArgs g, const int32_t* __restrict__ box_start, const double* __restrict__ u3, int64_t N,
+    const cplx<R>* __restrict__ qint, int P, cplx<R>* __restrict__ grid) {
+  const int64_t n3 = static_cast<int64_t>(g.n[0]) * g.n[1] * g.n[2];
+  int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= n3) return;
+  const int p0 = blockIdx.y * PB;
+  const int gz = static_cast<int>(idx % g.n[2]);
+  const int gy = static_cast<int>((idx / g.n[2]) % g.n[1]);
+  const int gx = static_cast<int>(idx / (static_cast<int64_t>(g.n[1]) * g.n[2]));
+  double ax[PB], ay[PB];
+#pragma unroll
+  for (int pp = 0; pp < PB; ++pp) ax[pp] = ay[pp] = 0.0;
+  const int bx0 = max(0, gx - Q), bx1 = min(gx, g.nint[0]);
+  const int by0 = max(0, gy - Q), by1 = min(gy, g.nint[1]);
+  const int bz0 = max(0, gz - Q), bz1 = min(gz, g.nint[2]);
+  for (int bx = bx0; bx <= bx1; ++bx) {
+    const int kx = gx - bx;
+    const double cx = basis_den_inv<Q>(kx);
+    for (int by = by0; by <= by1; ++by) {
+      const int ky = gy - by;
+      const double cxy = cx * basis_den_inv<Q>(ky);
+      for (int bz = bz0; bz <= bz1; ++bz) {
+        const int kz = gz - bz;
+        const double c = cxy * basis_den_inv<Q>(kz);
+        const int64_t b = (static_cast<int64_t>(bx) * g.nb[1] + by) * g.nb[2] + bz;
+        const int j0 = box_start[b], j1 = box_start[b + 1];
+        for (int j = j0; j < j1; ++j) {
+          const double w = c * basis_num<Q>(kx, u3[j]) * basis_num<Q>(ky, u3[N + j]) *
+                           basis_num<Q>(kz, u3[2 * N + j]);
+#pragma unroll
+          for (int pp = 0; pp < PB; ++pp) {
+            if (p0 + pp < P) {
+              cplx<R> qv = qint[static_cast<int64_t>(j) * P + p0 + pp];
+              ax[pp] += w * static_cast<double>(qv.x);
+              ay[pp] += w * static_cast<double>(qv.y);
+            }
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int pp = 0; pp < PB; ++pp)
+    if (p0 + pp < P)
+      grid[static_cast<int64_t>(p0 + pp) * n3 + idx] =
+          cmake<R>(static_cast<R>(ax[pp]), static_cast<R>(ay[pp]));
+}
+
+// ---------------------------------------------------------------------------
+// Step 3: interpolation from a grid to points (also the far zone's Step 3)
+// ---------------------------------------------------------------------------
+
+template <typename R, int Q, int PB>
+__global__ void __launch_bounds__(256) k_interp(
+    GridArgs g, const int32_t* __restrict__ s3, const double* __restrict__ u3, int64_t N,
+    const cplx<R>* __restrict__ grid, int P, cplx<R>* __restrict__ uint, int accumulate) {
+  int64_t m = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (m >= N) return;
+  const int p0 = blockIdx.y * PB;
+  const int64_t n3 = static_cast<int64_t>(g.n[0]) * g.n[1] * g.n[2];
+  double wx[Q + 1], wy[Q + 1], wz[Q + 1];
+  lagrange_all<Q, double>(u3[m], wx);
+  lagrange_all<Q, double>(u3[N + m], wy);
+  lagrange_all<Q, double>(u3[2 * N + m], wz);
+  const int sx = s3[m], sy = s3[N + m], sz = s3[2 * N + m];
+  double ax[PB], ay[PB];
+#pragma unroll
+  for (int pp = 0; pp < PB; ++pp) ax[pp] = ay[pp] = 0.0;
+  for (int kx = 0; kx <= Q; ++kx) {
+    for (int ky = 0; ky <= Q; ++ky) {
+      const double wxy = wx[kx] * wy[ky];
+      const int64_t row = (static_cast<int64_t>(sx + kx) * g.n[1] + (sy + ky)) * g.n[2] + sz;
+#pragma unroll
+      for (int kz = 0; kz <= Q; ++kz) {
+        const double w = wxy * wz[kz];
+#pragma unroll
+        for (int pp = 0; pp < PB; ++pp) {
+          if (p0 + pp < P) {
+            cplx<R> v = grid[static_cast<int64_t>(p0 + pp) * n3 + row + kz];
+            ax[pp] += w * static_cast<double>(v.x);
+            ay[pp] += w * static_cast<double>(v.y);
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int pp = 0; pp < PB; ++pp) {
+    if (p0 + pp < P) {
+      cplx<R>* o = uint + m * P + p0 + pp;
+      cplx<R> r = cmake<R>(static_cast<R>(ax[pp]), static_cast<R>(ay[pp]));
+      if (accumulate) r = cadd(*o, r);
+      *o = r;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Step 2: FFT passes in LDS
+// ---------------------------------------------------------------------------
+
+__device__ inline int bitrev(int j, int logM) {
+  return logM == 0 ? 0 : static_cast<int>(__brev(static_cast<unsigned>(j)) >> (32 - logM));
+}
+
+// Radix-2 stages on T lines of length M held in LDS.
+// DIT: bit-reversed input -> natural output.  DIF: natural -> bit-reversed.
+// inverse selects exp(+2 pi i ...) (conjugated twiddles).
+template <typename R>
+__device__ inline void lds_dit(cplx<R>* x, int T, int M, int logM, const cplx<R>* __restrict__ tw,
+                               bool inverse) {
+  const int nb = T * (M >> 1);
+  for (int lh = 0; lh < logM; ++lh) {
+    const int half = 1 << lh;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+      const int t = b >> (logM - 1);
+      const int k = b & ((M >> 1) - 1);
+      const int pos = k & (half - 1);
+      const int i0 = ((k >> lh) << (lh + 1)) + pos;
+      cplx<R> w = tw[pos << (logM - 1 - lh)];
+      if (inverse) w.y = -w.y;
+      cplx<R>* line = x + t * M;
+      cplx<R> a = line[i0];
+      cplx<R> c = cmul(line[i0 + half], w);
+      line[i0] = cadd(a, c);
+      line[i0 + half] = csub(a, c);
+    }
+    __syncthreads();
+  }
+}
+
+template <typename R>
+__device__ inline void lds_dif(cplx<R>* x, int T, int M, int logM, const cplx<R>* __restrict__ tw,
+                               bool inverse) {
+  const int nb = T * (M >> 1);
+  for (int lh = logM - 1; lh >= 0; --lh) {
+    const int half = 1 << lh;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+      const int t = b >> (logM - 1);
+      const int k = b & ((M >> 1) - 1);
+      const int pos = k & (half - 1);
+      const int i0 = ((k >> lh) << (lh + 1)) + pos;
+      cplx<R> w = tw[pos << (logM - 1 - lh)];
+      if (inverse) w.y = -w.y;
+      cplx<R>* line = x + t * M;
+      cplx<R> a = line[i0];
+      cplx<R> c = line[i0 + half];
+      line[i0] = cadd(a, c);
+      line[i0 + half] = cmul(csub(a, c), w);
+    }
+    __syncthreads();
+  }
+}
+
+// MODE 0: forward transform (bit-reversed load, DIT, natural store).
+// MODE 1: inverse transform (natural load, DIF, bit-reversed store).
+// MODE 2: forward DIT, multiply by spec (conjugated if conj_spec), inverse DIF.
+template <typename R, int MODE>
+__global__ void __launch_bounds__(256) k_fft_pass(const cplx<R>* in,
+                                                  cplx<R>* out, FftPassDesc d,
+                                                  const cplx<R>* __restrict__ tw,
+                                                  const cplx<R>* __restrict__ spec, int conj_spec) {
+  extern __shared__ unsigned char lds_raw[];
+  cplx<R>* x = reinterpret_cast<cplx<R>*>(lds_raw);
+  const int T = d.T, M = d.M, logM = d.logM;
+  int64_t outer = 0, c0 = 0, outer0 = 0;
+  int nlines = T;
+  if (d.contig) {
+    outer0 = static_cast<int64_t>(blockIdx.x) * T;
+    nlines = static_cast<int>(min<int64_t>(T, d.nouter - outer0));
+  } else {
+    const int64_t tiles = d.ncols / T;
+    outer = blockIdx.x / tiles;
+    c0 = (blockIdx.x % tiles) * T;
+  }
+  for (int idx = threadIdx.x; idx < T * M; idx += blockDim.x) {
+    int t, j;
+    if (d.contig) {
+      t = idx / M;
+      j = idx - t * M;
+    } else {
+      t = idx % T;
+      j = idx / T;
+    }
+    cplx<R> v = cmake<R>(R(0), R(0));
+    if (t < nlines && j < d.n_in) {
+      int64_t a = d.contig ? (outer0 + t) * d.in_outer + j * d.in_line
+                           : outer * d.in_outer + (c0 + t) * d.in_col + j * d.in_line;
+      v = in[a];
+    }
+    const int pos = (MODE == 1) ? j : bitrev(j, logM);
+    x[t * M + pos] = v;
+  }
+  __syncthreads();
+  if (MODE == 0 || MODE == 2) lds_dit<R>(x, T, M, logM, tw, false);
+  if (MODE == 2) {
+    for (int idx = threadIdx.x; idx < T * M; idx += blockDim.x) {
+      const int t = idx / M;
+      const int k = idx - t * M;
+      if (t < nlines) {
+        cplx<R> s = spec[static_cast<int64_t>(k) * d.spec_line + (c0 + t) * d.spec_col];
+        if (conj_spec) s.y = -s.y;
+        x[idx] = cmul(x[idx], s);
+      }
+    }
+    __syncthreads();
+  }
+  if (MODE == 1 || MODE == 2) lds_dif<R>(x, T, M, logM, tw, true);
+  for (int idx = threadIdx.x; idx < T * d.n_out; idx += blockDim.x) {
+    int t, j;
+    if (d.contig) {
+      t = idx / d.n_out;
+      j = idx - t * d.n_out;
+    } else {
+      t = idx % T;
+      j = idx / T;
+    }
+    if (t >= nlines) continue;
+    const int pos = (MODE == 0) ? j : bitrev(j, logM);
+    int64_t a = d.contig ? (outer0 + t) * d.out_outer + j * d.out_line
+                         : outer * d.out_outer + (c0 + t) * d.out_col + j * d.out_line;
+    out[a] = x[t * M + pos];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// plan time: near-zone table G^p_near at node offsets, circularly embedded
+// ---------------------------------------------------------------------------
+
+__global__ void k_near_table(cplx<double>* __restrict__ T, NearTableArgs a) {
+  int64_t total = static_cast<int64_t>(a.M[0]) * a.M[1] * a.M[2];
+  int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  int i[3];
+  i[2] = static_cast<int>(idx % a.M[2]);
+  i[1] = static_cast<int>((idx / a.M[2]) % a.M[1]);
+  i[0] = static_cast<int>(idx / (static_cast<int64_t>(a.M[1]) * a.M[2]));
+  int e[3];
+  bool inside = true;
+  for (int c = 0; c < 3; ++c) {
+    e[c] = i[c] < a.n[c] ? i[c] : i[c] - a.M[c];
+    if (e[c] > a.n[c] - 1 || e[c] < -(a.n[c] - 1)) inside = false;
+  }
+  double sr = 0.0, si = 0.0;
+  if (inside) {
+    for (int k = 0; k < a.nimg; ++k) {
+      int f[3];
+      for (int c = 0; c < 3; ++c) f[c] = e[c] - a.img[3 * k + c] * a.nint[c];
+      if (f[0] == 0 && f[1] == 0 && f[2] == 0) continue;  // singular term set to 0
+      double dx = f[0] * a.h[0], dy = f[1] * a.h[1], dz = f[2] * a.h[2];
+      double r = sqrt(dx * dx + dy * dy + dz * dz);
+      double s, c;
+      sincos(a.k0 * r, &s, &c);
+      double inv = 1.0 / (4.0 * M_PI * r);
+      // phase * exp(-j k0 r) / (4 pi r)
+      double gr = c * inv, gi = -s * inv;
+      sr += a.phase[2 * k] * gr - a.phase[2 * k + 1] * gi;
+      si += a.phase[2 * k] * gi + a.phase[2 * k + 1] * gr;
+    }
+  }
+  T[idx] = cmake<double>(sr, si);
+}
+
+template <typename R>
+__global__ void k_scale_convert(const cplx<double>* __restrict__ in, cplx<R>* __restrict__ out,
+                                int64_t n, double s) {
+  int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= n) return;
+  cplx<double> v = in[idx];
+  out[idx] = cmake<R>(static_cast<R>(v.x * s), static_cast<R>(v.y * s));
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+static inline unsigned blocks_for(int64_t n, int bs) { return static_cast<unsigned>((n + bs - 1) / bs); }
+
+template <typename R>
+void launch_pack(const void* qu, void* qint, const int32_t* perm, int64_t N, int nrhs, int P,
+                 bool real_in, bool use_perm, hipStream_t st) {
+  unsigned nb = blocks_for(N * P, 256);
+  if (real_in)
+    hipLaunchKernelGGL((k_pack<R, true>), dim3(nb), dim3(256), 0, st, qu,
+                       static_cast<cplx<R>*>(qint), perm, N, nrhs, P, use_perm ? 1 : 0);
+  else
+    hipLaunchKernelGGL((k_pack<R, false>), dim3(nb), dim3(256), 0, st, qu,
+                       static_cast<cplx<R>*>(qint), perm, N, nrhs, P, use_perm ? 1 : 0);
+}
+
+template <typename R>
+void launch_unpack(const void* uint, void* uu, const int32_t* perm, int64_t N, int nrhs, int P,
+                   bool real_out, bool use_perm, const double* mean, hipStream_t st) {
+  unsigned nb = blocks_for(N * P, 256);
+  if (real_out)
+    hipLaunchKernelGGL((k_unpack<R, true>), dim3(nb), dim3(256), 0, st,
+                       static_cast<const cplx<R>*>(uint), uu, perm, N, nrhs, P, use_perm ? 1 : 0, mean);
+  else
+    hipLaunchKernelGGL((k_unpack<R, false>), dim3(nb), dim3(256), 0, st,
+                       static_cast<const cplx<R>*>(uint), uu, perm, N, nrhs, P, use_perm ? 1 : 0, mean);
+}
+
+template <typename R>
+void launch_plane_sums(const void* v, int64_t N, int P, double* out, hipStream_t st) {
+  hipLaunchKernelGGL((k_plane_sums<R>), dim3(P), dim3(256), 0, st, static_cast<const cplx<R>*>(v), N, P, out);
+}
+
+void launch_check_neutral(const double* sums, int P, double tol, int* status, hipStream_t st) {
+  hipLaunchKernelGGL(k_check_neutral, dim3(1), dim3(64), 0, st, sums, P, tol, status);
+}
+
+void launch_mean_from_sums(const double* sums, int P, int64_t N, double* mean, hipStream_t st) {
+  hipLaunchKernelGGL(k_mean_from_sums, dim3(1), dim3(64), 0, st, sums, P, 1.0 / static_cast<double>(N), mean);
+}
+
+#define FFTPIM_PB_DISPATCH(P, CALL) \
+  do {                               \
+    if ((P) >= 8) {                  \
+      constexpr int PB = 8;          \
+      CALL;                          \
+    } else if ((P) >= 4) {           \
+      constexpr int PB = 4;          \
+      CALL;                          \
+    } else if ((P) >= 2) {           \
+      constexpr int PB = 2;          \
+      CALL;                          \
+    } else {                         \
+      constexpr int PB = 1;          \
+      CALL;                          \
+    }                                \
+  } while (0)
+
+template <typename R, int Q>
+static void spread_q(const GridArgs& g, const int32_t* box_start, const double* u3, int64_t N,
+                     const void* qint, int P, void* grid, hipStream_t st) {
+  const int64_t n3 = static_cast<int64_t>(g.n[0]) * g.n[1] * g.n[2];
+  FFTPIM_PB_DISPATCH(P, {
+    dim3 gr(blocks_for(n3, 256), (P + PB - 1) / PB);
+    hipLaunchKernelGGL((k_spread_near<R, Q, PB>), gr, dim3(256), 0, st, g, box_start, u3, N,
+                       static_cast<const cplx<R>*>(qint), P, static_cast<cplx<R>*>(grid));
+  });
+}
+
+template <typename R>
+int launch_spread_near(int q, const GridArgs& g, const int32_t* box_start, const double* u3, int64_t N,
+                       const void* qint, int P, void* grid, hipStream_t st) {
+  switch (q) {
+    case 1: spread_q<R, 1>(g, box_start, u3, N, qint, P, grid, st); break;
+    case 2: spread_q<R, 2>(g, box_start, u3, N, qint, P, grid, st); break;
+    case 3: spread_q<R, 3>(g, box_start, u3, N, qint, P, grid, st); break;
+    case 4: spread_q<R, 4>(g, box_start, u3, N, qint, P, grid, st); break;
+    case 5: spread_q<R, 5>(g, box_start, u3, N, qint, P, grid, st); break;
+    case 6: spread_q<R, 6>(g, box_start, u3, N, qint, P, grid, st); break;
+    case 7: spread_q<R, 7>(g, box_start, u3, N, qint, P, grid, st); break;
+    case 8: spread_q<R, 8>(g, box_start, u3, N, qint, P, grid, st); break;
+    default: return FFTPIM_ERR_UNSUPPORTED;
+  }
+  return FFTPIM_OK;
+}
+
+template <typename R, int Q>
+static void interp_q(const GridArgs& g, const int32_t* s3, const double* u3, int64_t N, const void* grid,
+                     int P, void* uint, bool acc, hipStream_t st) {
+  FFTPIM_PB_DISPATCH(P, {
+    dim3 gr(blocks_for(N, 256), (P + PB - 1) / PB);
+    hipLaunchKernelGGL((k_interp<R, Q, PB>), gr, dim3(256), 0, st, g, s3, u3, N,
+                       static_cast<const cplx<R>*>(grid), P, static_cast<cplx<R>*>(uint), acc ? 1 : 0);
+  });
+}
+
+template <typename R>
+int launch_interp(int q, const GridArgs& g, const int32_t* s3, const double* u3, int64_t N, const void* grid,
+                  int P, void* uint, bool acc, hipStream_t st) {
+  switch (q) {
+    case 1: interp_q<R, 1>(g, s3, u3, N, grid, P, uint, acc, st); break;
+    case 2: interp_q<R, 2>(g, s3, u3, N, grid, P, uint, acc, st); break;
+    case 3: interp_q<R, 3>(g, s3, u3, N, grid, P, uint, acc, st); break;
+    case 4: interp_q<R, 4>(g, s3, u3, N, grid, P, uint, acc, st); break;
+    case 5: interp_q<R, 5>(g, s3, u3, N, grid, P, uint, acc, st); break;
+    case 6: interp_q<R, 6>(g, s3, u3, N, grid, P, uint, acc, st); break;
+    case 7: interp_q<R, 7>(g, s3, u3, N, grid, P, uint, acc, st); break;
+    case 8: interp_q<R, 8>(g, s3, u3, N, grid, P, uint, acc, st); break;
+    case 9: interp_q<R, 9>(g, s3, u3, N, grid, P, uint, acc, st); break;
+    default: return FFTPIM_ERR_UNSUPPORTED;
+  }
+  return FFTPIM_OK;
+}
+
+template <typename R>
+void launch_fft_pass(int mode, const void* in, void* out, const FftPassDesc& d, const void* tw,
+                     const void* spec, bool conj_spec, hipStream_t st) {
+  unsigned nblocks = d.contig ? blocks_for(d.nouter, d.T)
+                              : static_cast<unsigned>(d.nouter * (d.ncols / d.T));
+  size_t lds = static_cast<size_t>(d.T) * d.M * sizeof(cplx<R>);
+  const cplx<R>* i = static_cast<const cplx<R>*>(in);
+  cplx<R>* o = static_cast<cplx<R>*>(out);
+  const cplx<R>* t = static_cast<const cplx<R>*>(tw);
+  const cplx<R>* s = static_cast<const cplx<R>*>(spec);
+  if (mode == 0)
+    hipLaunchKernelGGL((k_fft_pass<R, 0>), dim3(nblocks), dim3(256), lds, st, i, o, d, t, s, 0);
+  else if (mode == 1)
+    hipLaunchKernelGGL((k_fft_pass<R, 1>), dim3(nblocks), dim3(256), lds, st, i, o, d, t, s, 0);
+  else
+    hipLaunchKernelGGL((k_fft_pass<R, 2>), dim3(nblocks), dim3(256), lds, st, i, o, d, t, s,
+                       conj_spec ? 1 : 0);
+}
+
+void launch_near_table(void* T, const NearTableArgs& a, hipStream_t st) {
+  int64_t total = static_cast<int64_t>(a.M[0]) * a.M[1] * a.M[2];
+  hipLaunchKernelGGL(k_near_table, dim3(blocks_for(total, 256)), dim3(256), 0, st,
+                     static_cast<cplx<double>*>(T), a);
+}
+
+template <typename R>
+void launch_scale_convert(const void* in, void* out, int64_t n, double s, hipStream_t st) {
+  hipLaunchKernelGGL((k_scale_convert<R>), dim3(blocks_for(n, 256)), dim3(256), 0, st,
+                     static_cast<const cplx<double>*>(in), static_cast<cplx<R>*>(out), n, s);
+}
+
+// explicit instantiations
+#define FFTPIM_INST_GRID(R)                                                                              \
+  template void launch_pack<R>(const void*, void*, const int32_t*, int64_t, int, int, bool, bool,        \
+                               hipStream_t);                                                             \
+  template void launch_unpack<R>(const void*, void*, const int32_t*, int64_t, int, int, bool, bool,      \
+                                 const double*, hipStream_t);                                            \
+  template void launch_plane_sums<R>(const void*, int64_t, int, double*, hipStream_t);                   \
+  template int launch_spread_near<R>(int, const GridArgs&, const int32_t*, const double*, int64_t,       \
+                                     const void*, int, void*, hipStream_t);                              \
+  template int launch_interp<R>(int, const GridArgs&, const int32_t*, const double*, int64_t,            \
+                                const void*, int, void*, bool, hipStream_t);                             \
+  template void launch_fft_pass<R>(int, const void*, void*, const FftPassDesc&, const void*, const void*, \
+                                   bool, hipStream_t);                                                   \
+  template void launch_scale_convert<R>(const void*, void*, int64_t, double, hipStream_t);
+
+FFTPIM_INST_GRID(double)
+FFTPIM_INST_GRID(float)
+
+}  // namespace fftpim

@@ -1,0 +1,41 @@
+// Host FP64 periodic Green's function (Sec. 2, Eq. (pgf) and Eq. (lgf)) used to
+// tabulate the far-zone kernel of Sec. 3.2.
+#pragma once
+
+#include <complex>
+#include <cstdint>
+#include <vector>
+
+namespace fftpim {
+
+using cd = std::complex<double>;
+
+struct Lattice {
+  int dims;       // periodic axes: x (1), x,y (2), x,y,z (3)
+  double L[3];    // periods
+  double k0;      // free-space wavenumber (real)
+  double kt[3];   // phase-shift wavenumbers (real)
+  bool npsp() const { return k0 == 0.0 && kt[0] == 0.0 && kt[1] == 0.0 && kt[2] == 0.0; }
+};
+
+double bessel_k0(double x);
+cd g0(double r, double k0);
+double lgf3(double x, double y, double z, double Lx, double Ly, double Lz);
+double lgf2(double x, double y, double z, double Lx, double Ly);
+double lgf1(double x, double rho, double Lx);
+cd pgf2(double x, double y, double z, double Lx, double Ly, double k0, double kx0, double ky0);
+cd pgf3(double x, double y, double z, const double L[3], double k0, const double kt[3]);
+cd pgf_reduced(const Lattice& lat, const double r[3]);
+// Full G^p (Bloch factor included); r must not be a lattice vector.
+cd pgf(const Lattice& lat, const double r[3]);
+// Eq. (4): images |i_c| <= i_d on the periodic axes.
+cd g_near(const Lattice& lat, const double r[3], int i_d);
+// Nonzero when this evaluator does not cover the problem class.
+int check_supported(const Lattice& lat);
+bool wood_anomaly(const Lattice& lat);
+// G^p_far at the offsets (d - 1/2) * delta, d_c in [-(nf_c - 1), nf_c - 1],
+// x slowest; table size (2 nf_x - 1)(2 nf_y - 1)(2 nf_z - 1).
+void far_table(const Lattice& lat, int i_d, const int nf[3], const double delta[3],
+               std::vector<cd>& table);
+
+}  // namespace fftpim

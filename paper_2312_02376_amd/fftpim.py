@@ -1,0 +1,244 @@
+"""Python binding of libfftpim.so (the C ABI in include/fftpim.h).
+
+Argument marshalling only: every step of the apply runs in the library's HIP
+kernels.  PyTorch supplies device memory and the current stream.  Importing
+this module does not build anything; if the shared library is missing every
+call raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfftpim.so")
+
+F64, F32 = 0, 1
+REAL, COMPLEX = 0, 1
+SELF_IMAGES, SELF_EXCLUDE = 0, 1
+ORDER_USER, ORDER_PLAN = 0, 1
+PART_NEAR_GRID, PART_NEAR_CORR, PART_FAR, PART_ALL = 1, 2, 4, 7
+
+STATUS = {
+    0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_CELL", 3: "NOT_NEUTRAL", 4: "WOOD_ANOMALY",
+    5: "UNSUPPORTED", 6: "NO_MEMORY", 7: "DEVICE", 8: "UNIMPLEMENTED",
+}
+
+# the entry points declared in include/fftpim.h
+EXPORTS = (
+    "fftpim_default_params", "fftpim_plan", "fftpim_apply", "fftpim_apply_adjoint",
+    "fftpim_apply_parts", "fftpim_get_permutation", "fftpim_plan_info", "fftpim_last_status",
+    "fftpim_destroy", "fftpim_error_string", "fftpim_eval_pgf", "fftpim_stage_times",
+)
+STAGES = ("pack", "near_spread", "near_fft", "near_interp", "near_corr", "far", "unpack")
+
+
+class FFTPIMError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        self.name = STATUS.get(code, str(code))
+        super().__init__("%s failed: %s (%d)" % (where, self.name, code))
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("periodic_dims", ctypes.c_int), ("L", ctypes.c_double * 3), ("k0", ctypes.c_double),
+                ("kt", ctypes.c_double * 3), ("has_box", ctypes.c_int), ("box_lo", ctypes.c_double * 3),
+                ("box_hi", ctypes.c_double * 3)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("near_n", ctypes.c_int * 3), ("near_order", ctypes.c_int), ("corr_radius", ctypes.c_int),
+                ("far_n", ctypes.c_int * 3), ("far_order", ctypes.c_int), ("n_images", ctypes.c_int),
+                ("precision", ctypes.c_int), ("value_type", ctypes.c_int), ("self_mode", ctypes.c_int),
+                ("order_io", ctypes.c_int), ("nrhs_max", ctypes.c_int)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("n_src", ctypes.c_int64), ("n_obs", ctypes.c_int64), ("near_n", ctypes.c_int * 3),
+                ("near_fft", ctypes.c_int * 3), ("near_cells", ctypes.c_int * 3), ("near_h", ctypes.c_double * 3),
+                ("domain_lo", ctypes.c_double * 3), ("domain_hi", ctypes.c_double * 3),
+                ("far_n", ctypes.c_int * 3), ("far_cells", ctypes.c_int * 3), ("far_h", ctypes.c_double * 3),
+                ("corr_nnz", ctypes.c_int64), ("device_bytes", ctypes.c_int64), ("nplanes_max", ctypes.c_int),
+                ("plan_seconds", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libfftpim.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libfftpim.so is not built; run `python -m paper_2312_02376_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+        L.fftpim_default_params.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Params)]
+        L.fftpim_plan.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Problem), ctypes.POINTER(Params), i64, vp,
+                                  i64, vp, vp]
+        L.fftpim_apply.argtypes = [vp, vp, vp, ci, vp]
+        L.fftpim_apply_adjoint.argtypes = [vp, vp, vp, ci, vp]
+        L.fftpim_apply_parts.argtypes = [vp, ci, ci, vp, vp, ci, vp]
+        L.fftpim_get_permutation.argtypes = [vp, ci, vp]
+        L.fftpim_plan_info.argtypes = [vp, ctypes.POINTER(Info)]
+        L.fftpim_last_status.argtypes = [vp]
+        L.fftpim_destroy.argtypes = [vp]
+        L.fftpim_error_string.argtypes = [ci]
+        L.fftpim_error_string.restype = ctypes.c_char_p
+        L.fftpim_eval_pgf.argtypes = [ctypes.POINTER(Problem), i64, vp, vp]
+        L.fftpim_stage_times.argtypes = [vp, ci, vp, vp]
+        for name in EXPORTS:
+            if name != "fftpim_error_string":
+                getattr(L, name).restype = ci
+        _lib = L
+    return _lib
+
+
+def _check(code, where):
+    if code != 0:
+        raise FFTPIMError(code, where)
+
+
+def make_problem(periodic_dims, L, k0=0.0, kt=(0.0, 0.0, 0.0), box=None):
+    pr = Problem()
+    pr.periodic_dims = int(periodic_dims)
+    Lv = list(np.broadcast_to(np.asarray(L, float), (3,))) if np.ndim(L) == 0 else list(L) + [1.0] * (3 - len(L))
+    for c in range(3):
+        pr.L[c] = float(Lv[c])
+        pr.kt[c] = float(kt[c]) if c < len(kt) else 0.0
+    pr.k0 = float(k0)
+    if box is not None:
+        pr.has_box = 1
+        for c in range(3):
+            pr.box_lo[c] = float(box[0][c])
+            pr.box_hi[c] = float(box[1][c])
+    return pr
+
+
+def eval_pgf(r, periodic_dims, L, k0=0.0, kt=(0.0, 0.0, 0.0)):
+    """The library's host evaluator of G^p (used for the far-zone table) at
+    host points r (n, 3); returns complex128 (n,).  No GPU is touched."""
+    r = np.ascontiguousarray(np.asarray(r, dtype=np.float64).reshape(-1, 3))
+    out = np.empty((r.shape[0], 2))
+    pr = make_problem(periodic_dims, L, k0, kt)
+    _check(lib().fftpim_eval_pgf(ctypes.byref(pr), r.shape[0], r.ctypes.data, out.ctypes.data), "fftpim_eval_pgf")
+    return out[:, 0] + 1j * out[:, 1]
+
+
+def _stream_handle(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Plan:
+    """An FFT-PIM plan over coinciding sources and observers.
+
+    positions: torch CUDA float64 tensor (N, 3) in the zeroth cell.
+    The remaining arguments map one-to-one onto fftpim_problem_t and
+    fftpim_params_t (include/fftpim.h).
+    """
+
+    def __init__(self, positions, periodic_dims, L, k0=0.0, kt=(0.0, 0.0, 0.0), near_n=(16, 16, 16),
+                 near_order=4, corr_radius=6, far_n=(16, 16, 16), far_order=7, n_images=1, precision="f64",
+                 value_type="complex", order="user", nrhs_max=1, box=None, self_mode="images", stream=None):
+        import torch
+        if not (isinstance(positions, torch.Tensor) and positions.is_cuda and positions.dtype == torch.float64):
+            raise TypeError("positions must be a CUDA float64 tensor of shape (N, 3)")
+        pos = positions.contiguous()
+        self.N = int(pos.shape[0])
+        self.problem = make_problem(periodic_dims, L, k0, kt, box)
+        pm = Params()
+        for c in range(3):
+            pm.near_n[c] = int(np.broadcast_to(near_n, (3,))[c])
+            pm.far_n[c] = int(np.broadcast_to(far_n, (3,))[c])
+        pm.near_order = int(near_order)
+        pm.corr_radius = int(corr_radius)
+        pm.far_order = int(far_order)
+        pm.n_images = int(n_images)
+        pm.precision = {"f64": F64, "f32": F32}[precision]
+        pm.value_type = {"real": REAL, "complex": COMPLEX}[value_type]
+        pm.self_mode = {"images": SELF_IMAGES, "exclude": SELF_EXCLUDE}[self_mode]
+        pm.order_io = {"user": ORDER_USER, "plan": ORDER_PLAN}[order]
+        pm.nrhs_max = int(nrhs_max)
+        self.params = pm
+        self.precision = precision
+        self.value_type = value_type
+        if precision == "f64":
+            self.dtype = torch.float64 if value_type == "real" else torch.complex128
+        else:
+            self.dtype = torch.float32 if value_type == "real" else torch.complex64
+        self.device = pos.device
+        h = ctypes.c_void_p()
+        _check(lib().fftpim_plan(ctypes.byref(h), ctypes.byref(self.problem), ctypes.byref(pm), self.N,
+                                 ctypes.c_void_p(pos.data_ptr()), 0, None, _stream_handle(stream)), "fftpim_plan")
+        self._h = h
+
+    def _io(self, x, out):
+        import torch
+        if x.dtype != self.dtype or not x.is_cuda:
+            raise TypeError("expected a CUDA %s tensor" % self.dtype)
+        squeeze = x.dim() == 1
+        x2 = x.reshape(1, -1) if squeeze else x
+        if x2.shape[1] != self.N:
+            raise ValueError("expected %d points, got %d" % (self.N, x2.shape[1]))
+        x2 = x2.contiguous()
+        if out is None:
+            out = torch.empty_like(x2)
+        return x2, out, squeeze
+
+    def apply(self, q, out=None, stream=None):
+        """u = A q, q of shape (nrhs, N) or (N,)."""
+        q2, out, sq = self._io(q, out)
+        _check(lib().fftpim_apply(self._h, ctypes.c_void_p(q2.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                  q2.shape[0], _stream_handle(stream)), "fftpim_apply")
+        return out[0] if sq else out
+
+    def adjoint(self, v, out=None, stream=None):
+        """w = A^H v (mean removed for the neutral static case)."""
+        v2, out, sq = self._io(v, out)
+        _check(lib().fftpim_apply_adjoint(self._h, ctypes.c_void_p(v2.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                          v2.shape[0], _stream_handle(stream)), "fftpim_apply_adjoint")
+        return out[0] if sq else out
+
+    def apply_parts(self, q, parts, adjoint=False, out=None, stream=None):
+        q2, out, sq = self._io(q, out)
+        _check(lib().fftpim_apply_parts(self._h, int(parts), 1 if adjoint else 0, ctypes.c_void_p(q2.data_ptr()),
+                                        ctypes.c_void_p(out.data_ptr()), q2.shape[0], _stream_handle(stream)),
+               "fftpim_apply_parts")
+        return out[0] if sq else out
+
+    def permutation(self):
+        import torch
+        perm = torch.empty(self.N, dtype=torch.int32, device=self.device)
+        _check(lib().fftpim_get_permutation(self._h, 0, ctypes.c_void_p(perm.data_ptr())), "fftpim_get_permutation")
+        return perm
+
+    def info(self):
+        inf = Info()
+        _check(lib().fftpim_plan_info(self._h, ctypes.byref(inf)), "fftpim_plan_info")
+        return {f: (list(getattr(inf, f)) if hasattr(getattr(inf, f), "__len__") else getattr(inf, f))
+                for f, _ in Info._fields_}
+
+    def stage_times(self, enable):
+        """Start (enable=True) or stop per-stage HIP-event timing; returns
+        {stage: (total_ms, launches)} accumulated since timing was started."""
+        ms = np.zeros(len(STAGES))
+        calls = np.zeros(len(STAGES), dtype=np.int64)
+        _check(lib().fftpim_stage_times(self._h, 1 if enable else 0, ms.ctypes.data, calls.ctypes.data),
+               "fftpim_stage_times")
+        return {s: (float(ms[i]), int(calls[i])) for i, s in enumerate(STAGES)}
+
+    def last_status(self):
+        return int(lib().fftpim_last_status(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().fftpim_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

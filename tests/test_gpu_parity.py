@@ -1,0 +1,184 @@
+"""GPU parity: the HIP library (through its C ABI) against the step-by-step
+FP64 oracle of Sec. 3, stage by stage and whole, forward and conjugate
+transpose, on small seeded problems that span several grid tiles, odd point
+counts and every problem class the library takes."""
+import numpy as np
+import pytest
+
+from oracle import pgf as P
+from oracle import steps as S
+from paper_2312_02376_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TWO_PI = 2 * np.pi
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def _fftpim():
+    from paper_2312_02376_amd import fftpim
+    return fftpim
+
+
+# name: (lattice kwargs, points, nrhs, value type, near n, q, rc, far n, qf)
+CASES = {
+    "npsp3_real": (dict(dims=3, L=[1, 1, 1]), "cube", 3, "real", (16, 16, 16), 4, 5, (10, 10, 10), 5),
+    "helm2_bloch": (dict(dims=2, L=[1, 1], k0=TWO_PI, kt=[0.3 * TWO_PI, 0.1 * TWO_PI]), "surface", 2, "complex",
+                    (16, 16, 8), 4, 4, (10, 10, 8), 5),
+    "phase3_static": (dict(dims=3, L=[1, 1.2, 0.9], k0=0.0, kt=[0.5, 0.3, 0.2]), "cube", 1, "complex",
+                      (16, 16, 16), 3, 4, (9, 9, 9), 4),
+    "helm3": (dict(dims=3, L=[1, 1, 1], k0=5.0, kt=[0.0, 0.0, 0.0]), "cube", 1, "complex", (16, 16, 16), 4, 4,
+              (10, 10, 10), 5),
+    "npsp2_real": (dict(dims=2, L=[1, 1.3]), "slab", 2, "real", (16, 16, 8), 4, 4, (10, 10, 8), 5),
+    "npsp1_real": (dict(dims=1, L=[1.0]), "rod", 2, "real", (16, 8, 8), 2, 3, (10, 8, 8), 3),
+}
+
+
+def _points(kind, N, seed):
+    rng = np.random.default_rng(seed)
+    if kind == "cube":
+        return W.uniform_cube(N, seed, (1.0, 1.0, 1.0))
+    if kind == "surface":
+        return W.smooth_closed_surface(N, seed)
+    if kind == "slab":
+        p = rng.random((N, 3)) * np.array([1.0, 1.3, 0.4])
+        return p
+    if kind == "rod":
+        p = rng.random((N, 3)) * np.array([1.0, 0.5, 0.3])
+        return p
+    raise ValueError(kind)
+
+
+def _setup(name, N=257, seed=31, precision="f64"):
+    latkw, kind, nrhs, vt, nn, q, rc, nf, qf = CASES[name]
+    lat = P.Lattice(latkw["dims"], latkw["L"], latkw.get("k0", 0.0), latkw.get("kt", [0, 0, 0]))
+    src = _points(kind, N, seed)
+    if kind == "cube":
+        src = src * np.asarray((latkw["L"] + [1, 1, 1])[:3])
+    ref = S.FFTPIM(lat, S.Params(nn, q, rc, nf, qf, 1), src)
+    rng = np.random.default_rng(seed + 1)
+    if vt == "real":
+        qv = rng.standard_normal((nrhs, N))
+        qv -= qv.mean(axis=1, keepdims=True)
+    else:
+        qv = rng.standard_normal((nrhs, N)) + 1j * rng.standard_normal((nrhs, N))
+    fp = _fftpim()
+    pos = torch.tensor(src, dtype=torch.float64, device="cuda")
+    plan = fp.Plan(pos, latkw["dims"], latkw["L"], k0=latkw.get("k0", 0.0), kt=latkw.get("kt", [0, 0, 0]),
+                   near_n=nn, near_order=q, corr_radius=rc, far_n=nf, far_order=qf, n_images=1,
+                   precision=precision, value_type=vt, nrhs_max=4)
+    return lat, ref, plan, qv
+
+
+def _to_dev(plan, x):
+    return torch.tensor(np.ascontiguousarray(x), dtype=plan.dtype, device="cuda")
+
+
+PARTS = {"near_grid": 1, "near_corr": 2, "far": 4}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_stage_parity_fp64(name, adjoint):
+    print("case", name, "adjoint", adjoint, flush=True)
+    lat, ref, plan, qv = _setup(name)
+    qd = _to_dev(plan, qv)
+    for part, bit in PARTS.items():
+        got = plan.apply_parts(qd, bit, adjoint=adjoint).cpu().numpy()
+        want = (ref.adjoint if adjoint else ref.apply)(qv, parts=(part,))
+        err = rel(got, want)
+        print("  ", part, "rel %.2e" % err, flush=True)
+        assert err < 1e-11, (name, part, adjoint, err)
+    got = plan.apply_parts(qd, 7, adjoint=adjoint).cpu().numpy()
+    want = (ref.adjoint if adjoint else ref.apply)(qv)
+    assert rel(got, want) < 1e-11
+
+
+@pytest.mark.parametrize("name", ["npsp3_real", "helm2_bloch"])
+def test_full_apply_and_adjoint(name):
+    lat, ref, plan, qv = _setup(name)
+    qd = _to_dev(plan, qv)
+    u = plan.apply(qd).cpu().numpy()
+    assert plan.last_status() == 0
+    assert rel(u, ref.apply(qv)) < 1e-11
+    w = plan.adjoint(qd).cpu().numpy()
+    want = ref.adjoint(qv)
+    if lat.npsp:
+        # only the zero-mean part of A^H v is defined for the neutral static case
+        want = want - want.mean(axis=-1, keepdims=True)
+    assert rel(w, want) < 1e-11
+
+
+@pytest.mark.parametrize("name", ["npsp3_real", "helm2_bloch"])
+def test_fp32_mode(name):
+    lat, ref, plan, qv = _setup(name, precision="f32")
+    qd = _to_dev(plan, qv)
+    u = plan.apply_parts(qd, 7).cpu().numpy()
+    assert rel(u, ref.apply(qv)) < 2e-5
+    w = plan.apply_parts(qd, 7, adjoint=True).cpu().numpy()
+    assert rel(w, ref.adjoint(qv)) < 2e-5
+
+
+def test_adjoint_identity_on_device():
+    lat, ref, plan, qv = _setup("helm2_bloch", N=301, seed=5)
+    rng = np.random.default_rng(6)
+    v = rng.standard_normal(qv.shape) + 1j * rng.standard_normal(qv.shape)
+    Aq = plan.apply(_to_dev(plan, qv)).cpu().numpy()
+    AHv = plan.adjoint(_to_dev(plan, v)).cpu().numpy()
+    lhs = np.vdot(v, Aq)
+    rhs = np.vdot(AHv, qv)
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+def test_plan_order_io_and_permutation():
+    latkw, kind, nrhs, vt, nn, q, rc, nf, qf = CASES["npsp3_real"]
+    fp = _fftpim()
+    src = W.uniform_cube(300, 41)
+    qv = W.gaussian_neutral(2, 300, 41)
+    pos = torch.tensor(src, dtype=torch.float64, device="cuda")
+    kw = dict(near_n=nn, near_order=q, corr_radius=rc, far_n=nf, far_order=qf, value_type="real", nrhs_max=2)
+    pu = fp.Plan(pos, 3, [1, 1, 1], order="user", **kw)
+    pp = fp.Plan(pos, 3, [1, 1, 1], order="plan", **kw)
+    perm = pu.permutation().cpu().numpy().astype(np.int64)
+    assert sorted(perm.tolist()) == list(range(300))
+    uu = pu.apply(torch.tensor(qv, device="cuda")).cpu().numpy()
+    up = pp.apply(torch.tensor(qv[:, perm].copy(), device="cuda")).cpu().numpy()
+    np.testing.assert_allclose(up, uu[:, perm], rtol=0, atol=1e-13 * np.abs(uu).max())
+
+
+def test_non_neutral_input_is_reported():
+    fp = _fftpim()
+    src = W.uniform_cube(200, 3)
+    pos = torch.tensor(src, dtype=torch.float64, device="cuda")
+    plan = fp.Plan(pos, 3, [1, 1, 1], near_n=(16, 16, 16), corr_radius=4, far_n=(10, 10, 10), far_order=5,
+                   value_type="real")
+    q = torch.ones(200, dtype=torch.float64, device="cuda")
+    plan.apply(q)
+    assert plan.last_status() == 3
+    q2 = torch.tensor(W.plus_minus_charges(200, 3), device="cuda")
+    plan.apply(q2)
+    assert plan.last_status() == 0
+
+
+def test_repeated_applies_bitwise_identical():
+    lat, ref, plan, qv = _setup("helm2_bloch", N=333, seed=8)
+    qd = _to_dev(plan, qv)
+    a = plan.apply(qd).cpu().numpy()
+    b = plan.apply(qd).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+def test_single_point_and_tiny_problems():
+    fp = _fftpim()
+    lat = P.Lattice(2, [1, 1], TWO_PI, [0.3 * TWO_PI, 0.1 * TWO_PI])
+    src = np.array([[0.25, 0.5, 0.3]])
+    ref = S.FFTPIM(lat, S.Params((16, 16, 8), 4, 4, (10, 10, 8), 5, 1), src)
+    plan = fp.Plan(torch.tensor(src, device="cuda"), 2, [1, 1], k0=TWO_PI, kt=[0.3 * TWO_PI, 0.1 * TWO_PI],
+                   near_n=(16, 16, 8), corr_radius=4, far_n=(10, 10, 8), far_order=5)
+    q = np.array([1.0 + 0.5j])
+    u = plan.apply(torch.tensor(q, device="cuda")).cpu().numpy()
+    np.testing.assert_allclose(u, ref.apply(q), rtol=1e-11)
