@@ -505,6 +505,8 @@ int build_correction(fftpim_plan_s* p, const std::vector<int32_t>& s_host, const
   HIPCHK(hipStreamSynchronize(st));
   for (int64_t m = 0; m < p->N; ++m) rowptr[m + 1] += rowptr[m];
   p->nnz = rowptr[p->N];
+  if (std::getenv("FFTPIM_LOG"))
+    std::fprintf(stderr, "fftpim plan: correction nnz %lld\n", static_cast<long long>(p->nnz));
   CHK(upload(p, &p->rowptr, rowptr));
   CHK(dalloc(p, &p->col, p->nnz));
   const bool cv = p->complex_kernel;
@@ -534,7 +536,16 @@ int build_correction(fftpim_plan_s* p, const std::vector<int32_t>& s_host, const
   return FFTPIM_OK;
 }
 
+void plan_log(const char* what, std::chrono::steady_clock::time_point t0) {
+  static const bool on = std::getenv("FFTPIM_LOG") != nullptr;
+  if (!on) return;
+  double s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  std::fprintf(stderr, "fftpim plan: %-28s %8.3f s\n", what, s);
+  std::fflush(stderr);
+}
+
 int build_plan(fftpim_plan_s* p, int64_t N, const double* src_dev, hipStream_t st) {
+  const auto t0 = std::chrono::steady_clock::now();
   const fftpim_problem_t& pr = p->problem;
   const fftpim_params_t& pm = p->prm;
   const int dims = pr.periodic_dims;
@@ -637,11 +648,14 @@ int build_plan(fftpim_plan_s* p, int64_t N, const double* src_dev, hipStream_t s
   double* dpos = nullptr;
   CHK(upload(p, &dpos, pos_sorted));
 
+  plan_log("geometry and sort", t0);
   if (pm.precision == FFTPIM_F32)
     CHK(build_tables<float>(p, st));
   else
     CHK(build_tables<double>(p, st));
+  plan_log("near and far tables", t0);
   CHK(build_correction(p, s_sorted, dpos, st));
+  plan_log("correction operator", t0);
   dfree(p, dpos);
 
   // workspace
