@@ -240,7 +240,7 @@ int run_apply(fftpim_plan_s* p, int parts, bool adjoint, const void* in, void* o
     // Steps 1-3 of Sec. 3.3 (the same grid serves sources and observers)
     {
       StageTimer t(p, st, FFTPIM_STAGE_NEAR_SPREAD);
-      CHK(launch_spread_near<R>(p->ng.q, ga, p->box_start, p->near_u, N, p->q_int, P, p->grid0, st));
+      CHK(launch_spread_near<R>(p->ng.q, ga, p->box_start, p->near_s, p->near_u, N, p->q_int, P, p->grid0, st));
     }
     {
       StageTimer t(p, st, FFTPIM_STAGE_NEAR_FFT);
@@ -270,7 +270,7 @@ int run_apply(fftpim_plan_s* p, int parts, bool adjoint, const void* in, void* o
     StageTimer t(p, st, FFTPIM_STAGE_FAR);
     CHK(launch_far_moments<R>(qf, fa, fbs, fpm, fu_in, N, p->q_int, P, p->far_mom, st));
     CHK(launch_far_gather<R>(qf, fa, p->far_mom, P, p->far_q, st));
-    launch_far_apply<R>(fa, p->far_table, p->far_q, p->far_u, P, adjoint, st);
+    launch_far_apply<R>(fa, p->far_table, p->far_q, p->far_u, p->far_part, P, adjoint, st);
     CHK(launch_interp<R>(qf, grid_args(p->fg), fs_out, fu_out, N, p->far_u, P, p->u_int, true, st));
   }
   const double* mean = nullptr;
@@ -682,6 +682,10 @@ int build_plan(fftpim_plan_s* p, int64_t N, const double* src_dev, hipStream_t s
   p->far_q = b;
   CHK(dalloc(p, &b, static_cast<size_t>(Ngf) * P * es));
   p->far_u = b;
+  // the split count never exceeds min(64, ceil(Ngf / 256)) for any nrhs
+  const int64_t max_splits = std::min<int64_t>(64, std::max<int64_t>(1, (Ngf + 255) / 256));
+  CHK(dalloc(p, &b, static_cast<size_t>(max_splits) * Ngf * P * es));
+  p->far_part = b;
   CHK(dalloc(p, &p->sums, static_cast<size_t>(6) * P));
   CHK(dalloc(p, &p->status_dev, 1));
   HIPCHK(hipMemsetAsync(p->status_dev, 0, sizeof(int), st));

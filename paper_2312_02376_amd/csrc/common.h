@@ -180,6 +180,7 @@ struct fftpim_plan_s {
   void* far_mom = nullptr;        // [far boxes][(qf+1)^3][planes]
   void* far_q = nullptr;          // [planes][Ngf]
   void* far_u = nullptr;          // [planes][Ngf]
+  void* far_part = nullptr;       // [splits][planes][Ngf] partial grid sums
   double* sums = nullptr;         // [2][planes] neutrality / mean sums
   int* status_dev = nullptr;      // latched device-detected error
 

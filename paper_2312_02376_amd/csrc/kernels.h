@@ -70,8 +70,8 @@ void launch_plane_sums(const void* v, int64_t N, int P, double* out, hipStream_t
 void launch_check_neutral(const double* sums, int P, double tol, int* status, hipStream_t st);
 void launch_mean_from_sums(const double* sums, int P, int64_t N, double* mean, hipStream_t st);
 template <typename R>
-int launch_spread_near(int q, const GridArgs& g, const int32_t* box_start, const double* u3, int64_t N,
-                       const void* qint, int P, void* grid, hipStream_t st);
+int launch_spread_near(int q, const GridArgs& g, const int32_t* box_start, const int32_t* s3, const double* u3,
+                       int64_t N, const void* qint, int P, void* grid, hipStream_t st);
 template <typename R>
 int launch_interp(int q, const GridArgs& g, const int32_t* s3, const double* u3, int64_t N, const void* grid,
                   int P, void* uint, bool acc, hipStream_t st);
@@ -98,8 +98,10 @@ int launch_far_moments(int qf, const FarArgs& f, const int32_t* fbox_start, cons
                        const double* u3, int64_t N, const void* qint, int P, void* mom, hipStream_t st);
 template <typename R>
 int launch_far_gather(int qf, const FarArgs& f, const void* mom, int P, void* grid, hipStream_t st);
+// the far grid sum splits its inner dimension over this many blocks
+int far_apply_splits(int64_t Ngf, int P);
 template <typename R>
-void launch_far_apply(const FarArgs& f, const void* table, const void* in, void* out, int P, bool adjoint,
-                      hipStream_t st);
+void launch_far_apply(const FarArgs& f, const void* table, const void* in, void* out, void* part, int P,
+                      bool adjoint, hipStream_t st);
 
 }  // namespace fftpim

@@ -9,9 +9,16 @@
 //     stored (the table stays in L2).  The conjugate transpose uses
 //     conj(K[n', m']) from the same table.
 //   Step 3 (Eq. (interpolation)): the generic grid-to-point interpolation.
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace fftpim {
+
+// One block per far box, one thread per local stencil node; the box's points
+// are staged through LDS in chunks with their 1D weights, so every thread
+// only multiplies three staged weights per point.
+constexpr int kMomChunk = 64;
 
 template <typename R, int QF, int PB>
 __global__ void k_far_moments(FarArgs f, const int32_t* __restrict__ fbox_start, const int32_t* __restrict__ fperm,
@@ -19,32 +26,51 @@ __global__ void k_far_moments(FarArgs f, const int32_t* __restrict__ fbox_start,
                               cplx<R>* __restrict__ mom) {
   constexpr int K1 = QF + 1;
   constexpr int K = K1 * K1 * K1;
+  constexpr int CH = kMomChunk;
+  __shared__ double sw[CH][3][K1];
+  __shared__ cplx<R> sq[CH][PB];
   const int k = threadIdx.x;
-  if (k >= K) return;
   const int64_t b = blockIdx.x;
   const int p0 = blockIdx.y * PB;
   const int kx = k / (K1 * K1), ky = (k / K1) % K1, kz = k % K1;
-  const double c = basis_den_inv<QF>(kx) * basis_den_inv<QF>(ky) * basis_den_inv<QF>(kz);
   double ar[PB], ai[PB];
 #pragma unroll
   for (int pp = 0; pp < PB; ++pp) ar[pp] = ai[pp] = 0.0;
   const int j0 = fbox_start[b], j1 = fbox_start[b + 1];
-  for (int j = j0; j < j1; ++j) {
-    const int n = fperm[j];
-    const double w = c * basis_num<QF>(kx, u3[n]) * basis_num<QF>(ky, u3[N + n]) * basis_num<QF>(kz, u3[2 * N + n]);
+  for (int base = j0; base < j1; base += CH) {
+    __syncthreads();
+    if (k < CH && base + k < j1) {
+      const int n = fperm[base + k];
+      double w[K1];
 #pragma unroll
-    for (int pp = 0; pp < PB; ++pp) {
-      if (p0 + pp < P) {
-        cplx<R> q = qint[static_cast<int64_t>(n) * P + p0 + pp];
-        ar[pp] += w * static_cast<double>(q.x);
-        ai[pp] += w * static_cast<double>(q.y);
+      for (int c = 0; c < 3; ++c) {
+        lagrange_all<QF, double>(u3[c * N + n], w);
+#pragma unroll
+        for (int a = 0; a < K1; ++a) sw[k][c][a] = w[a];
+      }
+#pragma unroll
+      for (int pp = 0; pp < PB; ++pp)
+        sq[k][pp] = (p0 + pp < P) ? qint[static_cast<int64_t>(n) * P + p0 + pp] : cmake<R>(R(0), R(0));
+    }
+    __syncthreads();
+    const int cnt = min(CH, j1 - base);
+    if (k < K) {
+      for (int i = 0; i < cnt; ++i) {
+        const double w = sw[i][0][kx] * sw[i][1][ky] * sw[i][2][kz];
+#pragma unroll
+        for (int pp = 0; pp < PB; ++pp) {
+          ar[pp] += w * static_cast<double>(sq[i][pp].x);
+          ai[pp] += w * static_cast<double>(sq[i][pp].y);
+        }
       }
     }
   }
+  if (k < K) {
 #pragma unroll
-  for (int pp = 0; pp < PB; ++pp)
-    if (p0 + pp < P)
-      mom[(b * K + k) * P + p0 + pp] = cmake<R>(static_cast<R>(ar[pp]), static_cast<R>(ai[pp]));
+    for (int pp = 0; pp < PB; ++pp)
+      if (p0 + pp < P)
+        mom[(b * K + k) * P + p0 + pp] = cmake<R>(static_cast<R>(ar[pp]), static_cast<R>(ai[pp]));
+  }
 }
 
 template <typename R, int QF>
@@ -71,19 +97,22 @@ __global__ void k_far_gather(FarArgs f, const cplx<R>* __restrict__ mom, int P, 
   grid[static_cast<int64_t>(p) * f.Ngf + g] = cmake<R>(static_cast<R>(ar), static_cast<R>(ai));
 }
 
-// out[p][i] = sum_j K(i, j) in[p][j] with K(i, j) = table[base(i) - off(j)]
-// (forward) or conj(table[base(j) - off(i)]) (conjugate transpose), where
-// base(i) = ((ix + nfx - 1) sy + iy + nfy - 1) sz + iz + nfz - 1 and
-// off(j) = (jx sy + jy) sz + jz index the (2 nf - 1)^3 offset table.
+// part[s][p][i] = sum_{j in split s} K(i, j) in[p][j], with K(i, j) =
+// table[base(i) - off(j)] (forward) or conj(table[base(j) - off(i)])
+// (conjugate transpose), base(i) = ((ix + nfx - 1) sy + iy + nfy - 1) sz +
+// iz + nfz - 1 and off(j) = (jx sy + jy) sz + jz indexing the (2 nf - 1)^3
+// offset table.  The splits over j are summed in a fixed order afterwards.
 template <typename R, int PB>
 __global__ void __launch_bounds__(256) k_far_apply(FarArgs f, const cplx<R>* __restrict__ table,
-                                                   const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out,
-                                                   int P, int adjoint) {
+                                                   const cplx<R>* __restrict__ in, cplx<R>* __restrict__ part,
+                                                   int P, int adjoint, int64_t jlen) {
   __shared__ cplx<R> sh[PB][256];
   __shared__ int64_t shi[256];
   const int64_t sy = 2 * f.nf[1] - 1, sz = 2 * f.nf[2] - 1;
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   const int p0 = blockIdx.y * PB;
+  const int split = blockIdx.z;
+  const int64_t jbeg = split * jlen, jend = min<int64_t>(f.Ngf, jbeg + jlen);
   const bool active = i < f.Ngf;
   int64_t base_i = 0, off_i = 0;
   if (active) {
@@ -96,9 +125,9 @@ __global__ void __launch_bounds__(256) k_far_apply(FarArgs f, const cplx<R>* __r
   R ar[PB], ai[PB];
 #pragma unroll
   for (int pp = 0; pp < PB; ++pp) ar[pp] = ai[pp] = R(0);
-  for (int64_t jc = 0; jc < f.Ngf; jc += 256) {
+  for (int64_t jc = jbeg; jc < jend; jc += 256) {
     const int64_t j = jc + threadIdx.x;
-    if (j < f.Ngf) {
+    if (j < jend) {
       const int jz = static_cast<int>(j % f.nf[2]);
       const int jy = static_cast<int>((j / f.nf[2]) % f.nf[1]);
       const int jx = static_cast<int>(j / (static_cast<int64_t>(f.nf[1]) * f.nf[2]));
@@ -109,7 +138,7 @@ __global__ void __launch_bounds__(256) k_far_apply(FarArgs f, const cplx<R>* __r
         sh[pp][threadIdx.x] = (p0 + pp < P) ? in[static_cast<int64_t>(p0 + pp) * f.Ngf + j] : cmake<R>(R(0), R(0));
     }
     __syncthreads();
-    const int cnt = static_cast<int>(min<int64_t>(256, f.Ngf - jc));
+    const int cnt = static_cast<int>(min<int64_t>(256, jend - jc));
     if (active) {
       for (int jj = 0; jj < cnt; ++jj) {
         const int64_t t = adjoint ? (shi[jj] - off_i) : (base_i - shi[jj]);
@@ -128,8 +157,18 @@ __global__ void __launch_bounds__(256) k_far_apply(FarArgs f, const cplx<R>* __r
   if (active) {
 #pragma unroll
     for (int pp = 0; pp < PB; ++pp)
-      if (p0 + pp < P) out[static_cast<int64_t>(p0 + pp) * f.Ngf + i] = cmake<R>(ar[pp], ai[pp]);
+      if (p0 + pp < P)
+        part[(static_cast<int64_t>(split) * P + p0 + pp) * f.Ngf + i] = cmake<R>(ar[pp], ai[pp]);
   }
+}
+
+template <typename R>
+__global__ void k_far_reduce(const cplx<R>* __restrict__ part, cplx<R>* __restrict__ out, int64_t n, int nsplit) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= n) return;
+  cplx<R> s = part[idx];
+  for (int k = 1; k < nsplit; ++k) s = cadd(s, part[static_cast<int64_t>(k) * n + idx]);
+  out[idx] = s;
 }
 
 // ---------------------------------------------------------------------------
@@ -198,15 +237,25 @@ int launch_far_gather(int qf, const FarArgs& f, const void* mom, int P, void* gr
   return FFTPIM_OK;
 }
 
+int far_apply_splits(int64_t Ngf, int P) {
+  const int64_t blocks = ((Ngf + 255) / 256) * ((P + 3) / 4);
+  int s = static_cast<int>(std::min<int64_t>(64, std::max<int64_t>(1, (2048 + blocks - 1) / blocks)));
+  return static_cast<int>(std::min<int64_t>(s, std::max<int64_t>(1, (Ngf + 255) / 256)));
+}
+
 template <typename R>
-void launch_far_apply(const FarArgs& f, const void* table, const void* in, void* out, int P, bool adjoint,
-                      hipStream_t st) {
+void launch_far_apply(const FarArgs& f, const void* table, const void* in, void* out, void* part, int P,
+                      bool adjoint, hipStream_t st) {
   const unsigned nb = static_cast<unsigned>((f.Ngf + 255) / 256);
+  const int ns = far_apply_splits(f.Ngf, P);
+  const int64_t jlen = (((f.Ngf + ns - 1) / ns + 255) / 256) * 256;
+  const int nsplit = static_cast<int>((f.Ngf + jlen - 1) / jlen);
 #define FFTPIM_FARAPPLY(PBV)                                                                               \
   do {                                                                                                     \
-    dim3 gr(nb, (P + PBV - 1) / PBV);                                                                      \
+    dim3 gr(nb, (P + PBV - 1) / PBV, nsplit);                                                              \
     hipLaunchKernelGGL((k_far_apply<R, PBV>), gr, dim3(256), 0, st, f, static_cast<const cplx<R>*>(table), \
-                       static_cast<const cplx<R>*>(in), static_cast<cplx<R>*>(out), P, adjoint ? 1 : 0);   \
+                       static_cast<const cplx<R>*>(in), static_cast<cplx<R>*>(part), P, adjoint ? 1 : 0,   \
+                       jlen);                                                                              \
   } while (0)
   if (P >= 4)
     FFTPIM_FARAPPLY(4);
@@ -215,13 +264,17 @@ void launch_far_apply(const FarArgs& f, const void* table, const void* in, void*
   else
     FFTPIM_FARAPPLY(1);
 #undef FFTPIM_FARAPPLY
+  const int64_t n = f.Ngf * P;
+  hipLaunchKernelGGL((k_far_reduce<R>), dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st,
+                     static_cast<const cplx<R>*>(part), static_cast<cplx<R>*>(out), n, nsplit);
 }
 
 #define FFTPIM_INST_FAR(R)                                                                                 \
   template int launch_far_moments<R>(int, const FarArgs&, const int32_t*, const int32_t*, const double*,   \
                                      int64_t, const void*, int, void*, hipStream_t);                       \
   template int launch_far_gather<R>(int, const FarArgs&, const void*, int, void*, hipStream_t);            \
-  template void launch_far_apply<R>(const FarArgs&, const void*, const void*, void*, int, bool, hipStream_t);
+  template void launch_far_apply<R>(const FarArgs&, const void*, const void*, void*, void*, int, bool,         \
+                                    hipStream_t);
 
 FFTPIM_INST_FAR(double)
 FFTPIM_INST_FAR(float)

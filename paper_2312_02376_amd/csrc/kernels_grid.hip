@@ -111,54 +111,105 @@ __global__ void k_mean_from_sums(const double* __restrict__ sums, int P, double 
 // Step 1: projection onto the near grid (gather form)
 // ---------------------------------------------------------------------------
 
+// A block owns a tile of TX x TY x TZ grid nodes (one thread per node) and
+// gathers every point whose stencil covers the tile: the points of the boxes
+// [tile - q, tile] per axis, which form (TX+q)(TY+q) contiguous runs of the
+// box-sorted point list.  Points are staged through LDS in chunks together
+// with their 1D Lagrange weights and amplitudes; each thread then sums the
+// staged points that cover its node, always in the same order (no atomics,
+// bitwise reproducible).
+constexpr int kSpreadTX = 4, kSpreadTY = 8, kSpreadTZ = 8, kSpreadChunk = 128;
+
 template <typename R, int Q, int PB>
 __global__ void __launch_bounds__(256) k_spread_near(
-    GridArgs g, const int32_t* __restrict__ box_start, const double* __restrict__ u3, int64_t N,
-    const cplx<R>* __restrict__ qint, int P, cplx<R>* __restrict__ grid) {
-  const int64_t n3 = static_cast<int64_t>(g.n[0]) * g.n[1] * g.n[2];
-  int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (idx >= n3) return;
+    GridArgs g, const int32_t* __restrict__ box_start, const int32_t* __restrict__ s3,
+    const double* __restrict__ u3, int64_t N, const cplx<R>* __restrict__ qint, int P,
+    cplx<R>* __restrict__ grid) {
+  constexpr int TX = kSpreadTX, TY = kSpreadTY, TZ = kSpreadTZ, CH = kSpreadChunk;
+  constexpr int NR = (TX + Q) * (TY + Q);
+  __shared__ int rstart[NR + 1];
+  __shared__ int rbase[NR];
+  __shared__ R sw[CH][3][Q + 1];
+  __shared__ int sb[CH][3];
+  __shared__ cplx<R> sq[CH][PB];
+  const int ntx = (g.n[0] + TX - 1) / TX, nty = (g.n[1] + TY - 1) / TY, ntz = (g.n[2] + TZ - 1) / TZ;
+  const int tile = blockIdx.x;
+  const int tz = tile % ntz, ty = (tile / ntz) % nty, tx = tile / (ntz * nty);
+  (void)ntx;
+  const int gx0 = tx * TX, gy0 = ty * TY, gz0 = tz * TZ;
+  const int tid = threadIdx.x;
+  const int gx = gx0 + tid / (TY * TZ), gy = gy0 + (tid / TZ) % TY, gz = gz0 + tid % TZ;
+  const bool valid = gx < g.n[0] && gy < g.n[1] && gz < g.n[2];
   const int p0 = blockIdx.y * PB;
-  const int gz = static_cast<int>(idx % g.n[2]);
-  const int gy = static_cast<int>((idx / g.n[2]) % g.n[1]);
-  const int gx = static_cast<int>(idx / (static_cast<int64_t>(g.n[1]) * g.n[2]));
-  double ax[PB], ay[PB];
+  // runs of the influence region
+  const int bx0 = max(0, gx0 - Q), bx1 = min(g.nint[0], gx0 + TX - 1);
+  const int by0 = max(0, gy0 - Q), by1 = min(g.nint[1], gy0 + TY - 1);
+  const int bz0 = max(0, gz0 - Q), bz1 = min(g.nint[2], gz0 + TZ - 1);
+  const int nbx = max(0, bx1 - bx0 + 1), nby = max(0, by1 - by0 + 1);
+  const int nr = (bz1 >= bz0) ? nbx * nby : 0;
+  if (tid < nr) {
+    const int ix = tid / nby, iy = tid % nby;
+    const int64_t bf = (static_cast<int64_t>(bx0 + ix) * g.nb[1] + (by0 + iy)) * g.nb[2] + bz0;
+    const int64_t bl = bf + (bz1 - bz0);
+    rbase[tid] = box_start[bf];
+    rstart[tid + 1] = box_start[bl + 1] - box_start[bf];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    rstart[0] = 0;
+    for (int r = 0; r < nr; ++r) rstart[r + 1] += rstart[r];
+  }
+  __syncthreads();
+  const int total = rstart[nr];
+  R ax[PB], ay[PB];
 #pragma unroll
-  for (int pp = 0; pp < PB; ++pp) ax[pp] = ay[pp] = 0.0;
-  const int bx0 = max(0, gx - Q), bx1 = min(gx, g.nint[0]);
-  const int by0 = max(0, gy - Q), by1 = min(gy, g.nint[1]);
-  const int bz0 = max(0, gz - Q), bz1 = min(gz, g.nint[2]);
-  for (int bx = bx0; bx <= bx1; ++bx) {
-    const int kx = gx - bx;
-    const double cx = basis_den_inv<Q>(kx);
-    for (int by = by0; by <= by1; ++by) {
-      const int ky = gy - by;
-      const double cxy = cx * basis_den_inv<Q>(ky);
-      for (int bz = bz0; bz <= bz1; ++bz) {
-        const int kz = gz - bz;
-        const double c = cxy * basis_den_inv<Q>(kz);
-        const int64_t b = (static_cast<int64_t>(bx) * g.nb[1] + by) * g.nb[2] + bz;
-        const int j0 = box_start[b], j1 = box_start[b + 1];
-        for (int j = j0; j < j1; ++j) {
-          const double w = c * basis_num<Q>(kx, u3[j]) * basis_num<Q>(ky, u3[N + j]) *
-                           basis_num<Q>(kz, u3[2 * N + j]);
+  for (int pp = 0; pp < PB; ++pp) ax[pp] = ay[pp] = R(0);
+  for (int base = 0; base < total; base += CH) {
+    __syncthreads();
+    const int k = base + tid;
+    if (tid < CH && k < total) {
+      int lo = 0, hi = nr - 1;  // run r with rstart[r] <= k < rstart[r + 1]
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (rstart[mid] <= k) lo = mid; else hi = mid - 1;
+      }
+      const int64_t j = rbase[lo] + (k - rstart[lo]);
+      double w[Q + 1];
 #pragma unroll
-          for (int pp = 0; pp < PB; ++pp) {
-            if (p0 + pp < P) {
-              cplx<R> qv = qint[static_cast<int64_t>(j) * P + p0 + pp];
-              ax[pp] += w * static_cast<double>(qv.x);
-              ay[pp] += w * static_cast<double>(qv.y);
-            }
-          }
+      for (int c = 0; c < 3; ++c) {
+        sb[tid][c] = s3[c * N + j];
+        lagrange_all<Q, double>(u3[c * N + j], w);
+#pragma unroll
+        for (int a = 0; a <= Q; ++a) sw[tid][c][a] = static_cast<R>(w[a]);
+      }
+#pragma unroll
+      for (int pp = 0; pp < PB; ++pp)
+        sq[tid][pp] = (p0 + pp < P) ? qint[j * P + p0 + pp] : cmake<R>(R(0), R(0));
+    }
+    __syncthreads();
+    const int cnt = min(CH, total - base);
+    if (valid) {
+      for (int i = 0; i < cnt; ++i) {
+        const unsigned kx = static_cast<unsigned>(gx - sb[i][0]);
+        const unsigned ky = static_cast<unsigned>(gy - sb[i][1]);
+        const unsigned kz = static_cast<unsigned>(gz - sb[i][2]);
+        if (kx > static_cast<unsigned>(Q) || ky > static_cast<unsigned>(Q) || kz > static_cast<unsigned>(Q)) continue;
+        const R w = sw[i][0][kx] * sw[i][1][ky] * sw[i][2][kz];
+#pragma unroll
+        for (int pp = 0; pp < PB; ++pp) {
+          ax[pp] += w * sq[i][pp].x;
+          ay[pp] += w * sq[i][pp].y;
         }
       }
     }
   }
+  if (valid) {
+    const int64_t n3 = static_cast<int64_t>(g.n[0]) * g.n[1] * g.n[2];
+    const int64_t node = (static_cast<int64_t>(gx) * g.n[1] + gy) * g.n[2] + gz;
 #pragma unroll
-  for (int pp = 0; pp < PB; ++pp)
-    if (p0 + pp < P)
-      grid[static_cast<int64_t>(p0 + pp) * n3 + idx] =
-          cmake<R>(static_cast<R>(ax[pp]), static_cast<R>(ay[pp]));
+    for (int pp = 0; pp < PB; ++pp)
+      if (p0 + pp < P) grid[static_cast<int64_t>(p0 + pp) * n3 + node] = cmake<R>(ax[pp], ay[pp]);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -446,28 +497,30 @@ void launch_mean_from_sums(const double* sums, int P, int64_t N, double* mean, h
   } while (0)
 
 template <typename R, int Q>
-static void spread_q(const GridArgs& g, const int32_t* box_start, const double* u3, int64_t N,
-                     const void* qint, int P, void* grid, hipStream_t st) {
-  const int64_t n3 = static_cast<int64_t>(g.n[0]) * g.n[1] * g.n[2];
+static void spread_q(const GridArgs& g, const int32_t* box_start, const int32_t* s3, const double* u3,
+                     int64_t N, const void* qint, int P, void* grid, hipStream_t st) {
+  const unsigned tiles = static_cast<unsigned>(((g.n[0] + kSpreadTX - 1) / kSpreadTX) *
+                                               ((g.n[1] + kSpreadTY - 1) / kSpreadTY) *
+                                               ((g.n[2] + kSpreadTZ - 1) / kSpreadTZ));
   FFTPIM_PB_DISPATCH(P, {
-    dim3 gr(blocks_for(n3, 256), (P + PB - 1) / PB);
-    hipLaunchKernelGGL((k_spread_near<R, Q, PB>), gr, dim3(256), 0, st, g, box_start, u3, N,
+    dim3 gr(tiles, (P + PB - 1) / PB);
+    hipLaunchKernelGGL((k_spread_near<R, Q, PB>), gr, dim3(256), 0, st, g, box_start, s3, u3, N,
                        static_cast<const cplx<R>*>(qint), P, static_cast<cplx<R>*>(grid));
   });
 }
 
 template <typename R>
-int launch_spread_near(int q, const GridArgs& g, const int32_t* box_start, const double* u3, int64_t N,
-                       const void* qint, int P, void* grid, hipStream_t st) {
+int launch_spread_near(int q, const GridArgs& g, const int32_t* box_start, const int32_t* s3, const double* u3,
+                       int64_t N, const void* qint, int P, void* grid, hipStream_t st) {
   switch (q) {
-    case 1: spread_q<R, 1>(g, box_start, u3, N, qint, P, grid, st); break;
-    case 2: spread_q<R, 2>(g, box_start, u3, N, qint, P, grid, st); break;
-    case 3: spread_q<R, 3>(g, box_start, u3, N, qint, P, grid, st); break;
-    case 4: spread_q<R, 4>(g, box_start, u3, N, qint, P, grid, st); break;
-    case 5: spread_q<R, 5>(g, box_start, u3, N, qint, P, grid, st); break;
-    case 6: spread_q<R, 6>(g, box_start, u3, N, qint, P, grid, st); break;
-    case 7: spread_q<R, 7>(g, box_start, u3, N, qint, P, grid, st); break;
-    case 8: spread_q<R, 8>(g, box_start, u3, N, qint, P, grid, st); break;
+    case 1: spread_q<R, 1>(g, box_start, s3, u3, N, qint, P, grid, st); break;
+    case 2: spread_q<R, 2>(g, box_start, s3, u3, N, qint, P, grid, st); break;
+    case 3: spread_q<R, 3>(g, box_start, s3, u3, N, qint, P, grid, st); break;
+    case 4: spread_q<R, 4>(g, box_start, s3, u3, N, qint, P, grid, st); break;
+    case 5: spread_q<R, 5>(g, box_start, s3, u3, N, qint, P, grid, st); break;
+    case 6: spread_q<R, 6>(g, box_start, s3, u3, N, qint, P, grid, st); break;
+    case 7: spread_q<R, 7>(g, box_start, s3, u3, N, qint, P, grid, st); break;
+    case 8: spread_q<R, 8>(g, box_start, s3, u3, N, qint, P, grid, st); break;
     default: return FFTPIM_ERR_UNSUPPORTED;
   }
   return FFTPIM_OK;
@@ -539,8 +592,8 @@ void launch_scale_convert(const void* in, void* out, int64_t n, double s, hipStr
   template void launch_unpack<R>(const void*, void*, const int32_t*, int64_t, int, int, bool, bool,      \
                                  const double*, hipStream_t);                                            \
   template void launch_plane_sums<R>(const void*, int64_t, int, double*, hipStream_t);                   \
-  template int launch_spread_near<R>(int, const GridArgs&, const int32_t*, const double*, int64_t,       \
-                                     const void*, int, void*, hipStream_t);                              \
+  template int launch_spread_near<R>(int, const GridArgs&, const int32_t*, const int32_t*, const double*, \
+                                     int64_t, const void*, int, void*, hipStream_t);                     \
   template int launch_interp<R>(int, const GridArgs&, const int32_t*, const double*, int64_t,            \
                                 const void*, int, void*, bool, hipStream_t);                             \
   template void launch_fft_pass<R>(int, const void*, void*, const FftPassDesc&, const void*, const void*, \
