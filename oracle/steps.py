@@ -231,12 +231,33 @@ class FFTPIM:
             out[r] = V[:n[0], :n[1], :n[2]].ravel()
         return out
 
-    def _far_matrix(self):
+    def _far_matrix(self, rows=None):
+        """Dense K[m', n'] = G^p_far(x^o_m' - x^s_n') of Eq. (8) (rows m' only
+        when given)."""
         nf = self.prm.far_n
         idx = np.stack(np.meshgrid(*[np.arange(nf[c]) for c in range(3)], indexing="ij"),
                        axis=-1).reshape(-1, 3)
-        dif = idx[:, None, :] - idx[None, :, :] + (nf - 1)
+        ri = idx if rows is None else idx[rows]
+        dif = ri[:, None, :] - idx[None, :, :] + (nf - 1)
         return self.far_table[dif[..., 0], dif[..., 1], dif[..., 2]]
+
+    def _far_grid_sum(self, Q, adjoint=False, block=1024):
+        """Eq. (8), u_g = K q_g, or its conjugate transpose K^H q_g, computed
+        one block of output grid nodes at a time.  Q: (nrhs, Ngf)."""
+        nf = self.prm.far_n
+        idx = np.stack(np.meshgrid(*[np.arange(nf[c]) for c in range(3)], indexing="ij"),
+                       axis=-1).reshape(-1, 3)
+        out = np.empty_like(Q)
+        for s0 in range(0, self.Ngf, block):
+            r = np.arange(s0, min(s0 + block, self.Ngf))
+            if adjoint:
+                # (K^H)[r, :] = conj(K[:, r])^T, K[m', n'] = table[m' - n']
+                dif = idx[None, :, :] - idx[r][:, None, :] + (nf - 1)
+                Kh = np.conj(self.far_table[dif[..., 0], dif[..., 1], dif[..., 2]])
+            else:
+                Kh = self._far_matrix(r)
+            out[:, r] = (Kh @ Q.T).T
+        return out
 
     # ------------------------------------------------------------------
     def correction_block(self, obs_rows, src_cols):
@@ -322,11 +343,9 @@ class FFTPIM:
         observer grid, applies K^H and interpolates from the source grid."""
         if adjoint:
             Qfo = _spread(self.fst_obs, qv, self.Ngf)
-            Ufs = (np.conj(self._far_matrix()).T @ Qfo.T).T
-            return _interp(self.fst_src, Ufs, rows)
+            return _interp(self.fst_src, self._far_grid_sum(Qfo, adjoint=True), rows)
         Qf = _spread(self.fst_src, qv, self.Ngf)
-        Uf = (self._far_matrix() @ Qf.T).T
-        return _interp(self.fst_obs, Uf, rows)
+        return _interp(self.fst_obs, self._far_grid_sum(Qf), rows)
 
     @staticmethod
     def _vec(q):

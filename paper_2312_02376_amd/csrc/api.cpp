@@ -83,6 +83,26 @@ void stencil(double x, double origin, double h, int q, int n, int32_t& s, double
   u = t - si;
 }
 
+// 1D Lagrange weights of the q+1 stencil nodes at offset u (Sec. 3.2, the
+// q-th order interpolation of Eq. (PGF_interp)), as a [3][q+1][N] array.
+std::vector<double> weights_soa(const std::vector<double>& u_soa, int64_t N, int q) {
+  std::vector<double> w(static_cast<size_t>(3) * (q + 1) * N);
+  for (int c = 0; c < 3; ++c)
+    for (int64_t j = 0; j < N; ++j) {
+      const double x = u_soa[c * N + j];
+      for (int a = 0; a <= q; ++a) {
+        double num = 1.0, den = 1.0;
+        for (int b = 0; b <= q; ++b)
+          if (b != a) {
+            num *= x - b;
+            den *= a - b;
+          }
+        w[(static_cast<size_t>(c) * (q + 1) + a) * N + j] = num / den;
+      }
+    }
+  return w;
+}
+
 // Stable counting sort of keys in [0, nkeys): order[] lists indices by key,
 // start[k] = first position of key k (start[nkeys] = count).
 void counting_sort(const std::vector<int64_t>& key, int64_t nkeys, std::vector<int32_t>& order,
@@ -240,14 +260,14 @@ int run_apply(fftpim_plan_s* p, int parts, bool adjoint, const void* in, void* o
     // Steps 1-3 of Sec. 3.3 (the same grid serves sources and observers)
     {
       StageTimer t(p, st, FFTPIM_STAGE_NEAR_SPREAD);
-      CHK(launch_spread_near<R>(p->ng.q, ga, p->box_start, p->near_s, p->near_u, N, p->q_int, P, p->grid0, st));
+      CHK(launch_spread_near<R>(p->ng.q, ga, p->box_start, p->near_s, p->near_w, N, p->q_int, P, p->grid0, st));
     }
     {
       StageTimer t(p, st, FFTPIM_STAGE_NEAR_FFT);
       near_convolution<R>(p, P, adjoint, st);
     }
     StageTimer t(p, st, FFTPIM_STAGE_NEAR_INTERP);
-    CHK(launch_interp<R>(p->ng.q, ga, p->near_s, p->near_u, N, p->grid0, P, p->u_int, false, st));
+    CHK(launch_interp<R>(p->ng.q, ga, p->near_s, p->near_w, N, p->grid0, P, p->u_int, false, st));
   } else {
     HIPCHK(hipMemsetAsync(p->u_int, 0, static_cast<size_t>(N) * P * sizeof(cplx<R>), st));
   }
@@ -264,9 +284,9 @@ int run_apply(fftpim_plan_s* p, int parts, bool adjoint, const void* in, void* o
     const int qf = p->fg.q;
     const int32_t* fbs = adjoint ? p->fbox_start_o : p->fbox_start_s;
     const int32_t* fpm = adjoint ? p->fperm_o : p->fperm_s;
-    const double* fu_in = adjoint ? p->fo_u : p->fs_u;
+    const double* fu_in = adjoint ? p->fo_w : p->fs_w;
     const int32_t* fs_out = adjoint ? p->fs_s : p->fo_s;
-    const double* fu_out = adjoint ? p->fs_u : p->fo_u;
+    const double* fu_out = adjoint ? p->fs_w : p->fo_w;
     StageTimer t(p, st, FFTPIM_STAGE_FAR);
     CHK(launch_far_moments<R>(qf, fa, fbs, fpm, fu_in, N, p->q_int, P, p->far_mom, st));
     CHK(launch_far_gather<R>(qf, fa, p->far_mom, P, p->far_q, st));
@@ -641,6 +661,9 @@ int build_plan(fftpim_plan_s* p, int64_t N, const double* src_dev, hipStream_t s
   CHK(upload(p, &p->fs_u, fs_u));
   CHK(upload(p, &p->fo_s, fo_s));
   CHK(upload(p, &p->fo_u, fo_u));
+  CHK(upload(p, &p->near_w, weights_soa(u_sorted, N, g.q)));
+  CHK(upload(p, &p->fs_w, weights_soa(fs_u, N, f.q)));
+  CHK(upload(p, &p->fo_w, weights_soa(fo_u, N, f.q)));
   CHK(upload(p, &p->fperm_s, forder_s));
   CHK(upload(p, &p->fbox_start_s, fstart_s));
   CHK(upload(p, &p->fperm_o, forder_o));

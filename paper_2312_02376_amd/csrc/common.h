@@ -147,6 +147,9 @@ struct fftpim_plan_s {
   int32_t* perm = nullptr;        // plan position -> caller index
   int32_t* near_s = nullptr;      // [3][N] stencil starts (= near boxes)
   double* near_u = nullptr;       // [3][N] position within the stencil
+  double* near_w = nullptr;       // [3][q+1][N] 1D Lagrange weights
+  double* fs_w = nullptr;         // [3][qf+1][N] far source-grid weights
+  double* fo_w = nullptr;         // [3][qf+1][N] far observer-grid weights
   int32_t* box_start = nullptr;   // [nb^3 + 1] first point of each box
   int32_t* fs_s = nullptr;        // far source-grid stencils [3][N]
   double* fs_u = nullptr;

@@ -6,6 +6,9 @@
 
 namespace fftpim {
 
+// Per-point interpolation data used by the kernels: stencil starts s3[c][N]
+// and the 1D Lagrange weights w3[c][a][N] (a = 0..q), both in plan order.
+
 // Geometry of one grid as the kernels see it.
 struct GridArgs {
   int n[3];     // nodes per axis

@@ -172,7 +172,24 @@ __global__ void __launch_bounds__(64) k_corr_fill(
   }
 }
 
-// One wavefront per row; lanes stride over the row; wave-level reduction.
+// One wavefront per row; lanes stride over the row two entries at a time
+// (independent accumulators keep more loads in flight); the column and value
+// streams are read once, so they are loaded non-temporally and leave the
+// cache to the gathered amplitudes.  Wave-level reduction at the end.
+typedef double dbl2_t __attribute__((ext_vector_type(2)));
+
+template <bool CPLX>
+__device__ inline void load_val(const void* __restrict__ val_v, int64_t j, double& vr, double& vi) {
+  if (CPLX) {
+    const dbl2_t v = __builtin_nontemporal_load(static_cast<const dbl2_t*>(val_v) + j);
+    vr = v.x;
+    vi = v.y;
+  } else {
+    vr = __builtin_nontemporal_load(static_cast<const double*>(val_v) + j);
+    vi = 0.0;
+  }
+}
+
 template <typename R, bool CPLX, int PB>
 __global__ void __launch_bounds__(256) k_corr_spmv(const int64_t* __restrict__ rowptr,
                                                    const int32_t* __restrict__ col,
@@ -183,32 +200,49 @@ __global__ void __launch_bounds__(256) k_corr_spmv(const int64_t* __restrict__ r
   const int64_t row = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (row >= N) return;
   const int p0 = blockIdx.y * PB;
-  double ar[PB], ai[PB];
+  double ar[PB], ai[PB], br[PB], bi[PB];
 #pragma unroll
-  for (int pp = 0; pp < PB; ++pp) ar[pp] = ai[pp] = 0.0;
+  for (int pp = 0; pp < PB; ++pp) ar[pp] = ai[pp] = br[pp] = bi[pp] = 0.0;
   const int64_t j1 = rowptr[row + 1];
-  for (int64_t j = rowptr[row] + lane; j < j1; j += 64) {
-    const int n = col[j];
-    double vr, vi = 0.0;
-    if (CPLX) {
-      cplx<double> v = static_cast<const cplx<double>*>(val_v)[j];
-      vr = v.x;
-      vi = v.y;
-    } else {
-      vr = static_cast<const double*>(val_v)[j];
-    }
+  int64_t j = rowptr[row] + lane;
+  for (; j + 64 < j1; j += 128) {
+    const int n0 = __builtin_nontemporal_load(col + j);
+    const int n1 = __builtin_nontemporal_load(col + j + 64);
+    double v0r, v0i, v1r, v1i;
+    load_val<CPLX>(val_v, j, v0r, v0i);
+    load_val<CPLX>(val_v, j + 64, v1r, v1i);
 #pragma unroll
     for (int pp = 0; pp < PB; ++pp) {
       if (p0 + pp < P) {
-        cplx<R> q = qint[static_cast<int64_t>(n) * P + p0 + pp];
-        const double qr = static_cast<double>(q.x), qi = static_cast<double>(q.y);
-        ar[pp] += vr * qr - vi * qi;
-        ai[pp] += vr * qi + vi * qr;
+        const cplx<R> q0 = qint[static_cast<int64_t>(n0) * P + p0 + pp];
+        const cplx<R> q1 = qint[static_cast<int64_t>(n1) * P + p0 + pp];
+        const double q0r = static_cast<double>(q0.x), q0i = static_cast<double>(q0.y);
+        const double q1r = static_cast<double>(q1.x), q1i = static_cast<double>(q1.y);
+        ar[pp] += v0r * q0r - v0i * q0i;
+        ai[pp] += v0r * q0i + v0i * q0r;
+        br[pp] += v1r * q1r - v1i * q1i;
+        bi[pp] += v1r * q1i + v1i * q1r;
+      }
+    }
+  }
+  if (j < j1) {
+    const int n0 = __builtin_nontemporal_load(col + j);
+    double v0r, v0i;
+    load_val<CPLX>(val_v, j, v0r, v0i);
+#pragma unroll
+    for (int pp = 0; pp < PB; ++pp) {
+      if (p0 + pp < P) {
+        const cplx<R> q0 = qint[static_cast<int64_t>(n0) * P + p0 + pp];
+        const double q0r = static_cast<double>(q0.x), q0i = static_cast<double>(q0.y);
+        ar[pp] += v0r * q0r - v0i * q0i;
+        ai[pp] += v0r * q0i + v0i * q0r;
       }
     }
   }
 #pragma unroll
   for (int pp = 0; pp < PB; ++pp) {
+    ar[pp] += br[pp];
+    ai[pp] += bi[pp];
     for (int off = 32; off > 0; off >>= 1) {
       ar[pp] += __shfl_down(ar[pp], off, 64);
       ai[pp] += __shfl_down(ai[pp], off, 64);

@@ -22,7 +22,7 @@ constexpr int kMomChunk = 64;
 
 template <typename R, int QF, int PB>
 __global__ void k_far_moments(FarArgs f, const int32_t* __restrict__ fbox_start, const int32_t* __restrict__ fperm,
-                              const double* __restrict__ u3, int64_t N, const cplx<R>* __restrict__ qint, int P,
+                              const double* __restrict__ w3, int64_t N, const cplx<R>* __restrict__ qint, int P,
                               cplx<R>* __restrict__ mom) {
   constexpr int K1 = QF + 1;
   constexpr int K = K1 * K1 * K1;
@@ -41,13 +41,10 @@ __global__ void k_far_moments(FarArgs f, const int32_t* __restrict__ fbox_start,
     __syncthreads();
     if (k < CH && base + k < j1) {
       const int n = fperm[base + k];
-      double w[K1];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        lagrange_all<QF, double>(u3[c * N + n], w);
+      for (int c = 0; c < 3; ++c)
 #pragma unroll
-        for (int a = 0; a < K1; ++a) sw[k][c][a] = w[a];
-      }
+        for (int a = 0; a < K1; ++a) sw[k][c][a] = w3[(c * K1 + a) * N + n];
 #pragma unroll
       for (int pp = 0; pp < PB; ++pp)
         sq[k][pp] = (p0 + pp < P) ? qint[static_cast<int64_t>(n) * P + p0 + pp] : cmake<R>(R(0), R(0));

@@ -118,14 +118,19 @@ __global__ void k_mean_from_sums(const double* __restrict__ sums, int P, double 
 // with their 1D Lagrange weights and amplitudes; each thread then sums the
 // staged points that cover its node, always in the same order (no atomics,
 // bitwise reproducible).
-constexpr int kSpreadTX = 4, kSpreadTY = 8, kSpreadTZ = 8, kSpreadChunk = 128;
+constexpr int kSpreadTX = 4, kSpreadTY = 8, kSpreadTZ = 8, kSpreadChunk = 256;
 
 template <typename R, int Q, int PB>
 __global__ void __launch_bounds__(256) k_spread_near(
     GridArgs g, const int32_t* __restrict__ box_start, const int32_t* __restrict__ s3,
-    const double* __restrict__ u3, int64_t N, const cplx<R>* __restrict__ qint, int P,
+    const double* __restrict__ w3, int64_t N, const cplx<R>* __restrict__ qint, int P,
     cplx<R>* __restrict__ grid) {
-  constexpr int TX = kSpreadTX, TY = kSpreadTY, TZ = kSpreadTZ, CH = kSpreadChunk;
+  constexpr int TX = kSpreadTX, TY = kSpreadTY, TZ = kSpreadTZ;
+  // staged bytes per point: weights, amplitudes, box; keep the chunk within 48 KB of LDS
+  constexpr int kPerPoint = 3 * (Q + 1) * static_cast<int>(sizeof(R)) + PB * 2 * static_cast<int>(sizeof(R)) + 12;
+  constexpr int CH = (kSpreadChunk * kPerPoint <= 49152) ? kSpreadChunk
+                     : ((kSpreadChunk / 2) * kPerPoint <= 49152 ? kSpreadChunk / 2 : kSpreadChunk / 4);
+  static_assert(CH <= TX * TY * TZ, "one staging thread per chunk slot");
   constexpr int NR = (TX + Q) * (TY + Q);
   __shared__ int rstart[NR + 1];
   __shared__ int rbase[NR];
@@ -174,13 +179,11 @@ __global__ void __launch_bounds__(256) k_spread_near(
         if (rstart[mid] <= k) lo = mid; else hi = mid - 1;
       }
       const int64_t j = rbase[lo] + (k - rstart[lo]);
-      double w[Q + 1];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         sb[tid][c] = s3[c * N + j];
-        lagrange_all<Q, double>(u3[c * N + j], w);
 #pragma unroll
-        for (int a = 0; a <= Q; ++a) sw[tid][c][a] = static_cast<R>(w[a]);
+        for (int a = 0; a <= Q; ++a) sw[tid][c][a] = static_cast<R>(w3[(c * (Q + 1) + a) * N + j]);
       }
 #pragma unroll
       for (int pp = 0; pp < PB; ++pp)
@@ -218,16 +221,19 @@ __global__ void __launch_bounds__(256) k_spread_near(
 
 template <typename R, int Q, int PB>
 __global__ void __launch_bounds__(256) k_interp(
-    GridArgs g, const int32_t* __restrict__ s3, const double* __restrict__ u3, int64_t N,
+    GridArgs g, const int32_t* __restrict__ s3, const double* __restrict__ w3, int64_t N,
     const cplx<R>* __restrict__ grid, int P, cplx<R>* __restrict__ uint, int accumulate) {
   int64_t m = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (m >= N) return;
   const int p0 = blockIdx.y * PB;
   const int64_t n3 = static_cast<int64_t>(g.n[0]) * g.n[1] * g.n[2];
   double wx[Q + 1], wy[Q + 1], wz[Q + 1];
-  lagrange_all<Q, double>(u3[m], wx);
-  lagrange_all<Q, double>(u3[N + m], wy);
-  lagrange_all<Q, double>(u3[2 * N + m], wz);
+#pragma unroll
+  for (int a = 0; a <= Q; ++a) {
+    wx[a] = w3[a * N + m];
+    wy[a] = w3[(Q + 1 + a) * N + m];
+    wz[a] = w3[(2 * (Q + 1) + a) * N + m];
+  }
   const int sx = s3[m], sy = s3[N + m], sz = s3[2 * N + m];
   double ax[PB], ay[PB];
 #pragma unroll

@@ -1,0 +1,70 @@
+"""Write the stored exact potentials used by the full-size workload tests.
+
+Every value is computed by the FP64 direct-sum oracle (oracle.psp) on the
+seeded inputs of paper_2312_02376_amd.workloads; nothing here touches the GPU
+library.  Run from the repository root:
+
+    python tests/golden/make_golden.py [coulomb_1k] [helmholtz_100k] [coulomb_1m]
+"""
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from oracle import pgf as P  # noqa: E402
+from oracle.psp import host_workers, psp_adjoint, psp_forward  # noqa: E402
+from paper_2312_02376_amd import workloads as W  # noqa: E402
+
+OUT = os.path.dirname(os.path.abspath(__file__))
+
+
+def _save(name, header, cols):
+    path = os.path.join(OUT, name)
+    np.savetxt(path, np.column_stack(cols), header=header, fmt="%.17g")
+    print("wrote", path)
+
+
+def coulomb_1k():
+    src, q = W.coulomb_cube_1k()
+    lat = P.Lattice(3, [1.0, 1.0, 1.0])
+    u = psp_forward(lat, src, q, workers=host_workers())
+    _save("coulomb_cube_1k_exact.txt",
+          "3D-periodic Coulomb, unit cube, 1000 uniform points, +-1 charges (workloads.coulomb_cube_1k);\n"
+          "exact u = sum_n G^p(r_m - r_n) q_n (singular self image dropped), all 1000 observers.\n"
+          "columns: index, u", [np.arange(1000), u.real])
+
+
+def helmholtz_100k(nrows=16):
+    src, q64 = W.helmholtz_surface_100k()
+    q = q64.astype(np.complex128)
+    v = W.gaussian_complex(1, len(src), 102)[0].astype(np.complex128)
+    k = 2 * np.pi
+    lat = P.Lattice(2, [1.0, 1.0], k, [0.3 * k, 0.1 * k])
+    rows = np.sort(np.random.default_rng(7).choice(len(src), nrows, replace=False))
+    u = psp_forward(lat, src, q, obs_index=rows, workers=host_workers())
+    w = psp_adjoint(lat, src, v, src_index=rows, workers=host_workers())
+    _save("helmholtz_surface_100k_rows.txt",
+          "2D-periodic Helmholtz, k0 = 2 pi, kt = (0.3, 0.1) k0, 100k surface points "
+          "(workloads.helmholtz_surface_100k);\nexact forward u = A q and conjugate transpose w = A^H v "
+          "(v = workloads.gaussian_complex(1, N, 102)) at sampled rows.\ncolumns: row, Re u, Im u, Re w, Im w",
+          [rows, u.real, u.imag, w.real, w.imag])
+
+
+def coulomb_1m(nrows=6):
+    src, q = W.coulomb_cube_1m_batched()
+    lat = P.Lattice(3, [1.0, 1.0, 1.0])
+    rows = np.sort(np.random.default_rng(11).choice(len(src), nrows, replace=False))
+    u = psp_forward(lat, src, q.astype(np.float64), obs_index=rows, workers=host_workers())
+    cols = [np.repeat(rows, q.shape[0]), np.tile(np.arange(q.shape[0]), nrows), u.real.T.ravel()]
+    _save("coulomb_cube_1m_rows.txt",
+          "3D-periodic Coulomb, 1M uniform points, 64 neutral Gaussian right-hand sides "
+          "(workloads.coulomb_cube_1m_batched);\nexact u at sampled rows.\ncolumns: row, rhs, u", cols)
+
+
+if __name__ == "__main__":
+    which = sys.argv[1:] or ["coulomb_1k", "helmholtz_100k", "coulomb_1m"]
+    for w in which:
+        globals()[w]()
