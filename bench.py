@@ -36,6 +36,65 @@ WORKLOAD = dict(
     near_n=(64, 64, 32), near_order=4, corr_radius=10, far_n=(24, 24, 16), far_order=7, n_images=1,
 )
 
+# secondary workloads (--workload): timed the same way, without the oracle leg
+SECONDARY = {
+    "coulomb_1k": dict(name="3D-periodic Coulomb, unit cube, 1000 uniform points, +-1 charges, FP64",
+                       dims=3, L=(1.0, 1.0, 1.0), precision="f64", value_type="real", nrhs=1,
+                       near_n=(16, 16, 16), near_order=4, corr_radius=14, far_n=(16, 16, 16), far_order=7),
+    "coulomb_1m_batched": dict(name="3D-periodic Coulomb, 1M uniform points, 64 neutral Gaussian right-hand "
+                                    "sides, FP32 bulk with FP64 correction",
+                               dims=3, L=(1.0, 1.0, 1.0), precision="f32", value_type="real", nrhs=64,
+                               near_n=(128, 128, 128), near_order=4, corr_radius=5, far_n=(14, 14, 14),
+                               far_order=5),
+}
+
+
+def run_secondary(args, key):
+    import numpy as np
+    import torch
+
+    from paper_2312_02376_amd import fftpim as fp
+    from paper_2312_02376_amd import workloads as W
+    wl = SECONDARY[key]
+    if key == "coulomb_1k":
+        src, q = W.coulomb_cube_1k()
+        q = q[None, :]
+    else:
+        src, q = W.coulomb_cube_1m_batched()
+    N, nrhs = src.shape[0], q.shape[0]
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    plan = fp.Plan(torch.tensor(src, device=dev), wl["dims"], list(wl["L"]), near_n=wl["near_n"],
+                   near_order=wl["near_order"], corr_radius=wl["corr_radius"], far_n=wl["far_n"],
+                   far_order=wl["far_order"], n_images=1, precision=wl["precision"],
+                   value_type=wl["value_type"], order="plan", nrhs_max=nrhs)
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    perm = plan.permutation().long()
+    qd = torch.tensor(q, device=dev)[:, perm].contiguous()
+    u = torch.empty_like(qd)
+    w = torch.empty_like(qd)
+    for _ in range(args.warmup):
+        plan.apply(qd, out=u)
+        plan.adjoint(qd, out=w)
+    torch.cuda.synchronize()
+    plan.stage_times(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.apply(qd, out=u)
+        plan.adjoint(qd, out=w)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stages = plan.stage_times(False)
+    ms = 1e3 * elapsed / args.steps
+    info = plan.info()
+    print("stages (ms per launch): " + ", ".join(
+        "%s %.4f" % (k, t / c) for k, (t, c) in stages.items() if c), file=sys.stderr, flush=True)
+    print(json.dumps({"workload": wl["name"], "value": N * nrhs / (ms * 1e-3), "unit": "observer points/s",
+                      "ms_per_step": ms, "steps": args.steps, "N": N, "nrhs": nrhs, "dtype": wl["precision"],
+                      "corr_nnz": info["corr_nnz"], "plan_seconds": plan_s}), flush=True)
+    plan.close()
+
 
 def measured_traffic(corr_radius, nnz):
     """HBM bytes per launch of the correction kernel from the committed
@@ -62,6 +121,8 @@ def main():
     ap.add_argument("--corr-radius", type=int, default=WORKLOAD["corr_radius"])
     ap.add_argument("--oracle-rows", type=int, default=24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="helmholtz_100k",
+                    choices=["helmholtz_100k"] + sorted(SECONDARY))
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (scale for the HBM byte counters)")
     args = ap.parse_args()
@@ -81,6 +142,10 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 3}))
+        return
+
+    if args.workload != "helmholtz_100k":
+        run_secondary(args, args.workload)
         return
 
     from paper_2312_02376_amd import fftpim as fp

@@ -251,9 +251,48 @@ int run_apply(fftpim_plan_s* p, int parts, bool adjoint, const void* in, void* o
     StageTimer t(p, st, FFTPIM_STAGE_PACK);
     launch_pack<R>(in, p->q_int, p->perm, N, nrhs, P, real_io, use_perm, st);
     if (finalize && !adjoint && p->lat.npsp()) {
-      launch_plane_sums<R>(p->q_int, N, P, p->sums, st);
+      launch_plane_sums<R>(p->q_int, nullptr, nullptr, N, P, p->sums, st);
       launch_check_neutral(p->sums, P, p->prm.precision == FFTPIM_F32 ? 1e-5 : 1e-10, p->status_dev, st);
     }
+  }
+  // Fork: the correction (Sec. 3.3 Step 4) and the far zone (Sec. 3.2) only
+  // read the packed amplitudes, so they run on their own streams while the
+  // near-grid steps run on the caller's stream (the paper runs near and far
+  // zones concurrently on two streams, Sec. 4.2).  Each part writes its own
+  // buffer; the unpack sums them in a fixed order.
+  const bool do_corr = (parts & FFTPIM_PART_NEAR_CORR) != 0;
+  const bool do_far = (parts & FFTPIM_PART_FAR) != 0;
+  HIPCHK(hipEventRecord(p->ev_fork, st));
+  if (do_corr) {
+    hipStream_t sc = p->s_corr;
+    HIPCHK(hipStreamWaitEvent(sc, p->ev_fork, 0));
+    const void* v = (adjoint && p->helmholtz) ? p->val_adj : p->val;
+    {
+      StageTimer t(p, sc, FFTPIM_STAGE_NEAR_CORR);
+      launch_corr_spmv<R>(p->complex_kernel, p->rowptr, p->col, v, N, p->q_int, P, p->u_corr, sc);
+    }
+    HIPCHK(hipEventRecord(p->ev_corr, sc));
+  }
+  if (do_far) {
+    // Steps 1-3 of Sec. 3.2; the adjoint projects with the observer-grid
+    // weights, applies K^H and interpolates from the source grid
+    hipStream_t sf = p->s_far;
+    HIPCHK(hipStreamWaitEvent(sf, p->ev_fork, 0));
+    const FarArgs fa = far_args(p);
+    const int qf = p->fg.q;
+    const int32_t* fbs = adjoint ? p->fbox_start_o : p->fbox_start_s;
+    const int32_t* fpm = adjoint ? p->fperm_o : p->fperm_s;
+    const double* fw_in = adjoint ? p->fo_w : p->fs_w;
+    const int32_t* fs_out = adjoint ? p->fs_s : p->fo_s;
+    const double* fw_out = adjoint ? p->fs_w : p->fo_w;
+    {
+      StageTimer t(p, sf, FFTPIM_STAGE_FAR);
+      CHK(launch_far_moments<R>(qf, fa, fbs, fpm, fw_in, N, p->q_int, P, p->far_mom, sf));
+      CHK(launch_far_gather<R>(qf, fa, p->far_mom, P, p->far_q, sf));
+      launch_far_apply<R>(fa, p->far_table, p->far_q, p->far_u, p->far_part, P, adjoint, sf);
+      CHK(launch_interp<R>(qf, grid_args(p->fg), fs_out, fw_out, N, p->far_u, P, p->u_far, false, sf));
+    }
+    HIPCHK(hipEventRecord(p->ev_far, sf));
   }
   const GridArgs ga = grid_args(p->ng);
   if (parts & FFTPIM_PART_NEAR_GRID) {
@@ -268,41 +307,23 @@ int run_apply(fftpim_plan_s* p, int parts, bool adjoint, const void* in, void* o
     }
     StageTimer t(p, st, FFTPIM_STAGE_NEAR_INTERP);
     CHK(launch_interp<R>(p->ng.q, ga, p->near_s, p->near_w, N, p->grid0, P, p->u_int, false, st));
-  } else {
-    HIPCHK(hipMemsetAsync(p->u_int, 0, static_cast<size_t>(N) * P * sizeof(cplx<R>), st));
   }
-  if (parts & FFTPIM_PART_NEAR_CORR) {
-    // Step 4 of Sec. 3.3
-    const void* v = (adjoint && p->helmholtz) ? p->val_adj : p->val;
-    StageTimer t(p, st, FFTPIM_STAGE_NEAR_CORR);
-    launch_corr_spmv<R>(p->complex_kernel, p->rowptr, p->col, v, N, p->q_int, P, p->u_int, st);
-  }
-  if (parts & FFTPIM_PART_FAR) {
-    // Steps 1-3 of Sec. 3.2; the adjoint projects with the observer-grid
-    // weights, applies K^H and interpolates from the source grid
-    const FarArgs fa = far_args(p);
-    const int qf = p->fg.q;
-    const int32_t* fbs = adjoint ? p->fbox_start_o : p->fbox_start_s;
-    const int32_t* fpm = adjoint ? p->fperm_o : p->fperm_s;
-    const double* fu_in = adjoint ? p->fo_w : p->fs_w;
-    const int32_t* fs_out = adjoint ? p->fs_s : p->fo_s;
-    const double* fu_out = adjoint ? p->fs_w : p->fo_w;
-    StageTimer t(p, st, FFTPIM_STAGE_FAR);
-    CHK(launch_far_moments<R>(qf, fa, fbs, fpm, fu_in, N, p->q_int, P, p->far_mom, st));
-    CHK(launch_far_gather<R>(qf, fa, p->far_mom, P, p->far_q, st));
-    launch_far_apply<R>(fa, p->far_table, p->far_q, p->far_u, p->far_part, P, adjoint, st);
-    CHK(launch_interp<R>(qf, grid_args(p->fg), fs_out, fu_out, N, p->far_u, P, p->u_int, true, st));
-  }
+  // join
+  if (do_corr) HIPCHK(hipStreamWaitEvent(st, p->ev_corr, 0));
+  if (do_far) HIPCHK(hipStreamWaitEvent(st, p->ev_far, 0));
+  const void* un = (parts & FFTPIM_PART_NEAR_GRID) ? p->u_int : nullptr;
+  const void* uc = do_corr ? p->u_corr : nullptr;
+  const void* uf = do_far ? p->u_far : nullptr;
   const double* mean = nullptr;
   if (finalize && adjoint && p->lat.npsp()) {
     // only the zero-mean part of A^H v is defined for the neutral static case
-    launch_plane_sums<R>(p->u_int, N, P, p->sums, st);
+    launch_plane_sums<R>(un, uc, uf, N, P, p->sums, st);
     launch_mean_from_sums(p->sums, P, N, p->sums + 4 * p->nplanes_max, st);
     mean = p->sums + 4 * p->nplanes_max;
   }
   {
     StageTimer t(p, st, FFTPIM_STAGE_UNPACK);
-    launch_unpack<R>(p->u_int, out, p->perm, N, nrhs, P, real_io, use_perm, mean, st);
+    launch_unpack<R>(un, uc, uf, out, p->perm, N, nrhs, P, real_io, use_perm, mean, st);
   }
   if (hipPeekAtLastError() != hipSuccess) return FFTPIM_ERR_DEVICE;
   return FFTPIM_OK;
@@ -691,6 +712,15 @@ int build_plan(fftpim_plan_s* p, int64_t N, const double* src_dev, hipStream_t s
   p->q_int = b;
   CHK(dalloc(p, &b, static_cast<size_t>(N) * P * es));
   p->u_int = b;
+  CHK(dalloc(p, &b, static_cast<size_t>(N) * P * es));
+  p->u_corr = b;
+  CHK(dalloc(p, &b, static_cast<size_t>(N) * P * es));
+  p->u_far = b;
+  HIPCHK(hipStreamCreateWithFlags(&p->s_corr, hipStreamNonBlocking));
+  HIPCHK(hipStreamCreateWithFlags(&p->s_far, hipStreamNonBlocking));
+  HIPCHK(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&p->ev_corr, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&p->ev_far, hipEventDisableTiming));
   CHK(dalloc(p, &b, static_cast<size_t>(n3) * P * es));
   p->grid0 = b;
   CHK(dalloc(p, &b, static_cast<size_t>(g.n[0]) * g.n[1] * p->M[2] * P * es));
@@ -858,8 +888,16 @@ int fftpim_stage_times(fftpim_plan_t plan, int enable, double* ms_out, int64_t* 
 
 int fftpim_destroy(fftpim_plan_t plan) {
   if (!plan) return FFTPIM_OK;
+  // the plan's streams may still be reading its buffers
+  for (hipStream_t s : {plan->s_corr, plan->s_far})
+    if (s) hipStreamSynchronize(s);
+  hipStreamSynchronize(plan->last_stream);
   for (hipEvent_t e : plan->ev_pool) hipEventDestroy(e);
   plan->ev_pool.clear();
+  for (hipEvent_t e : {plan->ev_fork, plan->ev_corr, plan->ev_far})
+    if (e) hipEventDestroy(e);
+  for (hipStream_t s : {plan->s_corr, plan->s_far})
+    if (s) hipStreamDestroy(s);
   for (void* ptr : plan->allocations) hipFree(ptr);
   plan->allocations.clear();
   delete plan;

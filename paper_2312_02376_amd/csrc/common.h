@@ -176,7 +176,13 @@ struct fftpim_plan_s {
   // workspace
   int nplanes_max = 0;
   void* q_int = nullptr;          // [N][planes] complex R (plan order)
-  void* u_int = nullptr;          // [N][planes] complex R
+  void* u_int = nullptr;          // [N][planes] complex R: near-grid part
+  void* u_corr = nullptr;         // [N][planes] correction part
+  void* u_far = nullptr;          // [N][planes] far-zone part
+  // the correction and the far zone run on their own streams, forked from and
+  // joined back into the caller's stream with events (default priority)
+  hipStream_t s_corr = nullptr, s_far = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_corr = nullptr, ev_far = nullptr;
   void* grid0 = nullptr;          // [planes][n^3]
   void* bufA = nullptr;           // [planes][nx][ny][Mz]
   void* bufB = nullptr;           // [planes][nx][My][Mz]

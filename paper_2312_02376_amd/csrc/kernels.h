@@ -65,11 +65,26 @@ struct FarArgs {
 template <typename R>
 void launch_pack(const void* qu, void* qint, const int32_t* perm, int64_t N, int nrhs, int P, bool real_in,
                  bool use_perm, hipStream_t st);
+// Up to three part buffers summed elementwise in a fixed order (null = absent).
 template <typename R>
-void launch_unpack(const void* uint, void* uu, const int32_t* perm, int64_t N, int nrhs, int P,
-                   bool real_out, bool use_perm, const double* mean, hipStream_t st);
+struct PartPtrs {
+  const cplx<R>* a;
+  const cplx<R>* b;
+  const cplx<R>* c;
+  __device__ cplx<R> sum(int64_t i) const {
+    cplx<R> s = cmake<R>(R(0), R(0));
+    if (a) s = cadd(s, a[i]);
+    if (b) s = cadd(s, b[i]);
+    if (c) s = cadd(s, c[i]);
+    return s;
+  }
+};
+
 template <typename R>
-void launch_plane_sums(const void* v, int64_t N, int P, double* out, hipStream_t st);
+void launch_unpack(const void* u_near, const void* u_corr, const void* u_far, void* uu, const int32_t* perm,
+                   int64_t N, int nrhs, int P, bool real_out, bool use_perm, const double* mean, hipStream_t st);
+template <typename R>
+void launch_plane_sums(const void* a, const void* b, const void* c, int64_t N, int P, double* out, hipStream_t st);
 void launch_check_neutral(const double* sums, int P, double tol, int* status, hipStream_t st);
 void launch_mean_from_sums(const double* sums, int P, int64_t N, double* mean, hipStream_t st);
 template <typename R>

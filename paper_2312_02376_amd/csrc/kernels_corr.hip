@@ -172,6 +172,7 @@ __global__ void __launch_bounds__(64) k_corr_fill(
   }
 }
 
+// Writes (does not accumulate) the correction of every row.
 // One wavefront per row; lanes stride over the row two entries at a time
 // (independent accumulators keep more loads in flight); the column and value
 // streams are read once, so they are loaded non-temporally and leave the
@@ -252,12 +253,54 @@ __global__ void __launch_bounds__(256) k_corr_spmv(const int64_t* __restrict__ r
 #pragma unroll
     for (int pp = 0; pp < PB; ++pp) {
       if (p0 + pp < P) {
-        cplx<R>* o = uint + row * P + p0 + pp;
-        cplx<R> u = *o;
-        u.x = static_cast<R>(static_cast<double>(u.x) + ar[pp]);
-        u.y = static_cast<R>(static_cast<double>(u.y) + ai[pp]);
-        *o = u;
+        uint[row * P + p0 + pp] = cmake<R>(static_cast<R>(ar[pp]), static_cast<R>(ai[pp]));
       }
+    }
+  }
+}
+
+// Many right-hand sides: the 64 lanes of a wavefront cover LP planes x
+// (64 / LP) entries of one row, so every CSR entry is read once per row and
+// the amplitudes of one source are one contiguous, coalesced load.  Partial
+// sums over the entry slots are combined with lane shuffles in a fixed order.
+template <typename R, bool CPLX, int LP>
+__global__ void __launch_bounds__(256) k_corr_spmm(const int64_t* __restrict__ rowptr,
+                                                   const int32_t* __restrict__ col,
+                                                   const void* __restrict__ val_v, int64_t N,
+                                                   const cplx<R>* __restrict__ qint, int P,
+                                                   cplx<R>* __restrict__ uint) {
+  constexpr int E = 64 / LP;
+  const int lane = threadIdx.x & 63;
+  const int e = lane / LP, pl = lane % LP;
+  const int64_t row = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (row >= N) return;
+  const int64_t j0 = rowptr[row], j1 = rowptr[row + 1];
+  for (int pc = 0; pc < P; pc += LP) {
+    const int p = pc + pl;
+    double ar = 0.0, ai = 0.0;
+    for (int64_t j = j0 + e; j < j1; j += E) {
+      const int n = col[j];
+      double vr, vi = 0.0;
+      if (CPLX) {
+        const cplx<double> v = static_cast<const cplx<double>*>(val_v)[j];
+        vr = v.x;
+        vi = v.y;
+      } else {
+        vr = static_cast<const double*>(val_v)[j];
+      }
+      if (p < P) {
+        const cplx<R> q = qint[static_cast<int64_t>(n) * P + p];
+        const double qr = static_cast<double>(q.x), qi = static_cast<double>(q.y);
+        ar += vr * qr - vi * qi;
+        ai += vr * qi + vi * qr;
+      }
+    }
+    for (int off = LP; off < 64; off <<= 1) {
+      ar += __shfl_xor(ar, off, 64);
+      ai += __shfl_xor(ai, off, 64);
+    }
+    if (e == 0 && p < P) {
+      uint[row * P + p] = cmake<R>(static_cast<R>(ar), static_cast<R>(ai));
     }
   }
 }
@@ -314,6 +357,25 @@ void launch_corr_spmv(bool cplx_vals, const int64_t* rowptr, const int32_t* col,
   const cplx<R>* q = static_cast<const cplx<R>*>(qint);
   cplx<R>* u = static_cast<cplx<R>*>(uint);
   unsigned nb = static_cast<unsigned>((N + 3) / 4);
+  if (P > 4) {
+#define FFTPIM_SPMM(LPV)                                                                                   \
+  do {                                                                                                     \
+    if (cplx_vals)                                                                                         \
+      hipLaunchKernelGGL((k_corr_spmm<R, true, LPV>), dim3(nb), dim3(256), 0, st, rowptr, col, val, N, q, P, u); \
+    else                                                                                                   \
+      hipLaunchKernelGGL((k_corr_spmm<R, false, LPV>), dim3(nb), dim3(256), 0, st, rowptr, col, val, N, q, P, u); \
+  } while (0)
+    if (P <= 8)
+      FFTPIM_SPMM(8);
+    else if (P <= 16)
+      FFTPIM_SPMM(16);
+    else if (P <= 32)
+      FFTPIM_SPMM(32);
+    else
+      FFTPIM_SPMM(64);
+#undef FFTPIM_SPMM
+    return;
+  }
 #define FFTPIM_SPMV(PBV)                                                                                   \
   do {                                                                                                     \
     dim3 gr(nb, (P + PBV - 1) / PBV);                                                                      \

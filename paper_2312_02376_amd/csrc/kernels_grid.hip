@@ -39,16 +39,18 @@ __global__ void k_pack(const void* __restrict__ qu, cplx<R>* __restrict__ qint,
   qint[m * P + p] = v;
 }
 
+// Sums the parts of the apply that were computed (near grid, correction, far
+// zone; absent parts are null) in that fixed order and writes the caller's
+// layout, removing a per-plane mean when one is given.
 template <typename R, bool REAL_OUT>
-__global__ void k_unpack(const cplx<R>* __restrict__ uint, void* __restrict__ uu,
-                         const int32_t* __restrict__ perm, int64_t N, int nrhs, int P, int use_perm,
-                         const double* __restrict__ mean) {
+__global__ void k_unpack(PartPtrs<R> parts, void* __restrict__ uu, const int32_t* __restrict__ perm, int64_t N,
+                         int nrhs, int P, int use_perm, const double* __restrict__ mean) {
   int64_t tid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (tid >= N * P) return;
   int p = static_cast<int>(tid / N);
   int64_t m = tid - static_cast<int64_t>(p) * N;
   int64_t dst = use_perm ? perm[m] : m;
-  cplx<R> v = uint[m * P + p];
+  cplx<R> v = parts.sum(m * P + p);
   if (mean) {
     v.x -= static_cast<R>(mean[2 * p]);
     v.y -= static_cast<R>(mean[2 * p + 1]);
@@ -67,12 +69,12 @@ __global__ void k_unpack(const cplx<R>* __restrict__ uint, void* __restrict__ uu
 // Per-plane sums over points, deterministic (one block per plane):
 // out[4p + 0/1] = sum of re/im, out[4p + 2/3] = sum of |re| / |im|.
 template <typename R>
-__global__ void k_plane_sums(const cplx<R>* __restrict__ v, int64_t N, int P, double* __restrict__ out) {
+__global__ void k_plane_sums(PartPtrs<R> v, int64_t N, int P, double* __restrict__ out) {
   __shared__ double sh[4][256];
   int p = blockIdx.x;
   double a = 0, b = 0, c = 0, d = 0;
   for (int64_t m = threadIdx.x; m < N; m += blockDim.x) {
-    cplx<R> t = v[m * P + p];
+    cplx<R> t = v.sum(m * P + p);
     a += t.x;
     b += t.y;
     c += fabs(static_cast<double>(t.x));
@@ -461,20 +463,30 @@ void launch_pack(const void* qu, void* qint, const int32_t* perm, int64_t N, int
 }
 
 template <typename R>
-void launch_unpack(const void* uint, void* uu, const int32_t* perm, int64_t N, int nrhs, int P,
-                   bool real_out, bool use_perm, const double* mean, hipStream_t st) {
-  unsigned nb = blocks_for(N * P, 256);
-  if (real_out)
-    hipLaunchKernelGGL((k_unpack<R, true>), dim3(nb), dim3(256), 0, st,
-                       static_cast<const cplx<R>*>(uint), uu, perm, N, nrhs, P, use_perm ? 1 : 0, mean);
-  else
-    hipLaunchKernelGGL((k_unpack<R, false>), dim3(nb), dim3(256), 0, st,
-                       static_cast<const cplx<R>*>(uint), uu, perm, N, nrhs, P, use_perm ? 1 : 0, mean);
+static PartPtrs<R> part_ptrs(const void* a, const void* b, const void* c) {
+  PartPtrs<R> s;
+  s.a = static_cast<const cplx<R>*>(a);
+  s.b = static_cast<const cplx<R>*>(b);
+  s.c = static_cast<const cplx<R>*>(c);
+  return s;
 }
 
 template <typename R>
-void launch_plane_sums(const void* v, int64_t N, int P, double* out, hipStream_t st) {
-  hipLaunchKernelGGL((k_plane_sums<R>), dim3(P), dim3(256), 0, st, static_cast<const cplx<R>*>(v), N, P, out);
+void launch_unpack(const void* u_near, const void* u_corr, const void* u_far, void* uu, const int32_t* perm,
+                   int64_t N, int nrhs, int P, bool real_out, bool use_perm, const double* mean, hipStream_t st) {
+  unsigned nb = blocks_for(N * P, 256);
+  PartPtrs<R> s = part_ptrs<R>(u_near, u_corr, u_far);
+  if (real_out)
+    hipLaunchKernelGGL((k_unpack<R, true>), dim3(nb), dim3(256), 0, st, s, uu, perm, N, nrhs, P, use_perm ? 1 : 0,
+                       mean);
+  else
+    hipLaunchKernelGGL((k_unpack<R, false>), dim3(nb), dim3(256), 0, st, s, uu, perm, N, nrhs, P,
+                       use_perm ? 1 : 0, mean);
+}
+
+template <typename R>
+void launch_plane_sums(const void* a, const void* b, const void* c, int64_t N, int P, double* out, hipStream_t st) {
+  hipLaunchKernelGGL((k_plane_sums<R>), dim3(P), dim3(256), 0, st, part_ptrs<R>(a, b, c), N, P, out);
 }
 
 void launch_check_neutral(const double* sums, int P, double tol, int* status, hipStream_t st) {
@@ -595,9 +607,10 @@ void launch_scale_convert(const void* in, void* out, int64_t n, double s, hipStr
 #define FFTPIM_INST_GRID(R)                                                                              \
   template void launch_pack<R>(const void*, void*, const int32_t*, int64_t, int, int, bool, bool,        \
                                hipStream_t);                                                             \
-  template void launch_unpack<R>(const void*, void*, const int32_t*, int64_t, int, int, bool, bool,      \
-                                 const double*, hipStream_t);                                            \
-  template void launch_plane_sums<R>(const void*, int64_t, int, double*, hipStream_t);                   \
+  template void launch_unpack<R>(const void*, const void*, const void*, void*, const int32_t*, int64_t,  \
+                                 int, int, bool, bool, const double*, hipStream_t);                      \
+  template void launch_plane_sums<R>(const void*, const void*, const void*, int64_t, int, double*,       \
+                                     hipStream_t);                                                       \
   template int launch_spread_near<R>(int, const GridArgs&, const int32_t*, const int32_t*, const double*, \
                                      int64_t, const void*, int, void*, hipStream_t);                     \
   template int launch_interp<R>(int, const GridArgs&, const int32_t*, const double*, int64_t,            \

@@ -53,8 +53,9 @@ def _points(kind, N, seed):
     raise ValueError(kind)
 
 
-def _setup(name, N=257, seed=31, precision="f64"):
-    latkw, kind, nrhs, vt, nn, q, rc, nf, qf = CASES[name]
+def _setup(name, N=257, seed=31, precision="f64", nrhs=None):
+    latkw, kind, nrhs0, vt, nn, q, rc, nf, qf = CASES[name]
+    nrhs = nrhs0 if nrhs is None else nrhs
     lat = P.Lattice(latkw["dims"], latkw["L"], latkw.get("k0", 0.0), latkw.get("kt", [0, 0, 0]))
     src = _points(kind, N, seed)
     if kind == "cube":
@@ -70,7 +71,7 @@ def _setup(name, N=257, seed=31, precision="f64"):
     pos = torch.tensor(src, dtype=torch.float64, device="cuda")
     plan = fp.Plan(pos, latkw["dims"], latkw["L"], k0=latkw.get("k0", 0.0), kt=latkw.get("kt", [0, 0, 0]),
                    near_n=nn, near_order=q, corr_radius=rc, far_n=nf, far_order=qf, n_images=1,
-                   precision=precision, value_type=vt, nrhs_max=4)
+                   precision=precision, value_type=vt, nrhs_max=max(4, nrhs))
     return lat, ref, plan, qv
 
 
@@ -182,3 +183,17 @@ def test_single_point_and_tiny_problems():
     q = np.array([1.0 + 0.5j])
     u = plan.apply(torch.tensor(q, device="cuda")).cpu().numpy()
     np.testing.assert_allclose(u, ref.apply(q), rtol=1e-11)
+
+
+@pytest.mark.parametrize("name,nrhs", [("npsp3_real", 19), ("helm2_bloch", 9), ("helm2_bloch", 40)])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_many_right_hand_sides(name, nrhs, precision):
+    # more than four planes: the correction runs as a lanes-over-planes SpMM
+    lat, ref, plan, qv = _setup(name, N=211, seed=13, precision=precision, nrhs=nrhs)
+    qd = _to_dev(plan, qv)
+    tol = 1e-11 if precision == "f64" else 2e-5
+    for adjoint in (False, True):
+        for part, bit in PARTS.items():
+            got = plan.apply_parts(qd, bit, adjoint=adjoint).cpu().numpy()
+            want = (ref.adjoint if adjoint else ref.apply)(qv, parts=(part,))
+            assert rel(got, want) < tol, (part, adjoint)
