@@ -97,7 +97,14 @@ typedef struct {
   int order_io;      /* FFTPIM_ORDER_USER: q/u indexed like the input points;
                         FFTPIM_ORDER_PLAN: indexed in the plan's sorted order */
   int nrhs_max;      /* largest nrhs a single apply may pass */
+  int corr_layout;   /* FFTPIM_CORR_AUTO, FFTPIM_CORR_CSR or FFTPIM_CORR_SYM */
 } fftpim_params_t;
+
+/* Storage of the near-zone correction of Eq. (er): one CSR row per observer,
+ * or (SYM) the in-cell part once per unordered pair of near-grid boxes (the
+ * image-0 correction is symmetric in source and observer) plus a CSR of the
+ * close-image part.  AUTO picks SYM when boxes hold several points each. */
+enum { FFTPIM_CORR_AUTO = 0, FFTPIM_CORR_CSR = 1, FFTPIM_CORR_SYM = 2 };
 
 typedef struct {
   int64_t n_src, n_obs;

@@ -26,6 +26,7 @@ SOURCES = [
     ("kernels_grid.hip", []),
     ("kernels_corr.hip", []),
     ("kernels_far.hip", []),
+    ("kernels_sym.hip", []),
     ("api.cpp", ["-x", "hip"]),
     ("pgf_host.cpp", []),
 ]

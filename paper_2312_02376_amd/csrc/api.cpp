@@ -178,6 +178,35 @@ void near_convolution(fftpim_plan_s* p, int P, bool adjoint, hipStream_t st) {
   launch_fft_pass<R>(1, p->bufA, p->grid0, iz, p->twiddle[2], nullptr, false, st);
 }
 
+SymArgs sym_args(const fftpim_plan_s* p) {
+  SymArgs a{};
+  const SymDev& d = p->symd;
+  a.N = p->N;
+  for (int c = 0; c < 3; ++c) a.nb[c] = p->nb[c];
+  a.R = p->prm.corr_radius + p->ng.q;
+  a.W = 2 * a.R + 1;
+  a.k0 = p->lat.k0;
+  a.max_box = d.max_box;
+  a.npairs = d.npairs;
+  a.nitems = d.nitems;
+  a.box_start = p->box_start;
+  a.ebox = d.ebox;
+  a.ebox_of_box = d.ebox_of_box;
+  a.box_of_point = d.box_of_point;
+  a.pair_ebox_o = d.pair_ebox_o;
+  a.pair_ebox_s = d.pair_ebox_s;
+  a.pair_voff = d.pair_voff;
+  a.pair_zoff = d.pair_zoff;
+  a.item_ebox = d.item_ebox;
+  a.item_pbeg = d.item_pbeg;
+  a.item_pend = d.item_pend;
+  a.item_yoff = d.item_yoff;
+  a.ebox_item_beg = d.ebox_item_beg;
+  a.in_beg = d.in_beg;
+  a.in_zoff = d.in_zoff;
+  return a;
+}
+
 GridArgs grid_args(const GridGeom& g) {
   GridArgs a{};
   for (int c = 0; c < 3; ++c) {
@@ -269,7 +298,15 @@ int run_apply(fftpim_plan_s* p, int parts, bool adjoint, const void* in, void* o
     const void* v = (adjoint && p->helmholtz) ? p->val_adj : p->val;
     {
       StageTimer t(p, sc, FFTPIM_STAGE_NEAR_CORR);
-      launch_corr_spmv<R>(p->complex_kernel, p->rowptr, p->col, v, N, p->q_int, P, p->u_corr, sc);
+      if (p->sym) {
+        // in-cell part: A^H of a complex-symmetric block is conj(X conj(v))
+        launch_sym_apply<R>(p->complex_kernel, sym_args(p), p->sym_vals, p->q_int, P, adjoint, p->sym_ypart,
+                            p->sym_zpart, p->u_corr, false, sc);
+        if (p->nnz > 0)
+          launch_corr_spmv<R>(p->complex_kernel, p->rowptr, p->col, v, N, p->q_int, P, p->u_corr, true, sc);
+      } else {
+        launch_corr_spmv<R>(p->complex_kernel, p->rowptr, p->col, v, N, p->q_int, P, p->u_corr, false, sc);
+      }
     }
     HIPCHK(hipEventRecord(p->ev_corr, sc));
   }
@@ -365,6 +402,7 @@ int validate(const fftpim_problem_t* pr, const fftpim_params_t* pm) {
   if (pm->self_mode != FFTPIM_SELF_IMAGES && pm->self_mode != FFTPIM_SELF_EXCLUDE) return FFTPIM_ERR_INVALID_ARG;
   if (pm->order_io != FFTPIM_ORDER_USER && pm->order_io != FFTPIM_ORDER_PLAN) return FFTPIM_ERR_INVALID_ARG;
   if (pm->nrhs_max < 1 || pm->nrhs_max > 4096) return FFTPIM_ERR_INVALID_ARG;
+  if (pm->corr_layout < FFTPIM_CORR_AUTO || pm->corr_layout > FFTPIM_CORR_SYM) return FFTPIM_ERR_INVALID_ARG;
   return FFTPIM_OK;
 }
 
@@ -461,7 +499,111 @@ int build_tables(fftpim_plan_s* p, hipStream_t st) {
   return FFTPIM_OK;
 }
 
-int build_correction(fftpim_plan_s* p, const std::vector<int32_t>& s_host, const double* pos3_dev,
+// Symmetric in-cell blocks: pairs (B, B') of non-empty near-grid boxes with
+// B <= B' (box id order) within r_c boxes (no image shift), grouped into work
+// items of up to kPairsPerItem pairs of one box; values filled on the device.
+constexpr int kPairsPerItem = 32;
+
+int build_sym(fftpim_plan_s* p, const std::vector<int32_t>& start, const double* pos3_dev, const void* g0tab,
+              const CorrArgs& ca, hipStream_t st) {
+  const int nbx = p->nb[0], nby = p->nb[1], nbz = p->nb[2];
+  const int64_t nboxes = static_cast<int64_t>(nbx) * nby * nbz;
+  const int rc = p->prm.corr_radius;
+  std::vector<int32_t> ebox, ebox_of_box(nboxes, -1), box_of_point(p->N);
+  int max_box = 0;
+  for (int64_t b = 0; b < nboxes; ++b) {
+    const int cnt = start[b + 1] - start[b];
+    if (cnt > 0) {
+      ebox_of_box[b] = static_cast<int32_t>(ebox.size());
+      ebox.push_back(static_cast<int32_t>(b));
+      max_box = std::max(max_box, cnt);
+      for (int j = start[b]; j < start[b + 1]; ++j) box_of_point[j] = static_cast<int32_t>(b);
+    }
+  }
+  const int64_t E = static_cast<int64_t>(ebox.size());
+  std::vector<int32_t> po, ps, item_ebox, ebox_item_beg(E + 1, 0);
+  std::vector<int64_t> pvoff, pzoff, item_pbeg, item_pend, item_yoff;
+  std::vector<std::vector<int64_t>> incoming(E);
+  int64_t voff = 0, zoff = 0, yoff = 0;
+  for (int64_t k = 0; k < E; ++k) {
+    const int64_t B = ebox[k];
+    const int bz = static_cast<int>(B % nbz), by = static_cast<int>((B / nbz) % nby),
+              bx = static_cast<int>(B / (static_cast<int64_t>(nbz) * nby));
+    const int nB = start[B + 1] - start[B];
+    const int64_t pfirst = static_cast<int64_t>(po.size());
+    for (int cx = std::max(0, bx - rc); cx <= std::min(nbx - 1, bx + rc); ++cx)
+      for (int cy = std::max(0, by - rc); cy <= std::min(nby - 1, by + rc); ++cy)
+        for (int cz = std::max(0, bz - rc); cz <= std::min(nbz - 1, bz + rc); ++cz) {
+          const int64_t Bp = (static_cast<int64_t>(cx) * nby + cy) * nbz + cz;
+          if (Bp < B || ebox_of_box[Bp] < 0) continue;
+          const int nBp = start[Bp + 1] - start[Bp];
+          po.push_back(static_cast<int32_t>(k));
+          ps.push_back(ebox_of_box[Bp]);
+          pvoff.push_back(voff);
+          voff += static_cast<int64_t>(nB) * nBp;
+          if (Bp != B) {
+            pzoff.push_back(zoff);
+            incoming[ebox_of_box[Bp]].push_back(zoff);
+            zoff += nBp;
+          } else {
+            pzoff.push_back(-1);
+          }
+        }
+    const int64_t plast = static_cast<int64_t>(po.size());
+    ebox_item_beg[k] = static_cast<int32_t>(item_ebox.size());
+    for (int64_t a0 = pfirst; a0 < plast; a0 += kPairsPerItem) {
+      item_ebox.push_back(static_cast<int32_t>(k));
+      item_pbeg.push_back(a0);
+      item_pend.push_back(std::min(plast, a0 + kPairsPerItem));
+      item_yoff.push_back(yoff);
+      yoff += nB;
+    }
+  }
+  ebox_item_beg[E] = static_cast<int32_t>(item_ebox.size());
+  std::vector<int64_t> in_beg(E + 1, 0), in_zoff;
+  for (int64_t k = 0; k < E; ++k) {
+    in_beg[k] = static_cast<int64_t>(in_zoff.size());
+    in_zoff.insert(in_zoff.end(), incoming[k].begin(), incoming[k].end());
+  }
+  in_beg[E] = static_cast<int64_t>(in_zoff.size());
+  SymDev& d = p->symd;
+  d.npairs = static_cast<int64_t>(po.size());
+  d.nitems = static_cast<int64_t>(item_ebox.size());
+  d.nebox = E;
+  d.yslots = yoff;
+  d.zslots = zoff;
+  d.max_box = max_box;
+  CHK(upload(p, &d.ebox, ebox));
+  CHK(upload(p, &d.ebox_of_box, ebox_of_box));
+  CHK(upload(p, &d.box_of_point, box_of_point));
+  CHK(upload(p, &d.pair_ebox_o, po));
+  CHK(upload(p, &d.pair_ebox_s, ps));
+  CHK(upload(p, &d.pair_voff, pvoff));
+  CHK(upload(p, &d.pair_zoff, pzoff));
+  CHK(upload(p, &d.item_ebox, item_ebox));
+  CHK(upload(p, &d.item_pbeg, item_pbeg));
+  CHK(upload(p, &d.item_pend, item_pend));
+  CHK(upload(p, &d.item_yoff, item_yoff));
+  CHK(upload(p, &d.ebox_item_beg, ebox_item_beg));
+  CHK(upload(p, &d.in_beg, in_beg));
+  CHK(upload(p, &d.in_zoff, in_zoff));
+  p->sym_nvals = voff;
+  unsigned char* v = nullptr;
+  CHK(dalloc(p, &v, static_cast<size_t>(voff) * (p->complex_kernel ? 16 : 8)));
+  p->sym_vals = v;
+  SymArgs sa = sym_args(p);
+  sa.R = ca.R;
+  sa.W = ca.W;
+  CHK(launch_sym_fill(p->ng.q, p->complex_kernel, sa, p->near_w, pos3_dev, g0tab, p->sym_vals, st));
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipGetLastError());
+  if (std::getenv("FFTPIM_LOG"))
+    std::fprintf(stderr, "fftpim plan: symmetric blocks: %lld boxes, %lld pairs, %lld values, max box %d\n",
+                 static_cast<long long>(E), static_cast<long long>(d.npairs), static_cast<long long>(voff), max_box);
+  return FFTPIM_OK;
+}
+
+int build_correction(fftpim_plan_s* p, const std::vector<int32_t>& start, const double* pos3_dev,
                      hipStream_t st) {
   const int q = p->ng.q, rc = p->prm.corr_radius, id = p->prm.n_images;
   const int dims = p->lat.dims;
@@ -480,6 +622,7 @@ int build_correction(fftpim_plan_s* p, const std::vector<int32_t>& s_host, const
   ca.N = p->N;
   ca.k0 = p->lat.k0;
   ca.nimg_axis = A;
+  ca.images_only = p->sym ? 1 : 0;
   // image phases indexed by (gx, gy, gz), image g - id on periodic axes
   std::vector<double> ph(2 * A * A * A, 0.0);
   for (int gx = 0; gx < A; ++gx)
@@ -537,6 +680,7 @@ int build_correction(fftpim_plan_s* p, const std::vector<int32_t>& s_host, const
       }
   cplx<double>* dg0 = nullptr;
   CHK(upload(p, &dg0, g0t));
+  if (p->sym) CHK(build_sym(p, start, pos3_dev, dg0, ca, st));
   // count, scan, fill
   int64_t* dcount = nullptr;
   CHK(dalloc(p, &dcount, p->N));
@@ -573,7 +717,6 @@ int build_correction(fftpim_plan_s* p, const std::vector<int32_t>& s_host, const
     dfree(p, doff[c]);
     dfree(p, dent[c]);
   }
-  (void)s_host;
   return FFTPIM_OK;
 }
 
@@ -698,7 +841,29 @@ int build_plan(fftpim_plan_s* p, int64_t N, const double* src_dev, hipStream_t s
   else
     CHK(build_tables<double>(p, st));
   plan_log("near and far tables", t0);
-  CHK(build_correction(p, s_sorted, dpos, st));
+  // correction layout: symmetric box-pair blocks when boxes hold several
+  // points each and a box's amplitudes fit the kernel's LDS staging
+  {
+    int64_t nonempty = 0;
+    int max_box = 0;
+    for (int64_t b = 0; b < nboxes; ++b) {
+      const int cnt = start[b + 1] - start[b];
+      nonempty += cnt > 0;
+      max_box = std::max(max_box, cnt);
+    }
+    const int Pm = planes_for(p, pm.nrhs_max);
+    // LDS: the fill stages a (2q+1)^3 complex table slice, the apply stages a
+    // box's amplitudes and row sums
+    const bool fits = static_cast<int64_t>(max_box) * Pm <= 2048 && g.q <= 7;
+    const bool dense = static_cast<double>(N) >= 3.0 * static_cast<double>(std::max<int64_t>(nonempty, 1));
+    if (pm.corr_layout == FFTPIM_CORR_SYM) {
+      if (!fits) return FFTPIM_ERR_INVALID_ARG;
+      p->sym = true;
+    } else if (pm.corr_layout == FFTPIM_CORR_AUTO) {
+      p->sym = fits && dense;
+    }
+  }
+  CHK(build_correction(p, start, dpos, st));
   plan_log("correction operator", t0);
   dfree(p, dpos);
 
@@ -739,6 +904,12 @@ int build_plan(fftpim_plan_s* p, int64_t N, const double* src_dev, hipStream_t s
   const int64_t max_splits = std::min<int64_t>(64, std::max<int64_t>(1, (Ngf + 255) / 256));
   CHK(dalloc(p, &b, static_cast<size_t>(max_splits) * Ngf * P * es));
   p->far_part = b;
+  if (p->sym) {
+    CHK(dalloc(p, &b, static_cast<size_t>(std::max<int64_t>(p->symd.yslots, 1)) * P * 16));
+    p->sym_ypart = b;
+    CHK(dalloc(p, &b, static_cast<size_t>(std::max<int64_t>(p->symd.zslots, 1)) * P * 16));
+    p->sym_zpart = b;
+  }
   CHK(dalloc(p, &p->sums, static_cast<size_t>(6) * P));
   CHK(dalloc(p, &p->status_dev, 1));
   HIPCHK(hipMemsetAsync(p->status_dev, 0, sizeof(int), st));
@@ -766,6 +937,7 @@ int fftpim_default_params(const fftpim_problem_t* problem, fftpim_params_t* para
   p.self_mode = FFTPIM_SELF_IMAGES;
   p.order_io = FFTPIM_ORDER_USER;
   p.nrhs_max = 1;
+  p.corr_layout = FFTPIM_CORR_AUTO;
   *params = p;
   return FFTPIM_OK;
 }
@@ -852,7 +1024,7 @@ int fftpim_plan_info(fftpim_plan_t plan, fftpim_info_t* info) {
     r.far_cells[c] = plan->fg.nint[c];
     r.far_h[c] = plan->fg.h[c];
   }
-  r.corr_nnz = plan->nnz;
+  r.corr_nnz = plan->nnz + plan->sym_nvals;
   r.device_bytes = plan->device_bytes;
   r.nplanes_max = plan->nplanes_max;
   r.plan_seconds = plan->plan_seconds;

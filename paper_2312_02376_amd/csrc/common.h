@@ -120,6 +120,20 @@ __host__ __device__ inline double basis_num(int k, double u) {
   return num;
 }
 
+// Device pointers and sizes of the symmetric in-cell correction structure
+// (mirrors the kernel-side SymArgs).
+struct SymDev {
+  int64_t npairs = 0, nitems = 0, nebox = 0, yslots = 0, zslots = 0;
+  int max_box = 0;
+  int32_t *ebox = nullptr, *ebox_of_box = nullptr, *box_of_point = nullptr;
+  int32_t *pair_ebox_o = nullptr, *pair_ebox_s = nullptr;
+  int64_t *pair_voff = nullptr, *pair_zoff = nullptr;
+  int32_t* item_ebox = nullptr;
+  int64_t *item_pbeg = nullptr, *item_pend = nullptr, *item_yoff = nullptr;
+  int32_t* ebox_item_beg = nullptr;
+  int64_t *in_beg = nullptr, *in_zoff = nullptr;
+};
+
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
@@ -165,6 +179,15 @@ struct fftpim_plan_s {
   void* twiddle[3] = {nullptr, nullptr, nullptr};  // per axis, M/2 complex R
   void* far_table = nullptr;      // [(2nf-1)^3] complex R
   double self_value[2] = {0.0, 0.0};
+
+  // in-cell correction as symmetric box-pair blocks (when sym is set), the
+  // CSR below then holds only the close-image part
+  bool sym = false;
+  fftpim::SymDev symd;
+  void* sym_vals = nullptr;
+  int64_t sym_nvals = 0;
+  void* sym_ypart = nullptr;      // [item slots][planes] complex double
+  void* sym_zpart = nullptr;      // [pair slots][planes] complex double
 
   // correction (FP64 values)
   int64_t* rowptr = nullptr;

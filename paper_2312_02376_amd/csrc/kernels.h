@@ -54,6 +54,33 @@ struct CorrArgs {
   // marking image g - id (g = 0 only on non-periodic axes) as close
   const int32_t* loff[3];
   const int32_t* lent[3];
+  int images_only;     // 1: drop the image-0 term (it is stored as symmetric blocks)
+};
+
+// In-cell correction stored once per unordered pair of non-empty near-grid
+// boxes ("ebox" = index into the list of non-empty boxes).
+struct SymArgs {
+  int64_t N;
+  int nb[3];
+  int R, W;             // g0 table geometry (as in CorrArgs)
+  double k0;
+  int max_box;          // largest point count of a box
+  int64_t npairs, nitems;
+  const int32_t* box_start;      // [nb^3 + 1]
+  const int32_t* ebox;           // [E] box id of each non-empty box
+  const int32_t* ebox_of_box;    // [nb^3] ebox index or -1
+  const int32_t* box_of_point;   // [N]
+  const int32_t* pair_ebox_o;    // [npairs] observer-side box (B)
+  const int32_t* pair_ebox_s;    // [npairs] source-side box (B' >= B)
+  const int64_t* pair_voff;      // [npairs] first value of the block
+  const int64_t* pair_zoff;      // [npairs] first point slot of the column partials
+  const int32_t* item_ebox;      // [nitems]
+  const int64_t* item_pbeg;      // [nitems] pair range of the item
+  const int64_t* item_pend;
+  const int64_t* item_yoff;      // [nitems] first point slot of the row partials
+  const int32_t* ebox_item_beg;  // [E + 1] items of each box
+  const int64_t* in_beg;         // [E + 1] column partials addressed to each box
+  const int64_t* in_zoff;        // [..] their first point slots
 };
 
 struct FarArgs {
@@ -108,7 +135,12 @@ int launch_corr_fill(int q, bool cplx_vals, bool adj, const CorrArgs& a, const i
                      int32_t* col, void* val, void* val_adj, hipStream_t st);
 template <typename R>
 void launch_corr_spmv(bool cplx_vals, const int64_t* rowptr, const int32_t* col, const void* val, int64_t N,
-                      const void* qint, int P, void* uint, hipStream_t st);
+                      const void* qint, int P, void* uint, bool accumulate, hipStream_t st);
+int launch_sym_fill(int q, bool cplx_vals, const SymArgs& a, const double* w3, const double* pos3,
+                    const void* g0tab, void* vals, hipStream_t st);
+template <typename R>
+void launch_sym_apply(bool cplx_vals, const SymArgs& a, const void* vals, const void* x, int P, bool conj_io,
+                      void* ypart, void* zpart, void* u, bool accumulate, hipStream_t st);
 
 // far zone
 template <typename R>

@@ -36,12 +36,15 @@ __global__ void k_corr_count(CorrArgs a, const int32_t* __restrict__ s3, const i
   axis_range(loff1, s3[a.N + m], y0, y1);
   axis_range(loff2, s3[2 * a.N + m], z0, z1);
   int64_t cnt = 0;
+  const int z0b = a.per[0] ? 1 << a.id : 1, z1b = a.per[1] ? 1 << a.id : 1, z2b = a.per[2] ? 1 << a.id : 1;
   for (int ix = x0; ix < x1; ++ix) {
     int bx = lent0[ix] & 0xffff;
     for (int iy = y0; iy < y1; ++iy) {
       int by = lent1[iy] & 0xffff;
       for (int iz = z0; iz < z1; ++iz) {
         int bz = lent2[iz] & 0xffff;
+        if (a.images_only && (lent0[ix] >> 16) == z0b && (lent1[iy] >> 16) == z1b && (lent2[iz] >> 16) == z2b)
+          continue;  // only the image-0 term is close: it lives in the symmetric blocks
         int64_t b = (static_cast<int64_t>(bx) * a.nb[1] + by) * a.nb[2] + bz;
         cnt += box_start[b + 1] - box_start[b];
       }
@@ -75,12 +78,14 @@ __global__ void __launch_bounds__(64) k_corr_fill(
   double* valr = static_cast<double*>(val_v);
   cplx<double>* valc = static_cast<cplx<double>*>(val_v);
   cplx<double>* vadj = static_cast<cplx<double>*>(vadj_v);
+  const int z0b = a.per[0] ? 1 << a.id : 1, z1b = a.per[1] ? 1 << a.id : 1, z2b = a.per[2] ? 1 << a.id : 1;
   for (int ix = lo[0]; ix < hi[0]; ++ix) {
     const int bx = lent0[ix] & 0xffff, mx = lent0[ix] >> 16;
     for (int iy = lo[1]; iy < hi[1]; ++iy) {
       const int by = lent1[iy] & 0xffff, my = lent1[iy] >> 16;
       for (int iz = lo[2]; iz < hi[2]; ++iz) {
         const int bz = lent2[iz] & 0xffff, mz = lent2[iz] >> 16;
+        if (a.images_only && mx == z0b && my == z1b && mz == z2b) continue;
         const int64_t b = (static_cast<int64_t>(bx) * a.nb[1] + by) * a.nb[2] + bz;
         const int n0 = box_start[b], n1 = box_start[b + 1];
         for (int n = n0; n < n1; ++n) {
@@ -104,6 +109,7 @@ __global__ void __launch_bounds__(64) k_corr_fill(
               for (int gz = 0; gz < A; ++gz) {
                 if (!((mz >> gz) & 1)) continue;
                 const int imz = gz - a.id * a.per[2];
+                if (a.images_only && imx == 0 && imy == 0 && imz == 0) continue;
                 const int D[3] = {S[0] - bx - imx * a.nint[0], S[1] - by - imy * a.nint[1],
                                   S[2] - bz - imz * a.nint[2]};
                 // exact part
@@ -196,7 +202,7 @@ __global__ void __launch_bounds__(256) k_corr_spmv(const int64_t* __restrict__ r
                                                    const int32_t* __restrict__ col,
                                                    const void* __restrict__ val_v, int64_t N,
                                                    const cplx<R>* __restrict__ qint, int P,
-                                                   cplx<R>* __restrict__ uint) {
+                                                   cplx<R>* __restrict__ uint, int accumulate) {
   const int lane = threadIdx.x & 63;
   const int64_t row = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (row >= N) return;
@@ -253,7 +259,13 @@ __global__ void __launch_bounds__(256) k_corr_spmv(const int64_t* __restrict__ r
 #pragma unroll
     for (int pp = 0; pp < PB; ++pp) {
       if (p0 + pp < P) {
-        uint[row * P + p0 + pp] = cmake<R>(static_cast<R>(ar[pp]), static_cast<R>(ai[pp]));
+        cplx<R> o = cmake<R>(static_cast<R>(ar[pp]), static_cast<R>(ai[pp]));
+        if (accumulate) {
+          const cplx<R> prev = uint[row * P + p0 + pp];
+          o = cmake<R>(static_cast<R>(static_cast<double>(prev.x) + ar[pp]),
+                       static_cast<R>(static_cast<double>(prev.y) + ai[pp]));
+        }
+        uint[row * P + p0 + pp] = o;
       }
     }
   }
@@ -268,7 +280,7 @@ __global__ void __launch_bounds__(256) k_corr_spmm(const int64_t* __restrict__ r
                                                    const int32_t* __restrict__ col,
                                                    const void* __restrict__ val_v, int64_t N,
                                                    const cplx<R>* __restrict__ qint, int P,
-                                                   cplx<R>* __restrict__ uint) {
+                                                   cplx<R>* __restrict__ uint, int accumulate) {
   constexpr int E = 64 / LP;
   const int lane = threadIdx.x & 63;
   const int e = lane / LP, pl = lane % LP;
@@ -300,7 +312,12 @@ __global__ void __launch_bounds__(256) k_corr_spmm(const int64_t* __restrict__ r
       ai += __shfl_xor(ai, off, 64);
     }
     if (e == 0 && p < P) {
-      uint[row * P + p] = cmake<R>(static_cast<R>(ar), static_cast<R>(ai));
+      cplx<R> o = cmake<R>(static_cast<R>(ar), static_cast<R>(ai));
+      if (accumulate) {
+        const cplx<R> prev = uint[row * P + p];
+        o = cmake<R>(static_cast<R>(static_cast<double>(prev.x) + ar), static_cast<R>(static_cast<double>(prev.y) + ai));
+      }
+      uint[row * P + p] = o;
     }
   }
 }
@@ -353,7 +370,8 @@ int launch_corr_fill(int q, bool cplx_vals, bool adj, const CorrArgs& a, const i
 
 template <typename R>
 void launch_corr_spmv(bool cplx_vals, const int64_t* rowptr, const int32_t* col, const void* val, int64_t N,
-                      const void* qint, int P, void* uint, hipStream_t st) {
+                      const void* qint, int P, void* uint, bool accumulate, hipStream_t st) {
+  const int acc = accumulate ? 1 : 0;
   const cplx<R>* q = static_cast<const cplx<R>*>(qint);
   cplx<R>* u = static_cast<cplx<R>*>(uint);
   unsigned nb = static_cast<unsigned>((N + 3) / 4);
@@ -361,9 +379,9 @@ void launch_corr_spmv(bool cplx_vals, const int64_t* rowptr, const int32_t* col,
 #define FFTPIM_SPMM(LPV)                                                                                   \
   do {                                                                                                     \
     if (cplx_vals)                                                                                         \
-      hipLaunchKernelGGL((k_corr_spmm<R, true, LPV>), dim3(nb), dim3(256), 0, st, rowptr, col, val, N, q, P, u); \
+      hipLaunchKernelGGL((k_corr_spmm<R, true, LPV>), dim3(nb), dim3(256), 0, st, rowptr, col, val, N, q, P, u, acc); \
     else                                                                                                   \
-      hipLaunchKernelGGL((k_corr_spmm<R, false, LPV>), dim3(nb), dim3(256), 0, st, rowptr, col, val, N, q, P, u); \
+      hipLaunchKernelGGL((k_corr_spmm<R, false, LPV>), dim3(nb), dim3(256), 0, st, rowptr, col, val, N, q, P, u, acc); \
   } while (0)
     if (P <= 8)
       FFTPIM_SPMM(8);
@@ -380,9 +398,9 @@ void launch_corr_spmv(bool cplx_vals, const int64_t* rowptr, const int32_t* col,
   do {                                                                                                     \
     dim3 gr(nb, (P + PBV - 1) / PBV);                                                                      \
     if (cplx_vals)                                                                                         \
-      hipLaunchKernelGGL((k_corr_spmv<R, true, PBV>), gr, dim3(256), 0, st, rowptr, col, val, N, q, P, u); \
+      hipLaunchKernelGGL((k_corr_spmv<R, true, PBV>), gr, dim3(256), 0, st, rowptr, col, val, N, q, P, u, acc); \
     else                                                                                                   \
-      hipLaunchKernelGGL((k_corr_spmv<R, false, PBV>), gr, dim3(256), 0, st, rowptr, col, val, N, q, P, u); \
+      hipLaunchKernelGGL((k_corr_spmv<R, false, PBV>), gr, dim3(256), 0, st, rowptr, col, val, N, q, P, u, acc); \
   } while (0)
   if (P >= 8)
     FFTPIM_SPMV(8);
@@ -396,8 +414,8 @@ void launch_corr_spmv(bool cplx_vals, const int64_t* rowptr, const int32_t* col,
 }
 
 template void launch_corr_spmv<double>(bool, const int64_t*, const int32_t*, const void*, int64_t, const void*,
-                                       int, void*, hipStream_t);
+                                       int, void*, bool, hipStream_t);
 template void launch_corr_spmv<float>(bool, const int64_t*, const int32_t*, const void*, int64_t, const void*,
-                                      int, void*, hipStream_t);
+                                      int, void*, bool, hipStream_t);
 
 }  // namespace fftpim

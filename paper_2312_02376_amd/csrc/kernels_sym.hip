@@ -1,0 +1,354 @@
+// Near-zone correction (Sec. 3.3 Step 4, Eq. (er)) for in-cell pairs, stored
+// once per unordered pair of near-grid boxes.
+//
+// For image 0 the entry X_0(m, n) = G0(r_m - r_n) - G_grid,0(m, n) is symmetric
+// in (m, n) (both terms are even in r_m - r_n and the double sum of Eq. (er_2)
+// is symmetric), so the block of box pair (B, B') with B <= B' serves both
+// u_B += X x_B' and u_B' += X^T x_B.  The conjugate transpose of this part is
+// conj(X conj(v)), so the same values serve the adjoint.  Close images (i != 0)
+// are not symmetric under a phase shift and stay in a separate CSR.
+//
+// Apply: one wavefront per work item (a box and a run of its upper pairs)
+// reads every block once, lanes over the block's columns: the column sums
+// X^T x_B (for the partner box) accumulate in registers, the row sums X x_B'
+// come from a register reduce-scatter across the wavefront.  Row sums go to
+// per-item partials, column sums to per-pair partials; a second kernel adds,
+// for every point, its box's item partials and the column partials addressed
+// to its box, in a fixed order (no atomics).
+#include "kernels.h"
+
+namespace fftpim {
+
+// ---------------------------------------------------------------------------
+// plan time: block values
+// ---------------------------------------------------------------------------
+
+template <int Q, bool CPLX>
+__global__ void __launch_bounds__(64) k_sym_fill(SymArgs a, const double* __restrict__ w3,
+                                                 const double* __restrict__ pos3, const cplx<double>* __restrict__ g0tab,
+                                                 void* __restrict__ vals) {
+  constexpr int D = 2 * Q + 1;
+  __shared__ double gr[D * D * D], gi[D * D * D];
+  const int64_t pr = blockIdx.x;
+  const int kb = a.pair_ebox_o[pr], kbp = a.pair_ebox_s[pr];
+  const int B = a.ebox[kb], Bp = a.ebox[kbp];
+  const int bz = B % a.nb[2], by = (B / a.nb[2]) % a.nb[1], bx = B / (a.nb[2] * a.nb[1]);
+  const int cz = Bp % a.nb[2], cy = (Bp / a.nb[2]) % a.nb[1], cx = Bp / (a.nb[2] * a.nb[1]);
+  const int Dl[3] = {bx - cx, by - cy, bz - cz};
+  // the block's slice of the G0 node table: offsets Delta + d, d in [-q, q]^3
+  for (int t = threadIdx.x; t < D * D * D; t += blockDim.x) {
+    const int dz = t % D - Q, dy = (t / D) % D - Q, dx = t / (D * D) - Q;
+    const int64_t k = (static_cast<int64_t>(Dl[0] + dx + a.R) * a.W + (Dl[1] + dy + a.R)) * a.W + (Dl[2] + dz + a.R);
+    gr[t] = g0tab[k].x;
+    gi[t] = g0tab[k].y;
+  }
+  __syncthreads();
+  const int m0 = a.box_start[B], nB = a.box_start[B + 1] - m0;
+  const int n0 = a.box_start[Bp], nBp = a.box_start[Bp + 1] - n0;
+  const int64_t voff = a.pair_voff[pr];
+  const int64_t N = a.N;
+  for (int e = threadIdx.x; e < nB * nBp; e += blockDim.x) {
+    const int r = e / nBp, c = e - r * nBp;
+    const int m = m0 + r, n = n0 + c;
+    double C[3][D];
+    for (int ax = 0; ax < 3; ++ax) {
+      double wm[Q + 1], wn[Q + 1];
+      for (int k = 0; k <= Q; ++k) {
+        wm[k] = w3[(ax * (Q + 1) + k) * N + m];
+        wn[k] = w3[(ax * (Q + 1) + k) * N + n];
+      }
+      for (int d = -Q; d <= Q; ++d) {
+        double s = 0.0;
+        for (int aa = max(0, d); aa <= min(Q, Q + d); ++aa) s += wm[aa] * wn[aa - d];
+        C[ax][d + Q] = s;
+      }
+    }
+    double sr = 0.0, si = 0.0;
+    for (int dx = 0; dx < D; ++dx)
+      for (int dy = 0; dy < D; ++dy) {
+        const double cxy = C[0][dx] * C[1][dy];
+        const int t0 = (dx * D + dy) * D;
+        double zr = 0.0, zi = 0.0;
+        for (int dz = 0; dz < D; ++dz) {
+          zr += C[2][dz] * gr[t0 + dz];
+          if (CPLX) zi += C[2][dz] * gi[t0 + dz];
+        }
+        sr += cxy * zr;
+        si += cxy * zi;
+      }
+    double er = 0.0, ei = 0.0;
+    if (m != n) {
+      const double dx = pos3[m] - pos3[n], dy = pos3[N + m] - pos3[N + n], dz = pos3[2 * N + m] - pos3[2 * N + n];
+      const double rr = sqrt(dx * dx + dy * dy + dz * dz);
+      const double inv = 1.0 / (4.0 * M_PI * rr);
+      if (CPLX) {
+        double s, c2;
+        sincos(a.k0 * rr, &s, &c2);
+        er = c2 * inv;
+        ei = -s * inv;
+      } else {
+        er = inv;
+      }
+    }
+    if (CPLX)
+      static_cast<cplx<double>*>(vals)[voff + e] = cmake<double>(er - sr, ei - si);
+    else
+      static_cast<double*>(vals)[voff + e] = er - sr;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// apply
+// ---------------------------------------------------------------------------
+
+template <typename R>
+__device__ inline void load_planes(const cplx<R>* __restrict__ x, int64_t pt, int P, int p, bool conj_in, double& re,
+                                   double& im) {
+  const cplx<R> v = x[pt * P + p];
+  re = static_cast<double>(v.x);
+  im = conj_in ? -static_cast<double>(v.y) : static_cast<double>(v.y);
+}
+
+// Reduce-scatter of 8 values per lane over the 64 lanes of a wavefront:
+// afterwards lanes with bits 5,4,3 = (b5, b4, b3) hold the total of value
+// 4 b5 + 2 b4 + b3 (all lanes of an 8-lane group hold the same total).
+__device__ inline double wave_reduce_scatter8(double v[8], int lane) {
+  const bool u32 = (lane & 32) != 0, u16 = (lane & 16) != 0, u8 = (lane & 8) != 0;
+  double a[4], b[2];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double send = u32 ? v[k] : v[k + 4];
+    const double keep = u32 ? v[k + 4] : v[k];
+    a[k] = keep + __shfl_xor(send, 32, 64);
+  }
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const double send = u16 ? a[k] : a[k + 2];
+    const double keep = u16 ? a[k + 2] : a[k];
+    b[k] = keep + __shfl_xor(send, 16, 64);
+  }
+  double s = (u8 ? b[1] : b[0]) + __shfl_xor(u8 ? b[0] : b[1], 8, 64);
+  s += __shfl_xor(s, 4, 64);
+  s += __shfl_xor(s, 2, 64);
+  s += __shfl_xor(s, 1, 64);
+  return s;
+}
+
+// One wavefront per item.  All pairs of an item share the observer box B, so
+// consecutive pairs are laid side by side across the 64 lanes (a lane owns
+// one column of one pair's block); eight rows of values are loaded back to
+// back, each lane accumulates its column sum (X^T x_B, for the partner box)
+// in registers, and the row sums (X x_B' over all pairs of the group) come
+// from a register reduce-scatter.  A pair with more than 64 columns is
+// processed alone in column chunks.  LDS holds x_B and the row accumulators.
+template <typename R, bool CPLX>
+__device__ inline void sym_rows(const SymArgs& a, const double* __restrict__ vr, const cplx<double>* __restrict__ vc,
+                                const cplx<double>* xb, cplx<double>* yacc, int nB, int P, int p, int lane, bool act,
+                                int64_t voff, int nBp, int c, double xsr, double xsi, double& zr, double& zi) {
+  const int krow = ((lane >> 5) & 1) * 4 + ((lane >> 4) & 1) * 2 + ((lane >> 3) & 1);
+  for (int r0 = 0; r0 < nB; r0 += 8) {
+    double wr[8], wi[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      wr[k] = 0.0;
+      wi[k] = 0.0;
+      if (act && r0 + k < nB) {
+        const int64_t idx = voff + static_cast<int64_t>(r0 + k) * nBp + c;
+        if (CPLX) {
+          const cplx<double> w = vc[idx];
+          wr[k] = w.x;
+          wi[k] = w.y;
+        } else {
+          wr[k] = vr[idx];
+        }
+      }
+    }
+    double pr_[8], pi_[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (r0 + k < nB) {
+        const cplx<double> xv = xb[(r0 + k) * P + p];
+        zr += wr[k] * xv.x - wi[k] * xv.y;
+        zi += wr[k] * xv.y + wi[k] * xv.x;
+      }
+      pr_[k] = wr[k] * xsr - wi[k] * xsi;
+      pi_[k] = wr[k] * xsi + wi[k] * xsr;
+    }
+    const double sr = wave_reduce_scatter8(pr_, lane);
+    const double si = wave_reduce_scatter8(pi_, lane);
+    if ((lane & 7) == 0 && r0 + krow < nB) {
+      cplx<double> acc = yacc[(r0 + krow) * P + p];
+      acc.x += sr;
+      acc.y += si;
+      yacc[(r0 + krow) * P + p] = acc;
+    }
+  }
+}
+
+template <typename R, bool CPLX>
+__global__ void __launch_bounds__(64) k_sym_apply(SymArgs a, const void* __restrict__ vals,
+                                                  const cplx<R>* __restrict__ x, int P, int conj_in,
+                                                  cplx<double>* __restrict__ ypart, cplx<double>* __restrict__ zpart) {
+  extern __shared__ unsigned char lds_raw[];
+  const int item = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int kb = a.item_ebox[item];
+  const int B = a.ebox[kb];
+  const int m0 = a.box_start[B], nB = a.box_start[B + 1] - m0;
+  cplx<double>* xb = reinterpret_cast<cplx<double>*>(lds_raw);          // [nB][P]
+  cplx<double>* yacc = xb + static_cast<int64_t>(a.max_box) * P;         // [nB][P]
+  for (int t = lane; t < nB * P; t += 64) {
+    double re, im;
+    load_planes<R>(x, m0 + t / P, P, t % P, conj_in, re, im);
+    xb[t] = cmake<double>(re, im);
+    yacc[t] = cmake<double>(0.0, 0.0);
+  }
+  __syncthreads();
+  const double* vr = static_cast<const double*>(vals);
+  const cplx<double>* vc = static_cast<const cplx<double>*>(vals);
+  const int64_t pend = a.item_pend[item];
+  for (int64_t pr = a.item_pbeg[item]; pr < pend;) {
+    // group consecutive pairs while their columns fit the 64 lanes
+    int cum = 0;
+    int64_t pg = pr, mine = -1;
+    int my_c = 0;
+    while (pg < pend) {
+      const int Bj = a.ebox[a.pair_ebox_s[pg]];
+      const int nj = a.box_start[Bj + 1] - a.box_start[Bj];
+      if (cum > 0 && cum + nj > 64) break;
+      if (lane >= cum && lane < cum + nj) {
+        mine = pg;
+        my_c = lane - cum;
+      }
+      cum += nj;
+      ++pg;
+      if (cum >= 64) break;
+    }
+    if (cum <= 64) {
+      const bool act = mine >= 0;
+      int n0 = 0, nBp = 1;
+      int64_t voff = 0;
+      bool diag = true;
+      if (act) {
+        const int kbp = a.pair_ebox_s[mine];
+        const int Bp = a.ebox[kbp];
+        n0 = a.box_start[Bp];
+        nBp = a.box_start[Bp + 1] - n0;
+        voff = a.pair_voff[mine];
+        diag = kbp == kb;
+      }
+      for (int p = 0; p < P; ++p) {
+        double xsr = 0.0, xsi = 0.0, zr = 0.0, zi = 0.0;
+        if (act) load_planes<R>(x, n0 + my_c, P, p, conj_in, xsr, xsi);
+        sym_rows<R, CPLX>(a, vr, vc, xb, yacc, nB, P, p, lane, act, voff, nBp, my_c, xsr, xsi, zr, zi);
+        if (act && !diag) zpart[(a.pair_zoff[mine] + my_c) * P + p] = cmake<double>(zr, zi);
+      }
+    } else {
+      // one pair wider than the wavefront
+      const int kbp = a.pair_ebox_s[pr];
+      const int Bp = a.ebox[kbp];
+      const int n0 = a.box_start[Bp], nBp = a.box_start[Bp + 1] - n0;
+      const int64_t voff = a.pair_voff[pr];
+      const bool diag = kbp == kb;
+      for (int p = 0; p < P; ++p) {
+        for (int c0 = 0; c0 < nBp; c0 += 64) {
+          const int c = c0 + lane;
+          const bool act = c < nBp;
+          double xsr = 0.0, xsi = 0.0, zr = 0.0, zi = 0.0;
+          if (act) load_planes<R>(x, n0 + c, P, p, conj_in, xsr, xsi);
+          sym_rows<R, CPLX>(a, vr, vc, xb, yacc, nB, P, p, lane, act, voff, nBp, c, xsr, xsi, zr, zi);
+          if (act && !diag) zpart[(a.pair_zoff[pr] + c) * P + p] = cmake<double>(zr, zi);
+        }
+      }
+    }
+    pr = pg;
+  }
+  __syncthreads();
+  const int64_t yoff = a.item_yoff[item];
+  for (int t = lane; t < nB * P; t += 64) ypart[yoff * P + t] = yacc[t];
+}
+
+// Per point: its box's item partials (in item order) plus the column partials
+// sent to its box (in pair order); result written (or added) to u.
+template <typename R>
+__global__ void k_sym_gather(SymArgs a, const cplx<double>* __restrict__ ypart, const cplx<double>* __restrict__ zpart,
+                             int P, int conj_out, cplx<R>* __restrict__ u, int accumulate) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= a.N * P) return;
+  const int64_t m = t / P;
+  const int p = static_cast<int>(t % P);
+  const int B = a.box_of_point[m];
+  const int kb = a.ebox_of_box[B];
+  const int r = static_cast<int>(m - a.box_start[B]);
+  double sr = 0.0, si = 0.0;
+  for (int it = a.ebox_item_beg[kb]; it < a.ebox_item_beg[kb + 1]; ++it) {
+    const cplx<double> v = ypart[(a.item_yoff[it] + r) * P + p];
+    sr += v.x;
+    si += v.y;
+  }
+  for (int64_t k = a.in_beg[kb]; k < a.in_beg[kb + 1]; ++k) {
+    const cplx<double> v = zpart[(a.in_zoff[k] + r) * P + p];
+    sr += v.x;
+    si += v.y;
+  }
+  if (conj_out) si = -si;
+  cplx<R> out = cmake<R>(static_cast<R>(sr), static_cast<R>(si));
+  if (accumulate) out = cadd(u[t], out);
+  u[t] = out;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+int launch_sym_fill(int q, bool cplx_vals, const SymArgs& a, const double* w3, const double* pos3,
+                    const void* g0tab, void* vals, hipStream_t st) {
+  const cplx<double>* g = static_cast<const cplx<double>*>(g0tab);
+#define FFTPIM_SYMFILL(QV)                                                                                  \
+  do {                                                                                                      \
+    if (cplx_vals)                                                                                          \
+      hipLaunchKernelGGL((k_sym_fill<QV, true>), dim3(static_cast<unsigned>(a.npairs)), dim3(64), 0, st, a, w3, \
+                         pos3, g, vals);                                                                    \
+    else                                                                                                    \
+      hipLaunchKernelGGL((k_sym_fill<QV, false>), dim3(static_cast<unsigned>(a.npairs)), dim3(64), 0, st, a, \
+                         w3, pos3, g, vals);                                                                \
+  } while (0)
+  switch (q) {
+    case 1: FFTPIM_SYMFILL(1); break;
+    case 2: FFTPIM_SYMFILL(2); break;
+    case 3: FFTPIM_SYMFILL(3); break;
+    case 4: FFTPIM_SYMFILL(4); break;
+    case 5: FFTPIM_SYMFILL(5); break;
+    case 6: FFTPIM_SYMFILL(6); break;
+    case 7: FFTPIM_SYMFILL(7); break;
+    case 8: FFTPIM_SYMFILL(8); break;
+    default: return FFTPIM_ERR_UNSUPPORTED;
+  }
+#undef FFTPIM_SYMFILL
+  return FFTPIM_OK;
+}
+
+template <typename R>
+void launch_sym_apply(bool cplx_vals, const SymArgs& a, const void* vals, const void* x, int P, bool conj_io,
+                      void* ypart, void* zpart, void* u, bool accumulate, hipStream_t st) {
+  const size_t lds = static_cast<size_t>(2) * a.max_box * P * sizeof(cplx<double>);
+  const cplx<R>* xx = static_cast<const cplx<R>*>(x);
+  cplx<double>* yp = static_cast<cplx<double>*>(ypart);
+  cplx<double>* zp = static_cast<cplx<double>*>(zpart);
+  if (cplx_vals)
+    hipLaunchKernelGGL((k_sym_apply<R, true>), dim3(static_cast<unsigned>(a.nitems)), dim3(64), lds, st, a, vals, xx,
+                       P, conj_io ? 1 : 0, yp, zp);
+  else
+    hipLaunchKernelGGL((k_sym_apply<R, false>), dim3(static_cast<unsigned>(a.nitems)), dim3(64), lds, st, a, vals,
+                       xx, P, conj_io ? 1 : 0, yp, zp);
+  const int64_t n = a.N * P;
+  hipLaunchKernelGGL((k_sym_gather<R>), dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st, a, yp, zp, P,
+                     conj_io ? 1 : 0, static_cast<cplx<R>*>(u), accumulate ? 1 : 0);
+}
+
+template void launch_sym_apply<double>(bool, const SymArgs&, const void*, const void*, int, bool, void*, void*, void*,
+                                       bool, hipStream_t);
+template void launch_sym_apply<float>(bool, const SymArgs&, const void*, const void*, int, bool, void*, void*, void*,
+                                      bool, hipStream_t);
+
+}  // namespace fftpim

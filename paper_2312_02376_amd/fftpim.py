@@ -50,7 +50,7 @@ class Params(ctypes.Structure):
     _fields_ = [("near_n", ctypes.c_int * 3), ("near_order", ctypes.c_int), ("corr_radius", ctypes.c_int),
                 ("far_n", ctypes.c_int * 3), ("far_order", ctypes.c_int), ("n_images", ctypes.c_int),
                 ("precision", ctypes.c_int), ("value_type", ctypes.c_int), ("self_mode", ctypes.c_int),
-                ("order_io", ctypes.c_int), ("nrhs_max", ctypes.c_int)]
+                ("order_io", ctypes.c_int), ("nrhs_max", ctypes.c_int), ("corr_layout", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -141,7 +141,8 @@ class Plan:
 
     def __init__(self, positions, periodic_dims, L, k0=0.0, kt=(0.0, 0.0, 0.0), near_n=(16, 16, 16),
                  near_order=4, corr_radius=6, far_n=(16, 16, 16), far_order=7, n_images=1, precision="f64",
-                 value_type="complex", order="user", nrhs_max=1, box=None, self_mode="images", stream=None):
+                 value_type="complex", order="user", nrhs_max=1, box=None, self_mode="images",
+                 corr_layout="auto", stream=None):
         import torch
         if not (isinstance(positions, torch.Tensor) and positions.is_cuda and positions.dtype == torch.float64):
             raise TypeError("positions must be a CUDA float64 tensor of shape (N, 3)")
@@ -161,6 +162,7 @@ class Plan:
         pm.self_mode = {"images": SELF_IMAGES, "exclude": SELF_EXCLUDE}[self_mode]
         pm.order_io = {"user": ORDER_USER, "plan": ORDER_PLAN}[order]
         pm.nrhs_max = int(nrhs_max)
+        pm.corr_layout = {"auto": 0, "csr": 1, "sym": 2}[corr_layout]
         self.params = pm
         self.precision = precision
         self.value_type = value_type

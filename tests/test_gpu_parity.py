@@ -53,7 +53,7 @@ def _points(kind, N, seed):
     raise ValueError(kind)
 
 
-def _setup(name, N=257, seed=31, precision="f64", nrhs=None):
+def _setup(name, N=257, seed=31, precision="f64", nrhs=None, corr_layout="auto"):
     latkw, kind, nrhs0, vt, nn, q, rc, nf, qf = CASES[name]
     nrhs = nrhs0 if nrhs is None else nrhs
     lat = P.Lattice(latkw["dims"], latkw["L"], latkw.get("k0", 0.0), latkw.get("kt", [0, 0, 0]))
@@ -71,7 +71,7 @@ def _setup(name, N=257, seed=31, precision="f64", nrhs=None):
     pos = torch.tensor(src, dtype=torch.float64, device="cuda")
     plan = fp.Plan(pos, latkw["dims"], latkw["L"], k0=latkw.get("k0", 0.0), kt=latkw.get("kt", [0, 0, 0]),
                    near_n=nn, near_order=q, corr_radius=rc, far_n=nf, far_order=qf, n_images=1,
-                   precision=precision, value_type=vt, nrhs_max=max(4, nrhs))
+                   precision=precision, value_type=vt, nrhs_max=max(4, nrhs), corr_layout=corr_layout)
     return lat, ref, plan, qv
 
 
@@ -197,3 +197,28 @@ def test_many_right_hand_sides(name, nrhs, precision):
             got = plan.apply_parts(qd, bit, adjoint=adjoint).cpu().numpy()
             want = (ref.adjoint if adjoint else ref.apply)(qv, parts=(part,))
             assert rel(got, want) < tol, (part, adjoint)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_symmetric_block_layout(name):
+    # the in-cell correction stored once per box pair (+ a close-image CSR)
+    # must give the same operator, forward and conjugate transpose
+    lat, ref, plan, qv = _setup(name, N=400, seed=17, corr_layout="sym")
+    qd = _to_dev(plan, qv)
+    for adjoint in (False, True):
+        got = plan.apply_parts(qd, 2, adjoint=adjoint).cpu().numpy()
+        want = (ref.adjoint if adjoint else ref.apply)(qv, parts=("near_corr",))
+        assert rel(got, want) < 1e-11, adjoint
+        got = plan.apply_parts(qd, 7, adjoint=adjoint).cpu().numpy()
+        want = (ref.adjoint if adjoint else ref.apply)(qv)
+        assert rel(got, want) < 1e-11, adjoint
+
+
+def test_symmetric_layout_dense_boxes_many_rhs():
+    # clustered points (many per box) and several planes through the block path
+    lat, ref, plan, qv = _setup("helm2_bloch", N=1500, seed=19, corr_layout="sym", nrhs=3)
+    qd = _to_dev(plan, qv)
+    for adjoint in (False, True):
+        got = plan.apply_parts(qd, 2, adjoint=adjoint).cpu().numpy()
+        want = (ref.adjoint if adjoint else ref.apply)(qv, parts=("near_corr",))
+        assert rel(got, want) < 1e-11, adjoint
