@@ -96,21 +96,41 @@ def run_secondary(args, key):
     plan.close()
 
 
-def measured_traffic(corr_radius, nnz):
-    """HBM bytes per launch of the correction kernel from the committed
-    rocprofv3 FETCH_SIZE / WRITE_SIZE summary (scaled by a plain copy of known
-    size), or None when that summary was taken on a different kernel source or
-    workload."""
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "hbm_traffic_near_correction_helmholtz_surface_100k.json")
+CORR_SOURCES = ["paper_2312_02376_amd/csrc/kernels_sym.hip", "paper_2312_02376_amd/csrc/kernels_corr.hip"]
+
+
+def corr_source_hash():
     import hashlib
-    path = os.path.join(ROOT, "profiles", "hbm_traffic_k_corr_spmv_helmholtz_surface_100k.json")
+    h = hashlib.sha256()
+    for s in CORR_SOURCES:
+        h.update(open(os.path.join(ROOT, s), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(nnz):
+    """HBM bytes per apply of the near-zone correction kernels from the
+    committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary (scaled by a plain copy
+    of known size), or None when that summary was taken on a different kernel
+    source or workload."""
     try:
-        rec = json.load(open(path))
-        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
-    except (OSError, ValueError, KeyError):
+        rec = json.load(open(TRAFFIC_RECORD))
+    except (OSError, ValueError):
         return None
-    if hashlib.sha256(src).hexdigest() != rec.get("source_sha256") or rec.get("corr_nnz") != nnz:
+    if rec.get("source_sha256") != corr_source_hash() or rec.get("corr_nnz") != nnz:
         return None
     return rec["traffic_bytes_per_launch"]
+
+
+def correction_bytes(info, N, planes, amp_bytes=16):
+    """Algorithmic bytes of one correction apply: every stored FP64 value once
+    (box-pair blocks; CSR values with their int32 columns and int64 row
+    pointers), the amplitudes once and the result once."""
+    vb = info["corr_value_bytes"]
+    b = info["corr_sym_values"] * vb
+    if info["corr_csr_nnz"] > 0 or info["corr_layout_used"] == 1:
+        b += info["corr_csr_nnz"] * (vb + 4) + (N + 1) * 8
+    return b + 2 * N * planes * amp_bytes
 
 
 def main():
@@ -197,19 +217,21 @@ def main():
     print("stages (ms per launch): " + ", ".join(
         "%s %.4f" % (k, t / c) for k, (t, c) in stages.items() if c), file=sys.stderr, flush=True)
 
-    # dominant kernel: the FP64 correction SpMV (near Step 4)
+    # dominant kernel: the FP64 near-zone correction (Sec. 3.3 Step 4)
     corr_ms, corr_calls = stages["near_corr"]
     corr_avg_s = corr_ms / max(corr_calls, 1) * 1e-3
     nnz = info["corr_nnz"]
-    corr_bytes = nnz * (16 + 4) + (N + 1) * 8 + N * 16 + 2 * N * 16
+    corr_bytes = correction_bytes(info, N, 1)
+    kname = ("k_sym_apply + k_sym_gather (near-zone correction, FP64 complex box-pair blocks)"
+             if info["corr_layout_used"] == 2 else "k_corr_spmv (near-zone correction, FP64 complex CSR)")
     roofline = {
-        "kernel": "k_corr_spmv (near-zone correction, FP64 complex CSR)",
+        "kernel": kname,
         "bound": "hbm",
         "achieved": corr_bytes / corr_avg_s / 1e9,
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": corr_bytes / corr_avg_s / 1e9 / HBM_PEAK_GBS,
-        "traffic": measured_traffic(wl["corr_radius"], nnz),
+        "traffic": measured_traffic(nnz),
         "bytes_per_launch": corr_bytes,
         "avg_launch_ms": corr_avg_s * 1e3,
     }

@@ -112,7 +112,11 @@ typedef struct {
   double near_h[3], domain_lo[3], domain_hi[3];
   int far_n[3], far_cells[3];
   double far_h[3];
-  int64_t corr_nnz;           /* stored correction entries */
+  int64_t corr_nnz;           /* stored correction entries (all parts) */
+  int64_t corr_sym_values;    /* entries in symmetric box-pair blocks */
+  int64_t corr_csr_nnz;       /* entries in the CSR part */
+  int corr_value_bytes;       /* 8 (real) or 16 (complex) per FP64 entry */
+  int corr_layout_used;       /* FFTPIM_CORR_CSR or FFTPIM_CORR_SYM */
   int64_t device_bytes;       /* device memory held by the plan */
   int nplanes_max;            /* complex grid planes for nrhs_max */
   double plan_seconds;        /* wall time of fftpim_plan */

@@ -196,6 +196,7 @@ SymArgs sym_args(const fftpim_plan_s* p) {
   a.pair_ebox_o = d.pair_ebox_o;
   a.pair_ebox_s = d.pair_ebox_s;
   a.pair_voff = d.pair_voff;
+  a.pair_stride = d.pair_stride;
   a.pair_zoff = d.pair_zoff;
   a.item_ebox = d.item_ebox;
   a.item_pbeg = d.item_pbeg;
@@ -203,7 +204,6 @@ SymArgs sym_args(const fftpim_plan_s* p) {
   a.item_yoff = d.item_yoff;
   a.ebox_item_beg = d.ebox_item_beg;
   a.in_beg = d.in_beg;
-  a.in_zoff = d.in_zoff;
   return a;
 }
 
@@ -521,14 +521,38 @@ int build_sym(fftpim_plan_s* p, const std::vector<int32_t>& start, const double*
     }
   }
   const int64_t E = static_cast<int64_t>(ebox.size());
+  auto box_coords = [&](int64_t B, int& bx, int& by, int& bz) {
+    bz = static_cast<int>(B % nbz);
+    by = static_cast<int>((B / nbz) % nby);
+    bx = static_cast<int>(B / (static_cast<int64_t>(nbz) * nby));
+  };
+  // pass 1: number of partner boxes B < B' sending column sums to each box
+  std::vector<int64_t> n_in(E, 0);
+  for (int64_t k = 0; k < E; ++k) {
+    int bx, by, bz;
+    box_coords(ebox[k], bx, by, bz);
+    for (int cx = std::max(0, bx - rc); cx <= std::min(nbx - 1, bx + rc); ++cx)
+      for (int cy = std::max(0, by - rc); cy <= std::min(nby - 1, by + rc); ++cy)
+        for (int cz = std::max(0, bz - rc); cz <= std::min(nbz - 1, bz + rc); ++cz) {
+          const int64_t Bp = (static_cast<int64_t>(cx) * nby + cy) * nbz + cz;
+          if (Bp > ebox[k] && ebox_of_box[Bp] >= 0) n_in[ebox_of_box[Bp]]++;
+        }
+  }
+  // column partials are grouped by destination box: the j-th sender of box
+  // B' (senders in box order) writes slots in_beg[B'] + j n_B' .. + n_B' - 1
+  std::vector<int64_t> in_beg(E + 1, 0);
+  for (int64_t k = 0; k < E; ++k) {
+    const int64_t nk = start[ebox[k] + 1] - start[ebox[k]];
+    in_beg[k + 1] = in_beg[k] + n_in[k] * nk;
+  }
+  std::vector<int64_t> in_fill(E, 0);
   std::vector<int32_t> po, ps, item_ebox, ebox_item_beg(E + 1, 0);
   std::vector<int64_t> pvoff, pzoff, item_pbeg, item_pend, item_yoff;
-  std::vector<std::vector<int64_t>> incoming(E);
-  int64_t voff = 0, zoff = 0, yoff = 0;
+  int64_t voff = 0, yoff = 0;
   for (int64_t k = 0; k < E; ++k) {
     const int64_t B = ebox[k];
-    const int bz = static_cast<int>(B % nbz), by = static_cast<int>((B / nbz) % nby),
-              bx = static_cast<int>(B / (static_cast<int64_t>(nbz) * nby));
+    int bx, by, bz;
+    box_coords(B, bx, by, bz);
     const int nB = start[B + 1] - start[B];
     const int64_t pfirst = static_cast<int64_t>(po.size());
     for (int cx = std::max(0, bx - rc); cx <= std::min(nbx - 1, bx + rc); ++cx)
@@ -536,15 +560,15 @@ int build_sym(fftpim_plan_s* p, const std::vector<int32_t>& start, const double*
         for (int cz = std::max(0, bz - rc); cz <= std::min(nbz - 1, bz + rc); ++cz) {
           const int64_t Bp = (static_cast<int64_t>(cx) * nby + cy) * nbz + cz;
           if (Bp < B || ebox_of_box[Bp] < 0) continue;
+          const int kp = ebox_of_box[Bp];
           const int nBp = start[Bp + 1] - start[Bp];
           po.push_back(static_cast<int32_t>(k));
-          ps.push_back(ebox_of_box[Bp]);
+          ps.push_back(kp);
           pvoff.push_back(voff);
           voff += static_cast<int64_t>(nB) * nBp;
           if (Bp != B) {
-            pzoff.push_back(zoff);
-            incoming[ebox_of_box[Bp]].push_back(zoff);
-            zoff += nBp;
+            pzoff.push_back(in_beg[kp] + in_fill[kp] * nBp);
+            in_fill[kp]++;
           } else {
             pzoff.push_back(-1);
           }
@@ -560,12 +584,38 @@ int build_sym(fftpim_plan_s* p, const std::vector<int32_t>& start, const double*
     }
   }
   ebox_item_beg[E] = static_cast<int32_t>(item_ebox.size());
-  std::vector<int64_t> in_beg(E + 1, 0), in_zoff;
-  for (int64_t k = 0; k < E; ++k) {
-    in_beg[k] = static_cast<int64_t>(in_zoff.size());
-    in_zoff.insert(in_zoff.end(), incoming[k].begin(), incoming[k].end());
+  const int64_t zoff = in_beg[E];
+  // value layout: within each item, consecutive pairs are grouped while their
+  // columns fit 64 lanes (the apply kernel forms the same groups) and a
+  // group's blocks are stored interleaved row by row
+  std::vector<int64_t> pstride(po.size(), 0);
+  voff = 0;
+  for (size_t it = 0; it < item_ebox.size(); ++it) {
+    const int64_t B = ebox[item_ebox[it]];
+    const int nB = start[B + 1] - start[B];
+    int64_t pr = item_pbeg[it];
+    while (pr < item_pend[it]) {
+      int cum = 0;
+      int64_t pg = pr;
+      while (pg < item_pend[it]) {
+        const int64_t Bj = ebox[ps[pg]];
+        const int nj = start[Bj + 1] - start[Bj];
+        if (cum > 0 && cum + nj > 64) break;
+        cum += nj;
+        ++pg;
+        if (cum >= 64) break;
+      }
+      int col = 0;
+      for (int64_t j = pr; j < pg; ++j) {
+        const int64_t Bj = ebox[ps[j]];
+        pvoff[j] = voff + col;
+        pstride[j] = cum;
+        col += start[Bj + 1] - start[Bj];
+      }
+      voff += static_cast<int64_t>(nB) * cum;
+      pr = pg;
+    }
   }
-  in_beg[E] = static_cast<int64_t>(in_zoff.size());
   SymDev& d = p->symd;
   d.npairs = static_cast<int64_t>(po.size());
   d.nitems = static_cast<int64_t>(item_ebox.size());
@@ -579,6 +629,7 @@ int build_sym(fftpim_plan_s* p, const std::vector<int32_t>& start, const double*
   CHK(upload(p, &d.pair_ebox_o, po));
   CHK(upload(p, &d.pair_ebox_s, ps));
   CHK(upload(p, &d.pair_voff, pvoff));
+  CHK(upload(p, &d.pair_stride, pstride));
   CHK(upload(p, &d.pair_zoff, pzoff));
   CHK(upload(p, &d.item_ebox, item_ebox));
   CHK(upload(p, &d.item_pbeg, item_pbeg));
@@ -586,7 +637,6 @@ int build_sym(fftpim_plan_s* p, const std::vector<int32_t>& start, const double*
   CHK(upload(p, &d.item_yoff, item_yoff));
   CHK(upload(p, &d.ebox_item_beg, ebox_item_beg));
   CHK(upload(p, &d.in_beg, in_beg));
-  CHK(upload(p, &d.in_zoff, in_zoff));
   p->sym_nvals = voff;
   unsigned char* v = nullptr;
   CHK(dalloc(p, &v, static_cast<size_t>(voff) * (p->complex_kernel ? 16 : 8)));
@@ -1025,6 +1075,10 @@ int fftpim_plan_info(fftpim_plan_t plan, fftpim_info_t* info) {
     r.far_h[c] = plan->fg.h[c];
   }
   r.corr_nnz = plan->nnz + plan->sym_nvals;
+  r.corr_sym_values = plan->sym_nvals;
+  r.corr_csr_nnz = plan->nnz;
+  r.corr_value_bytes = plan->complex_kernel ? 16 : 8;
+  r.corr_layout_used = plan->sym ? FFTPIM_CORR_SYM : FFTPIM_CORR_CSR;
   r.device_bytes = plan->device_bytes;
   r.nplanes_max = plan->nplanes_max;
   r.plan_seconds = plan->plan_seconds;

@@ -127,11 +127,11 @@ struct SymDev {
   int max_box = 0;
   int32_t *ebox = nullptr, *ebox_of_box = nullptr, *box_of_point = nullptr;
   int32_t *pair_ebox_o = nullptr, *pair_ebox_s = nullptr;
-  int64_t *pair_voff = nullptr, *pair_zoff = nullptr;
+  int64_t *pair_voff = nullptr, *pair_zoff = nullptr, *pair_stride = nullptr;
   int32_t* item_ebox = nullptr;
   int64_t *item_pbeg = nullptr, *item_pend = nullptr, *item_yoff = nullptr;
   int32_t* ebox_item_beg = nullptr;
-  int64_t *in_beg = nullptr, *in_zoff = nullptr;
+  int64_t* in_beg = nullptr;
 };
 
 struct DevBuf {

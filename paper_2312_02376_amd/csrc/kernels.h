@@ -72,15 +72,16 @@ struct SymArgs {
   const int32_t* box_of_point;   // [N]
   const int32_t* pair_ebox_o;    // [npairs] observer-side box (B)
   const int32_t* pair_ebox_s;    // [npairs] source-side box (B' >= B)
-  const int64_t* pair_voff;      // [npairs] first value of the block
+  const int64_t* pair_voff;      // [npairs] value of row 0, column 0 of the block
+  const int64_t* pair_stride;    // [npairs] row stride (width of the pair's lane group)
   const int64_t* pair_zoff;      // [npairs] first point slot of the column partials
   const int32_t* item_ebox;      // [nitems]
   const int64_t* item_pbeg;      // [nitems] pair range of the item
   const int64_t* item_pend;
   const int64_t* item_yoff;      // [nitems] first point slot of the row partials
   const int32_t* ebox_item_beg;  // [E + 1] items of each box
-  const int64_t* in_beg;         // [E + 1] column partials addressed to each box
-  const int64_t* in_zoff;        // [..] their first point slots
+  const int64_t* in_beg;         // [E + 1] slots of the column partials sent to each box
+                                 // (consecutive groups of n_B slots, senders in box order)
 };
 
 struct FarArgs {

@@ -46,6 +46,7 @@ __global__ void __launch_bounds__(64) k_sym_fill(SymArgs a, const double* __rest
   const int m0 = a.box_start[B], nB = a.box_start[B + 1] - m0;
   const int n0 = a.box_start[Bp], nBp = a.box_start[Bp + 1] - n0;
   const int64_t voff = a.pair_voff[pr];
+  const int64_t stride = a.pair_stride[pr];
   const int64_t N = a.N;
   for (int e = threadIdx.x; e < nB * nBp; e += blockDim.x) {
     const int r = e / nBp, c = e - r * nBp;
@@ -90,16 +91,19 @@ __global__ void __launch_bounds__(64) k_sym_fill(SymArgs a, const double* __rest
         er = inv;
       }
     }
+    const int64_t idx = voff + static_cast<int64_t>(r) * stride + c;
     if (CPLX)
-      static_cast<cplx<double>*>(vals)[voff + e] = cmake<double>(er - sr, ei - si);
+      static_cast<cplx<double>*>(vals)[idx] = cmake<double>(er - sr, ei - si);
     else
-      static_cast<double*>(vals)[voff + e] = er - sr;
+      static_cast<double*>(vals)[idx] = er - sr;
   }
 }
 
 // ---------------------------------------------------------------------------
 // apply
 // ---------------------------------------------------------------------------
+
+typedef double dbl2v __attribute__((ext_vector_type(2)));
 
 template <typename R>
 __device__ inline void load_planes(const cplx<R>* __restrict__ x, int64_t pt, int P, int p, bool conj_in, double& re,
@@ -136,7 +140,9 @@ __device__ inline double wave_reduce_scatter8(double v[8], int lane) {
 
 // One wavefront per item.  All pairs of an item share the observer box B, so
 // consecutive pairs are laid side by side across the 64 lanes (a lane owns
-// one column of one pair's block); eight rows of values are loaded back to
+// one column of one pair's block; the plan stores such a group's blocks
+// interleaved row by row with the same grouping rule, so a row of the group
+// is one contiguous load); eight rows of values are loaded back to
 // back, each lane accumulates its column sum (X^T x_B, for the partner box)
 // in registers, and the row sums (X x_B' over all pairs of the group) come
 // from a register reduce-scatter.  A pair with more than 64 columns is
@@ -144,7 +150,7 @@ __device__ inline double wave_reduce_scatter8(double v[8], int lane) {
 template <typename R, bool CPLX>
 __device__ inline void sym_rows(const SymArgs& a, const double* __restrict__ vr, const cplx<double>* __restrict__ vc,
                                 const cplx<double>* xb, cplx<double>* yacc, int nB, int P, int p, int lane, bool act,
-                                int64_t voff, int nBp, int c, double xsr, double xsi, double& zr, double& zi) {
+                                int64_t voff, int64_t stride, int c, double xsr, double xsi, double& zr, double& zi) {
   const int krow = ((lane >> 5) & 1) * 4 + ((lane >> 4) & 1) * 2 + ((lane >> 3) & 1);
   for (int r0 = 0; r0 < nB; r0 += 8) {
     double wr[8], wi[8];
@@ -153,7 +159,8 @@ __device__ inline void sym_rows(const SymArgs& a, const double* __restrict__ vr,
       wr[k] = 0.0;
       wi[k] = 0.0;
       if (act && r0 + k < nB) {
-        const int64_t idx = voff + static_cast<int64_t>(r0 + k) * nBp + c;
+        // a group's blocks are interleaved row by row: one contiguous load per row
+        const int64_t idx = voff + static_cast<int64_t>(r0 + k) * stride + c;
         if (CPLX) {
           const cplx<double> w = vc[idx];
           wr[k] = w.x;
@@ -226,21 +233,19 @@ __global__ void __launch_bounds__(64) k_sym_apply(SymArgs a, const void* __restr
     }
     if (cum <= 64) {
       const bool act = mine >= 0;
-      int n0 = 0, nBp = 1;
+      int n0 = 0;
       int64_t voff = 0;
       bool diag = true;
       if (act) {
         const int kbp = a.pair_ebox_s[mine];
-        const int Bp = a.ebox[kbp];
-        n0 = a.box_start[Bp];
-        nBp = a.box_start[Bp + 1] - n0;
+        n0 = a.box_start[a.ebox[kbp]];
         voff = a.pair_voff[mine];
         diag = kbp == kb;
       }
       for (int p = 0; p < P; ++p) {
         double xsr = 0.0, xsi = 0.0, zr = 0.0, zi = 0.0;
         if (act) load_planes<R>(x, n0 + my_c, P, p, conj_in, xsr, xsi);
-        sym_rows<R, CPLX>(a, vr, vc, xb, yacc, nB, P, p, lane, act, voff, nBp, my_c, xsr, xsi, zr, zi);
+        sym_rows<R, CPLX>(a, vr, vc, xb, yacc, nB, P, p, lane, act, voff, cum, my_c, xsr, xsi, zr, zi);
         if (act && !diag) zpart[(a.pair_zoff[mine] + my_c) * P + p] = cmake<double>(zr, zi);
       }
     } else {
@@ -268,26 +273,30 @@ __global__ void __launch_bounds__(64) k_sym_apply(SymArgs a, const void* __restr
   for (int t = lane; t < nB * P; t += 64) ypart[yoff * P + t] = yacc[t];
 }
 
-// Per point: its box's item partials (in item order) plus the column partials
-// sent to its box (in pair order); result written (or added) to u.
+// One thread per (point, plane): the row partials of the point's box's items,
+// then the column partials sent to its box (senders in box order), added in
+// that fixed order.
 template <typename R>
-__global__ void k_sym_gather(SymArgs a, const cplx<double>* __restrict__ ypart, const cplx<double>* __restrict__ zpart,
-                             int P, int conj_out, cplx<R>* __restrict__ u, int accumulate) {
+__global__ void __launch_bounds__(256) k_sym_gather(SymArgs a, const cplx<double>* __restrict__ ypart,
+                                                    const cplx<double>* __restrict__ zpart, int P, int conj_out,
+                                                    cplx<R>* __restrict__ u, int accumulate) {
   const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= a.N * P) return;
   const int64_t m = t / P;
-  const int p = static_cast<int>(t % P);
+  const int p = static_cast<int>(t - m * P);
   const int B = a.box_of_point[m];
   const int kb = a.ebox_of_box[B];
-  const int r = static_cast<int>(m - a.box_start[B]);
+  const int m0 = a.box_start[B], nB = a.box_start[B + 1] - m0;
+  const int r = static_cast<int>(m - m0);
   double sr = 0.0, si = 0.0;
   for (int it = a.ebox_item_beg[kb]; it < a.ebox_item_beg[kb + 1]; ++it) {
     const cplx<double> v = ypart[(a.item_yoff[it] + r) * P + p];
     sr += v.x;
     si += v.y;
   }
-  for (int64_t k = a.in_beg[kb]; k < a.in_beg[kb + 1]; ++k) {
-    const cplx<double> v = zpart[(a.in_zoff[k] + r) * P + p];
+  const int64_t zend = a.in_beg[kb + 1];
+  for (int64_t z = a.in_beg[kb] + r; z < zend; z += nB) {
+    const cplx<double> v = zpart[z * P + p];
     sr += v.x;
     si += v.y;
   }

@@ -58,7 +58,9 @@ class Info(ctypes.Structure):
                 ("near_fft", ctypes.c_int * 3), ("near_cells", ctypes.c_int * 3), ("near_h", ctypes.c_double * 3),
                 ("domain_lo", ctypes.c_double * 3), ("domain_hi", ctypes.c_double * 3),
                 ("far_n", ctypes.c_int * 3), ("far_cells", ctypes.c_int * 3), ("far_h", ctypes.c_double * 3),
-                ("corr_nnz", ctypes.c_int64), ("device_bytes", ctypes.c_int64), ("nplanes_max", ctypes.c_int),
+                ("corr_nnz", ctypes.c_int64), ("corr_sym_values", ctypes.c_int64), ("corr_csr_nnz", ctypes.c_int64),
+                ("corr_value_bytes", ctypes.c_int), ("corr_layout_used", ctypes.c_int),
+                ("device_bytes", ctypes.c_int64), ("nplanes_max", ctypes.c_int),
                 ("plan_seconds", ctypes.c_double)]
 
 
