@@ -204,6 +204,7 @@ SymArgs sym_args(const fftpim_plan_s* p) {
   a.item_yoff = d.item_yoff;
   a.ebox_item_beg = d.ebox_item_beg;
   a.in_beg = d.in_beg;
+  a.nebox = d.nebox;
   return a;
 }
 

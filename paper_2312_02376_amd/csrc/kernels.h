@@ -82,6 +82,7 @@ struct SymArgs {
   const int32_t* ebox_item_beg;  // [E + 1] items of each box
   const int64_t* in_beg;         // [E + 1] slots of the column partials sent to each box
                                  // (consecutive groups of n_B slots, senders in box order)
+  int64_t nebox;                 // E
 };
 
 struct FarArgs {

@@ -273,37 +273,60 @@ __global__ void __launch_bounds__(64) k_sym_apply(SymArgs a, const void* __restr
   for (int t = lane; t < nB * P; t += 64) ypart[yoff * P + t] = yacc[t];
 }
 
-// One thread per (point, plane): the row partials of the point's box's items,
-// then the column partials sent to its box (senders in box order), added in
-// that fixed order.
+// One workgroup per non-empty box B.  Its partial sums come in runs of n_B P
+// contiguous values: one run per work item of B (row sums, ypart) and one
+// per box sending column sums to B (zpart, senders in box order).  Threads
+// split into S slices of n_B P lanes; slice s adds runs s, s + S, ...; the
+// slices are then added in slice order (a fixed order: results do not depend
+// on scheduling).
+constexpr int kGatherThreads = 256;
+
 template <typename R>
-__global__ void __launch_bounds__(256) k_sym_gather(SymArgs a, const cplx<double>* __restrict__ ypart,
-                                                    const cplx<double>* __restrict__ zpart, int P, int conj_out,
-                                                    cplx<R>* __restrict__ u, int accumulate) {
-  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= a.N * P) return;
-  const int64_t m = t / P;
-  const int p = static_cast<int>(t - m * P);
-  const int B = a.box_of_point[m];
-  const int kb = a.ebox_of_box[B];
+__global__ void __launch_bounds__(kGatherThreads) k_sym_gather(SymArgs a, const cplx<double>* __restrict__ ypart,
+                                                               const cplx<double>* __restrict__ zpart, int P,
+                                                               int conj_out, cplx<R>* __restrict__ u,
+                                                               int accumulate) {
+  __shared__ double sr_[kGatherThreads], si_[kGatherThreads];
+  const int kb = blockIdx.x;
+  const int t = threadIdx.x;
+  const int B = a.ebox[kb];
   const int m0 = a.box_start[B], nB = a.box_start[B + 1] - m0;
-  const int r = static_cast<int>(m - m0);
-  double sr = 0.0, si = 0.0;
-  for (int it = a.ebox_item_beg[kb]; it < a.ebox_item_beg[kb + 1]; ++it) {
-    const cplx<double> v = ypart[(a.item_yoff[it] + r) * P + p];
-    sr += v.x;
-    si += v.y;
+  const int it0 = a.ebox_item_beg[kb], nit = a.ebox_item_beg[kb + 1] - it0;
+  const int64_t y0 = a.item_yoff[it0] * P;
+  const int64_t z0 = a.in_beg[kb] * P;
+  const int run = nB * P;
+  const int64_t nruns = nit + (a.in_beg[kb + 1] - a.in_beg[kb]) / nB;
+  const int S = run <= kGatherThreads ? kGatherThreads / run : 1;
+  for (int e0 = 0; e0 < run; e0 += kGatherThreads) {
+    const int s = S > 1 ? t / run : 0;
+    const int e = S > 1 ? t - s * run : e0 + t;
+    const bool act = s < S && e < run;
+    double xr = 0.0, xi = 0.0;
+    if (act) {
+      for (int64_t k = s; k < nruns; k += S) {
+        const cplx<double> v = k < nit ? ypart[y0 + k * run + e] : zpart[z0 + (k - nit) * run + e];
+        xr += v.x;
+        xi += v.y;
+      }
+    }
+    sr_[t] = xr;
+    si_[t] = xi;
+    __syncthreads();
+    const int nout = S > 1 ? run : min(kGatherThreads, run - e0);
+    if (t < nout) {
+      double tr = 0.0, ti = 0.0;
+      for (int k = 0; k < S; ++k) {
+        tr += sr_[k * (S > 1 ? run : 0) + t];
+        ti += si_[k * (S > 1 ? run : 0) + t];
+      }
+      if (conj_out) ti = -ti;
+      const int64_t o = static_cast<int64_t>(m0) * P + (S > 1 ? t : e0 + t);
+      cplx<R> out = cmake<R>(static_cast<R>(tr), static_cast<R>(ti));
+      if (accumulate) out = cadd(u[o], out);
+      u[o] = out;
+    }
+    __syncthreads();
   }
-  const int64_t zend = a.in_beg[kb + 1];
-  for (int64_t z = a.in_beg[kb] + r; z < zend; z += nB) {
-    const cplx<double> v = zpart[z * P + p];
-    sr += v.x;
-    si += v.y;
-  }
-  if (conj_out) si = -si;
-  cplx<R> out = cmake<R>(static_cast<R>(sr), static_cast<R>(si));
-  if (accumulate) out = cadd(u[t], out);
-  u[t] = out;
 }
 
 // ---------------------------------------------------------------------------
@@ -350,8 +373,7 @@ void launch_sym_apply(bool cplx_vals, const SymArgs& a, const void* vals, const 
   else
     hipLaunchKernelGGL((k_sym_apply<R, false>), dim3(static_cast<unsigned>(a.nitems)), dim3(64), lds, st, a, vals,
                        xx, P, conj_io ? 1 : 0, yp, zp);
-  const int64_t n = a.N * P;
-  hipLaunchKernelGGL((k_sym_gather<R>), dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st, a, yp, zp, P,
+  hipLaunchKernelGGL((k_sym_gather<R>), dim3(static_cast<unsigned>(a.nebox)), dim3(kGatherThreads), 0, st, a, yp, zp, P,
                      conj_io ? 1 : 0, static_cast<cplx<R>*>(u), accumulate ? 1 : 0);
 }
 
