@@ -189,22 +189,21 @@ SymArgs sym_args(const fftpim_plan_s* p) {
   a.max_box = d.max_box;
   a.npairs = d.npairs;
   a.nitems = d.nitems;
+  a.nebox = d.nebox;
   a.box_start = p->box_start;
   a.ebox = d.ebox;
-  a.ebox_of_box = d.ebox_of_box;
-  a.box_of_point = d.box_of_point;
   a.pair_ebox_o = d.pair_ebox_o;
   a.pair_ebox_s = d.pair_ebox_s;
   a.pair_voff = d.pair_voff;
   a.pair_stride = d.pair_stride;
-  a.pair_zoff = d.pair_zoff;
+  a.groups = d.groups;
+  a.item_order = d.item_order;
   a.item_ebox = d.item_ebox;
-  a.item_pbeg = d.item_pbeg;
-  a.item_pend = d.item_pend;
+  a.item_gbeg = d.item_gbeg;
   a.item_yoff = d.item_yoff;
   a.ebox_item_beg = d.ebox_item_beg;
-  a.in_beg = d.in_beg;
-  a.nebox = d.nebox;
+  a.in_ptr = d.in_ptr;
+  a.in_base = d.in_base;
   return a;
 }
 
@@ -501,16 +500,19 @@ int build_tables(fftpim_plan_s* p, hipStream_t st) {
 }
 
 // Symmetric in-cell blocks: pairs (B, B') of non-empty near-grid boxes with
-// B <= B' (box id order) within r_c boxes (no image shift), grouped into work
-// items of up to kPairsPerItem pairs of one box; values filled on the device.
-constexpr int kPairsPerItem = 32;
+// B <= B' (box id order) within r_c boxes (no image shift).  The pairs of a
+// box are cut into lane groups (SymGroup) and the groups into work items of
+// at most kGroupsPerItem groups; values are filled on the device.
+constexpr int kGroupsPerItem = 12;
+constexpr int kLanes = 64;
+inline int64_t zround(int64_t n) { return (n + kSymZAlign - 1) / kSymZAlign * kSymZAlign; }
 
 int build_sym(fftpim_plan_s* p, const std::vector<int32_t>& start, const double* pos3_dev, const void* g0tab,
               const CorrArgs& ca, hipStream_t st) {
   const int nbx = p->nb[0], nby = p->nb[1], nbz = p->nb[2];
   const int64_t nboxes = static_cast<int64_t>(nbx) * nby * nbz;
   const int rc = p->prm.corr_radius;
-  std::vector<int32_t> ebox, ebox_of_box(nboxes, -1), box_of_point(p->N);
+  std::vector<int32_t> ebox, ebox_of_box(nboxes, -1);
   int max_box = 0;
   for (int64_t b = 0; b < nboxes; ++b) {
     const int cnt = start[b + 1] - start[b];
@@ -518,126 +520,170 @@ int build_sym(fftpim_plan_s* p, const std::vector<int32_t>& start, const double*
       ebox_of_box[b] = static_cast<int32_t>(ebox.size());
       ebox.push_back(static_cast<int32_t>(b));
       max_box = std::max(max_box, cnt);
-      for (int j = start[b]; j < start[b + 1]; ++j) box_of_point[j] = static_cast<int32_t>(b);
     }
   }
   const int64_t E = static_cast<int64_t>(ebox.size());
-  auto box_coords = [&](int64_t B, int& bx, int& by, int& bz) {
-    bz = static_cast<int>(B % nbz);
-    by = static_cast<int>((B / nbz) % nby);
-    bx = static_cast<int>(B / (static_cast<int64_t>(nbz) * nby));
-  };
-  // pass 1: number of partner boxes B < B' sending column sums to each box
-  std::vector<int64_t> n_in(E, 0);
-  for (int64_t k = 0; k < E; ++k) {
-    int bx, by, bz;
-    box_coords(ebox[k], bx, by, bz);
-    for (int cx = std::max(0, bx - rc); cx <= std::min(nbx - 1, bx + rc); ++cx)
-      for (int cy = std::max(0, by - rc); cy <= std::min(nby - 1, by + rc); ++cy)
-        for (int cz = std::max(0, bz - rc); cz <= std::min(nbz - 1, bz + rc); ++cz) {
-          const int64_t Bp = (static_cast<int64_t>(cx) * nby + cy) * nbz + cz;
-          if (Bp > ebox[k] && ebox_of_box[Bp] >= 0) n_in[ebox_of_box[Bp]]++;
-        }
-  }
-  // column partials are grouped by destination box: the j-th sender of box
-  // B' (senders in box order) writes slots in_beg[B'] + j n_B' .. + n_B' - 1
-  std::vector<int64_t> in_beg(E + 1, 0);
-  for (int64_t k = 0; k < E; ++k) {
-    const int64_t nk = start[ebox[k] + 1] - start[ebox[k]];
-    in_beg[k + 1] = in_beg[k] + n_in[k] * nk;
-  }
-  std::vector<int64_t> in_fill(E, 0);
   std::vector<int32_t> po, ps, item_ebox, ebox_item_beg(E + 1, 0);
-  std::vector<int64_t> pvoff, pzoff, item_pbeg, item_pend, item_yoff;
-  int64_t voff = 0, yoff = 0;
+  std::vector<int64_t> pvoff, pstride, item_gbeg, item_yoff;
+  std::vector<SymGroup> groups;
+  // senders of column partials to each box, in box order: (destination, slot)
+  std::vector<std::vector<int64_t>> in_lists(E);
+  int64_t voff = 0, zoff = 0, yoff = 0;
+  std::vector<int64_t> gpairs;  // pairs of the open group
+  bool layout_ok = true;
+  // source point of column c of a group (the apply kernel's rule)
+  auto col_point = [](const SymGroup& g, int c) {
+    int n = g.n0[0] + c;
+    if (c >= g.end[0]) n = g.n0[1] + c - g.end[0];
+    if (c >= g.end[1]) n = g.n0[2] + c - g.end[1];
+    if (c >= g.end[2]) n = g.n0[3] + c - g.end[2];
+    return n;
+  };
   for (int64_t k = 0; k < E; ++k) {
     const int64_t B = ebox[k];
-    int bx, by, bz;
-    box_coords(B, bx, by, bz);
+    const int bz = static_cast<int>(B % nbz), by = static_cast<int>((B / nbz) % nby),
+              bx = static_cast<int>(B / (static_cast<int64_t>(nbz) * nby));
     const int nB = start[B + 1] - start[B];
-    const int64_t pfirst = static_cast<int64_t>(po.size());
+    const int64_t gfirst = static_cast<int64_t>(groups.size());
+    SymGroup g{};
+    int nseg = 0;
+    auto open_group = [&]() {
+      g = SymGroup{};
+      g.voff = voff;
+      g.zoff = zoff;
+      for (int s = 0; s < 4; ++s) g.end[s] = kLanes;
+      nseg = 0;
+      gpairs.clear();
+    };
+    auto close_group = [&]() {
+      if (g.cum == 0) return;
+      g.stride = g.cum;
+      int col = 0;
+      for (int64_t j : gpairs) {
+        pvoff[j] = g.voff + col;
+        pstride[j] = g.cum;
+        const int64_t Bp = ebox[ps[j]];
+        const int nj = start[Bp + 1] - start[Bp];
+        // the kernel's column -> point map must give this pair's points
+        if (col_point(g, col) != start[Bp] || col_point(g, col + nj - 1) != start[Bp] + nj - 1) layout_ok = false;
+        if (ps[j] != k) in_lists[ps[j]].push_back(g.zoff + col);
+        col += nj;
+      }
+      if (col != g.cum || g.cum > kLanes) layout_ok = false;
+      groups.push_back(g);
+      voff += static_cast<int64_t>(nB) * g.cum;
+      zoff += zround(g.cum);
+    };
+    open_group();
     for (int cx = std::max(0, bx - rc); cx <= std::min(nbx - 1, bx + rc); ++cx)
       for (int cy = std::max(0, by - rc); cy <= std::min(nby - 1, by + rc); ++cy)
         for (int cz = std::max(0, bz - rc); cz <= std::min(nbz - 1, bz + rc); ++cz) {
           const int64_t Bp = (static_cast<int64_t>(cx) * nby + cy) * nbz + cz;
           if (Bp < B || ebox_of_box[Bp] < 0) continue;
           const int kp = ebox_of_box[Bp];
-          const int nBp = start[Bp + 1] - start[Bp];
+          const int n0 = start[Bp], nj = start[Bp + 1] - n0;
+          const int64_t j = static_cast<int64_t>(po.size());
           po.push_back(static_cast<int32_t>(k));
           ps.push_back(kp);
-          pvoff.push_back(voff);
-          voff += static_cast<int64_t>(nB) * nBp;
-          if (Bp != B) {
-            pzoff.push_back(in_beg[kp] + in_fill[kp] * nBp);
-            in_fill[kp]++;
-          } else {
-            pzoff.push_back(-1);
+          pvoff.push_back(0);
+          pstride.push_back(0);
+          if (nj > kLanes) {
+            // a pair wider than the wavefront: its own block, cut into column chunks
+            close_group();
+            pvoff[j] = voff;
+            pstride[j] = nj;
+            if (kp != k) in_lists[kp].push_back(zoff);
+            for (int c0 = 0; c0 < nj; c0 += kLanes) {
+              SymGroup w{};
+              w.voff = voff + c0;
+              w.zoff = zoff + c0;
+              w.cum = std::min(kLanes, nj - c0);
+              w.stride = nj;
+              w.n0[0] = n0 + c0;
+              w.end[0] = w.cum;
+              for (int s = 1; s < 4; ++s) w.end[s] = kLanes;
+              if (kp == k) w.diag_hi = w.cum;
+              groups.push_back(w);
+            }
+            voff += static_cast<int64_t>(nB) * nj;
+            zoff += zround(nj);
+            open_group();
+            continue;
           }
+          const bool contiguous = nseg > 0 && n0 == g.n0[nseg - 1] + (g.end[nseg - 1] - (nseg > 1 ? g.end[nseg - 2] : 0));
+          if (g.cum + nj > kLanes || (!contiguous && nseg == 4)) {
+            close_group();
+            open_group();
+          }
+          const bool cont = nseg > 0 && n0 == g.n0[nseg - 1] + (g.end[nseg - 1] - (nseg > 1 ? g.end[nseg - 2] : 0));
+          if (cont) {
+            g.end[nseg - 1] += nj;
+          } else {
+            g.n0[nseg] = n0;
+            g.end[nseg] = g.cum + nj;
+            ++nseg;
+          }
+          if (kp == k) {
+            g.diag_lo = g.cum;
+            g.diag_hi = g.cum + nj;
+          }
+          g.cum += nj;
+          gpairs.push_back(j);
         }
-    const int64_t plast = static_cast<int64_t>(po.size());
+    close_group();
+    const int64_t glast = static_cast<int64_t>(groups.size());
     ebox_item_beg[k] = static_cast<int32_t>(item_ebox.size());
-    for (int64_t a0 = pfirst; a0 < plast; a0 += kPairsPerItem) {
+    for (int64_t a0 = gfirst; a0 < glast; a0 += kGroupsPerItem) {
       item_ebox.push_back(static_cast<int32_t>(k));
-      item_pbeg.push_back(a0);
-      item_pend.push_back(std::min(plast, a0 + kPairsPerItem));
+      item_gbeg.push_back(a0);
       item_yoff.push_back(yoff);
       yoff += nB;
     }
   }
   ebox_item_beg[E] = static_cast<int32_t>(item_ebox.size());
-  const int64_t zoff = in_beg[E];
-  // value layout: within each item, consecutive pairs are grouped while their
-  // columns fit 64 lanes (the apply kernel forms the same groups) and a
-  // group's blocks are stored interleaved row by row
-  std::vector<int64_t> pstride(po.size(), 0);
-  voff = 0;
-  for (size_t it = 0; it < item_ebox.size(); ++it) {
+  item_gbeg.push_back(static_cast<int64_t>(groups.size()));
+  for (const SymGroup& g : groups)
+    if (g.cum < 1 || g.cum > kLanes || g.diag_lo < 0 || g.diag_hi > g.cum || g.diag_lo > g.diag_hi ||
+        col_point(g, 0) < 0 || col_point(g, g.cum - 1) >= p->N)
+      layout_ok = false;
+  if (!layout_ok) return FFTPIM_ERR_DEVICE;
+  // launch order: items by decreasing number of values (largest first keeps
+  // the tail of the launch short); ties by item index
+  const int64_t nit = static_cast<int64_t>(item_ebox.size());
+  std::vector<int64_t> cost(nit, 0);
+  for (int64_t it = 0; it < nit; ++it) {
     const int64_t B = ebox[item_ebox[it]];
-    const int nB = start[B + 1] - start[B];
-    int64_t pr = item_pbeg[it];
-    while (pr < item_pend[it]) {
-      int cum = 0;
-      int64_t pg = pr;
-      while (pg < item_pend[it]) {
-        const int64_t Bj = ebox[ps[pg]];
-        const int nj = start[Bj + 1] - start[Bj];
-        if (cum > 0 && cum + nj > 64) break;
-        cum += nj;
-        ++pg;
-        if (cum >= 64) break;
-      }
-      int col = 0;
-      for (int64_t j = pr; j < pg; ++j) {
-        const int64_t Bj = ebox[ps[j]];
-        pvoff[j] = voff + col;
-        pstride[j] = cum;
-        col += start[Bj + 1] - start[Bj];
-      }
-      voff += static_cast<int64_t>(nB) * cum;
-      pr = pg;
-    }
+    const int64_t nB = start[B + 1] - start[B];
+    for (int64_t gi = item_gbeg[it]; gi < item_gbeg[it + 1]; ++gi) cost[it] += nB * groups[gi].cum;
   }
+  std::vector<int32_t> item_order(nit);
+  for (int64_t it = 0; it < nit; ++it) item_order[it] = static_cast<int32_t>(it);
+  std::stable_sort(item_order.begin(), item_order.end(), [&](int32_t x, int32_t y) { return cost[x] > cost[y]; });
+  std::vector<int64_t> in_ptr(E + 1, 0), in_base;
+  for (int64_t k = 0; k < E; ++k) in_ptr[k + 1] = in_ptr[k] + static_cast<int64_t>(in_lists[k].size());
+  in_base.reserve(in_ptr[E]);
+  for (int64_t k = 0; k < E; ++k) in_base.insert(in_base.end(), in_lists[k].begin(), in_lists[k].end());
   SymDev& d = p->symd;
   d.npairs = static_cast<int64_t>(po.size());
   d.nitems = static_cast<int64_t>(item_ebox.size());
   d.nebox = E;
+  d.ngroups = static_cast<int64_t>(groups.size());
   d.yslots = yoff;
   d.zslots = zoff;
   d.max_box = max_box;
   CHK(upload(p, &d.ebox, ebox));
-  CHK(upload(p, &d.ebox_of_box, ebox_of_box));
-  CHK(upload(p, &d.box_of_point, box_of_point));
   CHK(upload(p, &d.pair_ebox_o, po));
   CHK(upload(p, &d.pair_ebox_s, ps));
   CHK(upload(p, &d.pair_voff, pvoff));
   CHK(upload(p, &d.pair_stride, pstride));
-  CHK(upload(p, &d.pair_zoff, pzoff));
+  CHK(upload(p, &d.groups, groups));
   CHK(upload(p, &d.item_ebox, item_ebox));
-  CHK(upload(p, &d.item_pbeg, item_pbeg));
-  CHK(upload(p, &d.item_pend, item_pend));
+  CHK(upload(p, &d.item_order, item_order));
+  CHK(upload(p, &d.item_gbeg, item_gbeg));
   CHK(upload(p, &d.item_yoff, item_yoff));
   CHK(upload(p, &d.ebox_item_beg, ebox_item_beg));
-  CHK(upload(p, &d.in_beg, in_beg));
+  CHK(upload(p, &d.in_ptr, in_ptr));
+  CHK(upload(p, &d.in_base, in_base));
   p->sym_nvals = voff;
   unsigned char* v = nullptr;
   CHK(dalloc(p, &v, static_cast<size_t>(voff) * (p->complex_kernel ? 16 : 8)));
@@ -649,8 +695,9 @@ int build_sym(fftpim_plan_s* p, const std::vector<int32_t>& start, const double*
   HIPCHK(hipStreamSynchronize(st));
   HIPCHK(hipGetLastError());
   if (std::getenv("FFTPIM_LOG"))
-    std::fprintf(stderr, "fftpim plan: symmetric blocks: %lld boxes, %lld pairs, %lld values, max box %d\n",
-                 static_cast<long long>(E), static_cast<long long>(d.npairs), static_cast<long long>(voff), max_box);
+    std::fprintf(stderr, "fftpim plan: symmetric blocks: %lld boxes, %lld pairs, %lld groups, %lld values, max box %d\n",
+                 static_cast<long long>(E), static_cast<long long>(d.npairs), static_cast<long long>(d.ngroups),
+                 static_cast<long long>(voff), max_box);
   return FFTPIM_OK;
 }
 

@@ -120,18 +120,40 @@ __host__ __device__ inline double basis_num(int k, double u) {
   return num;
 }
 
+// In-cell correction blocks (one per unordered pair of non-empty boxes).
+// The pairs (B, B') of one box B are cut into lane groups: consecutive pairs
+// whose columns fit one wavefront (a pair wider than 64 columns is cut into
+// column chunks).  A group's blocks are stored row-interleaved (row r at
+// voff + r * stride), and its columns map onto at most four runs of
+// consecutive source points (boxes that follow each other in box order hold
+// consecutive points after the box sort).
+// Column-partial runs start on, and are padded to, whole 64-byte segments
+// (kSymZAlign complex doubles): partial-segment writes cost a read-modify-write.
+constexpr int kSymZAlign = 4;
+
+struct alignas(16) SymGroup {
+  int64_t voff;         // value of row 0, column 0
+  int64_t zoff;         // column-partial slot of column 0 (columns contiguous)
+  int32_t n0[4];        // first source point of each column run
+  int32_t end[4];       // end column of each run (cumulative); unused runs: 64
+  int32_t cum;          // columns (<= 64)
+  int32_t stride;       // row stride of the values
+  int32_t diag_lo, diag_hi;  // columns of the diagonal block B' = B (empty: lo == hi)
+};
+
 // Device pointers and sizes of the symmetric in-cell correction structure
 // (mirrors the kernel-side SymArgs).
 struct SymDev {
-  int64_t npairs = 0, nitems = 0, nebox = 0, yslots = 0, zslots = 0;
+  int64_t npairs = 0, nitems = 0, nebox = 0, ngroups = 0, yslots = 0, zslots = 0;
   int max_box = 0;
-  int32_t *ebox = nullptr, *ebox_of_box = nullptr, *box_of_point = nullptr;
+  int32_t* ebox = nullptr;
   int32_t *pair_ebox_o = nullptr, *pair_ebox_s = nullptr;
-  int64_t *pair_voff = nullptr, *pair_zoff = nullptr, *pair_stride = nullptr;
-  int32_t* item_ebox = nullptr;
-  int64_t *item_pbeg = nullptr, *item_pend = nullptr, *item_yoff = nullptr;
+  int64_t *pair_voff = nullptr, *pair_stride = nullptr;
+  SymGroup* groups = nullptr;
+  int32_t *item_ebox = nullptr, *item_order = nullptr;
+  int64_t *item_gbeg = nullptr, *item_yoff = nullptr;
   int32_t* ebox_item_beg = nullptr;
-  int64_t* in_beg = nullptr;
+  int64_t *in_ptr = nullptr, *in_base = nullptr;
 };
 
 struct DevBuf {

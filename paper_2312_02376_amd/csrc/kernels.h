@@ -58,31 +58,29 @@ struct CorrArgs {
 };
 
 // In-cell correction stored once per unordered pair of non-empty near-grid
-// boxes ("ebox" = index into the list of non-empty boxes).
+// boxes ("ebox" = index into the list of non-empty boxes); see SymGroup.
 struct SymArgs {
   int64_t N;
   int nb[3];
   int R, W;             // g0 table geometry (as in CorrArgs)
   double k0;
   int max_box;          // largest point count of a box
-  int64_t npairs, nitems;
+  int64_t npairs, nitems, nebox;
   const int32_t* box_start;      // [nb^3 + 1]
   const int32_t* ebox;           // [E] box id of each non-empty box
-  const int32_t* ebox_of_box;    // [nb^3] ebox index or -1
-  const int32_t* box_of_point;   // [N]
-  const int32_t* pair_ebox_o;    // [npairs] observer-side box (B)
+  const int32_t* pair_ebox_o;    // [npairs] observer-side box (B)     (plan-time fill)
   const int32_t* pair_ebox_s;    // [npairs] source-side box (B' >= B)
   const int64_t* pair_voff;      // [npairs] value of row 0, column 0 of the block
-  const int64_t* pair_stride;    // [npairs] row stride (width of the pair's lane group)
-  const int64_t* pair_zoff;      // [npairs] first point slot of the column partials
-  const int32_t* item_ebox;      // [nitems]
-  const int64_t* item_pbeg;      // [nitems] pair range of the item
-  const int64_t* item_pend;
+  const int64_t* pair_stride;    // [npairs] row stride
+  const SymGroup* groups;        // lane groups, items' groups consecutive
+  const int32_t* item_order;     // [nitems] launch order of the items (largest first)
+  const int32_t* item_ebox;      // [nitems] box of each work item
+  const int64_t* item_gbeg;      // [nitems + 1] group range of each item
   const int64_t* item_yoff;      // [nitems] first point slot of the row partials
   const int32_t* ebox_item_beg;  // [E + 1] items of each box
-  const int64_t* in_beg;         // [E + 1] slots of the column partials sent to each box
-                                 // (consecutive groups of n_B slots, senders in box order)
-  int64_t nebox;                 // E
+  const int64_t* in_ptr;         // [E + 1] senders of column partials to each box ...
+  const int64_t* in_base;        // ... and the slot of the box's first point in each
+                                 //     sender's partials (senders in box order)
 };
 
 struct FarArgs {

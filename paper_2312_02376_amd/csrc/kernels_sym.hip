@@ -8,13 +8,13 @@
 // conj(X conj(v)), so the same values serve the adjoint.  Close images (i != 0)
 // are not symmetric under a phase shift and stay in a separate CSR.
 //
-// Apply: one wavefront per work item (a box and a run of its upper pairs)
-// reads every block once, lanes over the block's columns: the column sums
+// Apply: one wavefront per work item (a box and a run of its lane groups)
+// reads every block once, lanes over the blocks' columns: the column sums
 // X^T x_B (for the partner box) accumulate in registers, the row sums X x_B'
 // come from a register reduce-scatter across the wavefront.  Row sums go to
-// per-item partials, column sums to per-pair partials; a second kernel adds,
-// for every point, its box's item partials and the column partials addressed
-// to its box, in a fixed order (no atomics).
+// per-item partials, column sums to per-group partials; a second kernel adds,
+// for every box, its items' partials and the column partials addressed to
+// it, in a fixed order (no atomics).
 #include "kernels.h"
 
 namespace fftpim {
@@ -138,19 +138,17 @@ __device__ inline double wave_reduce_scatter8(double v[8], int lane) {
   return s;
 }
 
-// One wavefront per item.  All pairs of an item share the observer box B, so
-// consecutive pairs are laid side by side across the 64 lanes (a lane owns
-// one column of one pair's block; the plan stores such a group's blocks
-// interleaved row by row with the same grouping rule, so a row of the group
-// is one contiguous load); eight rows of values are loaded back to
-// back, each lane accumulates its column sum (X^T x_B, for the partner box)
-// in registers, and the row sums (X x_B' over all pairs of the group) come
-// from a register reduce-scatter.  A pair with more than 64 columns is
-// processed alone in column chunks.  LDS holds x_B and the row accumulators.
+// One wavefront per work item (a box B and a run of its lane groups).  A lane
+// owns one column of the group; eight rows of values are loaded back to back,
+// each lane accumulates its column sum (X^T x_B, sent to the partner box) in
+// registers, and the row sums (X x_B' over the group's pairs) come from a
+// register reduce-scatter.  The group record alone gives every address, so
+// the value and source loads of a group issue without waiting on other
+// tables.  LDS holds x_B and the row accumulators.
 template <typename R, bool CPLX>
-__device__ inline void sym_rows(const SymArgs& a, const double* __restrict__ vr, const cplx<double>* __restrict__ vc,
+__device__ inline void sym_rows(const double* __restrict__ vr, const cplx<double>* __restrict__ vc,
                                 const cplx<double>* xb, cplx<double>* yacc, int nB, int P, int p, int lane, bool act,
-                                int64_t voff, int64_t stride, int c, double xsr, double xsi, double& zr, double& zi) {
+                                int64_t voff, int64_t stride, double xsr, double xsi, double& zr, double& zi) {
   const int krow = ((lane >> 5) & 1) * 4 + ((lane >> 4) & 1) * 2 + ((lane >> 3) & 1);
   for (int r0 = 0; r0 < nB; r0 += 8) {
     double wr[8], wi[8];
@@ -159,14 +157,14 @@ __device__ inline void sym_rows(const SymArgs& a, const double* __restrict__ vr,
       wr[k] = 0.0;
       wi[k] = 0.0;
       if (act && r0 + k < nB) {
-        // a group's blocks are interleaved row by row: one contiguous load per row
-        const int64_t idx = voff + static_cast<int64_t>(r0 + k) * stride + c;
+        const int64_t idx = voff + static_cast<int64_t>(r0 + k) * stride + lane;
+        // the values are streamed once per apply: nontemporal loads keep
+        // them from displacing reused data in the caches
         if (CPLX) {
-          const cplx<double> w = vc[idx];
-          wr[k] = w.x;
-          wi[k] = w.y;
+          wr[k] = __builtin_nontemporal_load(reinterpret_cast<const double*>(vc + idx));
+          wi[k] = __builtin_nontemporal_load(reinterpret_cast<const double*>(vc + idx) + 1);
         } else {
-          wr[k] = vr[idx];
+          wr[k] = __builtin_nontemporal_load(vr + idx);
         }
       }
     }
@@ -193,14 +191,14 @@ __device__ inline void sym_rows(const SymArgs& a, const double* __restrict__ vr,
 }
 
 template <typename R, bool CPLX>
-__global__ void __launch_bounds__(64) k_sym_apply(SymArgs a, const void* __restrict__ vals,
-                                                  const cplx<R>* __restrict__ x, int P, int conj_in,
-                                                  cplx<double>* __restrict__ ypart, cplx<double>* __restrict__ zpart) {
+__global__ void __launch_bounds__(64) k_sym_apply(SymArgs a, const SymGroup* __restrict__ groups,
+                                                  const void* __restrict__ vals, const cplx<R>* __restrict__ x, int P,
+                                                  int conj_in, cplx<double>* __restrict__ ypart,
+                                                  cplx<double>* __restrict__ zpart) {
   extern __shared__ unsigned char lds_raw[];
-  const int item = blockIdx.x;
+  const int item = a.item_order[blockIdx.x];
   const int lane = threadIdx.x;
-  const int kb = a.item_ebox[item];
-  const int B = a.ebox[kb];
+  const int B = a.ebox[a.item_ebox[item]];
   const int m0 = a.box_start[B], nB = a.box_start[B + 1] - m0;
   cplx<double>* xb = reinterpret_cast<cplx<double>*>(lds_raw);          // [nB][P]
   cplx<double>* yacc = xb + static_cast<int64_t>(a.max_box) * P;         // [nB][P]
@@ -213,60 +211,26 @@ __global__ void __launch_bounds__(64) k_sym_apply(SymArgs a, const void* __restr
   __syncthreads();
   const double* vr = static_cast<const double*>(vals);
   const cplx<double>* vc = static_cast<const cplx<double>*>(vals);
-  const int64_t pend = a.item_pend[item];
-  for (int64_t pr = a.item_pbeg[item]; pr < pend;) {
-    // group consecutive pairs while their columns fit the 64 lanes
-    int cum = 0;
-    int64_t pg = pr, mine = -1;
-    int my_c = 0;
-    while (pg < pend) {
-      const int Bj = a.ebox[a.pair_ebox_s[pg]];
-      const int nj = a.box_start[Bj + 1] - a.box_start[Bj];
-      if (cum > 0 && cum + nj > 64) break;
-      if (lane >= cum && lane < cum + nj) {
-        mine = pg;
-        my_c = lane - cum;
-      }
-      cum += nj;
-      ++pg;
-      if (cum >= 64) break;
+  const int64_t gend = a.item_gbeg[item + 1];
+  for (int64_t gi = a.item_gbeg[item]; gi < gend; ++gi) {
+    // the record alone gives every address of the group (read through the
+    // scalar cache: the table is read-only here)
+    const SymGroup g = groups[gi];
+    const bool act = lane < g.cum;
+    // source point of this lane's column
+    int n = g.n0[0] + lane;
+    if (lane >= g.end[0]) n = g.n0[1] + lane - g.end[0];
+    if (lane >= g.end[1]) n = g.n0[2] + lane - g.end[1];
+    if (lane >= g.end[2]) n = g.n0[3] + lane - g.end[2];
+    for (int p = 0; p < P; ++p) {
+      double xsr = 0.0, xsi = 0.0, zr = 0.0, zi = 0.0;
+      if (act) load_planes<R>(x, n, P, p, conj_in, xsr, xsi);
+      sym_rows<R, CPLX>(vr, vc, xb, yacc, nB, P, p, lane, act, g.voff, g.stride, xsr, xsi, zr, zi);
+      // the run is written whole, padded to 64-byte segments (padding and
+      // diagonal-block columns are never read)
+      if (lane < (g.cum + kSymZAlign - 1) / kSymZAlign * kSymZAlign)
+        zpart[(g.zoff + lane) * P + p] = cmake<double>(zr, zi);
     }
-    if (cum <= 64) {
-      const bool act = mine >= 0;
-      int n0 = 0;
-      int64_t voff = 0;
-      bool diag = true;
-      if (act) {
-        const int kbp = a.pair_ebox_s[mine];
-        n0 = a.box_start[a.ebox[kbp]];
-        voff = a.pair_voff[mine];
-        diag = kbp == kb;
-      }
-      for (int p = 0; p < P; ++p) {
-        double xsr = 0.0, xsi = 0.0, zr = 0.0, zi = 0.0;
-        if (act) load_planes<R>(x, n0 + my_c, P, p, conj_in, xsr, xsi);
-        sym_rows<R, CPLX>(a, vr, vc, xb, yacc, nB, P, p, lane, act, voff, cum, my_c, xsr, xsi, zr, zi);
-        if (act && !diag) zpart[(a.pair_zoff[mine] + my_c) * P + p] = cmake<double>(zr, zi);
-      }
-    } else {
-      // one pair wider than the wavefront
-      const int kbp = a.pair_ebox_s[pr];
-      const int Bp = a.ebox[kbp];
-      const int n0 = a.box_start[Bp], nBp = a.box_start[Bp + 1] - n0;
-      const int64_t voff = a.pair_voff[pr];
-      const bool diag = kbp == kb;
-      for (int p = 0; p < P; ++p) {
-        for (int c0 = 0; c0 < nBp; c0 += 64) {
-          const int c = c0 + lane;
-          const bool act = c < nBp;
-          double xsr = 0.0, xsi = 0.0, zr = 0.0, zi = 0.0;
-          if (act) load_planes<R>(x, n0 + c, P, p, conj_in, xsr, xsi);
-          sym_rows<R, CPLX>(a, vr, vc, xb, yacc, nB, P, p, lane, act, voff, nBp, c, xsr, xsi, zr, zi);
-          if (act && !diag) zpart[(a.pair_zoff[pr] + c) * P + p] = cmake<double>(zr, zi);
-        }
-      }
-    }
-    pr = pg;
   }
   __syncthreads();
   const int64_t yoff = a.item_yoff[item];
@@ -293,9 +257,9 @@ __global__ void __launch_bounds__(kGatherThreads) k_sym_gather(SymArgs a, const 
   const int m0 = a.box_start[B], nB = a.box_start[B + 1] - m0;
   const int it0 = a.ebox_item_beg[kb], nit = a.ebox_item_beg[kb + 1] - it0;
   const int64_t y0 = a.item_yoff[it0] * P;
-  const int64_t z0 = a.in_beg[kb] * P;
+  const int64_t ip0 = a.in_ptr[kb];
   const int run = nB * P;
-  const int64_t nruns = nit + (a.in_beg[kb + 1] - a.in_beg[kb]) / nB;
+  const int64_t nruns = nit + (a.in_ptr[kb + 1] - ip0);
   const int S = run <= kGatherThreads ? kGatherThreads / run : 1;
   for (int e0 = 0; e0 < run; e0 += kGatherThreads) {
     const int s = S > 1 ? t / run : 0;
@@ -304,7 +268,7 @@ __global__ void __launch_bounds__(kGatherThreads) k_sym_gather(SymArgs a, const 
     double xr = 0.0, xi = 0.0;
     if (act) {
       for (int64_t k = s; k < nruns; k += S) {
-        const cplx<double> v = k < nit ? ypart[y0 + k * run + e] : zpart[z0 + (k - nit) * run + e];
+        const cplx<double> v = k < nit ? ypart[y0 + k * run + e] : zpart[a.in_base[ip0 + k - nit] * P + e];
         xr += v.x;
         xi += v.y;
       }
@@ -368,11 +332,11 @@ void launch_sym_apply(bool cplx_vals, const SymArgs& a, const void* vals, const 
   cplx<double>* yp = static_cast<cplx<double>*>(ypart);
   cplx<double>* zp = static_cast<cplx<double>*>(zpart);
   if (cplx_vals)
-    hipLaunchKernelGGL((k_sym_apply<R, true>), dim3(static_cast<unsigned>(a.nitems)), dim3(64), lds, st, a, vals, xx,
-                       P, conj_io ? 1 : 0, yp, zp);
+    hipLaunchKernelGGL((k_sym_apply<R, true>), dim3(static_cast<unsigned>(a.nitems)), dim3(64), lds, st, a, a.groups,
+                       vals, xx, P, conj_io ? 1 : 0, yp, zp);
   else
-    hipLaunchKernelGGL((k_sym_apply<R, false>), dim3(static_cast<unsigned>(a.nitems)), dim3(64), lds, st, a, vals,
-                       xx, P, conj_io ? 1 : 0, yp, zp);
+    hipLaunchKernelGGL((k_sym_apply<R, false>), dim3(static_cast<unsigned>(a.nitems)), dim3(64), lds, st, a, a.groups,
+                       vals, xx, P, conj_io ? 1 : 0, yp, zp);
   hipLaunchKernelGGL((k_sym_gather<R>), dim3(static_cast<unsigned>(a.nebox)), dim3(kGatherThreads), 0, st, a, yp, zp, P,
                      conj_io ? 1 : 0, static_cast<cplx<R>*>(u), accumulate ? 1 : 0);
 }
