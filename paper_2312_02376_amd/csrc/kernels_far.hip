@@ -159,6 +159,99 @@ __global__ void __launch_bounds__(256) k_far_apply(FarArgs f, const cplx<R>* __r
   }
 }
 
+// The same grid sum on the matrix cores once several planes are batched (a
+// GEMM, Eq. (8) applied to every right-hand side).  A wavefront owns a 16 x 16
+// tile of (grid nodes i) x (planes p) and walks its split of j four at a time
+// with 16x16x4 MFMA steps; the K fragment is generated from the offset table
+// (lane l supplies K(i0 + l % 16, j + l / 16)), the amplitude fragment is
+// in[p0 + l % 16][j + l / 16].  A complex product is four real MFMAs:
+// Re += Kr Qr - Ki Qi, Im += Kr Qi + Ki Qr.  Accumulator element r of lane l
+// holds column l % 16 and row 4 (l / 16) + r (FP32) or 4 r + l / 16 (FP64);
+// both layouts were read off the hardware with one-hot operands.
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+
+template <typename R>
+struct MfmaAcc;
+template <>
+struct MfmaAcc<float> {
+  typedef mfma_f4 T;
+  static __device__ inline T step(float a, float b, T c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  static __device__ inline int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+template <>
+struct MfmaAcc<double> {
+  typedef mfma_d4 T;
+  static __device__ inline T step(double a, double b, T c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  static __device__ inline int row(int lane, int r) { return 4 * r + (lane >> 4); }
+};
+
+constexpr int kFarMfmaWaves = 4;  // row tiles per block
+
+template <typename R>
+__global__ void __launch_bounds__(64 * kFarMfmaWaves) k_far_apply_mfma(FarArgs f, const cplx<R>* __restrict__ table,
+                                                                       const cplx<R>* __restrict__ in,
+                                                                       cplx<R>* __restrict__ part, int P, int adjoint,
+                                                                       int64_t jlen) {
+  typedef typename MfmaAcc<R>::T Acc;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t sy = 2 * f.nf[1] - 1, sz = 2 * f.nf[2] - 1;
+  const int64_t i0 = (static_cast<int64_t>(blockIdx.x) * kFarMfmaWaves + wave) * 16;
+  const int p0 = blockIdx.y * 16;
+  const int split = blockIdx.z;
+  const int64_t jbeg = split * jlen, jend = min<int64_t>(f.Ngf, jbeg + jlen);
+  // this lane's row of the K fragment and column (plane) of the amplitude fragment
+  const int64_t ia = i0 + (lane & 15);
+  const bool row_ok = ia < f.Ngf;
+  const int pb = p0 + (lane & 15);
+  const bool col_ok = pb < P;
+  const int kk = lane >> 4;
+  int64_t base_i = 0, off_i = 0;
+  if (row_ok) {
+    const int iz = static_cast<int>(ia % f.nf[2]);
+    const int iy = static_cast<int>((ia / f.nf[2]) % f.nf[1]);
+    const int ix = static_cast<int>(ia / (static_cast<int64_t>(f.nf[1]) * f.nf[2]));
+    base_i = ((ix + f.nf[0] - 1) * sy + iy + f.nf[1] - 1) * sz + iz + f.nf[2] - 1;
+    off_i = (ix * sy + iy) * sz + iz;
+  }
+  Acc accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
+  for (int64_t jc = jbeg; jc < jend; jc += 4) {
+    const int64_t j = jc + kk;
+    R kr = R(0), ki = R(0), qr = R(0), qi = R(0);
+    if (j < jend) {
+      const int jz = static_cast<int>(j % f.nf[2]);
+      const int jy = static_cast<int>((j / f.nf[2]) % f.nf[1]);
+      const int jx = static_cast<int>(j / (static_cast<int64_t>(f.nf[1]) * f.nf[2]));
+      if (row_ok) {
+        const int64_t t = adjoint ? (((jx + f.nf[0] - 1) * sy + jy + f.nf[1] - 1) * sz + jz + f.nf[2] - 1) - off_i
+                                  : base_i - ((jx * sy + jy) * sz + jz);
+        const cplx<R> kv = table[t];
+        kr = kv.x;
+        ki = adjoint ? -kv.y : kv.y;
+      }
+      if (col_ok) {
+        const cplx<R> qv = in[static_cast<int64_t>(pb) * f.Ngf + j];
+        qr = qv.x;
+        qi = qv.y;
+      }
+    }
+    accr = MfmaAcc<R>::step(kr, qr, accr);
+    accr = MfmaAcc<R>::step(-ki, qi, accr);
+    acci = MfmaAcc<R>::step(kr, qi, acci);
+    acci = MfmaAcc<R>::step(ki, qr, acci);
+  }
+  const int pc = p0 + (lane & 15);
+  if (pc < P) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t io = i0 + MfmaAcc<R>::row(lane, r);
+      if (io < f.Ngf)
+        part[(static_cast<int64_t>(split) * P + pc) * f.Ngf + io] = cmake<R>(accr[r], acci[r]);
+    }
+  }
+}
+
 template <typename R>
 __global__ void k_far_reduce(const cplx<R>* __restrict__ part, cplx<R>* __restrict__ out, int64_t n, int nsplit) {
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -240,9 +333,30 @@ int far_apply_splits(int64_t Ngf, int P) {
   return static_cast<int>(std::min<int64_t>(s, std::max<int64_t>(1, (Ngf + 255) / 256)));
 }
 
+// Planes at or above which the grid sum runs on the matrix cores.
+constexpr int kFarMfmaMinPlanes = 8;
+
 template <typename R>
 void launch_far_apply(const FarArgs& f, const void* table, const void* in, void* out, void* part, int P,
                       bool adjoint, hipStream_t st) {
+  if (P >= kFarMfmaMinPlanes) {
+    // split j so the launch has a few blocks per compute unit, within the
+    // part buffer's split capacity
+    const int64_t row_blocks = (f.Ngf + 16 * kFarMfmaWaves - 1) / (16 * kFarMfmaWaves);
+    const int64_t col_blocks = (P + 15) / 16;
+    int64_t ns = std::max<int64_t>(1, 1024 / std::max<int64_t>(1, row_blocks * col_blocks));
+    ns = std::min<int64_t>(ns, std::min<int64_t>(64, std::max<int64_t>(1, (f.Ngf + 255) / 256)));
+    const int64_t jlen = (((f.Ngf + ns - 1) / ns + 3) / 4) * 4;
+    const int nsplit = static_cast<int>((f.Ngf + jlen - 1) / jlen);
+    dim3 gr(static_cast<unsigned>(row_blocks), static_cast<unsigned>(col_blocks), static_cast<unsigned>(nsplit));
+    hipLaunchKernelGGL((k_far_apply_mfma<R>), gr, dim3(64 * kFarMfmaWaves), 0, st, f,
+                       static_cast<const cplx<R>*>(table), static_cast<const cplx<R>*>(in),
+                       static_cast<cplx<R>*>(part), P, adjoint ? 1 : 0, jlen);
+    const int64_t n = f.Ngf * P;
+    hipLaunchKernelGGL((k_far_reduce<R>), dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st,
+                       static_cast<const cplx<R>*>(part), static_cast<cplx<R>*>(out), n, nsplit);
+    return;
+  }
   const unsigned nb = static_cast<unsigned>((f.Ngf + 255) / 256);
   const int ns = far_apply_splits(f.Ngf, P);
   const int64_t jlen = (((f.Ngf + ns - 1) / ns + 255) / 256) * 256;
