@@ -303,9 +303,11 @@ int run_apply(fftpim_plan_s* p, int parts, bool adjoint, const void* in, void* o
         launch_sym_apply<R>(p->complex_kernel, sym_args(p), p->sym_vals, p->q_int, P, adjoint, p->sym_ypart,
                             p->sym_zpart, p->u_corr, false, sc);
         if (p->nnz > 0)
-          launch_corr_spmv<R>(p->complex_kernel, p->rowptr, p->col, v, N, p->q_int, P, p->u_corr, true, sc);
+          launch_corr_spmv<R>(p->complex_kernel, p->rowptr, p->col, v, N, p->corr_order, p->corr_slots, p->q_int, P,
+                              p->u_corr, true, sc);
       } else {
-        launch_corr_spmv<R>(p->complex_kernel, p->rowptr, p->col, v, N, p->q_int, P, p->u_corr, false, sc);
+        launch_corr_spmv<R>(p->complex_kernel, p->rowptr, p->col, v, N, p->corr_order, p->corr_slots, p->q_int, P,
+                            p->u_corr, false, sc);
       }
     }
     HIPCHK(hipEventRecord(p->ev_corr, sc));
@@ -701,6 +703,46 @@ int build_sym(fftpim_plan_s* p, const std::vector<int32_t>& start, const double*
   return FFTPIM_OK;
 }
 
+// Processing order of the CSR rows: tiles of kRowTile^3 near-grid boxes, each
+// tile's rows handed to one XCD (workgroups are dispatched to the XCDs round
+// robin, so slot block b runs on XCD b mod kXcds).  The rows of a tile share
+// most of their correction columns, so their amplitude gathers hit that XCD's
+// L2.  Tiles go, in tile order, to the least loaded XCD.
+constexpr int kRowTile = 8, kXcds = 8, kRowsPerBlock = 4;
+
+void build_row_order(const std::vector<int32_t>& start, const int nb[3], int64_t N, std::vector<int32_t>& order) {
+  int nt[3];
+  for (int c = 0; c < 3; ++c) nt[c] = (nb[c] + kRowTile - 1) / kRowTile;
+  std::vector<std::vector<int32_t>> seq(kXcds);
+  std::vector<int64_t> load(kXcds, 0);
+  std::vector<int32_t> rows;
+  for (int tx = 0; tx < nt[0]; ++tx)
+    for (int ty = 0; ty < nt[1]; ++ty)
+      for (int tz = 0; tz < nt[2]; ++tz) {
+        rows.clear();
+        for (int bx = tx * kRowTile; bx < std::min(nb[0], (tx + 1) * kRowTile); ++bx)
+          for (int by = ty * kRowTile; by < std::min(nb[1], (ty + 1) * kRowTile); ++by)
+            for (int bz = tz * kRowTile; bz < std::min(nb[2], (tz + 1) * kRowTile); ++bz) {
+              const int64_t b = (static_cast<int64_t>(bx) * nb[1] + by) * nb[2] + bz;
+              for (int32_t m = start[b]; m < start[b + 1]; ++m) rows.push_back(m);
+            }
+        if (rows.empty()) continue;
+        const int x = static_cast<int>(std::min_element(load.begin(), load.end()) - load.begin());
+        seq[x].insert(seq[x].end(), rows.begin(), rows.end());
+        load[x] += static_cast<int64_t>(rows.size());
+      }
+  int64_t maxlen = 0;
+  for (const auto& s : seq) maxlen = std::max<int64_t>(maxlen, static_cast<int64_t>(s.size()));
+  const int64_t per_xcd = (maxlen + kRowsPerBlock - 1) / kRowsPerBlock;
+  order.assign(static_cast<size_t>(per_xcd * kXcds * kRowsPerBlock), -1);
+  for (int x = 0; x < kXcds; ++x)
+    for (int64_t i = 0; i < static_cast<int64_t>(seq[x].size()); ++i) {
+      const int64_t blk = (i / kRowsPerBlock) * kXcds + x;
+      order[static_cast<size_t>(blk * kRowsPerBlock + i % kRowsPerBlock)] = seq[x][static_cast<size_t>(i)];
+    }
+  (void)N;
+}
+
 int build_correction(fftpim_plan_s* p, const std::vector<int32_t>& start, const double* pos3_dev,
                      hipStream_t st) {
   const int q = p->ng.q, rc = p->prm.corr_radius, id = p->prm.n_images;
@@ -791,6 +833,12 @@ int build_correction(fftpim_plan_s* p, const std::vector<int32_t>& start, const 
   if (std::getenv("FFTPIM_LOG"))
     std::fprintf(stderr, "fftpim plan: correction nnz %lld\n", static_cast<long long>(p->nnz));
   CHK(upload(p, &p->rowptr, rowptr));
+  {
+    std::vector<int32_t> order;
+    build_row_order(start, p->nb, p->N, order);
+    p->corr_slots = static_cast<int64_t>(order.size());
+    CHK(upload(p, &p->corr_order, order));
+  }
   CHK(dalloc(p, &p->col, p->nnz));
   const bool cv = p->complex_kernel;
   const size_t vb = cv ? 16 : 8;

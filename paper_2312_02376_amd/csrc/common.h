@@ -213,6 +213,8 @@ struct fftpim_plan_s {
 
   // correction (FP64 values)
   int64_t* rowptr = nullptr;
+  int32_t* corr_order = nullptr;   // [corr_slots] row of each wavefront slot (-1: idle)
+  int64_t corr_slots = 0;
   int32_t* col = nullptr;
   void* val = nullptr;            // double or complex double
   void* val_adj = nullptr;        // Helmholtz only: values of C^H on the same pattern

@@ -134,8 +134,11 @@ int launch_corr_fill(int q, bool cplx_vals, bool adj, const CorrArgs& a, const i
                      const double* pos3, const int32_t* box_start, const void* g0tab, const int64_t* rowptr,
                      int32_t* col, void* val, void* val_adj, hipStream_t st);
 template <typename R>
+// order (optional, nslots entries, -1 = idle slot): the row processed by each
+// wavefront slot, grouped so that a workgroup's rows are spatially close.
 void launch_corr_spmv(bool cplx_vals, const int64_t* rowptr, const int32_t* col, const void* val, int64_t N,
-                      const void* qint, int P, void* uint, bool accumulate, hipStream_t st);
+                      const int32_t* order, int64_t nslots, const void* qint, int P, void* uint, bool accumulate,
+                      hipStream_t st);
 int launch_sym_fill(int q, bool cplx_vals, const SymArgs& a, const double* w3, const double* pos3,
                     const void* g0tab, void* vals, hipStream_t st);
 template <typename R>

@@ -201,11 +201,13 @@ template <typename R, bool CPLX, int PB>
 __global__ void __launch_bounds__(256) k_corr_spmv(const int64_t* __restrict__ rowptr,
                                                    const int32_t* __restrict__ col,
                                                    const void* __restrict__ val_v, int64_t N,
+                                                   const int32_t* __restrict__ order,
                                                    const cplx<R>* __restrict__ qint, int P,
                                                    cplx<R>* __restrict__ uint, int accumulate) {
   const int lane = threadIdx.x & 63;
-  const int64_t row = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (row >= N) return;
+  const int64_t slot = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int64_t row = order != nullptr ? order[slot] : slot;
+  if (row < 0 || row >= N) return;
   const int p0 = blockIdx.y * PB;
   double ar[PB], ai[PB], br[PB], bi[PB];
 #pragma unroll
@@ -273,34 +275,54 @@ __global__ void __launch_bounds__(256) k_corr_spmv(const int64_t* __restrict__ r
 
 // Many right-hand sides: the 64 lanes of a wavefront cover LP planes x
 // (64 / LP) entries of one row, so every CSR entry is read once per row and
-// the amplitudes of one source are one contiguous, coalesced load.  Partial
-// sums over the entry slots are combined with lane shuffles in a fixed order.
+// the amplitudes of one source are one contiguous, coalesced load.  Four
+// entries per lane slot are in flight at once.  Partial sums over the entry
+// slots are combined with lane shuffles in a fixed order.
 template <typename R, bool CPLX, int LP>
 __global__ void __launch_bounds__(256) k_corr_spmm(const int64_t* __restrict__ rowptr,
                                                    const int32_t* __restrict__ col,
                                                    const void* __restrict__ val_v, int64_t N,
+                                                   const int32_t* __restrict__ order,
                                                    const cplx<R>* __restrict__ qint, int P,
                                                    cplx<R>* __restrict__ uint, int accumulate) {
   constexpr int E = 64 / LP;
+  constexpr int U = 4;
   const int lane = threadIdx.x & 63;
   const int e = lane / LP, pl = lane % LP;
-  const int64_t row = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (row >= N) return;
+  const int64_t slot = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int64_t row = order != nullptr ? order[slot] : slot;
+  if (row < 0 || row >= N) return;
   const int64_t j0 = rowptr[row], j1 = rowptr[row + 1];
   for (int pc = 0; pc < P; pc += LP) {
     const int p = pc + pl;
+    const bool pok = p < P;
     double ar = 0.0, ai = 0.0;
-    for (int64_t j = j0 + e; j < j1; j += E) {
-      const int n = col[j];
-      double vr, vi = 0.0;
-      if (CPLX) {
-        const cplx<double> v = static_cast<const cplx<double>*>(val_v)[j];
-        vr = v.x;
-        vi = v.y;
-      } else {
-        vr = static_cast<const double*>(val_v)[j];
+    int64_t j = j0 + e;
+    for (; j + (U - 1) * E < j1; j += U * E) {
+      int n[U];
+      double vr[U], vi[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        n[u] = __builtin_nontemporal_load(col + j + u * E);
+        load_val<CPLX>(val_v, j + u * E, vr[u], vi[u]);
       }
-      if (p < P) {
+      if (pok) {
+        cplx<R> q[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) q[u] = qint[static_cast<int64_t>(n[u]) * P + p];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const double qr = static_cast<double>(q[u].x), qi = static_cast<double>(q[u].y);
+          ar += vr[u] * qr - vi[u] * qi;
+          ai += vr[u] * qi + vi[u] * qr;
+        }
+      }
+    }
+    for (; j < j1; j += E) {
+      const int n = col[j];
+      double vr, vi;
+      load_val<CPLX>(val_v, j, vr, vi);
+      if (pok) {
         const cplx<R> q = qint[static_cast<int64_t>(n) * P + p];
         const double qr = static_cast<double>(q.x), qi = static_cast<double>(q.y);
         ar += vr * qr - vi * qi;
@@ -311,7 +333,7 @@ __global__ void __launch_bounds__(256) k_corr_spmm(const int64_t* __restrict__ r
       ar += __shfl_xor(ar, off, 64);
       ai += __shfl_xor(ai, off, 64);
     }
-    if (e == 0 && p < P) {
+    if (e == 0 && pok) {
       cplx<R> o = cmake<R>(static_cast<R>(ar), static_cast<R>(ai));
       if (accumulate) {
         const cplx<R> prev = uint[row * P + p];
@@ -370,18 +392,19 @@ int launch_corr_fill(int q, bool cplx_vals, bool adj, const CorrArgs& a, const i
 
 template <typename R>
 void launch_corr_spmv(bool cplx_vals, const int64_t* rowptr, const int32_t* col, const void* val, int64_t N,
-                      const void* qint, int P, void* uint, bool accumulate, hipStream_t st) {
+                      const int32_t* order, int64_t nslots, const void* qint, int P, void* uint, bool accumulate,
+                      hipStream_t st) {
   const int acc = accumulate ? 1 : 0;
   const cplx<R>* q = static_cast<const cplx<R>*>(qint);
   cplx<R>* u = static_cast<cplx<R>*>(uint);
-  unsigned nb = static_cast<unsigned>((N + 3) / 4);
+  const unsigned nb = static_cast<unsigned>(((order != nullptr ? nslots : N) + 3) / 4);
   if (P > 4) {
 #define FFTPIM_SPMM(LPV)                                                                                   \
   do {                                                                                                     \
     if (cplx_vals)                                                                                         \
-      hipLaunchKernelGGL((k_corr_spmm<R, true, LPV>), dim3(nb), dim3(256), 0, st, rowptr, col, val, N, q, P, u, acc); \
+      hipLaunchKernelGGL((k_corr_spmm<R, true, LPV>), dim3(nb), dim3(256), 0, st, rowptr, col, val, N, order, q, P, u, acc); \
     else                                                                                                   \
-      hipLaunchKernelGGL((k_corr_spmm<R, false, LPV>), dim3(nb), dim3(256), 0, st, rowptr, col, val, N, q, P, u, acc); \
+      hipLaunchKernelGGL((k_corr_spmm<R, false, LPV>), dim3(nb), dim3(256), 0, st, rowptr, col, val, N, order, q, P, u, acc); \
   } while (0)
     if (P <= 8)
       FFTPIM_SPMM(8);
@@ -398,9 +421,9 @@ void launch_corr_spmv(bool cplx_vals, const int64_t* rowptr, const int32_t* col,
   do {                                                                                                     \
     dim3 gr(nb, (P + PBV - 1) / PBV);                                                                      \
     if (cplx_vals)                                                                                         \
-      hipLaunchKernelGGL((k_corr_spmv<R, true, PBV>), gr, dim3(256), 0, st, rowptr, col, val, N, q, P, u, acc); \
+      hipLaunchKernelGGL((k_corr_spmv<R, true, PBV>), gr, dim3(256), 0, st, rowptr, col, val, N, order, q, P, u, acc); \
     else                                                                                                   \
-      hipLaunchKernelGGL((k_corr_spmv<R, false, PBV>), gr, dim3(256), 0, st, rowptr, col, val, N, q, P, u, acc); \
+      hipLaunchKernelGGL((k_corr_spmv<R, false, PBV>), gr, dim3(256), 0, st, rowptr, col, val, N, order, q, P, u, acc); \
   } while (0)
   if (P >= 8)
     FFTPIM_SPMV(8);
@@ -413,9 +436,9 @@ void launch_corr_spmv(bool cplx_vals, const int64_t* rowptr, const int32_t* col,
 #undef FFTPIM_SPMV
 }
 
-template void launch_corr_spmv<double>(bool, const int64_t*, const int32_t*, const void*, int64_t, const void*,
-                                       int, void*, bool, hipStream_t);
-template void launch_corr_spmv<float>(bool, const int64_t*, const int32_t*, const void*, int64_t, const void*,
-                                      int, void*, bool, hipStream_t);
+template void launch_corr_spmv<double>(bool, const int64_t*, const int32_t*, const void*, int64_t, const int32_t*,
+                                       int64_t, const void*, int, void*, bool, hipStream_t);
+template void launch_corr_spmv<float>(bool, const int64_t*, const int32_t*, const void*, int64_t, const int32_t*,
+                                      int64_t, const void*, int, void*, bool, hipStream_t);
 
 }  // namespace fftpim

@@ -222,3 +222,14 @@ def test_symmetric_layout_dense_boxes_many_rhs():
         got = plan.apply_parts(qd, 2, adjoint=adjoint).cpu().numpy()
         want = (ref.adjoint if adjoint else ref.apply)(qv, parts=("near_corr",))
         assert rel(got, want) < 1e-11, adjoint
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_csr_layout(name):
+    # every corrected triple in one CSR (rows processed in tile order)
+    lat, ref, plan, qv = _setup(name, N=400, seed=23, corr_layout="csr")
+    qd = _to_dev(plan, qv)
+    for adjoint in (False, True):
+        got = plan.apply_parts(qd, 2, adjoint=adjoint).cpu().numpy()
+        want = (ref.adjoint if adjoint else ref.apply)(qv, parts=("near_corr",))
+        assert rel(got, want) < 1e-11, adjoint
