@@ -148,33 +148,42 @@ FftPassDesc pass_desc(int M, int n_in, int n_out, bool contig, int64_t nouter, i
   d.T = contig ? lines_per_block(M, esize, 1 << 20) : lines_per_block(M, esize, ncols);
   d.spec_line = 0;
   d.spec_col = 0;
+  d.spec_div = 1;
   return d;
 }
 
 template <typename R>
 void near_convolution(fftpim_plan_s* p, int P, bool adjoint, hipStream_t st) {
+  // grids are [x][y][z][P]: a pass along one axis sees outer x line x columns,
+  // the columns being the axes after it together with the planes
   const int nx = p->ng.n[0], ny = p->ng.n[1], nz = p->ng.n[2];
   const int Mx = p->M[0], My = p->M[1], Mz = p->M[2];
   const size_t es = sizeof(cplx<R>);
-  // z: grid0 [P*nx*ny][nz] -> bufA [P*nx*ny][Mz]
-  FftPassDesc dz = pass_desc(Mz, nz, Mz, true, static_cast<int64_t>(P) * nx * ny, 1, 1, nz, 1, Mz, es);
+  const int64_t xy = static_cast<int64_t>(nx) * ny;
+  // z: grid0 [nx*ny][nz][P] -> bufA [nx*ny][Mz][P]
+  FftPassDesc dz = P == 1 ? pass_desc(Mz, nz, Mz, true, xy, 1, 1, nz, 1, Mz, es)
+                          : pass_desc(Mz, nz, Mz, false, xy, P, P, static_cast<int64_t>(nz) * P, P,
+                                      static_cast<int64_t>(Mz) * P, es);
   launch_fft_pass<R>(0, p->grid0, p->bufA, dz, p->twiddle[2], nullptr, false, st);
-  // y: bufA [P*nx][ny][Mz] -> bufB [P*nx][My][Mz]
-  FftPassDesc dy = pass_desc(My, ny, My, false, static_cast<int64_t>(P) * nx, Mz, Mz,
-                             static_cast<int64_t>(ny) * Mz, Mz, static_cast<int64_t>(My) * Mz, es);
+  // y: bufA [nx][ny][Mz*P] -> bufB [nx][My][Mz*P]
+  const int64_t zc = static_cast<int64_t>(Mz) * P;
+  FftPassDesc dy = pass_desc(My, ny, My, false, nx, zc, zc, ny * zc, zc, My * zc, es);
   launch_fft_pass<R>(0, p->bufA, p->bufB, dy, p->twiddle[1], nullptr, false, st);
-  // x: in place on bufB [P][nx][My*Mz], fused spectrum multiply
-  const int64_t cols = static_cast<int64_t>(My) * Mz;
-  FftPassDesc dx = pass_desc(Mx, nx, nx, false, P, cols, cols, nx * cols, cols, nx * cols, es);
-  dx.spec_line = cols;
+  // x: in place on bufB [nx][My*Mz*P], fused spectrum multiply (one spectrum
+  // value per (y, z) serves all planes)
+  const int64_t cols = My * zc;
+  FftPassDesc dx = pass_desc(Mx, nx, nx, false, 1, cols, cols, nx * cols, cols, nx * cols, es);
+  dx.spec_line = static_cast<int64_t>(My) * Mz;
   dx.spec_col = 1;
+  dx.spec_div = P;
   launch_fft_pass<R>(2, p->bufB, p->bufB, dx, p->twiddle[0], p->near_hat, adjoint, st);
-  // inverse y: bufB [P*nx][My][Mz] -> bufA [P*nx][ny][Mz]
-  FftPassDesc iy = pass_desc(My, My, ny, false, static_cast<int64_t>(P) * nx, Mz, Mz,
-                             static_cast<int64_t>(My) * Mz, Mz, static_cast<int64_t>(ny) * Mz, es);
+  // inverse y: bufB [nx][My][Mz*P] -> bufA [nx][ny][Mz*P]
+  FftPassDesc iy = pass_desc(My, My, ny, false, nx, zc, zc, My * zc, zc, ny * zc, es);
   launch_fft_pass<R>(1, p->bufB, p->bufA, iy, p->twiddle[1], nullptr, false, st);
-  // inverse z: bufA [P*nx*ny][Mz] -> grid0 [P*nx*ny][nz]
-  FftPassDesc iz = pass_desc(Mz, Mz, nz, true, static_cast<int64_t>(P) * nx * ny, 1, 1, Mz, 1, nz, es);
+  // inverse z: bufA [nx*ny][Mz][P] -> grid0 [nx*ny][nz][P]
+  FftPassDesc iz = P == 1 ? pass_desc(Mz, Mz, nz, true, xy, 1, 1, Mz, 1, nz, es)
+                          : pass_desc(Mz, Mz, nz, false, xy, P, P, static_cast<int64_t>(Mz) * P, P,
+                                      static_cast<int64_t>(nz) * P, es);
   launch_fft_pass<R>(1, p->bufA, p->grid0, iz, p->twiddle[2], nullptr, false, st);
 }
 

@@ -19,7 +19,10 @@ struct GridArgs {
 // One batched 1D FFT pass.  The data is viewed as outer x line x column; the
 // transform runs along the line.  contig = 1: lines are contiguous (in_line
 // = 1) and a block takes T consecutive outer indices; contig = 0: a block takes
-// one outer index and T consecutive columns (coalesced across the block).
+// one outer index and T consecutive columns (coalesced across the block; the
+// last tile of a row of columns may be partial).  Grids keep the planes
+// innermost ([x][y][z][P]), so for batched planes every node is one
+// contiguous run of P values.
 struct FftPassDesc {
   int M, logM;         // transform length (power of 2)
   int n_in, n_out;     // nonzero inputs / outputs kept along the line
@@ -28,7 +31,8 @@ struct FftPassDesc {
   int64_t ncols, nouter;
   int64_t in_line, in_col, in_outer;
   int64_t out_line, out_col, out_outer;
-  int64_t spec_line, spec_col;  // spectrum strides (fused pass only)
+  int64_t spec_line, spec_col;  // spectrum strides (fused pass only) ...
+  int64_t spec_div;             // ... applied to column / spec_div (planes share a spectrum)
 };
 
 struct NearTableArgs {

@@ -76,8 +76,8 @@ __global__ void k_far_gather(FarArgs f, const cplx<R>* __restrict__ mom, int P, 
   constexpr int K = K1 * K1 * K1;
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= f.Ngf * P) return;
-  const int p = static_cast<int>(idx / f.Ngf);
-  const int64_t g = idx - static_cast<int64_t>(p) * f.Ngf;
+  const int64_t g = idx / P;
+  const int p = static_cast<int>(idx - g * P);
   const int gz = static_cast<int>(g % f.nf[2]);
   const int gy = static_cast<int>((g / f.nf[2]) % f.nf[1]);
   const int gx = static_cast<int>(g / (static_cast<int64_t>(f.nf[1]) * f.nf[2]));
@@ -91,10 +91,10 @@ __global__ void k_far_gather(FarArgs f, const cplx<R>* __restrict__ mom, int P, 
         ar += static_cast<double>(v.x);
         ai += static_cast<double>(v.y);
       }
-  grid[static_cast<int64_t>(p) * f.Ngf + g] = cmake<R>(static_cast<R>(ar), static_cast<R>(ai));
+  grid[g * P + p] = cmake<R>(static_cast<R>(ar), static_cast<R>(ai));
 }
 
-// part[s][p][i] = sum_{j in split s} K(i, j) in[p][j], with K(i, j) =
+// part[s][i][p] = sum_{j in split s} K(i, j) in[j][p], with K(i, j) =
 // table[base(i) - off(j)] (forward) or conj(table[base(j) - off(i)])
 // (conjugate transpose), base(i) = ((ix + nfx - 1) sy + iy + nfy - 1) sz +
 // iz + nfz - 1 and off(j) = (jx sy + jy) sz + jz indexing the (2 nf - 1)^3
@@ -132,7 +132,7 @@ __global__ void __launch_bounds__(256) k_far_apply(FarArgs f, const cplx<R>* __r
                                  : (jx * sy + jy) * sz + jz;
 #pragma unroll
       for (int pp = 0; pp < PB; ++pp)
-        sh[pp][threadIdx.x] = (p0 + pp < P) ? in[static_cast<int64_t>(p0 + pp) * f.Ngf + j] : cmake<R>(R(0), R(0));
+        sh[pp][threadIdx.x] = (p0 + pp < P) ? in[j * P + p0 + pp] : cmake<R>(R(0), R(0));
     }
     __syncthreads();
     const int cnt = static_cast<int>(min<int64_t>(256, jend - jc));
@@ -155,7 +155,7 @@ __global__ void __launch_bounds__(256) k_far_apply(FarArgs f, const cplx<R>* __r
 #pragma unroll
     for (int pp = 0; pp < PB; ++pp)
       if (p0 + pp < P)
-        part[(static_cast<int64_t>(split) * P + p0 + pp) * f.Ngf + i] = cmake<R>(ar[pp], ai[pp]);
+        part[(static_cast<int64_t>(split) * f.Ngf + i) * P + p0 + pp] = cmake<R>(ar[pp], ai[pp]);
   }
 }
 
@@ -164,7 +164,7 @@ __global__ void __launch_bounds__(256) k_far_apply(FarArgs f, const cplx<R>* __r
 // tile of (grid nodes i) x (planes p) and walks its split of j four at a time
 // with 16x16x4 MFMA steps; the K fragment is generated from the offset table
 // (lane l supplies K(i0 + l % 16, j + l / 16)), the amplitude fragment is
-// in[p0 + l % 16][j + l / 16].  A complex product is four real MFMAs:
+// in[j + l / 16][p0 + l % 16].  A complex product is four real MFMAs:
 // Re += Kr Qr - Ki Qi, Im += Kr Qi + Ki Qr.  Accumulator element r of lane l
 // holds column l % 16 and row 4 (l / 16) + r (FP32) or 4 r + l / 16 (FP64);
 // both layouts were read off the hardware with one-hot operands.
@@ -231,7 +231,7 @@ __global__ void __launch_bounds__(64 * kFarMfmaWaves) k_far_apply_mfma(FarArgs f
         ki = adjoint ? -kv.y : kv.y;
       }
       if (col_ok) {
-        const cplx<R> qv = in[static_cast<int64_t>(pb) * f.Ngf + j];
+        const cplx<R> qv = in[j * P + pb];
         qr = qv.x;
         qi = qv.y;
       }
@@ -247,7 +247,7 @@ __global__ void __launch_bounds__(64 * kFarMfmaWaves) k_far_apply_mfma(FarArgs f
     for (int r = 0; r < 4; ++r) {
       const int64_t io = i0 + MfmaAcc<R>::row(lane, r);
       if (io < f.Ngf)
-        part[(static_cast<int64_t>(split) * P + pc) * f.Ngf + io] = cmake<R>(accr[r], acci[r]);
+        part[(static_cast<int64_t>(split) * f.Ngf + io) * P + pc] = cmake<R>(accr[r], acci[r]);
     }
   }
 }

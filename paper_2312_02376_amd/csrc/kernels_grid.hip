@@ -209,11 +209,10 @@ __global__ void __launch_bounds__(256) k_spread_near(
     }
   }
   if (valid) {
-    const int64_t n3 = static_cast<int64_t>(g.n[0]) * g.n[1] * g.n[2];
     const int64_t node = (static_cast<int64_t>(gx) * g.n[1] + gy) * g.n[2] + gz;
 #pragma unroll
     for (int pp = 0; pp < PB; ++pp)
-      if (p0 + pp < P) grid[static_cast<int64_t>(p0 + pp) * n3 + node] = cmake<R>(ax[pp], ay[pp]);
+      if (p0 + pp < P) grid[node * P + p0 + pp] = cmake<R>(ax[pp], ay[pp]);
   }
 }
 
@@ -228,7 +227,6 @@ __global__ void __launch_bounds__(256) k_interp(
   int64_t m = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (m >= N) return;
   const int p0 = blockIdx.y * PB;
-  const int64_t n3 = static_cast<int64_t>(g.n[0]) * g.n[1] * g.n[2];
   double wx[Q + 1], wy[Q + 1], wz[Q + 1];
 #pragma unroll
   for (int a = 0; a <= Q; ++a) {
@@ -250,7 +248,7 @@ __global__ void __launch_bounds__(256) k_interp(
 #pragma unroll
         for (int pp = 0; pp < PB; ++pp) {
           if (p0 + pp < P) {
-            cplx<R> v = grid[static_cast<int64_t>(p0 + pp) * n3 + row + kz];
+            cplx<R> v = grid[(row + kz) * P + p0 + pp];
             ax[pp] += w * static_cast<double>(v.x);
             ay[pp] += w * static_cast<double>(v.y);
           }
@@ -269,6 +267,52 @@ __global__ void __launch_bounds__(256) k_interp(
   }
 }
 
+// Batched planes: the lanes of a wavefront cover LP planes x (64 / LP)
+// points, so every stencil node is one contiguous, coalesced load of the
+// node's planes; the point's weights are shared by its lanes.
+template <typename R, int Q, int LP>
+__global__ void __launch_bounds__(256) k_interp_lp(
+    GridArgs g, const int32_t* __restrict__ s3, const double* __restrict__ w3, int64_t N,
+    const cplx<R>* __restrict__ grid, int P, cplx<R>* __restrict__ uint, int accumulate) {
+  constexpr int E = 64 / LP;
+  const int lane = threadIdx.x & 63;
+  const int e = lane / LP, pl = lane % LP;
+  const int64_t m = (static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6)) * E + e;
+  if (m >= N) return;
+  double wx[Q + 1], wy[Q + 1], wz[Q + 1];
+#pragma unroll
+  for (int a = 0; a <= Q; ++a) {
+    wx[a] = w3[a * N + m];
+    wy[a] = w3[(Q + 1 + a) * N + m];
+    wz[a] = w3[(2 * (Q + 1) + a) * N + m];
+  }
+  const int sx = s3[m], sy = s3[N + m], sz = s3[2 * N + m];
+  for (int pc = 0; pc < P; pc += LP) {
+    const int p = pc + pl;
+    if (p >= P) continue;
+    double ax = 0.0, ay = 0.0;
+    for (int kx = 0; kx <= Q; ++kx) {
+      for (int ky = 0; ky <= Q; ++ky) {
+        const double wxy = wx[kx] * wy[ky];
+        const cplx<R>* row = grid + ((static_cast<int64_t>(sx + kx) * g.n[1] + (sy + ky)) * g.n[2] + sz) * P + p;
+        cplx<R> v[Q + 1];
+#pragma unroll
+        for (int kz = 0; kz <= Q; ++kz) v[kz] = row[static_cast<int64_t>(kz) * P];
+#pragma unroll
+        for (int kz = 0; kz <= Q; ++kz) {
+          const double w = wxy * wz[kz];
+          ax += w * static_cast<double>(v[kz].x);
+          ay += w * static_cast<double>(v[kz].y);
+        }
+      }
+    }
+    cplx<R>* o = uint + m * P + p;
+    cplx<R> r = cmake<R>(static_cast<R>(ax), static_cast<R>(ay));
+    if (accumulate) r = cadd(*o, r);
+    *o = r;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Step 2: FFT passes in LDS
 // ---------------------------------------------------------------------------
@@ -277,25 +321,56 @@ __device__ inline int bitrev(int j, int logM) {
   return logM == 0 ? 0 : static_cast<int>(__brev(static_cast<unsigned>(j)) >> (32 - logM));
 }
 
-// Radix-2 stages on T lines of length M held in LDS.
-// DIT: bit-reversed input -> natural output.  DIF: natural -> bit-reversed.
-// inverse selects exp(+2 pi i ...) (conjugated twiddles).
+// Stages on T lines of length M held in LDS, two radix-2 stages at a time
+// (one radix-4 butterfly over elements base + {0, h, 2h, 3h}), a last
+// radix-2 stage when log2 M is odd.  tw holds exp(-2 pi i k / M), k < M / 2
+// (in LDS).  DIT: bit-reversed input -> natural output.  DIF: natural ->
+// bit-reversed.  inverse selects the conjugated twiddles.
 template <typename R>
-__device__ inline void lds_dit(cplx<R>* x, int T, int M, int logM, const cplx<R>* __restrict__ tw,
-                               bool inverse) {
-  const int nb = T * (M >> 1);
-  for (int lh = 0; lh < logM; ++lh) {
+__device__ inline cplx<R> twl(const cplx<R>* tw, int k, bool inverse) {
+  cplx<R> w = tw[k];
+  if (inverse) w.y = -w.y;
+  return w;
+}
+
+template <typename R>
+__device__ inline void lds_dit(cplx<R>* x, int T, int M, int logM, const cplx<R>* tw, bool inverse) {
+  int lh = 0;
+  for (; lh + 1 < logM; lh += 2) {
+    const int h = 1 << lh;
+    const int nq = T * (M >> 2);
+    for (int b = threadIdx.x; b < nq; b += blockDim.x) {
+      const int t = b >> (logM - 2);
+      const int k = b & ((M >> 2) - 1);
+      const int pos = k & (h - 1);
+      const int base = ((k >> lh) << (lh + 2)) + pos;
+      cplx<R>* line = x + t * M;
+      const cplx<R> w1 = twl(tw, pos << (logM - 1 - lh), inverse);
+      const cplx<R> w2 = twl(tw, pos << (logM - 2 - lh), inverse);
+      const cplx<R> w3 = twl(tw, (pos + h) << (logM - 2 - lh), inverse);
+      const cplx<R> x0 = line[base], x1 = line[base + h], x2 = line[base + 2 * h], x3 = line[base + 3 * h];
+      const cplx<R> b1 = cmul(x1, w1), d1 = cmul(x3, w1);
+      const cplx<R> a = cadd(x0, b1), bb = csub(x0, b1), c = cadd(x2, d1), d = csub(x2, d1);
+      const cplx<R> cw = cmul(c, w2), dw = cmul(d, w3);
+      line[base] = cadd(a, cw);
+      line[base + 2 * h] = csub(a, cw);
+      line[base + h] = cadd(bb, dw);
+      line[base + 3 * h] = csub(bb, dw);
+    }
+    __syncthreads();
+  }
+  if (lh < logM) {
     const int half = 1 << lh;
+    const int nb = T * (M >> 1);
     for (int b = threadIdx.x; b < nb; b += blockDim.x) {
       const int t = b >> (logM - 1);
       const int k = b & ((M >> 1) - 1);
       const int pos = k & (half - 1);
       const int i0 = ((k >> lh) << (lh + 1)) + pos;
-      cplx<R> w = tw[pos << (logM - 1 - lh)];
-      if (inverse) w.y = -w.y;
+      const cplx<R> w = twl(tw, pos << (logM - 1 - lh), inverse);
       cplx<R>* line = x + t * M;
-      cplx<R> a = line[i0];
-      cplx<R> c = cmul(line[i0 + half], w);
+      const cplx<R> a = line[i0];
+      const cplx<R> c = cmul(line[i0 + half], w);
       line[i0] = cadd(a, c);
       line[i0 + half] = csub(a, c);
     }
@@ -304,23 +379,44 @@ __device__ inline void lds_dit(cplx<R>* x, int T, int M, int logM, const cplx<R>
 }
 
 template <typename R>
-__device__ inline void lds_dif(cplx<R>* x, int T, int M, int logM, const cplx<R>* __restrict__ tw,
-                               bool inverse) {
-  const int nb = T * (M >> 1);
-  for (int lh = logM - 1; lh >= 0; --lh) {
-    const int half = 1 << lh;
+__device__ inline void lds_dif(cplx<R>* x, int T, int M, int logM, const cplx<R>* tw, bool inverse) {
+  int lh = logM - 2;
+  for (; lh >= 0; lh -= 2) {
+    // stage lh + 1 then stage lh
+    const int h = 1 << lh;
+    const int nq = T * (M >> 2);
+    for (int b = threadIdx.x; b < nq; b += blockDim.x) {
+      const int t = b >> (logM - 2);
+      const int k = b & ((M >> 2) - 1);
+      const int pos = k & (h - 1);
+      const int base = ((k >> lh) << (lh + 2)) + pos;
+      cplx<R>* line = x + t * M;
+      const cplx<R> w1 = twl(tw, pos << (logM - 1 - lh), inverse);
+      const cplx<R> w2 = twl(tw, pos << (logM - 2 - lh), inverse);
+      const cplx<R> w3 = twl(tw, (pos + h) << (logM - 2 - lh), inverse);
+      const cplx<R> x0 = line[base], x1 = line[base + h], x2 = line[base + 2 * h], x3 = line[base + 3 * h];
+      const cplx<R> a = cadd(x0, x2), c = cmul(csub(x0, x2), w2);
+      const cplx<R> bb = cadd(x1, x3), d = cmul(csub(x1, x3), w3);
+      line[base] = cadd(a, bb);
+      line[base + h] = cmul(csub(a, bb), w1);
+      line[base + 2 * h] = cadd(c, d);
+      line[base + 3 * h] = cmul(csub(c, d), w1);
+    }
+    __syncthreads();
+  }
+  if (lh == -1) {
+    // odd log2 M: the last stage (lh = 0) alone
+    const int nb = T * (M >> 1);
     for (int b = threadIdx.x; b < nb; b += blockDim.x) {
       const int t = b >> (logM - 1);
       const int k = b & ((M >> 1) - 1);
-      const int pos = k & (half - 1);
-      const int i0 = ((k >> lh) << (lh + 1)) + pos;
-      cplx<R> w = tw[pos << (logM - 1 - lh)];
-      if (inverse) w.y = -w.y;
+      const int i0 = k << 1;
+      const cplx<R> w = twl(tw, 0, inverse);
       cplx<R>* line = x + t * M;
-      cplx<R> a = line[i0];
-      cplx<R> c = line[i0 + half];
+      const cplx<R> a = line[i0];
+      const cplx<R> c = line[i0 + 1];
       line[i0] = cadd(a, c);
-      line[i0 + half] = cmul(csub(a, c), w);
+      line[i0 + 1] = cmul(csub(a, c), w);
     }
     __syncthreads();
   }
@@ -337,15 +433,18 @@ __global__ void __launch_bounds__(256) k_fft_pass(const cplx<R>* in,
   extern __shared__ unsigned char lds_raw[];
   cplx<R>* x = reinterpret_cast<cplx<R>*>(lds_raw);
   const int T = d.T, M = d.M, logM = d.logM;
+  cplx<R>* tws = x + static_cast<int64_t>(T) * M;  // [M / 2] twiddles
+  for (int k = threadIdx.x; k < (M >> 1); k += blockDim.x) tws[k] = tw[k];
   int64_t outer = 0, c0 = 0, outer0 = 0;
   int nlines = T;
   if (d.contig) {
     outer0 = static_cast<int64_t>(blockIdx.x) * T;
     nlines = static_cast<int>(min<int64_t>(T, d.nouter - outer0));
   } else {
-    const int64_t tiles = d.ncols / T;
+    const int64_t tiles = (d.ncols + T - 1) / T;
     outer = blockIdx.x / tiles;
     c0 = (blockIdx.x % tiles) * T;
+    nlines = static_cast<int>(min<int64_t>(T, d.ncols - c0));
   }
   for (int idx = threadIdx.x; idx < T * M; idx += blockDim.x) {
     int t, j;
@@ -366,20 +465,20 @@ __global__ void __launch_bounds__(256) k_fft_pass(const cplx<R>* in,
     x[t * M + pos] = v;
   }
   __syncthreads();
-  if (MODE == 0 || MODE == 2) lds_dit<R>(x, T, M, logM, tw, false);
+  if (MODE == 0 || MODE == 2) lds_dit<R>(x, T, M, logM, tws, false);
   if (MODE == 2) {
     for (int idx = threadIdx.x; idx < T * M; idx += blockDim.x) {
       const int t = idx / M;
       const int k = idx - t * M;
       if (t < nlines) {
-        cplx<R> s = spec[static_cast<int64_t>(k) * d.spec_line + (c0 + t) * d.spec_col];
+        cplx<R> s = spec[static_cast<int64_t>(k) * d.spec_line + ((c0 + t) / d.spec_div) * d.spec_col];
         if (conj_spec) s.y = -s.y;
         x[idx] = cmul(x[idx], s);
       }
     }
     __syncthreads();
   }
-  if (MODE == 1 || MODE == 2) lds_dif<R>(x, T, M, logM, tw, true);
+  if (MODE == 1 || MODE == 2) lds_dif<R>(x, T, M, logM, tws, true);
   for (int idx = threadIdx.x; idx < T * d.n_out; idx += blockDim.x) {
     int t, j;
     if (d.contig) {
@@ -547,6 +646,24 @@ int launch_spread_near(int q, const GridArgs& g, const int32_t* box_start, const
 template <typename R, int Q>
 static void interp_q(const GridArgs& g, const int32_t* s3, const double* u3, int64_t N, const void* grid,
                      int P, void* uint, bool acc, hipStream_t st) {
+  if (P >= 8) {
+    // lanes over planes: LP planes x 64 / LP points per wavefront, 4 wavefronts per block
+#define FFTPIM_INTERP_LP(LPV)                                                                              \
+  do {                                                                                                     \
+    const int64_t pts_per_block = 4 * (64 / LPV);                                                          \
+    hipLaunchKernelGGL((k_interp_lp<R, Q, LPV>), dim3(static_cast<unsigned>((N + pts_per_block - 1) / pts_per_block)), \
+                       dim3(256), 0, st, g, s3, u3, N, static_cast<const cplx<R>*>(grid), P,               \
+                       static_cast<cplx<R>*>(uint), acc ? 1 : 0);                                          \
+  } while (0)
+    if (P <= 16)
+      FFTPIM_INTERP_LP(16);
+    else if (P <= 32)
+      FFTPIM_INTERP_LP(32);
+    else
+      FFTPIM_INTERP_LP(64);
+#undef FFTPIM_INTERP_LP
+    return;
+  }
   FFTPIM_PB_DISPATCH(P, {
     dim3 gr(blocks_for(N, 256), (P + PB - 1) / PB);
     hipLaunchKernelGGL((k_interp<R, Q, PB>), gr, dim3(256), 0, st, g, s3, u3, N,
@@ -576,8 +693,8 @@ template <typename R>
 void launch_fft_pass(int mode, const void* in, void* out, const FftPassDesc& d, const void* tw,
                      const void* spec, bool conj_spec, hipStream_t st) {
   unsigned nblocks = d.contig ? blocks_for(d.nouter, d.T)
-                              : static_cast<unsigned>(d.nouter * (d.ncols / d.T));
-  size_t lds = static_cast<size_t>(d.T) * d.M * sizeof(cplx<R>);
+                              : static_cast<unsigned>(d.nouter * ((d.ncols + d.T - 1) / d.T));
+  size_t lds = (static_cast<size_t>(d.T) * d.M + d.M / 2) * sizeof(cplx<R>);
   const cplx<R>* i = static_cast<const cplx<R>*>(in);
   cplx<R>* o = static_cast<cplx<R>*>(out);
   const cplx<R>* t = static_cast<const cplx<R>*>(tw);
