@@ -321,7 +321,7 @@ __device__ inline int bitrev(int j, int logM) {
   return logM == 0 ? 0 : static_cast<int>(__brev(static_cast<unsigned>(j)) >> (32 - logM));
 }
 
-// Stages on T lines of length M held in LDS, two radix-2 stages at a time
+// Stages on T lines (T a power of 2) of length M held in LDS (line stride Ms), two radix-2 stages at a time
 // (one radix-4 butterfly over elements base + {0, h, 2h, 3h}), a last
 // radix-2 stage when log2 M is odd.  tw holds exp(-2 pi i k / M), k < M / 2
 // (in LDS).  DIT: bit-reversed input -> natural output.  DIF: natural ->
@@ -334,17 +334,20 @@ __device__ inline cplx<R> twl(const cplx<R>* tw, int k, bool inverse) {
 }
 
 template <typename R>
-__device__ inline void lds_dit(cplx<R>* x, int T, int M, int logM, const cplx<R>* tw, bool inverse) {
+__device__ inline void lds_dit(cplx<R>* x, int T, int M, int Ms, int logM, const cplx<R>* tw, bool inverse) {
+  // consecutive threads take consecutive lines (T is a power of 2; padded
+  // line stride keeps them on different banks)
+  const int logT = __ffs(T) - 1;
   int lh = 0;
   for (; lh + 1 < logM; lh += 2) {
     const int h = 1 << lh;
     const int nq = T * (M >> 2);
     for (int b = threadIdx.x; b < nq; b += blockDim.x) {
-      const int t = b >> (logM - 2);
-      const int k = b & ((M >> 2) - 1);
+      const int t = b & (T - 1);
+      const int k = b >> logT;
       const int pos = k & (h - 1);
       const int base = ((k >> lh) << (lh + 2)) + pos;
-      cplx<R>* line = x + t * M;
+      cplx<R>* line = x + t * Ms;
       const cplx<R> w1 = twl(tw, pos << (logM - 1 - lh), inverse);
       const cplx<R> w2 = twl(tw, pos << (logM - 2 - lh), inverse);
       const cplx<R> w3 = twl(tw, (pos + h) << (logM - 2 - lh), inverse);
@@ -363,12 +366,12 @@ __device__ inline void lds_dit(cplx<R>* x, int T, int M, int logM, const cplx<R>
     const int half = 1 << lh;
     const int nb = T * (M >> 1);
     for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-      const int t = b >> (logM - 1);
-      const int k = b & ((M >> 1) - 1);
+      const int t = b & (T - 1);
+      const int k = b >> logT;
       const int pos = k & (half - 1);
       const int i0 = ((k >> lh) << (lh + 1)) + pos;
       const cplx<R> w = twl(tw, pos << (logM - 1 - lh), inverse);
-      cplx<R>* line = x + t * M;
+      cplx<R>* line = x + t * Ms;
       const cplx<R> a = line[i0];
       const cplx<R> c = cmul(line[i0 + half], w);
       line[i0] = cadd(a, c);
@@ -379,18 +382,21 @@ __device__ inline void lds_dit(cplx<R>* x, int T, int M, int logM, const cplx<R>
 }
 
 template <typename R>
-__device__ inline void lds_dif(cplx<R>* x, int T, int M, int logM, const cplx<R>* tw, bool inverse) {
+__device__ inline void lds_dif(cplx<R>* x, int T, int M, int Ms, int logM, const cplx<R>* tw, bool inverse) {
+  // consecutive threads take consecutive lines (T is a power of 2; padded
+  // line stride keeps them on different banks)
+  const int logT = __ffs(T) - 1;
   int lh = logM - 2;
   for (; lh >= 0; lh -= 2) {
     // stage lh + 1 then stage lh
     const int h = 1 << lh;
     const int nq = T * (M >> 2);
     for (int b = threadIdx.x; b < nq; b += blockDim.x) {
-      const int t = b >> (logM - 2);
-      const int k = b & ((M >> 2) - 1);
+      const int t = b & (T - 1);
+      const int k = b >> logT;
       const int pos = k & (h - 1);
       const int base = ((k >> lh) << (lh + 2)) + pos;
-      cplx<R>* line = x + t * M;
+      cplx<R>* line = x + t * Ms;
       const cplx<R> w1 = twl(tw, pos << (logM - 1 - lh), inverse);
       const cplx<R> w2 = twl(tw, pos << (logM - 2 - lh), inverse);
       const cplx<R> w3 = twl(tw, (pos + h) << (logM - 2 - lh), inverse);
@@ -408,11 +414,11 @@ __device__ inline void lds_dif(cplx<R>* x, int T, int M, int logM, const cplx<R>
     // odd log2 M: the last stage (lh = 0) alone
     const int nb = T * (M >> 1);
     for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-      const int t = b >> (logM - 1);
-      const int k = b & ((M >> 1) - 1);
+      const int t = b & (T - 1);
+      const int k = b >> logT;
       const int i0 = k << 1;
       const cplx<R> w = twl(tw, 0, inverse);
-      cplx<R>* line = x + t * M;
+      cplx<R>* line = x + t * Ms;
       const cplx<R> a = line[i0];
       const cplx<R> c = line[i0 + 1];
       line[i0] = cadd(a, c);
@@ -433,7 +439,11 @@ __global__ void __launch_bounds__(256) k_fft_pass(const cplx<R>* in,
   extern __shared__ unsigned char lds_raw[];
   cplx<R>* x = reinterpret_cast<cplx<R>*>(lds_raw);
   const int T = d.T, M = d.M, logM = d.logM;
-  cplx<R>* tws = x + static_cast<int64_t>(T) * M;  // [M / 2] twiddles
+  // LDS lines are padded by one element so that the column-strided load and
+  // store phases do not all hit one bank
+  const int Ms = M + 1;
+  const int logT = __ffs(T) - 1;  // T is a power of 2
+  cplx<R>* tws = x + static_cast<int64_t>(T) * Ms;  // [M / 2] twiddles
   for (int k = threadIdx.x; k < (M >> 1); k += blockDim.x) tws[k] = tw[k];
   int64_t outer = 0, c0 = 0, outer0 = 0;
   int nlines = T;
@@ -446,53 +456,69 @@ __global__ void __launch_bounds__(256) k_fft_pass(const cplx<R>* in,
     c0 = (blockIdx.x % tiles) * T;
     nlines = static_cast<int>(min<int64_t>(T, d.ncols - c0));
   }
-  for (int idx = threadIdx.x; idx < T * M; idx += blockDim.x) {
-    int t, j;
-    if (d.contig) {
-      t = idx / M;
-      j = idx - t * M;
-    } else {
-      t = idx % T;
-      j = idx / T;
+  // load in batches of kFftLoadBatch elements per thread so that many loads
+  // are in flight before any of them is stored to LDS
+  constexpr int kFftLoadBatch = 8;
+  for (int base = 0; base < T * M; base += blockDim.x * kFftLoadBatch) {
+    cplx<R> v[kFftLoadBatch];
+    int li[kFftLoadBatch];
+#pragma unroll
+    for (int u = 0; u < kFftLoadBatch; ++u) {
+      const int idx = base + u * blockDim.x + threadIdx.x;
+      v[u] = cmake<R>(R(0), R(0));
+      li[u] = -1;
+      if (idx < T * M) {
+        int t, j;
+        if (d.contig) {
+          t = idx >> logM;
+          j = idx & (M - 1);
+        } else {
+          t = idx & (T - 1);
+          j = idx >> logT;
+        }
+        li[u] = t * Ms + ((MODE == 1) ? j : bitrev(j, logM));
+        if (t < nlines && j < d.n_in) {
+          const int64_t a = d.contig ? (outer0 + t) * d.in_outer + j * d.in_line
+                                     : outer * d.in_outer + (c0 + t) * d.in_col + j * d.in_line;
+          v[u] = in[a];
+        }
+      }
     }
-    cplx<R> v = cmake<R>(R(0), R(0));
-    if (t < nlines && j < d.n_in) {
-      int64_t a = d.contig ? (outer0 + t) * d.in_outer + j * d.in_line
-                           : outer * d.in_outer + (c0 + t) * d.in_col + j * d.in_line;
-      v = in[a];
-    }
-    const int pos = (MODE == 1) ? j : bitrev(j, logM);
-    x[t * M + pos] = v;
+#pragma unroll
+    for (int u = 0; u < kFftLoadBatch; ++u)
+      if (li[u] >= 0) x[li[u]] = v[u];
   }
   __syncthreads();
-  if (MODE == 0 || MODE == 2) lds_dit<R>(x, T, M, logM, tws, false);
+  if (MODE == 0 || MODE == 2) lds_dit<R>(x, T, M, Ms, logM, tws, false);
   if (MODE == 2) {
+    // the lines of a block share spectrum values: consecutive threads take
+    // consecutive lines at one frequency
     for (int idx = threadIdx.x; idx < T * M; idx += blockDim.x) {
-      const int t = idx / M;
-      const int k = idx - t * M;
+      const int k = idx >> logT;
+      const int t = idx & (T - 1);
       if (t < nlines) {
         cplx<R> s = spec[static_cast<int64_t>(k) * d.spec_line + ((c0 + t) / d.spec_div) * d.spec_col];
         if (conj_spec) s.y = -s.y;
-        x[idx] = cmul(x[idx], s);
+        x[t * Ms + k] = cmul(x[t * Ms + k], s);
       }
     }
     __syncthreads();
   }
-  if (MODE == 1 || MODE == 2) lds_dif<R>(x, T, M, logM, tws, true);
+  if (MODE == 1 || MODE == 2) lds_dif<R>(x, T, M, Ms, logM, tws, true);
   for (int idx = threadIdx.x; idx < T * d.n_out; idx += blockDim.x) {
     int t, j;
     if (d.contig) {
       t = idx / d.n_out;
       j = idx - t * d.n_out;
     } else {
-      t = idx % T;
-      j = idx / T;
+      t = idx & (T - 1);
+      j = idx >> logT;
     }
     if (t >= nlines) continue;
     const int pos = (MODE == 0) ? j : bitrev(j, logM);
     int64_t a = d.contig ? (outer0 + t) * d.out_outer + j * d.out_line
                          : outer * d.out_outer + (c0 + t) * d.out_col + j * d.out_line;
-    out[a] = x[t * M + pos];
+    out[a] = x[t * Ms + pos];
   }
 }
 
@@ -694,7 +720,7 @@ void launch_fft_pass(int mode, const void* in, void* out, const FftPassDesc& d, 
                      const void* spec, bool conj_spec, hipStream_t st) {
   unsigned nblocks = d.contig ? blocks_for(d.nouter, d.T)
                               : static_cast<unsigned>(d.nouter * ((d.ncols + d.T - 1) / d.T));
-  size_t lds = (static_cast<size_t>(d.T) * d.M + d.M / 2) * sizeof(cplx<R>);
+  size_t lds = (static_cast<size_t>(d.T) * (d.M + 1) + d.M / 2) * sizeof(cplx<R>);
   const cplx<R>* i = static_cast<const cplx<R>*>(in);
   cplx<R>* o = static_cast<cplx<R>*>(out);
   const cplx<R>* t = static_cast<const cplx<R>*>(tw);
