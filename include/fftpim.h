@@ -97,14 +97,19 @@ typedef struct {
   int order_io;      /* FFTPIM_ORDER_USER: q/u indexed like the input points;
                         FFTPIM_ORDER_PLAN: indexed in the plan's sorted order */
   int nrhs_max;      /* largest nrhs a single apply may pass */
-  int corr_layout;   /* FFTPIM_CORR_AUTO, FFTPIM_CORR_CSR or FFTPIM_CORR_SYM */
+  int corr_layout;   /* FFTPIM_CORR_AUTO, _CSR, _SYM or _TILE */
 } fftpim_params_t;
 
-/* Storage of the near-zone correction of Eq. (er): one CSR row per observer,
+/* Storage of the near-zone correction of Eq. (er): one CSR row per observer;
  * or (SYM) the in-cell part once per unordered pair of near-grid boxes (the
  * image-0 correction is symmetric in source and observer) plus a CSR of the
- * close-image part.  AUTO picks SYM when boxes hold several points each. */
-enum { FFTPIM_CORR_AUTO = 0, FFTPIM_CORR_CSR = 1, FFTPIM_CORR_SYM = 2 };
+ * close-image part; or (TILE, real static kernels only) dense blocks of 16
+ * observers by the union of their corrected sources, zeros included, applied
+ * as FP64 matrix-core products.  AUTO picks TILE for real values and at
+ * least eight planes, SYM for at most four planes when boxes hold several
+ * points each, CSR otherwise.  FFTPIM_CORR_TILE with complex values returns
+ * FFTPIM_ERR_UNSUPPORTED. */
+enum { FFTPIM_CORR_AUTO = 0, FFTPIM_CORR_CSR = 1, FFTPIM_CORR_SYM = 2, FFTPIM_CORR_TILE = 3 };
 
 typedef struct {
   int64_t n_src, n_obs;
@@ -115,8 +120,9 @@ typedef struct {
   int64_t corr_nnz;           /* stored correction entries (all parts) */
   int64_t corr_sym_values;    /* entries in symmetric box-pair blocks */
   int64_t corr_csr_nnz;       /* entries in the CSR part */
+  int64_t corr_tile_values;   /* entries stored in dense row tiles (zeros included) */
   int corr_value_bytes;       /* 8 (real) or 16 (complex) per FP64 entry */
-  int corr_layout_used;       /* FFTPIM_CORR_CSR or FFTPIM_CORR_SYM */
+  int corr_layout_used;       /* FFTPIM_CORR_CSR, FFTPIM_CORR_SYM or FFTPIM_CORR_TILE */
   int64_t device_bytes;       /* device memory held by the plan */
   int nplanes_max;            /* complex grid planes for nrhs_max */
   double plan_seconds;        /* wall time of fftpim_plan */

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <numeric>
+#include <thread>
 #include <vector>
 
 #include "kernels.h"
@@ -307,7 +308,12 @@ int run_apply(fftpim_plan_s* p, int parts, bool adjoint, const void* in, void* o
     const void* v = (adjoint && p->helmholtz) ? p->val_adj : p->val;
     {
       StageTimer t(p, sc, FFTPIM_STAGE_NEAR_CORR);
-      if (p->sym) {
+      if (p->tile) {
+        // real correction values: the operator is symmetric, so the
+        // conjugate transpose uses the same tiles
+        launch_corr_tile<R>(p->tile_rows, p->ntiles, p->tile_coff, p->tile_cols, p->tile_voff, p->tile_vals,
+                            p->q_int, P, p->u_corr, sc);
+      } else if (p->sym) {
         // in-cell part: A^H of a complex-symmetric block is conj(X conj(v))
         launch_sym_apply<R>(p->complex_kernel, sym_args(p), p->sym_vals, p->q_int, P, adjoint, p->sym_ypart,
                             p->sym_zpart, p->u_corr, false, sc);
@@ -413,7 +419,7 @@ int validate(const fftpim_problem_t* pr, const fftpim_params_t* pm) {
   if (pm->self_mode != FFTPIM_SELF_IMAGES && pm->self_mode != FFTPIM_SELF_EXCLUDE) return FFTPIM_ERR_INVALID_ARG;
   if (pm->order_io != FFTPIM_ORDER_USER && pm->order_io != FFTPIM_ORDER_PLAN) return FFTPIM_ERR_INVALID_ARG;
   if (pm->nrhs_max < 1 || pm->nrhs_max > 4096) return FFTPIM_ERR_INVALID_ARG;
-  if (pm->corr_layout < FFTPIM_CORR_AUTO || pm->corr_layout > FFTPIM_CORR_SYM) return FFTPIM_ERR_INVALID_ARG;
+  if (pm->corr_layout < FFTPIM_CORR_AUTO || pm->corr_layout > FFTPIM_CORR_TILE) return FFTPIM_ERR_INVALID_ARG;
   return FFTPIM_OK;
 }
 
@@ -752,6 +758,99 @@ void build_row_order(const std::vector<int32_t>& start, const int nb[3], int64_t
   (void)N;
 }
 
+// Dense row tiles for real correction values.  Observers are ordered by the
+// Morton key of their near-grid box (so 16 consecutive observers sit in a
+// compact group of boxes and share most corrected sources) and cut into
+// tiles of 16; a tile stores the 16 x C block over the union of its
+// observers' CSR columns, zeros included, and the CSR is released.
+constexpr int kTileRows = 16;
+
+inline uint64_t morton3(uint32_t x, uint32_t y, uint32_t z) {
+  uint64_t k = 0;
+  for (int i = 0; i < 21; ++i)
+    k |= (static_cast<uint64_t>((x >> i) & 1) << (3 * i + 2)) | (static_cast<uint64_t>((y >> i) & 1) << (3 * i + 1)) |
+         (static_cast<uint64_t>((z >> i) & 1) << (3 * i));
+  return k;
+}
+
+int build_tiles(fftpim_plan_s* p, const std::vector<int32_t>& start, const std::vector<int64_t>& rowptr,
+                hipStream_t st) {
+  const int64_t N = p->N;
+  const int nbx = p->nb[0], nby = p->nb[1], nbz = p->nb[2];
+  std::vector<uint64_t> key(N);
+  for (int bx = 0; bx < nbx; ++bx)
+    for (int by = 0; by < nby; ++by)
+      for (int bz = 0; bz < nbz; ++bz) {
+        const int64_t b = (static_cast<int64_t>(bx) * nby + by) * nbz + bz;
+        const uint64_t k = morton3(bx, by, bz);
+        for (int32_t m = start[b]; m < start[b + 1]; ++m) key[m] = k;
+      }
+  std::vector<int32_t> order(N);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return key[x] < key[y]; });
+  const int64_t ntiles = (N + kTileRows - 1) / kTileRows;
+  std::vector<int32_t> trows(static_cast<size_t>(ntiles * kTileRows), -1);
+  std::copy(order.begin(), order.end(), trows.begin());
+  // union of the CSR columns of each tile's observers (host threads)
+  std::vector<int32_t> hcol(static_cast<size_t>(p->nnz));
+  if (p->nnz > 0) HIPCHK(hipMemcpy(hcol.data(), p->col, p->nnz * sizeof(int32_t), hipMemcpyDeviceToHost));
+  std::vector<std::vector<int32_t>> tcols(ntiles);
+  const int nth = static_cast<int>(std::max<unsigned>(1, std::min<unsigned>(16, std::thread::hardware_concurrency())));
+  std::vector<std::thread> pool;
+  for (int w = 0; w < nth; ++w)
+    pool.emplace_back([&, w]() {
+      std::vector<int64_t> seen(N, -1);
+      for (int64_t t = w; t < ntiles; t += nth) {
+        std::vector<int32_t>& out = tcols[t];
+        for (int r = 0; r < kTileRows; ++r) {
+          const int32_t m = trows[t * kTileRows + r];
+          if (m < 0) continue;
+          for (int64_t j = rowptr[m]; j < rowptr[m + 1]; ++j) {
+            const int32_t n = hcol[j];
+            if (seen[n] != t) {
+              seen[n] = t;
+              out.push_back(n);
+            }
+          }
+        }
+        std::sort(out.begin(), out.end());
+      }
+    });
+  for (auto& th : pool) th.join();
+  std::vector<int64_t> coff(ntiles + 1, 0), voff(ntiles + 1, 0);
+  for (int64_t t = 0; t < ntiles; ++t) {
+    const int64_t C = static_cast<int64_t>(tcols[t].size());
+    coff[t + 1] = coff[t] + C;
+    voff[t + 1] = voff[t] + 64 * ((C + 3) / 4);
+  }
+  std::vector<int32_t> cols(static_cast<size_t>(coff[ntiles]));
+  for (int64_t t = 0; t < ntiles; ++t) std::copy(tcols[t].begin(), tcols[t].end(), cols.begin() + coff[t]);
+  tcols.clear();
+  CHK(upload(p, &p->tile_rows, trows));
+  CHK(upload(p, &p->tile_coff, coff));
+  CHK(upload(p, &p->tile_cols, cols));
+  CHK(upload(p, &p->tile_voff, voff));
+  CHK(dalloc(p, &p->tile_vals, static_cast<size_t>(voff[ntiles])));
+  HIPCHK(hipMemsetAsync(p->tile_vals, 0, static_cast<size_t>(voff[ntiles]) * sizeof(double), st));
+  launch_tile_fill(p->tile_rows, ntiles * kTileRows, p->rowptr, p->col, static_cast<const double*>(p->val),
+                   p->tile_coff, p->tile_cols, p->tile_voff, p->tile_vals, st);
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipGetLastError());
+  p->ntiles = ntiles;
+  p->tile_nvals = voff[ntiles];
+  // the tiles replace the CSR
+  p->device_bytes -= static_cast<int64_t>(p->nnz) * (sizeof(int32_t) + sizeof(double));
+  dfree(p, p->col);
+  dfree(p, p->val);
+  p->col = nullptr;
+  p->val = nullptr;
+  if (std::getenv("FFTPIM_LOG"))
+    std::fprintf(stderr, "fftpim plan: row tiles: %lld tiles, %lld union columns, %lld values (CSR nnz %lld)\n",
+                 static_cast<long long>(ntiles), static_cast<long long>(coff[ntiles]),
+                 static_cast<long long>(voff[ntiles]), static_cast<long long>(p->nnz));
+  return FFTPIM_OK;
+}
+
 int build_correction(fftpim_plan_s* p, const std::vector<int32_t>& start, const double* pos3_dev,
                      hipStream_t st) {
   const int q = p->ng.q, rc = p->prm.corr_radius, id = p->prm.n_images;
@@ -872,6 +971,7 @@ int build_correction(fftpim_plan_s* p, const std::vector<int32_t>& start, const 
     dfree(p, doff[c]);
     dfree(p, dent[c]);
   }
+  if (p->tile) CHK(build_tiles(p, start, rowptr, st));
   return FFTPIM_OK;
 }
 
@@ -1014,8 +1114,14 @@ int build_plan(fftpim_plan_s* p, int64_t N, const double* src_dev, hipStream_t s
     if (pm.corr_layout == FFTPIM_CORR_SYM) {
       if (!fits) return FFTPIM_ERR_INVALID_ARG;
       p->sym = true;
+    } else if (pm.corr_layout == FFTPIM_CORR_TILE) {
+      if (p->complex_kernel) return FFTPIM_ERR_UNSUPPORTED;
+      p->tile = true;
     } else if (pm.corr_layout == FFTPIM_CORR_AUTO) {
-      p->sym = fits && dense;
+      // many planes re-read a value per plane in the box-pair kernel; the
+      // dense tiles take them on the matrix cores (real values only)
+      p->tile = !p->complex_kernel && Pm >= 8;
+      p->sym = !p->tile && fits && dense && Pm <= 4;
     }
   }
   CHK(build_correction(p, start, dpos, st));
@@ -1181,9 +1287,10 @@ int fftpim_plan_info(fftpim_plan_t plan, fftpim_info_t* info) {
   }
   r.corr_nnz = plan->nnz + plan->sym_nvals;
   r.corr_sym_values = plan->sym_nvals;
-  r.corr_csr_nnz = plan->nnz;
+  r.corr_csr_nnz = plan->tile ? 0 : plan->nnz;
+  r.corr_tile_values = plan->tile_nvals;
   r.corr_value_bytes = plan->complex_kernel ? 16 : 8;
-  r.corr_layout_used = plan->sym ? FFTPIM_CORR_SYM : FFTPIM_CORR_CSR;
+  r.corr_layout_used = plan->tile ? FFTPIM_CORR_TILE : (plan->sym ? FFTPIM_CORR_SYM : FFTPIM_CORR_CSR);
   r.device_bytes = plan->device_bytes;
   r.nplanes_max = plan->nplanes_max;
   r.plan_seconds = plan->plan_seconds;

@@ -214,6 +214,14 @@ struct fftpim_plan_s {
   // correction (FP64 values)
   int64_t* rowptr = nullptr;
   int32_t* corr_order = nullptr;   // [corr_slots] row of each wavefront slot (-1: idle)
+  // dense row tiles (real correction values): see build_tiles
+  bool tile = false;
+  int64_t ntiles = 0, tile_nvals = 0;
+  int32_t* tile_rows = nullptr;    // [ntiles * 16] observers (-1: padding)
+  int64_t* tile_coff = nullptr;    // [ntiles + 1] union column ranges
+  int32_t* tile_cols = nullptr;    // union columns, ascending per tile
+  int64_t* tile_voff = nullptr;    // [ntiles + 1] value ranges (64 per k-step)
+  double* tile_vals = nullptr;
   int64_t corr_slots = 0;
   int32_t* col = nullptr;
   void* val = nullptr;            // double or complex double

@@ -137,9 +137,16 @@ int launch_corr_count(const CorrArgs& a, const int32_t* s3, const int32_t* box_s
 int launch_corr_fill(int q, bool cplx_vals, bool adj, const CorrArgs& a, const int32_t* s3, const double* u3,
                      const double* pos3, const int32_t* box_start, const void* g0tab, const int64_t* rowptr,
                      int32_t* col, void* val, void* val_adj, hipStream_t st);
+// Dense row tiles of real correction values (see kernels_corr.hip).
+void launch_tile_fill(const int32_t* tile_rows, int64_t nslots, const int64_t* rowptr, const int32_t* col,
+                      const double* val, const int64_t* coff, const int32_t* cols, const int64_t* voff, double* tv,
+                      hipStream_t st);
 template <typename R>
+void launch_corr_tile(const int32_t* tile_rows, int64_t ntiles, const int64_t* coff, const int32_t* cols,
+                      const int64_t* voff, const double* tv, const void* x, int P, void* u, hipStream_t st);
 // order (optional, nslots entries, -1 = idle slot): the row processed by each
 // wavefront slot, grouped so that a workgroup's rows are spatially close.
+template <typename R>
 void launch_corr_spmv(bool cplx_vals, const int64_t* rowptr, const int32_t* col, const void* val, int64_t N,
                       const int32_t* order, int64_t nslots, const void* qint, int P, void* uint, bool accumulate,
                       hipStream_t st);

@@ -345,6 +345,126 @@ __global__ void __launch_bounds__(256) k_corr_spmm(const int64_t* __restrict__ r
 }
 
 // ---------------------------------------------------------------------------
+// Dense row tiles (real correction values): 16 observers x the union of their
+// corrected sources, zeros where a pair is not corrected.  A tile's values are
+// stored in MFMA A-fragment order: k-step s holds 64 doubles, lane l = r +
+// 16 kk giving row r, tile column 4 s + kk.
+// ---------------------------------------------------------------------------
+
+// Plan time: scatter each observer's CSR entries into its tile (one thread
+// per observer, so repeated columns of several images add up without races).
+__global__ void k_tile_fill(const int32_t* __restrict__ tile_rows, int64_t nslots, const int64_t* __restrict__ rowptr,
+                            const int32_t* __restrict__ col, const double* __restrict__ val,
+                            const int64_t* __restrict__ coff, const int32_t* __restrict__ cols,
+                            const int64_t* __restrict__ voff, double* __restrict__ tv) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= nslots) return;
+  const int m = tile_rows[idx];
+  if (m < 0) return;
+  const int64_t t = idx >> 4;
+  const int r = static_cast<int>(idx & 15);
+  const int64_t c0 = coff[t], C = coff[t + 1] - c0;
+  for (int64_t j = rowptr[m]; j < rowptr[m + 1]; ++j) {
+    const int n = col[j];
+    int64_t lo = 0, hi = C - 1;  // the column is in the tile's sorted list
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (cols[c0 + mid] < n) lo = mid + 1; else hi = mid;
+    }
+    tv[voff[t] + (lo >> 2) * 64 + r + 16 * (lo & 3)] += val[j];
+  }
+}
+
+// Apply: one wavefront per tile.  The tile's real-column view of the
+// amplitudes ([N][2P] reals, re/im interleaved) is taken 64 columns at a time
+// as four 16-column MFMA chunks; each k-step gathers four source rows (one per
+// lane group) and runs four 16x16x4 FP64 MFMAs with the same value fragment.
+// FP64 accumulator element r of lane l holds row 4 r + l / 16, column l % 16.
+typedef double tile_d4 __attribute__((ext_vector_type(4)));
+constexpr int kTileWaves = 4;
+
+template <typename R>
+__global__ void __launch_bounds__(64 * kTileWaves) k_corr_tile(const int32_t* __restrict__ tile_rows, int64_t ntiles,
+                                                               const int64_t* __restrict__ coff,
+                                                               const int32_t* __restrict__ cols,
+                                                               const int64_t* __restrict__ voff,
+                                                               const double* __restrict__ tv,
+                                                               const R* __restrict__ x, int P2, R* __restrict__ u) {
+  const int lane = threadIdx.x & 63;
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * kTileWaves + (threadIdx.x >> 6);
+  if (t >= ntiles) return;
+  const int64_t c0 = coff[t], C = coff[t + 1] - c0;
+  const int64_t nks = (C + 3) >> 2;
+  const double* v = tv + voff[t];
+  const int kk = lane >> 4, jl = lane & 15;
+  for (int cg = 0; cg < P2; cg += 64) {
+    tile_d4 acc[4];
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) acc[ch] = tile_d4{0.0, 0.0, 0.0, 0.0};
+    // 64 union columns (16 k-steps) at a time: each lane loads one column
+    // index, the k-steps take theirs by lane shuffle, and two k-steps of
+    // value and amplitude loads are issued before their MFMAs
+    constexpr int U = 2;
+    for (int64_t cb = 0; cb < C; cb += 64) {
+      const int colv = (cb + lane < C) ? cols[c0 + cb + lane] : -1;
+      const int64_t sb = cb >> 2;
+      const int ns = static_cast<int>(min<int64_t>(16, nks - sb));
+      for (int s0 = 0; s0 < ns; s0 += U) {
+        double a[U];
+        R b[U][4];
+#pragma unroll
+        for (int uu = 0; uu < U; ++uu) {
+          const int s = s0 + uu;
+          const bool sok = s < ns;
+          a[uu] = sok ? __builtin_nontemporal_load(v + (sb + s) * 64 + lane) : 0.0;
+          const int n = __shfl(colv, (4 * s + kk) & 63, 64);
+#pragma unroll
+          for (int ch = 0; ch < 4; ++ch) {
+            const int j = cg + 16 * ch + jl;
+            b[uu][ch] = (sok && n >= 0 && j < P2) ? x[static_cast<int64_t>(n) * P2 + j] : R(0);
+          }
+        }
+#pragma unroll
+        for (int uu = 0; uu < U; ++uu)
+#pragma unroll
+          for (int ch = 0; ch < 4; ++ch)
+            acc[ch] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[uu], static_cast<double>(b[uu][ch]), acc[ch], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) {
+      const int j = cg + 16 * ch + jl;
+      if (j >= P2) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = tile_rows[t * 16 + 4 * r + kk];
+        if (m >= 0) u[static_cast<int64_t>(m) * P2 + j] = static_cast<R>(acc[ch][r]);
+      }
+    }
+  }
+}
+
+void launch_tile_fill(const int32_t* tile_rows, int64_t nslots, const int64_t* rowptr, const int32_t* col,
+                      const double* val, const int64_t* coff, const int32_t* cols, const int64_t* voff, double* tv,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_tile_fill, dim3(static_cast<unsigned>((nslots + 255) / 256)), dim3(256), 0, st, tile_rows,
+                     nslots, rowptr, col, val, coff, cols, voff, tv);
+}
+
+template <typename R>
+void launch_corr_tile(const int32_t* tile_rows, int64_t ntiles, const int64_t* coff, const int32_t* cols,
+                      const int64_t* voff, const double* tv, const void* x, int P, void* u, hipStream_t st) {
+  hipLaunchKernelGGL((k_corr_tile<R>), dim3(static_cast<unsigned>((ntiles + kTileWaves - 1) / kTileWaves)),
+                     dim3(64 * kTileWaves), 0, st, tile_rows, ntiles, coff, cols, voff, tv,
+                     static_cast<const R*>(x), 2 * P, static_cast<R*>(u));
+}
+
+template void launch_corr_tile<double>(const int32_t*, int64_t, const int64_t*, const int32_t*, const int64_t*,
+                                       const double*, const void*, int, void*, hipStream_t);
+template void launch_corr_tile<float>(const int32_t*, int64_t, const int64_t*, const int32_t*, const int64_t*,
+                                      const double*, const void*, int, void*, hipStream_t);
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 

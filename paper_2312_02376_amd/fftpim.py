@@ -59,6 +59,7 @@ class Info(ctypes.Structure):
                 ("domain_lo", ctypes.c_double * 3), ("domain_hi", ctypes.c_double * 3),
                 ("far_n", ctypes.c_int * 3), ("far_cells", ctypes.c_int * 3), ("far_h", ctypes.c_double * 3),
                 ("corr_nnz", ctypes.c_int64), ("corr_sym_values", ctypes.c_int64), ("corr_csr_nnz", ctypes.c_int64),
+                ("corr_tile_values", ctypes.c_int64),
                 ("corr_value_bytes", ctypes.c_int), ("corr_layout_used", ctypes.c_int),
                 ("device_bytes", ctypes.c_int64), ("nplanes_max", ctypes.c_int),
                 ("plan_seconds", ctypes.c_double)]
@@ -164,7 +165,7 @@ class Plan:
         pm.self_mode = {"images": SELF_IMAGES, "exclude": SELF_EXCLUDE}[self_mode]
         pm.order_io = {"user": ORDER_USER, "plan": ORDER_PLAN}[order]
         pm.nrhs_max = int(nrhs_max)
-        pm.corr_layout = {"auto": 0, "csr": 1, "sym": 2}[corr_layout]
+        pm.corr_layout = {"auto": 0, "csr": 1, "sym": 2, "tile": 3}[corr_layout]
         self.params = pm
         self.precision = precision
         self.value_type = value_type

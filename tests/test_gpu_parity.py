@@ -233,3 +233,25 @@ def test_csr_layout(name):
         got = plan.apply_parts(qd, 2, adjoint=adjoint).cpu().numpy()
         want = (ref.adjoint if adjoint else ref.apply)(qv, parts=("near_corr",))
         assert rel(got, want) < 1e-11, adjoint
+
+
+@pytest.mark.parametrize("name", ["npsp3_real", "npsp2_real", "npsp1_real"])
+@pytest.mark.parametrize("nrhs", [3, 19])
+def test_tile_layout(name, nrhs):
+    # real correction values in dense 16-observer tiles on the matrix cores
+    lat, ref, plan, qv = _setup(name, N=400, seed=29, nrhs=nrhs, corr_layout="tile")
+    assert plan.info()["corr_layout_used"] == 3
+    qd = _to_dev(plan, qv)
+    for adjoint in (False, True):
+        got = plan.apply_parts(qd, 2, adjoint=adjoint).cpu().numpy()
+        want = (ref.adjoint if adjoint else ref.apply)(qv, parts=("near_corr",))
+        assert rel(got, want) < 1e-11, adjoint
+
+
+def test_tile_layout_rejects_complex_values():
+    fp = _fftpim()
+    latkw, kind, nrhs, vt, nn, q, rc, nf, qf = CASES["helm3"]
+    src = W.uniform_cube(100, 4)
+    with pytest.raises(fp.FFTPIMError):
+        fp.Plan(torch.tensor(src, device="cuda"), 3, latkw["L"], k0=latkw["k0"], near_n=nn, near_order=q,
+                corr_radius=rc, far_n=nf, far_order=qf, corr_layout="tile")
