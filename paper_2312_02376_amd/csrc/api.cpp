@@ -290,7 +290,7 @@ int run_apply(fftpim_plan_s* p, int parts, bool adjoint, const void* in, void* o
     StageTimer t(p, st, FFTPIM_STAGE_PACK);
     launch_pack<R>(in, p->q_int, p->perm, N, nrhs, P, real_io, use_perm, st);
     if (finalize && !adjoint && p->lat.npsp()) {
-      launch_plane_sums<R>(p->q_int, nullptr, nullptr, N, P, p->sums, st);
+      launch_plane_sums<R>(p->q_int, nullptr, nullptr, N, P, p->sums_work, p->sums, st);
       launch_check_neutral(p->sums, P, p->prm.precision == FFTPIM_F32 ? 1e-5 : 1e-10, p->status_dev, st);
     }
   }
@@ -371,7 +371,7 @@ int run_apply(fftpim_plan_s* p, int parts, bool adjoint, const void* in, void* o
   const double* mean = nullptr;
   if (finalize && adjoint && p->lat.npsp()) {
     // only the zero-mean part of A^H v is defined for the neutral static case
-    launch_plane_sums<R>(un, uc, uf, N, P, p->sums, st);
+    launch_plane_sums<R>(un, uc, uf, N, P, p->sums_work, p->sums, st);
     launch_mean_from_sums(p->sums, P, N, p->sums + 4 * p->nplanes_max, st);
     mean = p->sums + 4 * p->nplanes_max;
   }
@@ -1172,6 +1172,7 @@ int build_plan(fftpim_plan_s* p, int64_t N, const double* src_dev, hipStream_t s
     p->sym_zpart = b;
   }
   CHK(dalloc(p, &p->sums, static_cast<size_t>(6) * P));
+  CHK(dalloc(p, &p->sums_work, static_cast<size_t>(plane_sums_chunks(N)) * P * 4));
   CHK(dalloc(p, &p->status_dev, 1));
   HIPCHK(hipMemsetAsync(p->status_dev, 0, sizeof(int), st));
   HIPCHK(hipStreamSynchronize(st));

@@ -213,6 +213,7 @@ struct fftpim_plan_s {
 
   // correction (FP64 values)
   int64_t* rowptr = nullptr;
+  double* sums_work = nullptr;     // scratch of the plane sums
   int32_t* corr_order = nullptr;   // [corr_slots] row of each wavefront slot (-1: idle)
   // dense row tiles (real correction values): see build_tiles
   bool tile = false;

@@ -114,8 +114,11 @@ struct PartPtrs {
 template <typename R>
 void launch_unpack(const void* u_near, const void* u_corr, const void* u_far, void* uu, const int32_t* perm,
                    int64_t N, int nrhs, int P, bool real_out, bool use_perm, const double* mean, hipStream_t st);
+// work: plane_sums_chunks(N) * P * 4 doubles of scratch
+int64_t plane_sums_chunks(int64_t N);
 template <typename R>
-void launch_plane_sums(const void* a, const void* b, const void* c, int64_t N, int P, double* out, hipStream_t st);
+void launch_plane_sums(const void* a, const void* b, const void* c, int64_t N, int P, double* work, double* out,
+                       hipStream_t st);
 void launch_check_neutral(const double* sums, int P, double tol, int* status, hipStream_t st);
 void launch_mean_from_sums(const double* sums, int P, int64_t N, double* mean, hipStream_t st);
 template <typename R>

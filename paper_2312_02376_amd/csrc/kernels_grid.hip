@@ -66,31 +66,48 @@ __global__ void k_unpack(PartPtrs<R> parts, void* __restrict__ uu, const int32_t
   }
 }
 
-// Per-plane sums over points, deterministic (one block per plane):
+// Per-plane sums over points, deterministic, in two stages:
 // out[4p + 0/1] = sum of re/im, out[4p + 2/3] = sum of |re| / |im|.
+// Stage 1: block (chunk c, plane tile) sums kPlaneSumChunk points; its 256
+// threads are 4 rows of 64 planes (coalesced across planes) and the rows are
+// added in order.  Stage 2: one thread per plane adds the chunks in order.
+constexpr int kPlaneSumChunk = 1024;
+
 template <typename R>
-__global__ void k_plane_sums(PartPtrs<R> v, int64_t N, int P, double* __restrict__ out) {
-  __shared__ double sh[4][256];
-  int p = blockIdx.x;
+__global__ void __launch_bounds__(256) k_plane_sums_part(PartPtrs<R> v, int64_t N, int P, double* __restrict__ part) {
+  __shared__ double sh[4][4][64];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int p = blockIdx.y * 64 + tx;
+  const int64_t m0 = static_cast<int64_t>(blockIdx.x) * kPlaneSumChunk;
+  const int64_t m1 = min<int64_t>(N, m0 + kPlaneSumChunk);
   double a = 0, b = 0, c = 0, d = 0;
-  for (int64_t m = threadIdx.x; m < N; m += blockDim.x) {
-    cplx<R> t = v.sum(m * P + p);
-    a += t.x;
-    b += t.y;
-    c += fabs(static_cast<double>(t.x));
-    d += fabs(static_cast<double>(t.y));
+  if (p < P) {
+    for (int64_t m = m0 + ty; m < m1; m += 4) {
+      const cplx<R> t = v.sum(m * P + p);
+      a += t.x;
+      b += t.y;
+      c += fabs(static_cast<double>(t.x));
+      d += fabs(static_cast<double>(t.y));
+    }
   }
-  sh[0][threadIdx.x] = a;
-  sh[1][threadIdx.x] = b;
-  sh[2][threadIdx.x] = c;
-  sh[3][threadIdx.x] = d;
+  sh[0][ty][tx] = a;
+  sh[1][ty][tx] = b;
+  sh[2][ty][tx] = c;
+  sh[3][ty][tx] = d;
   __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s)
-      for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
-    __syncthreads();
+  if (ty == 0 && p < P) {
+    double* o = part + (static_cast<int64_t>(blockIdx.x) * P + p) * 4;
+    for (int k = 0; k < 4; ++k) o[k] = ((sh[k][0][tx] + sh[k][1][tx]) + sh[k][2][tx]) + sh[k][3][tx];
   }
-  if (threadIdx.x < 4) out[4 * p + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ void k_plane_sums_final(const double* __restrict__ part, int64_t nchunks, int P, double* __restrict__ out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  double s[4] = {0, 0, 0, 0};
+  for (int64_t c = 0; c < nchunks; ++c)
+    for (int k = 0; k < 4; ++k) s[k] += part[(c * P + p) * 4 + k];
+  for (int k = 0; k < 4; ++k) out[4 * p + k] = s[k];
 }
 
 // Neutrality (Eq. (neutral)) per real right-hand side; latches the status.
@@ -609,9 +626,16 @@ void launch_unpack(const void* u_near, const void* u_corr, const void* u_far, vo
                        use_perm ? 1 : 0, mean);
 }
 
+int64_t plane_sums_chunks(int64_t N) { return (N + kPlaneSumChunk - 1) / kPlaneSumChunk; }
+
 template <typename R>
-void launch_plane_sums(const void* a, const void* b, const void* c, int64_t N, int P, double* out, hipStream_t st) {
-  hipLaunchKernelGGL((k_plane_sums<R>), dim3(P), dim3(256), 0, st, part_ptrs<R>(a, b, c), N, P, out);
+void launch_plane_sums(const void* a, const void* b, const void* c, int64_t N, int P, double* work, double* out,
+                       hipStream_t st) {
+  const int64_t nch = plane_sums_chunks(N);
+  hipLaunchKernelGGL((k_plane_sums_part<R>), dim3(static_cast<unsigned>(nch), static_cast<unsigned>((P + 63) / 64)),
+                     dim3(256), 0, st, part_ptrs<R>(a, b, c), N, P, work);
+  hipLaunchKernelGGL(k_plane_sums_final, dim3(static_cast<unsigned>((P + 63) / 64)), dim3(64), 0, st, work, nch, P,
+                     out);
 }
 
 void launch_check_neutral(const double* sums, int P, double tol, int* status, hipStream_t st) {
@@ -752,7 +776,7 @@ void launch_scale_convert(const void* in, void* out, int64_t n, double s, hipStr
                                hipStream_t);                                                             \
   template void launch_unpack<R>(const void*, const void*, const void*, void*, const int32_t*, int64_t,  \
                                  int, int, bool, bool, const double*, hipStream_t);                      \
-  template void launch_plane_sums<R>(const void*, const void*, const void*, int64_t, int, double*,       \
+  template void launch_plane_sums<R>(const void*, const void*, const void*, int64_t, int, double*, double*, \
                                      hipStream_t);                                                       \
   template int launch_spread_near<R>(int, const GridArgs&, const int32_t*, const int32_t*, const double*, \
                                      int64_t, const void*, int, void*, hipStream_t);                     \
