@@ -20,6 +20,8 @@ constexpr int kMaxNearOrder = 8;
 constexpr int kMaxFarOrder = 9;
 constexpr int kMaxCorrRadius = 40;
 constexpr size_t kLdsBudget = 64 * 1024;
+// planes up to which the near projection runs through the node-major weight CSR
+constexpr int kSpreadCsrPlanes = 4;
 
 #define HIPCHK(expr)                                  \
   do {                                                \
@@ -353,7 +355,11 @@ int run_apply(fftpim_plan_s* p, int parts, bool adjoint, const void* in, void* o
     // Steps 1-3 of Sec. 3.3 (the same grid serves sources and observers)
     {
       StageTimer t(p, st, FFTPIM_STAGE_NEAR_SPREAD);
-      CHK(launch_spread_near<R>(p->ng.q, ga, p->box_start, p->near_s, p->near_w, N, p->q_int, P, p->grid0, st));
+      if (p->wt_row != nullptr)
+        launch_spread_csr<R>(p->wt_row, p->wt_idx, p->wt_val, static_cast<int64_t>(p->ng.n[0]) * p->ng.n[1] * p->ng.n[2],
+                             p->q_int, P, p->grid0, st);
+      else
+        CHK(launch_spread_near<R>(p->ng.q, ga, p->box_start, p->near_s, p->near_w, N, p->q_int, P, p->grid0, st));
     }
     {
       StageTimer t(p, st, FFTPIM_STAGE_NEAR_FFT);
@@ -1080,7 +1086,37 @@ int build_plan(fftpim_plan_s* p, int64_t N, const double* src_dev, hipStream_t s
   CHK(upload(p, &p->fs_u, fs_u));
   CHK(upload(p, &p->fo_s, fo_s));
   CHK(upload(p, &p->fo_u, fo_u));
-  CHK(upload(p, &p->near_w, weights_soa(u_sorted, N, g.q)));
+  const std::vector<double> w_near = weights_soa(u_sorted, N, g.q);
+  CHK(upload(p, &p->near_w, w_near));
+  if (planes_for(p, pm.nrhs_max) <= kSpreadCsrPlanes) {
+    // W^T by grid node (Step 1 of Sec. 3.3 as a sparse product): entries of a
+    // node in increasing point order, weight = product of the 1D weights
+    const int K1 = g.q + 1;
+    const int64_t n3 = static_cast<int64_t>(g.n[0]) * g.n[1] * g.n[2];
+    std::vector<int64_t> wrow(n3 + 1, 0);
+    auto node_of = [&](int64_t m, int a, int b, int c) {
+      return (static_cast<int64_t>(s_sorted[m] + a) * g.n[1] + (s_sorted[N + m] + b)) * g.n[2] + (s_sorted[2 * N + m] + c);
+    };
+    for (int64_t m = 0; m < N; ++m)
+      for (int a = 0; a < K1; ++a)
+        for (int b = 0; b < K1; ++b)
+          for (int c = 0; c < K1; ++c) wrow[node_of(m, a, b, c) + 1]++;
+    for (int64_t k = 0; k < n3; ++k) wrow[k + 1] += wrow[k];
+    std::vector<int64_t> cur(wrow.begin(), wrow.end() - 1);
+    std::vector<int32_t> widx(static_cast<size_t>(wrow[n3]));
+    std::vector<double> wval(static_cast<size_t>(wrow[n3]));
+    for (int64_t m = 0; m < N; ++m)
+      for (int a = 0; a < K1; ++a)
+        for (int b = 0; b < K1; ++b)
+          for (int c = 0; c < K1; ++c) {
+            const int64_t k = cur[node_of(m, a, b, c)]++;
+            widx[k] = static_cast<int32_t>(m);
+            wval[k] = w_near[a * N + m] * w_near[(K1 + b) * N + m] * w_near[(2 * K1 + c) * N + m];
+          }
+    CHK(upload(p, &p->wt_row, wrow));
+    CHK(upload(p, &p->wt_idx, widx));
+    CHK(upload(p, &p->wt_val, wval));
+  }
   CHK(upload(p, &p->fs_w, weights_soa(fs_u, N, f.q)));
   CHK(upload(p, &p->fo_w, weights_soa(fo_u, N, f.q)));
   CHK(upload(p, &p->fperm_s, forder_s));

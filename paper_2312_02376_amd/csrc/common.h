@@ -214,6 +214,10 @@ struct fftpim_plan_s {
   // correction (FP64 values)
   int64_t* rowptr = nullptr;
   double* sums_work = nullptr;     // scratch of the plane sums
+  // node-major transposed near weights (plans with at most kSpreadCsrPlanes planes)
+  int64_t* wt_row = nullptr;
+  int32_t* wt_idx = nullptr;
+  double* wt_val = nullptr;
   int32_t* corr_order = nullptr;   // [corr_slots] row of each wavefront slot (-1: idle)
   // dense row tiles (real correction values): see build_tiles
   bool tile = false;

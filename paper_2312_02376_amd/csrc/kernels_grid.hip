@@ -233,6 +233,35 @@ __global__ void __launch_bounds__(256) k_spread_near(
   }
 }
 
+// Projection from a node-major weight list (few planes): the transposed
+// interpolation weights W^T as CSR by grid node, entries in increasing point
+// order, built at plan time.  16 lanes per node add its entries and combine
+// them by a fixed shuffle order; nodes without entries are written as zero.
+template <typename R>
+__global__ void __launch_bounds__(256) k_spread_csr(const int64_t* __restrict__ wrow, const int32_t* __restrict__ widx,
+                                                    const double* __restrict__ wval, int64_t n3,
+                                                    const cplx<R>* __restrict__ qint, int P,
+                                                    cplx<R>* __restrict__ grid) {
+  const int64_t node = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 4;
+  const int sl = threadIdx.x & 15;
+  if (node >= n3) return;  // all 16 lanes of a node leave together
+  const int64_t j0 = wrow[node], j1 = wrow[node + 1];
+  for (int p = 0; p < P; ++p) {
+    double ar = 0.0, ai = 0.0;
+    for (int64_t j = j0 + sl; j < j1; j += 16) {
+      const double w = wval[j];
+      const cplx<R> q = qint[static_cast<int64_t>(widx[j]) * P + p];
+      ar += w * static_cast<double>(q.x);
+      ai += w * static_cast<double>(q.y);
+    }
+    for (int off = 8; off > 0; off >>= 1) {
+      ar += __shfl_xor(ar, off, 16);
+      ai += __shfl_xor(ai, off, 16);
+    }
+    if (sl == 0) grid[node * P + p] = cmake<R>(static_cast<R>(ar), static_cast<R>(ai));
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Step 3: interpolation from a grid to points (also the far zone's Step 3)
 // ---------------------------------------------------------------------------
@@ -677,6 +706,13 @@ static void spread_q(const GridArgs& g, const int32_t* box_start, const int32_t*
 }
 
 template <typename R>
+void launch_spread_csr(const int64_t* wrow, const int32_t* widx, const double* wval, int64_t n3, const void* qint,
+                       int P, void* grid, hipStream_t st) {
+  hipLaunchKernelGGL((k_spread_csr<R>), dim3(blocks_for(n3 * 16, 256)), dim3(256), 0, st, wrow, widx, wval, n3,
+                     static_cast<const cplx<R>*>(qint), P, static_cast<cplx<R>*>(grid));
+}
+
+template <typename R>
 int launch_spread_near(int q, const GridArgs& g, const int32_t* box_start, const int32_t* s3, const double* u3,
                        int64_t N, const void* qint, int P, void* grid, hipStream_t st) {
   switch (q) {
@@ -778,6 +814,8 @@ void launch_scale_convert(const void* in, void* out, int64_t n, double s, hipStr
                                  int, int, bool, bool, const double*, hipStream_t);                      \
   template void launch_plane_sums<R>(const void*, const void*, const void*, int64_t, int, double*, double*, \
                                      hipStream_t);                                                       \
+  template void launch_spread_csr<R>(const int64_t*, const int32_t*, const double*, int64_t, const void*, int, \
+                                     void*, hipStream_t);                                                \
   template int launch_spread_near<R>(int, const GridArgs&, const int32_t*, const int32_t*, const double*, \
                                      int64_t, const void*, int, void*, hipStream_t);                     \
   template int launch_interp<R>(int, const GridArgs&, const int32_t*, const double*, int64_t,            \

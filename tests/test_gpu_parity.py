@@ -236,7 +236,7 @@ def test_csr_layout(name):
 
 
 @pytest.mark.parametrize("name", ["npsp3_real", "npsp2_real", "npsp1_real"])
-@pytest.mark.parametrize("nrhs", [3, 19])
+@pytest.mark.parametrize("nrhs", [3, 19, 80])
 def test_tile_layout(name, nrhs):
     # real correction values in dense 16-observer tiles on the matrix cores
     lat, ref, plan, qv = _setup(name, N=400, seed=29, nrhs=nrhs, corr_layout="tile")
