@@ -247,3 +247,36 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def _autograd_function():
+    import torch
+
+    class FFTPIMFunction(torch.autograd.Function):
+        """u = A q with dL/dq = A^H dL/du: the backward pass is the library's
+        conjugate-transpose apply (for a real loss of complex u, PyTorch's
+        gradient convention makes the gradient of q exactly A^H times the
+        gradient of u; for real static kernels A^H = A^T).  Gradients with
+        respect to positions are not provided."""
+
+        @staticmethod
+        def forward(ctx, q, plan):
+            ctx.plan = plan
+            return plan.apply(q)
+
+        @staticmethod
+        def backward(ctx, gu):
+            return ctx.plan.adjoint(gu.contiguous()), None
+
+    return FFTPIMFunction
+
+
+_FN = None
+
+
+def apply_autograd(plan, q):
+    """Differentiable u = A q (amplitudes only) for a Plan."""
+    global _FN
+    if _FN is None:
+        _FN = _autograd_function()
+    return _FN.apply(q, plan)
