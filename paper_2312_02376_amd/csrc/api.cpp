@@ -296,11 +296,11 @@ int run_apply(fftpim_plan_s* p, int parts, bool adjoint, const void* in, void* o
       launch_check_neutral(p->sums, P, p->prm.precision == FFTPIM_F32 ? 1e-5 : 1e-10, p->status_dev, st);
     }
   }
-  // Fork: the correction (Sec. 3.3 Step 4) and the far zone (Sec. 3.2) only
-  // read the packed amplitudes, so they run on their own streams while the
-  // near-grid steps run on the caller's stream (the paper runs near and far
-  // zones concurrently on two streams, Sec. 4.2).  Each part writes its own
-  // buffer; the unpack sums them in a fixed order.
+  // Fork: the correction (Sec. 3.3 Step 4), the near-grid steps and the far
+  // zone (Sec. 3.2) only read the packed amplitudes, so each runs on a stream
+  // of the plan (the paper runs near and far zones concurrently on two
+  // streams, Sec. 4.2) and the caller's stream joins them.  Each part writes
+  // its own buffer; the unpack sums them in a fixed order.
   const bool do_corr = (parts & FFTPIM_PART_NEAR_CORR) != 0;
   const bool do_far = (parts & FFTPIM_PART_FAR) != 0;
   HIPCHK(hipEventRecord(p->ev_fork, st));
@@ -351,26 +351,33 @@ int run_apply(fftpim_plan_s* p, int parts, bool adjoint, const void* in, void* o
     HIPCHK(hipEventRecord(p->ev_far, sf));
   }
   const GridArgs ga = grid_args(p->ng);
-  if (parts & FFTPIM_PART_NEAR_GRID) {
+  const bool do_near = (parts & FFTPIM_PART_NEAR_GRID) != 0;
+  if (do_near) {
     // Steps 1-3 of Sec. 3.3 (the same grid serves sources and observers)
+    hipStream_t sn = p->s_near;
+    HIPCHK(hipStreamWaitEvent(sn, p->ev_fork, 0));
     {
-      StageTimer t(p, st, FFTPIM_STAGE_NEAR_SPREAD);
+      StageTimer t(p, sn, FFTPIM_STAGE_NEAR_SPREAD);
       if (p->wt_row != nullptr)
         launch_spread_csr<R>(p->wt_row, p->wt_idx, p->wt_val, static_cast<int64_t>(p->ng.n[0]) * p->ng.n[1] * p->ng.n[2],
-                             p->q_int, P, p->grid0, st);
+                             p->q_int, P, p->grid0, sn);
       else
-        CHK(launch_spread_near<R>(p->ng.q, ga, p->box_start, p->near_s, p->near_w, N, p->q_int, P, p->grid0, st));
+        CHK(launch_spread_near<R>(p->ng.q, ga, p->box_start, p->near_s, p->near_w, N, p->q_int, P, p->grid0, sn));
     }
     {
-      StageTimer t(p, st, FFTPIM_STAGE_NEAR_FFT);
-      near_convolution<R>(p, P, adjoint, st);
+      StageTimer t(p, sn, FFTPIM_STAGE_NEAR_FFT);
+      near_convolution<R>(p, P, adjoint, sn);
     }
-    StageTimer t(p, st, FFTPIM_STAGE_NEAR_INTERP);
-    CHK(launch_interp<R>(p->ng.q, ga, p->near_s, p->near_w, N, p->grid0, P, p->u_int, false, st));
+    {
+      StageTimer t(p, sn, FFTPIM_STAGE_NEAR_INTERP);
+      CHK(launch_interp<R>(p->ng.q, ga, p->near_s, p->near_w, N, p->grid0, P, p->u_int, false, sn));
+    }
+    HIPCHK(hipEventRecord(p->ev_near, sn));
   }
   // join
   if (do_corr) HIPCHK(hipStreamWaitEvent(st, p->ev_corr, 0));
   if (do_far) HIPCHK(hipStreamWaitEvent(st, p->ev_far, 0));
+  if (do_near) HIPCHK(hipStreamWaitEvent(st, p->ev_near, 0));
   const void* un = (parts & FFTPIM_PART_NEAR_GRID) ? p->u_int : nullptr;
   const void* uc = do_corr ? p->u_corr : nullptr;
   const void* uf = do_far ? p->u_far : nullptr;
@@ -1180,9 +1187,11 @@ int build_plan(fftpim_plan_s* p, int64_t N, const double* src_dev, hipStream_t s
   p->u_far = b;
   HIPCHK(hipStreamCreateWithFlags(&p->s_corr, hipStreamNonBlocking));
   HIPCHK(hipStreamCreateWithFlags(&p->s_far, hipStreamNonBlocking));
+  HIPCHK(hipStreamCreateWithFlags(&p->s_near, hipStreamNonBlocking));
   HIPCHK(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&p->ev_corr, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&p->ev_far, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&p->ev_near, hipEventDisableTiming));
   CHK(dalloc(p, &b, static_cast<size_t>(n3) * P * es));
   p->grid0 = b;
   CHK(dalloc(p, &b, static_cast<size_t>(g.n[0]) * g.n[1] * p->M[2] * P * es));
@@ -1364,14 +1373,14 @@ int fftpim_stage_times(fftpim_plan_t plan, int enable, double* ms_out, int64_t* 
 int fftpim_destroy(fftpim_plan_t plan) {
   if (!plan) return FFTPIM_OK;
   // the plan's streams may still be reading its buffers
-  for (hipStream_t s : {plan->s_corr, plan->s_far})
+  for (hipStream_t s : {plan->s_corr, plan->s_far, plan->s_near})
     if (s) hipStreamSynchronize(s);
   hipStreamSynchronize(plan->last_stream);
   for (hipEvent_t e : plan->ev_pool) hipEventDestroy(e);
   plan->ev_pool.clear();
-  for (hipEvent_t e : {plan->ev_fork, plan->ev_corr, plan->ev_far})
+  for (hipEvent_t e : {plan->ev_fork, plan->ev_corr, plan->ev_far, plan->ev_near})
     if (e) hipEventDestroy(e);
-  for (hipStream_t s : {plan->s_corr, plan->s_far})
+  for (hipStream_t s : {plan->s_corr, plan->s_far, plan->s_near})
     if (s) hipStreamDestroy(s);
   for (void* ptr : plan->allocations) hipFree(ptr);
   plan->allocations.clear();

@@ -241,8 +241,8 @@ struct fftpim_plan_s {
   void* u_far = nullptr;          // [N][planes] far-zone part
   // the correction and the far zone run on their own streams, forked from and
   // joined back into the caller's stream with events (default priority)
-  hipStream_t s_corr = nullptr, s_far = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_corr = nullptr, ev_far = nullptr;
+  hipStream_t s_corr = nullptr, s_far = nullptr, s_near = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_corr = nullptr, ev_far = nullptr, ev_near = nullptr;
   void* grid0 = nullptr;          // [planes][n^3]
   void* bufA = nullptr;           // [planes][nx][ny][Mz]
   void* bufB = nullptr;           // [planes][nx][My][Mz]
