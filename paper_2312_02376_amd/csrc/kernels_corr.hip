@@ -402,33 +402,51 @@ __global__ void __launch_bounds__(64 * kTileWaves) k_corr_tile(const int32_t* __
 #pragma unroll
     for (int ch = 0; ch < 4; ++ch) acc[ch] = tile_d4{0.0, 0.0, 0.0, 0.0};
     // 64 union columns (16 k-steps) at a time: each lane loads one column
-    // index, the k-steps take theirs by lane shuffle, and two k-steps of
-    // value and amplitude loads are issued before their MFMAs
+    // index and the k-steps take theirs by lane shuffle.  Loads run one group
+    // of two k-steps ahead of the MFMAs (software pipelining); they are
+    // branch-free (idle slots read valid addresses and are zeroed), so the
+    // compiler keeps the next group's loads in flight across the MFMAs.
     constexpr int U = 2;
     for (int64_t cb = 0; cb < C; cb += 64) {
       const int colv = (cb + lane < C) ? cols[c0 + cb + lane] : -1;
       const int64_t sb = cb >> 2;
       const int ns = static_cast<int>(min<int64_t>(16, nks - sb));
-      for (int s0 = 0; s0 < ns; s0 += U) {
-        double a[U];
-        R b[U][4];
+      auto load_group = [&](int s0, double (&a)[U], R (&b)[U][4]) {
 #pragma unroll
         for (int uu = 0; uu < U; ++uu) {
           const int s = s0 + uu;
           const bool sok = s < ns;
-          a[uu] = sok ? __builtin_nontemporal_load(v + (sb + s) * 64 + lane) : 0.0;
+          const double av = __builtin_nontemporal_load(v + (sb + (sok ? s : 0)) * 64 + lane);
+          a[uu] = sok ? av : 0.0;
           const int n = __shfl(colv, (4 * s + kk) & 63, 64);
+          const bool nok = sok && n >= 0;
 #pragma unroll
           for (int ch = 0; ch < 4; ++ch) {
             const int j = cg + 16 * ch + jl;
-            b[uu][ch] = (sok && n >= 0 && j < P2) ? x[static_cast<int64_t>(n) * P2 + j] : R(0);
+            const bool ok = nok && j < P2;
+            const R xv = x[static_cast<int64_t>(ok ? n : 0) * P2 + (ok ? j : 0)];
+            b[uu][ch] = ok ? xv : R(0);
           }
         }
+      };
+      double a0[U];
+      R b0[U][4];
+      load_group(0, a0, b0);
+      for (int s0 = 0; s0 < ns; s0 += U) {
+        double a1[U];
+        R b1[U][4];
+        load_group(s0 + U, a1, b1);  // past the end: zeros from valid addresses
 #pragma unroll
         for (int uu = 0; uu < U; ++uu)
 #pragma unroll
           for (int ch = 0; ch < 4; ++ch)
-            acc[ch] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[uu], static_cast<double>(b[uu][ch]), acc[ch], 0, 0, 0);
+            acc[ch] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[uu], static_cast<double>(b0[uu][ch]), acc[ch], 0, 0, 0);
+#pragma unroll
+        for (int uu = 0; uu < U; ++uu) {
+          a0[uu] = a1[uu];
+#pragma unroll
+          for (int ch = 0; ch < 4; ++ch) b0[uu][ch] = b1[uu][ch];
+        }
       }
     }
 #pragma unroll

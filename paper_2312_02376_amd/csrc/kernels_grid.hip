@@ -698,11 +698,21 @@ static void spread_q(const GridArgs& g, const int32_t* box_start, const int32_t*
   const unsigned tiles = static_cast<unsigned>(((g.n[0] + kSpreadTX - 1) / kSpreadTX) *
                                                ((g.n[1] + kSpreadTY - 1) / kSpreadTY) *
                                                ((g.n[2] + kSpreadTZ - 1) / kSpreadTZ));
-  FFTPIM_PB_DISPATCH(P, {
-    dim3 gr(tiles, (P + PB - 1) / PB);
-    hipLaunchKernelGGL((k_spread_near<R, Q, PB>), gr, dim3(256), 0, st, g, box_start, s3, u3, N,
-                       static_cast<const cplx<R>*>(qint), P, static_cast<cplx<R>*>(grid));
-  });
+  // with many planes a tile takes up to 32 at once, so every staged point is
+  // read once per 32 planes rather than once per 8
+#define FFTPIM_SPREAD_PB(PBV)                                                                              \
+  do {                                                                                                     \
+    dim3 gr(tiles, (P + PBV - 1) / PBV);                                                                   \
+    hipLaunchKernelGGL((k_spread_near<R, Q, PBV>), gr, dim3(256), 0, st, g, box_start, s3, u3, N,          \
+                       static_cast<const cplx<R>*>(qint), P, static_cast<cplx<R>*>(grid));                 \
+  } while (0)
+  if (P >= 32)
+    FFTPIM_SPREAD_PB(32);
+  else if (P >= 16)
+    FFTPIM_SPREAD_PB(16);
+  else
+    FFTPIM_PB_DISPATCH(P, FFTPIM_SPREAD_PB(PB));
+#undef FFTPIM_SPREAD_PB
 }
 
 template <typename R>
