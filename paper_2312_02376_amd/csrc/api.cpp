@@ -346,7 +346,13 @@ int run_apply(fftpim_plan_s* p, int parts, bool adjoint, const void* in, void* o
       CHK(launch_far_moments<R>(qf, fa, fbs, fpm, fw_in, N, p->q_int, P, p->far_mom, sf));
       CHK(launch_far_gather<R>(qf, fa, p->far_mom, P, p->far_q, sf));
       launch_far_apply<R>(fa, p->far_table, p->far_q, p->far_u, p->far_part, P, adjoint, sf);
-      CHK(launch_interp<R>(qf, grid_args(p->fg), fs_out, fw_out, N, p->far_u, P, p->u_far, false, sf));
+      // interpolation side: observer-grid boxes (forward) or source-grid boxes (adjoint)
+      const int32_t* fbs_out = adjoint ? p->fbox_start_s : p->fbox_start_o;
+      const int32_t* fpm_out = adjoint ? p->fperm_s : p->fperm_o;
+      const int maxb_out = adjoint ? p->fmax_box_s : p->fmax_box_o;
+      if (!launch_far_interp_box<R>(qf, fa, fbs_out, fpm_out, maxb_out, fs_out, fw_out, N, p->far_u, P, p->u_far,
+                                    false, sf))
+        CHK(launch_interp<R>(qf, grid_args(p->fg), fs_out, fw_out, N, p->far_u, P, p->u_far, false, sf));
     }
     HIPCHK(hipEventRecord(p->ev_far, sf));
   }
@@ -1084,6 +1090,10 @@ int build_plan(fftpim_plan_s* p, int64_t N, const double* src_dev, hipStream_t s
   std::vector<int32_t> forder_s, fstart_s, forder_o, fstart_o;
   counting_sort(fkey_s, fboxes, forder_s, fstart_s);
   counting_sort(fkey_o, fboxes, forder_o, fstart_o);
+  for (int64_t k = 0; k < fboxes; ++k) {
+    p->fmax_box_s = std::max(p->fmax_box_s, fstart_s[k + 1] - fstart_s[k]);
+    p->fmax_box_o = std::max(p->fmax_box_o, fstart_o[k + 1] - fstart_o[k]);
+  }
 
   CHK(upload(p, &p->perm, order));
   CHK(upload(p, &p->near_s, s_sorted));

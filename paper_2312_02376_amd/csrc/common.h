@@ -195,6 +195,7 @@ struct fftpim_plan_s {
   int32_t* fbox_start_s = nullptr;
   int32_t* fperm_o = nullptr;     // points ordered by far observer box
   int32_t* fbox_start_o = nullptr;
+  int fmax_box_s = 0, fmax_box_o = 0;  // most points in one far box (source / observer grid)
 
   // tables
   void* near_hat = nullptr;       // [Mx][My][Mz] complex R, scaled by 1/(Mx My Mz)

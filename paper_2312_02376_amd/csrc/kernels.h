@@ -171,6 +171,12 @@ template <typename R>
 int launch_far_gather(int qf, const FarArgs& f, const void* mom, int P, void* grid, hipStream_t st);
 // the far grid sum splits its inner dimension over this many blocks
 int far_apply_splits(int64_t Ngf, int P);
+// Far-zone interpolation staged per far box (batched planes); returns false
+// (nothing launched) when the case is not covered, e.g. few planes.
+template <typename R>
+bool launch_far_interp_box(int qf, const FarArgs& f, const int32_t* fbox_start, const int32_t* fperm, int max_box,
+                           const int32_t* s3, const double* w3, int64_t N, const void* grid, int P, void* u, bool acc,
+                           hipStream_t st);
 template <typename R>
 void launch_far_apply(const FarArgs& f, const void* table, const void* in, void* out, void* part, int P,
                       bool adjoint, hipStream_t st);

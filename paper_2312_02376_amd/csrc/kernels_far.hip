@@ -252,6 +252,111 @@ __global__ void __launch_bounds__(64 * kFarMfmaWaves) k_far_apply_mfma(FarArgs f
   }
 }
 
+// Step 3 with batched planes.  All points of a far box share one stencil
+// (the boxes are keyed by the stencil start), so a block stages the box's
+// (qf+1)^3 nodes x P planes in LDS once and interpolates a chunk of the box's
+// points from there, lanes over planes (LP planes x 64 / LP points per
+// wavefront).
+constexpr int kFarInterpChunk = 256;
+
+template <typename R, int QF, int LP>
+__global__ void __launch_bounds__(256) k_far_interp_box(FarArgs f, const int32_t* __restrict__ fbox_start,
+                                                        const int32_t* __restrict__ fperm,
+                                                        const int32_t* __restrict__ s3, const double* __restrict__ w3,
+                                                        int64_t N, const cplx<R>* __restrict__ grid, int P,
+                                                        cplx<R>* __restrict__ u, int accumulate) {
+  extern __shared__ unsigned char lds_raw[];
+  cplx<R>* sg = reinterpret_cast<cplx<R>*>(lds_raw);  // [K][P]
+  constexpr int K1 = QF + 1;
+  constexpr int K = K1 * K1 * K1;
+  constexpr int E = 64 / LP;
+  const int64_t b = blockIdx.x;
+  const int jb = fbox_start[b] + blockIdx.y * kFarInterpChunk;
+  const int je = min(fbox_start[b + 1], jb + kFarInterpChunk);
+  if (jb >= je) return;  // the whole block leaves together
+  const int m0 = fperm[fbox_start[b]];
+  const int sx = s3[m0], sy = s3[N + m0], sz = s3[2 * N + m0];
+  for (int t = threadIdx.x; t < K * P; t += blockDim.x) {
+    const int k = t / P, p = t - k * P;
+    const int a = k / (K1 * K1), bb = (k / K1) % K1, c = k % K1;
+    const int64_t node = (static_cast<int64_t>(sx + a) * f.nf[1] + (sy + bb)) * f.nf[2] + (sz + c);
+    sg[t] = grid[node * P + p];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int e = lane / LP, pl = lane % LP;
+  const int slot = (threadIdx.x >> 6) * E + e;
+  for (int j = jb + slot; j < je; j += (blockDim.x >> 6) * E) {
+    const int m = fperm[j];
+    double wx[K1], wy[K1], wz[K1];
+#pragma unroll
+    for (int a = 0; a < K1; ++a) {
+      wx[a] = w3[a * N + m];
+      wy[a] = w3[(K1 + a) * N + m];
+      wz[a] = w3[(2 * K1 + a) * N + m];
+    }
+    for (int pc = 0; pc < P; pc += LP) {
+      const int p = pc + pl;
+      if (p >= P) continue;
+      double ar = 0.0, ai = 0.0;
+      for (int a = 0; a < K1; ++a)
+        for (int bb = 0; bb < K1; ++bb) {
+          const double wab = wx[a] * wy[bb];
+          const cplx<R>* row = sg + ((a * K1 + bb) * K1) * P + p;
+#pragma unroll
+          for (int c = 0; c < K1; ++c) {
+            const cplx<R> v = row[c * P];
+            const double w = wab * wz[c];
+            ar += w * static_cast<double>(v.x);
+            ai += w * static_cast<double>(v.y);
+          }
+        }
+      cplx<R>* o = u + static_cast<int64_t>(m) * P + p;
+      cplx<R> r = cmake<R>(static_cast<R>(ar), static_cast<R>(ai));
+      if (accumulate) r = cadd(*o, r);
+      *o = r;
+    }
+  }
+}
+
+template <typename R, int QF>
+static bool far_interp_box_q(const FarArgs& f, const int32_t* fbox_start, const int32_t* fperm, int max_box,
+                             const int32_t* s3, const double* w3, int64_t N, const void* grid, int P, void* u,
+                             bool acc, hipStream_t st) {
+  constexpr int K = (QF + 1) * (QF + 1) * (QF + 1);
+  const size_t lds = static_cast<size_t>(K) * P * sizeof(cplx<R>);
+  if (P < 8 || lds > 128 * 1024) return false;
+  dim3 gr(static_cast<unsigned>(f.nboxes), static_cast<unsigned>((max_box + kFarInterpChunk - 1) / kFarInterpChunk));
+#define FFTPIM_FIB(LPV)                                                                                    \
+  hipLaunchKernelGGL((k_far_interp_box<R, QF, LPV>), gr, dim3(256), lds, st, f, fbox_start, fperm, s3, w3, N, \
+                     static_cast<const cplx<R>*>(grid), P, static_cast<cplx<R>*>(u), acc ? 1 : 0)
+  if (P <= 16)
+    FFTPIM_FIB(16);
+  else if (P <= 32)
+    FFTPIM_FIB(32);
+  else
+    FFTPIM_FIB(64);
+#undef FFTPIM_FIB
+  return true;
+}
+
+template <typename R>
+bool launch_far_interp_box(int qf, const FarArgs& f, const int32_t* fbox_start, const int32_t* fperm, int max_box,
+                           const int32_t* s3, const double* w3, int64_t N, const void* grid, int P, void* u, bool acc,
+                           hipStream_t st) {
+  if (max_box <= 0) return false;
+  switch (qf) {
+    case 1: return far_interp_box_q<R, 1>(f, fbox_start, fperm, max_box, s3, w3, N, grid, P, u, acc, st);
+    case 2: return far_interp_box_q<R, 2>(f, fbox_start, fperm, max_box, s3, w3, N, grid, P, u, acc, st);
+    case 3: return far_interp_box_q<R, 3>(f, fbox_start, fperm, max_box, s3, w3, N, grid, P, u, acc, st);
+    case 4: return far_interp_box_q<R, 4>(f, fbox_start, fperm, max_box, s3, w3, N, grid, P, u, acc, st);
+    case 5: return far_interp_box_q<R, 5>(f, fbox_start, fperm, max_box, s3, w3, N, grid, P, u, acc, st);
+    case 6: return far_interp_box_q<R, 6>(f, fbox_start, fperm, max_box, s3, w3, N, grid, P, u, acc, st);
+    case 7: return far_interp_box_q<R, 7>(f, fbox_start, fperm, max_box, s3, w3, N, grid, P, u, acc, st);
+    default: return false;
+  }
+}
+
 template <typename R>
 __global__ void k_far_reduce(const cplx<R>* __restrict__ part, cplx<R>* __restrict__ out, int64_t n, int nsplit) {
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -276,7 +381,11 @@ static void moments_q(const FarArgs& f, const int32_t* fbox_start, const int32_t
     hipLaunchKernelGGL((k_far_moments<R, QF, PBV>), gr, dim3(bs), 0, st, f, fbox_start, fperm, u3, N,       \
                        static_cast<const cplx<R>*>(qint), P, static_cast<cplx<R>*>(mom));                   \
   } while (0)
-  if (P >= 4)
+  if (P >= 16)
+    FFTPIM_MOM(16);
+  else if (P >= 8)
+    FFTPIM_MOM(8);
+  else if (P >= 4)
     FFTPIM_MOM(4);
   else if (P >= 2)
     FFTPIM_MOM(2);
@@ -385,7 +494,9 @@ void launch_far_apply(const FarArgs& f, const void* table, const void* in, void*
                                      int64_t, const void*, int, void*, hipStream_t);                       \
   template int launch_far_gather<R>(int, const FarArgs&, const void*, int, void*, hipStream_t);            \
   template void launch_far_apply<R>(const FarArgs&, const void*, const void*, void*, void*, int, bool,         \
-                                    hipStream_t);
+                                    hipStream_t);                                                          \
+  template bool launch_far_interp_box<R>(int, const FarArgs&, const int32_t*, const int32_t*, int, const int32_t*, \
+                                         const double*, int64_t, const void*, int, void*, bool, hipStream_t);
 
 FFTPIM_INST_FAR(double)
 FFTPIM_INST_FAR(float)
