@@ -66,6 +66,86 @@ __global__ void k_unpack(PartPtrs<R> parts, void* __restrict__ uu, const int32_t
   }
 }
 
+// Tiled forms of pack / unpack for several planes: a block transposes 64
+// points x 32 planes through LDS, so both the caller's [rhs][N] side and the
+// point-major [N][P] side are read and written in contiguous runs.
+constexpr int kTpPts = 64, kTpPl = 32;
+
+template <typename R, bool REAL_IN>
+__global__ void __launch_bounds__(256) k_pack_tiled(const void* __restrict__ qu, cplx<R>* __restrict__ qint,
+                                                    const int32_t* __restrict__ perm, int64_t N, int nrhs, int P,
+                                                    int use_perm) {
+  __shared__ cplx<R> tile[kTpPl][kTpPts + 1];
+  const int64_t m0 = static_cast<int64_t>(blockIdx.x) * kTpPts;
+  const int pc = blockIdx.y * kTpPl;
+  const int t = threadIdx.x;
+  for (int i = t; i < kTpPl * kTpPts; i += blockDim.x) {
+    const int pp = i / kTpPts, mm = i % kTpPts;
+    const int64_t m = m0 + mm;
+    const int p = pc + pp;
+    cplx<R> v = cmake<R>(R(0), R(0));
+    if (m < N && p < P) {
+      const int64_t src = use_perm ? perm[m] : m;
+      if (REAL_IN) {
+        const R* q = static_cast<const R*>(qu);
+        const int r0 = 2 * p, r1 = 2 * p + 1;
+        v.x = r0 < nrhs ? q[static_cast<int64_t>(r0) * N + src] : R(0);
+        v.y = r1 < nrhs ? q[static_cast<int64_t>(r1) * N + src] : R(0);
+      } else {
+        v = static_cast<const cplx<R>*>(qu)[static_cast<int64_t>(p) * N + src];
+      }
+    }
+    tile[pp][mm] = v;
+  }
+  __syncthreads();
+  for (int i = t; i < kTpPl * kTpPts; i += blockDim.x) {
+    const int mm = i / kTpPl, pp = i % kTpPl;
+    const int64_t m = m0 + mm;
+    const int p = pc + pp;
+    if (m < N && p < P) qint[m * P + p] = tile[pp][mm];
+  }
+}
+
+template <typename R, bool REAL_OUT>
+__global__ void __launch_bounds__(256) k_unpack_tiled(PartPtrs<R> parts, void* __restrict__ uu,
+                                                      const int32_t* __restrict__ perm, int64_t N, int nrhs, int P,
+                                                      int use_perm, const double* __restrict__ mean) {
+  __shared__ cplx<R> tile[kTpPl][kTpPts + 1];
+  const int64_t m0 = static_cast<int64_t>(blockIdx.x) * kTpPts;
+  const int pc = blockIdx.y * kTpPl;
+  const int t = threadIdx.x;
+  for (int i = t; i < kTpPl * kTpPts; i += blockDim.x) {
+    const int mm = i / kTpPl, pp = i % kTpPl;
+    const int64_t m = m0 + mm;
+    const int p = pc + pp;
+    if (m < N && p < P) {
+      cplx<R> v = parts.sum(m * P + p);
+      if (mean) {
+        v.x -= static_cast<R>(mean[2 * p]);
+        v.y -= static_cast<R>(mean[2 * p + 1]);
+      }
+      tile[pp][mm] = v;
+    }
+  }
+  __syncthreads();
+  for (int i = t; i < kTpPl * kTpPts; i += blockDim.x) {
+    const int pp = i / kTpPts, mm = i % kTpPts;
+    const int64_t m = m0 + mm;
+    const int p = pc + pp;
+    if (m >= N || p >= P) continue;
+    const int64_t dst = use_perm ? perm[m] : m;
+    const cplx<R> v = tile[pp][mm];
+    if (REAL_OUT) {
+      R* u = static_cast<R*>(uu);
+      const int r0 = 2 * p, r1 = 2 * p + 1;
+      if (r0 < nrhs) u[static_cast<int64_t>(r0) * N + dst] = v.x;
+      if (r1 < nrhs) u[static_cast<int64_t>(r1) * N + dst] = v.y;
+    } else {
+      static_cast<cplx<R>*>(uu)[static_cast<int64_t>(p) * N + dst] = v;
+    }
+  }
+}
+
 // Per-plane sums over points, deterministic, in two stages:
 // out[4p + 0/1] = sum of re/im, out[4p + 2/3] = sum of |re| / |im|.
 // Stage 1: block (chunk c, plane tile) sums kPlaneSumChunk points; its 256
@@ -624,6 +704,16 @@ static inline unsigned blocks_for(int64_t n, int bs) { return static_cast<unsign
 template <typename R>
 void launch_pack(const void* qu, void* qint, const int32_t* perm, int64_t N, int nrhs, int P,
                  bool real_in, bool use_perm, hipStream_t st) {
+  if (P >= 4) {
+    dim3 gr(static_cast<unsigned>((N + kTpPts - 1) / kTpPts), static_cast<unsigned>((P + kTpPl - 1) / kTpPl));
+    if (real_in)
+      hipLaunchKernelGGL((k_pack_tiled<R, true>), gr, dim3(256), 0, st, qu, static_cast<cplx<R>*>(qint), perm, N,
+                         nrhs, P, use_perm ? 1 : 0);
+    else
+      hipLaunchKernelGGL((k_pack_tiled<R, false>), gr, dim3(256), 0, st, qu, static_cast<cplx<R>*>(qint), perm, N,
+                         nrhs, P, use_perm ? 1 : 0);
+    return;
+  }
   unsigned nb = blocks_for(N * P, 256);
   if (real_in)
     hipLaunchKernelGGL((k_pack<R, true>), dim3(nb), dim3(256), 0, st, qu,
@@ -645,8 +735,18 @@ static PartPtrs<R> part_ptrs(const void* a, const void* b, const void* c) {
 template <typename R>
 void launch_unpack(const void* u_near, const void* u_corr, const void* u_far, void* uu, const int32_t* perm,
                    int64_t N, int nrhs, int P, bool real_out, bool use_perm, const double* mean, hipStream_t st) {
-  unsigned nb = blocks_for(N * P, 256);
   PartPtrs<R> s = part_ptrs<R>(u_near, u_corr, u_far);
+  if (P >= 4) {
+    dim3 gr(static_cast<unsigned>((N + kTpPts - 1) / kTpPts), static_cast<unsigned>((P + kTpPl - 1) / kTpPl));
+    if (real_out)
+      hipLaunchKernelGGL((k_unpack_tiled<R, true>), gr, dim3(256), 0, st, s, uu, perm, N, nrhs, P, use_perm ? 1 : 0,
+                         mean);
+    else
+      hipLaunchKernelGGL((k_unpack_tiled<R, false>), gr, dim3(256), 0, st, s, uu, perm, N, nrhs, P,
+                         use_perm ? 1 : 0, mean);
+    return;
+  }
+  unsigned nb = blocks_for(N * P, 256);
   if (real_out)
     hipLaunchKernelGGL((k_unpack<R, true>), dim3(nb), dim3(256), 0, st, s, uu, perm, N, nrhs, P, use_perm ? 1 : 0,
                        mean);
