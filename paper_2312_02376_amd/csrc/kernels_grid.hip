@@ -618,14 +618,26 @@ __global__ void __launch_bounds__(256) k_fft_pass(const cplx<R>* in,
   if (MODE == 0 || MODE == 2) lds_dit<R>(x, T, M, Ms, logM, tws, false);
   if (MODE == 2) {
     // the lines of a block share spectrum values: consecutive threads take
-    // consecutive lines at one frequency
-    for (int idx = threadIdx.x; idx < T * M; idx += blockDim.x) {
-      const int k = idx >> logT;
-      const int t = idx & (T - 1);
-      if (t < nlines) {
-        cplx<R> s = spec[static_cast<int64_t>(k) * d.spec_line + ((c0 + t) / d.spec_div) * d.spec_col];
-        if (conj_spec) s.y = -s.y;
-        x[t * Ms + k] = cmul(x[t * Ms + k], s);
+    // consecutive lines at one frequency; the spectrum loads are issued
+    // kFftLoadBatch per thread before they are used
+    for (int base = 0; base < T * M; base += blockDim.x * kFftLoadBatch) {
+      cplx<R> s[kFftLoadBatch];
+      int li[kFftLoadBatch];
+#pragma unroll
+      for (int u = 0; u < kFftLoadBatch; ++u) {
+        const int idx = base + u * blockDim.x + threadIdx.x;
+        const int k = idx >> logT;
+        const int t = idx & (T - 1);
+        li[u] = (idx < T * M && t < nlines) ? t * Ms + k : -1;
+        s[u] = li[u] >= 0 ? spec[static_cast<int64_t>(k) * d.spec_line + ((c0 + t) / d.spec_div) * d.spec_col]
+                          : cmake<R>(R(0), R(0));
+      }
+#pragma unroll
+      for (int u = 0; u < kFftLoadBatch; ++u) {
+        if (li[u] < 0) continue;
+        cplx<R> sv = s[u];
+        if (conj_spec) sv.y = -sv.y;
+        x[li[u]] = cmul(x[li[u]], sv);
       }
     }
     __syncthreads();
