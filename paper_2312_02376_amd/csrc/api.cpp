@@ -523,7 +523,31 @@ int build_tables(fftpim_plan_s* p, hipStream_t st) {
   // far-zone table G^p_far at the offsets between observer and source grids
   std::vector<cd> ft;
   int nf[3] = {p->fg.n[0], p->fg.n[1], p->fg.n[2]};
-  far_table(p->lat, id, nf, p->fg.h, ft);
+  if (p->lat.dims == 2 && !p->lat.npsp()) {
+    // the Floquet series of Eq. (pgf_2) needs up to ~1e5 terms per entry at
+    // the smallest z offsets: evaluated on the device
+    FarTableArgs ta{};
+    for (int c = 0; c < 3; ++c) {
+      ta.nf[c] = nf[c];
+      ta.delta[c] = p->fg.h[c];
+      ta.L[c] = p->lat.L[c];
+      ta.kt[c] = p->lat.kt[c];
+    }
+    ta.k0 = p->lat.k0;
+    ta.id = id;
+    const int64_t total = static_cast<int64_t>(2 * nf[0] - 1) * (2 * nf[1] - 1) * (2 * nf[2] - 1);
+    cplx<double>* dt = nullptr;
+    CHK(dalloc(p, &dt, static_cast<size_t>(total)));
+    launch_far_table_pgf2(ta, dt, st);
+    std::vector<cplx<double>> ht(static_cast<size_t>(total));
+    HIPCHK(hipMemcpyAsync(ht.data(), dt, total * sizeof(cplx<double>), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    dfree(p, dt);
+    ft.resize(static_cast<size_t>(total));
+    for (int64_t i = 0; i < total; ++i) ft[i] = cd(ht[i].x, ht[i].y);
+  } else {
+    far_table(p->lat, id, nf, p->fg.h, ft);
+  }
   std::vector<cplx<R>> ftr(ft.size());
   for (size_t i = 0; i < ft.size(); ++i) {
     if (!std::isfinite(ft[i].real()) || !std::isfinite(ft[i].imag())) return FFTPIM_ERR_UNSUPPORTED;

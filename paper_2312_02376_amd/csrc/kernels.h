@@ -87,6 +87,17 @@ struct SymArgs {
                                  //     sender's partials (senders in box order)
 };
 
+// Far-zone table on the device (2D-periodic kernels with k0 or a phase shift).
+struct FarTableArgs {
+  int nf[3];        // far grid nodes per axis
+  double delta[3];  // far grid spacing
+  double L[3];
+  double k0;
+  double kt[3];
+  int id;           // near-zone images per periodic axis
+};
+void launch_far_table_pgf2(const FarTableArgs& a, void* table, hipStream_t st);
+
 struct FarArgs {
   int nf[3], nint[3], nb[3];
   int64_t Ngf;

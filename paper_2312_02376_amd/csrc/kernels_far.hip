@@ -367,6 +367,105 @@ __global__ void k_far_reduce(const cplx<R>* __restrict__ part, cplx<R>* __restri
 }
 
 // ---------------------------------------------------------------------------
+// plan time: the far-zone table for 2D-periodic kernels with k0 or a phase
+// shift, on the device.  Entry e is G^p(r) - sum_{|i| <= i_d} phase_i G0(r -
+// R_i) at the offset r of the shifted observer and source grids (Sec. 3.2),
+// G^p from the Floquet series of Eq. (pgf_2) after reducing r into the cell
+// (Bloch phase).  One block per entry; threads take Floquet orders m, loop
+// over n, and the partial sums are added in a fixed tree order.
+// ---------------------------------------------------------------------------
+
+constexpr int kTableThreads = 256;
+
+__global__ void __launch_bounds__(kTableThreads) k_far_table_pgf2(FarTableArgs a, cplx<double>* __restrict__ table) {
+  __shared__ double shr[kTableThreads], shi[kTableThreads];
+  const double pi = 3.14159265358979323846;
+  const int sy = 2 * a.nf[1] - 1, sz = 2 * a.nf[2] - 1;
+  const int64_t e = blockIdx.x;
+  const int dz = static_cast<int>(e % sz), dy = static_cast<int>((e / sz) % sy),
+            dx = static_cast<int>(e / (static_cast<int64_t>(sz) * sy));
+  const double r0[3] = {(dx - (a.nf[0] - 1) - 0.5) * a.delta[0], (dy - (a.nf[1] - 1) - 0.5) * a.delta[1],
+                        (dz - (a.nf[2] - 1) - 0.5) * a.delta[2]};
+  // reduce x, y into the cell; Bloch phase of the shift
+  double r[3] = {r0[0], r0[1], r0[2]};
+  double arg = 0.0;
+  for (int c = 0; c < 2; ++c) {
+    const double n = round(r[c] / a.L[c]);
+    r[c] -= n * a.L[c];
+    arg += a.kt[c] * n * a.L[c];
+  }
+  const double az = fabs(r[2]);
+  const double kreach = 41.0 / az + fabs(a.k0) + fabs(a.kt[0]) + fabs(a.kt[1]);
+  const int mmax = static_cast<int>(ceil(kreach * a.L[0] / (2.0 * pi))) + 1;
+  const int nmax = static_cast<int>(ceil(kreach * a.L[1] / (2.0 * pi))) + 1;
+  double sr = 0.0, si = 0.0;
+  for (int m = -mmax + static_cast<int>(threadIdx.x); m <= mmax; m += kTableThreads) {
+    const double kx = a.kt[0] + 2.0 * pi * m / a.L[0];
+    double pr = 0.0, pim = 0.0;
+    for (int n = -nmax; n <= nmax; ++n) {
+      const double ky = a.kt[1] + 2.0 * pi * n / a.L[1];
+      const double w = a.k0 * a.k0 - kx * kx - ky * ky;
+      double s, c;
+      if (w >= 0.0) {
+        // propagating: exp(-j (ky y + kz |z|)) / kz
+        const double kz = sqrt(w);
+        sincos(-(ky * r[1] + kz * az), &s, &c);
+        pr += c / kz;
+        pim += s / kz;
+      } else {
+        // evanescent, kz = -j kappa: j exp(-kappa |z|) exp(-j ky y) / kappa
+        const double kap = sqrt(-w);
+        sincos(-ky * r[1], &s, &c);
+        const double fct = exp(-kap * az) / kap;
+        pr -= s * fct;
+        pim += c * fct;
+      }
+    }
+    double s, c;
+    sincos(-kx * r[0], &s, &c);
+    sr += c * pr - s * pim;
+    si += c * pim + s * pr;
+  }
+  shr[threadIdx.x] = sr;
+  shi[threadIdx.x] = si;
+  __syncthreads();
+  for (int h = kTableThreads / 2; h > 0; h >>= 1) {
+    if (static_cast<int>(threadIdx.x) < h) {
+      shr[threadIdx.x] += shr[threadIdx.x + h];
+      shi[threadIdx.x] += shi[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  // divide by 2 j Lx Ly, apply the Bloch phase exp(-j arg)
+  const double inv = 1.0 / (2.0 * a.L[0] * a.L[1]);
+  const double gr = shi[0] * inv, gi = -shr[0] * inv;
+  double ps, pc;
+  sincos(-arg, &ps, &pc);
+  double outr = pc * gr - ps * gi, outi = pc * gi + ps * gr;
+  // minus the near-zone images (unreduced offset)
+  for (int ix = -a.id; ix <= a.id; ++ix)
+    for (int iy = -a.id; iy <= a.id; ++iy) {
+      const double Rx = ix * a.L[0], Ry = iy * a.L[1];
+      const double ddx = r0[0] - Rx, ddy = r0[1] - Ry, ddz = r0[2];
+      const double dist = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
+      double s1, c1, s2, c2;
+      sincos(-(a.kt[0] * Rx + a.kt[1] * Ry), &s1, &c1);
+      sincos(-a.k0 * dist, &s2, &c2);
+      const double g = 1.0 / (4.0 * pi * dist);
+      outr -= (c1 * c2 - s1 * s2) * g;
+      outi -= (c1 * s2 + s1 * c2) * g;
+    }
+  table[e] = cmake<double>(outr, outi);
+}
+
+void launch_far_table_pgf2(const FarTableArgs& a, void* table, hipStream_t st) {
+  const int64_t total = static_cast<int64_t>(2 * a.nf[0] - 1) * (2 * a.nf[1] - 1) * (2 * a.nf[2] - 1);
+  hipLaunchKernelGGL(k_far_table_pgf2, dim3(static_cast<unsigned>(total)), dim3(kTableThreads), 0, st, a,
+                     static_cast<cplx<double>*>(table));
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 
