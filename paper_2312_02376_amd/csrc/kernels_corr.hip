@@ -384,7 +384,8 @@ typedef double tile_d4 __attribute__((ext_vector_type(4)));
 constexpr int kTileWaves = 4;
 
 template <typename R>
-__global__ void __launch_bounds__(64 * kTileWaves) k_corr_tile(const int32_t* __restrict__ tile_rows, int64_t ntiles,
+// six waves per SIMD (register budget) hide the gather latency better than four
+__global__ void __launch_bounds__(64 * kTileWaves) __attribute__((amdgpu_waves_per_eu(6, 8))) k_corr_tile(const int32_t* __restrict__ tile_rows, int64_t ntiles,
                                                                const int64_t* __restrict__ coff,
                                                                const int32_t* __restrict__ cols,
                                                                const int64_t* __restrict__ voff,
