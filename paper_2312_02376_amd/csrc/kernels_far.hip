@@ -480,11 +480,7 @@ static void moments_q(const FarArgs& f, const int32_t* fbox_start, const int32_t
     hipLaunchKernelGGL((k_far_moments<R, QF, PBV>), gr, dim3(bs), 0, st, f, fbox_start, fperm, u3, N,       \
                        static_cast<const cplx<R>*>(qint), P, static_cast<cplx<R>*>(mom));                   \
   } while (0)
-  if (P >= 16)
-    FFTPIM_MOM(16);
-  else if (P >= 8)
-    FFTPIM_MOM(8);
-  else if (P >= 4)
+  if (P >= 4)
     FFTPIM_MOM(4);
   else if (P >= 2)
     FFTPIM_MOM(2);
