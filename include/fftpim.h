@@ -161,6 +161,20 @@ int fftpim_apply(fftpim_plan_t plan, const void* q_dev, void* u_dev, int nrhs,
 int fftpim_apply_adjoint(fftpim_plan_t plan, const void* v_dev, void* w_dev, int nrhs,
                          fftpim_stream_t stream);
 
+/* u = A q and w = A^H v in one call (the pair Krylov solvers of the BiCG
+ * family need every iteration; A as in Eq. (1) through Eq. (5)).  Both
+ * products are computed in full and equal those of fftpim_apply and
+ * fftpim_apply_adjoint up to the summation order; the box-pair correction
+ * layout reads each stored block once for both.  q_dev, v_dev, u_dev, w_dev:
+ * device arrays [nrhs][n], same element type as fftpim_apply; u and w are
+ * overwritten and must not overlap each other or the inputs.  The static
+ * no-phase case checks q for neutrality and removes the mean of w, as the two
+ * single calls do.  The first call on a plan allocates four work arrays of
+ * n x planes elements (planes = nrhs_max, or half of it for real values);
+ * later calls allocate nothing.  Errors: INVALID_ARG, NO_MEMORY, DEVICE. */
+int fftpim_apply_pair(fftpim_plan_t plan, const void* q_dev, void* u_dev, const void* v_dev,
+                      void* w_dev, int nrhs, fftpim_stream_t stream);
+
 /* Apply only some parts of the operator (FFTPIM_PART_* mask) - forward
  * (adjoint = 0) or conjugate transpose (adjoint = 1).  PART_ALL equals
  * fftpim_apply / fftpim_apply_adjoint except that no mean is removed and no

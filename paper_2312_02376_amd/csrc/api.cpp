@@ -156,7 +156,7 @@ FftPassDesc pass_desc(int M, int n_in, int n_out, bool contig, int64_t nouter, i
 }
 
 template <typename R>
-void near_convolution(fftpim_plan_s* p, int P, bool adjoint, hipStream_t st) {
+void near_convolution(fftpim_plan_s* p, const WorkSet& ws, int P, bool adjoint, hipStream_t st) {
   // grids are [x][y][z][P]: a pass along one axis sees outer x line x columns,
   // the columns being the axes after it together with the planes
   const int nx = p->ng.n[0], ny = p->ng.n[1], nz = p->ng.n[2];
@@ -167,11 +167,11 @@ void near_convolution(fftpim_plan_s* p, int P, bool adjoint, hipStream_t st) {
   FftPassDesc dz = P == 1 ? pass_desc(Mz, nz, Mz, true, xy, 1, 1, nz, 1, Mz, es)
                           : pass_desc(Mz, nz, Mz, false, xy, P, P, static_cast<int64_t>(nz) * P, P,
                                       static_cast<int64_t>(Mz) * P, es);
-  launch_fft_pass<R>(0, p->grid0, p->bufA, dz, p->twiddle[2], nullptr, false, st);
+  launch_fft_pass<R>(0, ws.grid0, ws.bufA, dz, p->twiddle[2], nullptr, false, st);
   // y: bufA [nx][ny][Mz*P] -> bufB [nx][My][Mz*P]
   const int64_t zc = static_cast<int64_t>(Mz) * P;
   FftPassDesc dy = pass_desc(My, ny, My, false, nx, zc, zc, ny * zc, zc, My * zc, es);
-  launch_fft_pass<R>(0, p->bufA, p->bufB, dy, p->twiddle[1], nullptr, false, st);
+  launch_fft_pass<R>(0, ws.bufA, ws.bufB, dy, p->twiddle[1], nullptr, false, st);
   // x: in place on bufB [nx][My*Mz*P], fused spectrum multiply (one spectrum
   // value per (y, z) serves all planes)
   const int64_t cols = My * zc;
@@ -179,15 +179,15 @@ void near_convolution(fftpim_plan_s* p, int P, bool adjoint, hipStream_t st) {
   dx.spec_line = static_cast<int64_t>(My) * Mz;
   dx.spec_col = 1;
   dx.spec_div = P;
-  launch_fft_pass<R>(2, p->bufB, p->bufB, dx, p->twiddle[0], p->near_hat, adjoint, st);
+  launch_fft_pass<R>(2, ws.bufB, ws.bufB, dx, p->twiddle[0], p->near_hat, adjoint, st);
   // inverse y: bufB [nx][My][Mz*P] -> bufA [nx][ny][Mz*P]
   FftPassDesc iy = pass_desc(My, My, ny, false, nx, zc, zc, My * zc, zc, ny * zc, es);
-  launch_fft_pass<R>(1, p->bufB, p->bufA, iy, p->twiddle[1], nullptr, false, st);
+  launch_fft_pass<R>(1, ws.bufB, ws.bufA, iy, p->twiddle[1], nullptr, false, st);
   // inverse z: bufA [nx*ny][Mz][P] -> grid0 [nx*ny][nz][P]
   FftPassDesc iz = P == 1 ? pass_desc(Mz, Mz, nz, true, xy, 1, 1, Mz, 1, nz, es)
                           : pass_desc(Mz, Mz, nz, false, xy, P, P, static_cast<int64_t>(Mz) * P, P,
                                       static_cast<int64_t>(nz) * P, es);
-  launch_fft_pass<R>(1, p->bufA, p->grid0, iz, p->twiddle[2], nullptr, false, st);
+  launch_fft_pass<R>(1, ws.bufA, ws.grid0, iz, p->twiddle[2], nullptr, false, st);
 }
 
 SymArgs sym_args(const fftpim_plan_s* p) {
@@ -279,6 +279,79 @@ void resolve_timers(fftpim_plan_s* p) {
   p->ev_used = 0;
 }
 
+// Step 4 of Sec. 3.3 (the correction) for one input, on stream sc.
+template <typename R>
+void correction_zone(fftpim_plan_s* p, bool adjoint, const void* in, int P, void* out, hipStream_t sc) {
+  const int64_t N = p->N;
+  const void* v = (adjoint && p->helmholtz) ? p->val_adj : p->val;
+  if (p->tile) {
+    // real correction values: the operator is symmetric, so the conjugate
+    // transpose uses the same tiles
+    launch_corr_tile<R>(p->tile_rows, p->ntiles, p->tile_coff, p->tile_cols, p->tile_voff, p->tile_vals, in, P, out, sc);
+  } else if (p->sym) {
+    // in-cell part: A^H of a complex-symmetric block is conj(X conj(v))
+    launch_sym_apply<R>(p->complex_kernel, sym_args(p), p->sym_vals, in, nullptr, P, P, adjoint, false, p->sym_ypart,
+                        p->sym_zpart, out, nullptr, false, sc);
+    if (p->nnz > 0)
+      launch_corr_spmv<R>(p->complex_kernel, p->rowptr, p->col, v, N, p->corr_order, p->corr_slots, in, P, out, true,
+                          sc);
+  } else {
+    launch_corr_spmv<R>(p->complex_kernel, p->rowptr, p->col, v, N, p->corr_order, p->corr_slots, in, P, out, false,
+                        sc);
+  }
+}
+
+// Steps 1-3 of Sec. 3.2 for one input, on stream sf.  The adjoint projects
+// with the observer-grid weights, applies K^H and interpolates from the
+// source grid.
+template <typename R>
+int far_zone(fftpim_plan_s* p, const WorkSet& ws, bool adjoint, const void* in, int P, void* out,
+             hipStream_t sf) {
+  const int64_t N = p->N;
+  const FarArgs fa = far_args(p);
+  const int qf = p->fg.q;
+  const int32_t* fbs = adjoint ? p->fbox_start_o : p->fbox_start_s;
+  const int32_t* fpm = adjoint ? p->fperm_o : p->fperm_s;
+  const double* fw_in = adjoint ? p->fo_w : p->fs_w;
+  const int32_t* fs_out = adjoint ? p->fs_s : p->fo_s;
+  const double* fw_out = adjoint ? p->fs_w : p->fo_w;
+  CHK(launch_far_moments<R>(qf, fa, fbs, fpm, fw_in, N, in, P, ws.far_mom, sf));
+  CHK(launch_far_gather<R>(qf, fa, ws.far_mom, P, ws.far_q, sf));
+  launch_far_apply<R>(fa, p->far_table, ws.far_q, ws.far_u, ws.far_part, P, adjoint, sf);
+  // interpolation side: observer-grid boxes (forward) or source-grid boxes (adjoint)
+  const int32_t* fbs_out = adjoint ? p->fbox_start_s : p->fbox_start_o;
+  const int32_t* fpm_out = adjoint ? p->fperm_s : p->fperm_o;
+  const int maxb_out = adjoint ? p->fmax_box_s : p->fmax_box_o;
+  if (!launch_far_interp_box<R>(qf, fa, fbs_out, fpm_out, maxb_out, fs_out, fw_out, N, ws.far_u, P, out, false, sf))
+    CHK(launch_interp<R>(qf, grid_args(p->fg), fs_out, fw_out, N, ws.far_u, P, out, false, sf));
+  return FFTPIM_OK;
+}
+
+// Steps 1-3 of Sec. 3.3 for one input, on stream sn (the same grid serves
+// sources and observers).
+template <typename R>
+int near_grid_zone(fftpim_plan_s* p, const WorkSet& ws, bool adjoint, const void* in, int P, void* out,
+                   hipStream_t sn) {
+  const GridArgs ga = grid_args(p->ng);
+  {
+    StageTimer t(p, sn, FFTPIM_STAGE_NEAR_SPREAD);
+    if (p->wt_row != nullptr)
+      launch_spread_csr<R>(p->wt_row, p->wt_idx, p->wt_val, static_cast<int64_t>(p->ng.n[0]) * p->ng.n[1] * p->ng.n[2],
+                           in, P, ws.grid0, sn);
+    else
+      CHK(launch_spread_near<R>(p->ng.q, ga, p->box_start, p->near_s, p->near_w, p->N, in, P, ws.grid0, sn));
+  }
+  {
+    StageTimer t(p, sn, FFTPIM_STAGE_NEAR_FFT);
+    near_convolution<R>(p, ws, P, adjoint, sn);
+  }
+  {
+    StageTimer t(p, sn, FFTPIM_STAGE_NEAR_INTERP);
+    CHK(launch_interp<R>(p->ng.q, ga, p->near_s, p->near_w, p->N, ws.grid0, P, out, false, sn));
+  }
+  return FFTPIM_OK;
+}
+
 template <typename R>
 int run_apply(fftpim_plan_s* p, int parts, bool adjoint, const void* in, void* out, int nrhs, hipStream_t st,
               bool finalize) {
@@ -303,88 +376,37 @@ int run_apply(fftpim_plan_s* p, int parts, bool adjoint, const void* in, void* o
   // its own buffer; the unpack sums them in a fixed order.
   const bool do_corr = (parts & FFTPIM_PART_NEAR_CORR) != 0;
   const bool do_far = (parts & FFTPIM_PART_FAR) != 0;
+  const bool do_near = (parts & FFTPIM_PART_NEAR_GRID) != 0;
   HIPCHK(hipEventRecord(p->ev_fork, st));
   if (do_corr) {
     hipStream_t sc = p->s_corr;
     HIPCHK(hipStreamWaitEvent(sc, p->ev_fork, 0));
-    const void* v = (adjoint && p->helmholtz) ? p->val_adj : p->val;
     {
       StageTimer t(p, sc, FFTPIM_STAGE_NEAR_CORR);
-      if (p->tile) {
-        // real correction values: the operator is symmetric, so the
-        // conjugate transpose uses the same tiles
-        launch_corr_tile<R>(p->tile_rows, p->ntiles, p->tile_coff, p->tile_cols, p->tile_voff, p->tile_vals,
-                            p->q_int, P, p->u_corr, sc);
-      } else if (p->sym) {
-        // in-cell part: A^H of a complex-symmetric block is conj(X conj(v))
-        launch_sym_apply<R>(p->complex_kernel, sym_args(p), p->sym_vals, p->q_int, P, adjoint, p->sym_ypart,
-                            p->sym_zpart, p->u_corr, false, sc);
-        if (p->nnz > 0)
-          launch_corr_spmv<R>(p->complex_kernel, p->rowptr, p->col, v, N, p->corr_order, p->corr_slots, p->q_int, P,
-                              p->u_corr, true, sc);
-      } else {
-        launch_corr_spmv<R>(p->complex_kernel, p->rowptr, p->col, v, N, p->corr_order, p->corr_slots, p->q_int, P,
-                            p->u_corr, false, sc);
-      }
+      correction_zone<R>(p, adjoint, p->q_int, P, p->u_corr, sc);
     }
     HIPCHK(hipEventRecord(p->ev_corr, sc));
   }
   if (do_far) {
-    // Steps 1-3 of Sec. 3.2; the adjoint projects with the observer-grid
-    // weights, applies K^H and interpolates from the source grid
     hipStream_t sf = p->s_far;
     HIPCHK(hipStreamWaitEvent(sf, p->ev_fork, 0));
-    const FarArgs fa = far_args(p);
-    const int qf = p->fg.q;
-    const int32_t* fbs = adjoint ? p->fbox_start_o : p->fbox_start_s;
-    const int32_t* fpm = adjoint ? p->fperm_o : p->fperm_s;
-    const double* fw_in = adjoint ? p->fo_w : p->fs_w;
-    const int32_t* fs_out = adjoint ? p->fs_s : p->fo_s;
-    const double* fw_out = adjoint ? p->fs_w : p->fo_w;
     {
       StageTimer t(p, sf, FFTPIM_STAGE_FAR);
-      CHK(launch_far_moments<R>(qf, fa, fbs, fpm, fw_in, N, p->q_int, P, p->far_mom, sf));
-      CHK(launch_far_gather<R>(qf, fa, p->far_mom, P, p->far_q, sf));
-      launch_far_apply<R>(fa, p->far_table, p->far_q, p->far_u, p->far_part, P, adjoint, sf);
-      // interpolation side: observer-grid boxes (forward) or source-grid boxes (adjoint)
-      const int32_t* fbs_out = adjoint ? p->fbox_start_s : p->fbox_start_o;
-      const int32_t* fpm_out = adjoint ? p->fperm_s : p->fperm_o;
-      const int maxb_out = adjoint ? p->fmax_box_s : p->fmax_box_o;
-      if (!launch_far_interp_box<R>(qf, fa, fbs_out, fpm_out, maxb_out, fs_out, fw_out, N, p->far_u, P, p->u_far,
-                                    false, sf))
-        CHK(launch_interp<R>(qf, grid_args(p->fg), fs_out, fw_out, N, p->far_u, P, p->u_far, false, sf));
+      CHK(far_zone<R>(p, p->ws, adjoint, p->q_int, P, p->u_far, sf));
     }
     HIPCHK(hipEventRecord(p->ev_far, sf));
   }
-  const GridArgs ga = grid_args(p->ng);
-  const bool do_near = (parts & FFTPIM_PART_NEAR_GRID) != 0;
   if (do_near) {
-    // Steps 1-3 of Sec. 3.3 (the same grid serves sources and observers)
     hipStream_t sn = p->s_near;
     HIPCHK(hipStreamWaitEvent(sn, p->ev_fork, 0));
-    {
-      StageTimer t(p, sn, FFTPIM_STAGE_NEAR_SPREAD);
-      if (p->wt_row != nullptr)
-        launch_spread_csr<R>(p->wt_row, p->wt_idx, p->wt_val, static_cast<int64_t>(p->ng.n[0]) * p->ng.n[1] * p->ng.n[2],
-                             p->q_int, P, p->grid0, sn);
-      else
-        CHK(launch_spread_near<R>(p->ng.q, ga, p->box_start, p->near_s, p->near_w, N, p->q_int, P, p->grid0, sn));
-    }
-    {
-      StageTimer t(p, sn, FFTPIM_STAGE_NEAR_FFT);
-      near_convolution<R>(p, P, adjoint, sn);
-    }
-    {
-      StageTimer t(p, sn, FFTPIM_STAGE_NEAR_INTERP);
-      CHK(launch_interp<R>(p->ng.q, ga, p->near_s, p->near_w, N, p->grid0, P, p->u_int, false, sn));
-    }
+    CHK(near_grid_zone<R>(p, p->ws, adjoint, p->q_int, P, p->u_int, sn));
     HIPCHK(hipEventRecord(p->ev_near, sn));
   }
   // join
   if (do_corr) HIPCHK(hipStreamWaitEvent(st, p->ev_corr, 0));
   if (do_far) HIPCHK(hipStreamWaitEvent(st, p->ev_far, 0));
   if (do_near) HIPCHK(hipStreamWaitEvent(st, p->ev_near, 0));
-  const void* un = (parts & FFTPIM_PART_NEAR_GRID) ? p->u_int : nullptr;
+  const void* un = do_near ? p->u_int : nullptr;
   const void* uc = do_corr ? p->u_corr : nullptr;
   const void* uf = do_far ? p->u_far : nullptr;
   const double* mean = nullptr;
@@ -397,6 +419,139 @@ int run_apply(fftpim_plan_s* p, int parts, bool adjoint, const void* in, void* o
   {
     StageTimer t(p, st, FFTPIM_STAGE_UNPACK);
     launch_unpack<R>(un, uc, uf, out, p->perm, N, nrhs, P, real_io, use_perm, mean, st);
+  }
+  if (hipPeekAtLastError() != hipSuccess) return FFTPIM_ERR_DEVICE;
+  return FFTPIM_OK;
+}
+
+int alloc_work_set(fftpim_plan_s* p, WorkSet& ws) {
+  const int P = p->nplanes_max;
+  const size_t es = cbytes(p);
+  const GridGeom& g = p->ng;
+  const GridGeom& f = p->fg;
+  unsigned char* b = nullptr;
+  CHK(dalloc(p, &b, static_cast<size_t>(g.n[0]) * g.n[1] * g.n[2] * P * es));
+  ws.grid0 = b;
+  CHK(dalloc(p, &b, static_cast<size_t>(g.n[0]) * g.n[1] * p->M[2] * P * es));
+  ws.bufA = b;
+  CHK(dalloc(p, &b, static_cast<size_t>(g.n[0]) * p->M[1] * p->M[2] * P * es));
+  ws.bufB = b;
+  const int K1 = f.q + 1;
+  const int64_t fboxes = static_cast<int64_t>(p->fnb[0]) * p->fnb[1] * p->fnb[2];
+  CHK(dalloc(p, &b, static_cast<size_t>(fboxes) * K1 * K1 * K1 * P * es));
+  ws.far_mom = b;
+  const int64_t Ngf = static_cast<int64_t>(f.n[0]) * f.n[1] * f.n[2];
+  CHK(dalloc(p, &b, static_cast<size_t>(Ngf) * P * es));
+  ws.far_q = b;
+  CHK(dalloc(p, &b, static_cast<size_t>(Ngf) * P * es));
+  ws.far_u = b;
+  // the split count never exceeds min(64, ceil(Ngf / 256)) for any nrhs
+  const int64_t max_splits = std::min<int64_t>(64, std::max<int64_t>(1, (Ngf + 255) / 256));
+  CHK(dalloc(p, &b, static_cast<size_t>(max_splits) * Ngf * P * es));
+  ws.far_part = b;
+  return FFTPIM_OK;
+}
+
+// Work arrays of the fused pair (packed v, the three parts of w and a second
+// near/far work set), made on the first pair call of a plan.
+int ensure_pair_buffers(fftpim_plan_s* p) {
+  if (p->v_int != nullptr) return FFTPIM_OK;
+  CHK(alloc_work_set(p, p->ws2));
+  const size_t bytes = static_cast<size_t>(p->N) * p->nplanes_max * cbytes(p);
+  unsigned char* b = nullptr;
+  void* bufs[4];
+  for (int k = 0; k < 4; ++k) {
+    CHK(dalloc(p, &b, bytes));
+    bufs[k] = b;
+  }
+  p->u_int2 = bufs[1];
+  p->u_corr2 = bufs[2];
+  p->u_far2 = bufs[3];
+  p->v_int = bufs[0];
+  return FFTPIM_OK;
+}
+
+// u = A q and w = A^H v in one pass.  The box-pair correction reads each
+// stored block once for both products (its planes are q's followed by v's,
+// the latter conjugated on the way in and out).  The near-grid and far-zone
+// passes of the two products share two streams crosswise (near of A q then
+// far of A^H v on one, far of A q then near of A^H v on the other), each
+// product with its own work set, so both streams carry about the same work.
+template <typename R>
+int run_apply_pair(fftpim_plan_s* p, const void* q, void* u, const void* v, void* w, int nrhs, hipStream_t st) {
+  const int64_t N = p->N;
+  const int P = planes_for(p, nrhs);
+  const bool real_io = p->prm.value_type == FFTPIM_REAL;
+  const bool use_perm = p->prm.order_io == FFTPIM_ORDER_USER;
+  CHK(ensure_pair_buffers(p));
+  p->last_stream = st;
+  if (p->timing && p->ev_used > 4096) resolve_timers(p);
+  {
+    StageTimer t(p, st, FFTPIM_STAGE_PACK);
+    launch_pack<R>(q, p->q_int, p->perm, N, nrhs, P, real_io, use_perm, st);
+    launch_pack<R>(v, p->v_int, p->perm, N, nrhs, P, real_io, use_perm, st);
+    if (p->lat.npsp()) {
+      launch_plane_sums<R>(p->q_int, nullptr, nullptr, N, P, p->sums_work, p->sums, st);
+      launch_check_neutral(p->sums, P, p->prm.precision == FFTPIM_F32 ? 1e-5 : 1e-10, p->status_dev, st);
+    }
+  }
+  HIPCHK(hipEventRecord(p->ev_fork, st));
+  {
+    hipStream_t sc = p->s_corr;
+    HIPCHK(hipStreamWaitEvent(sc, p->ev_fork, 0));
+    {
+      StageTimer t(p, sc, FFTPIM_STAGE_NEAR_CORR);
+      // the fused box-pair pass stages both inputs in LDS (at most 64 KB, as
+      // the single apply)
+      if (p->sym && static_cast<int64_t>(p->symd.max_box) * 2 * P <= 2048) {
+        launch_sym_apply<R>(p->complex_kernel, sym_args(p), p->sym_vals, p->q_int, p->v_int, P, 2 * P, false, true,
+                            p->sym_ypart, p->sym_zpart, p->u_corr, p->u_corr2, false, sc);
+        if (p->nnz > 0) {
+          launch_corr_spmv<R>(p->complex_kernel, p->rowptr, p->col, p->val, N, p->corr_order, p->corr_slots, p->q_int,
+                              P, p->u_corr, true, sc);
+          launch_corr_spmv<R>(p->complex_kernel, p->rowptr, p->col, p->helmholtz ? p->val_adj : p->val, N,
+                              p->corr_order, p->corr_slots, p->v_int, P, p->u_corr2, true, sc);
+        }
+      } else {
+        correction_zone<R>(p, false, p->q_int, P, p->u_corr, sc);
+        correction_zone<R>(p, true, p->v_int, P, p->u_corr2, sc);
+      }
+    }
+    HIPCHK(hipEventRecord(p->ev_corr, sc));
+  }
+  {
+    hipStream_t sf = p->s_far;
+    HIPCHK(hipStreamWaitEvent(sf, p->ev_fork, 0));
+    {
+      StageTimer t(p, sf, FFTPIM_STAGE_FAR);
+      CHK(far_zone<R>(p, p->ws, false, p->q_int, P, p->u_far, sf));
+    }
+    CHK(near_grid_zone<R>(p, p->ws2, true, p->v_int, P, p->u_int2, sf));
+    HIPCHK(hipEventRecord(p->ev_far, sf));
+  }
+  {
+    hipStream_t sn = p->s_near;
+    HIPCHK(hipStreamWaitEvent(sn, p->ev_fork, 0));
+    CHK(near_grid_zone<R>(p, p->ws, false, p->q_int, P, p->u_int, sn));
+    {
+      StageTimer t(p, sn, FFTPIM_STAGE_FAR);
+      CHK(far_zone<R>(p, p->ws2, true, p->v_int, P, p->u_far2, sn));
+    }
+    HIPCHK(hipEventRecord(p->ev_near, sn));
+  }
+  HIPCHK(hipStreamWaitEvent(st, p->ev_corr, 0));
+  HIPCHK(hipStreamWaitEvent(st, p->ev_far, 0));
+  HIPCHK(hipStreamWaitEvent(st, p->ev_near, 0));
+  const double* mean = nullptr;
+  if (p->lat.npsp()) {
+    launch_plane_sums<R>(p->u_int2, p->u_corr2, p->u_far2, N, P, p->sums_work, p->sums, st);
+    launch_mean_from_sums(p->sums, P, N, p->sums + 4 * p->nplanes_max, st);
+    mean = p->sums + 4 * p->nplanes_max;
+  }
+  {
+    StageTimer t(p, st, FFTPIM_STAGE_UNPACK);
+    launch_unpack<R>(p->u_int, p->u_corr, p->u_far, u, p->perm, N, nrhs, P, real_io, use_perm, nullptr, st);
+    launch_unpack<R>(p->u_int2, p->u_corr2, p->u_far2, w, p->perm, N, nrhs, P, real_io, use_perm, mean, st);
   }
   if (hipPeekAtLastError() != hipSuccess) return FFTPIM_ERR_DEVICE;
   return FFTPIM_OK;
@@ -1226,28 +1381,13 @@ int build_plan(fftpim_plan_s* p, int64_t N, const double* src_dev, hipStream_t s
   HIPCHK(hipEventCreateWithFlags(&p->ev_corr, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&p->ev_far, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&p->ev_near, hipEventDisableTiming));
-  CHK(dalloc(p, &b, static_cast<size_t>(n3) * P * es));
-  p->grid0 = b;
-  CHK(dalloc(p, &b, static_cast<size_t>(g.n[0]) * g.n[1] * p->M[2] * P * es));
-  p->bufA = b;
-  CHK(dalloc(p, &b, static_cast<size_t>(g.n[0]) * p->M[1] * p->M[2] * P * es));
-  p->bufB = b;
-  const int K1 = f.q + 1;
-  CHK(dalloc(p, &b, static_cast<size_t>(fboxes) * K1 * K1 * K1 * P * es));
-  p->far_mom = b;
-  const int64_t Ngf = static_cast<int64_t>(f.n[0]) * f.n[1] * f.n[2];
-  CHK(dalloc(p, &b, static_cast<size_t>(Ngf) * P * es));
-  p->far_q = b;
-  CHK(dalloc(p, &b, static_cast<size_t>(Ngf) * P * es));
-  p->far_u = b;
-  // the split count never exceeds min(64, ceil(Ngf / 256)) for any nrhs
-  const int64_t max_splits = std::min<int64_t>(64, std::max<int64_t>(1, (Ngf + 255) / 256));
-  CHK(dalloc(p, &b, static_cast<size_t>(max_splits) * Ngf * P * es));
-  p->far_part = b;
+  CHK(alloc_work_set(p, p->ws));
   if (p->sym) {
-    CHK(dalloc(p, &b, static_cast<size_t>(std::max<int64_t>(p->symd.yslots, 1)) * P * 16));
+    // partial sums for twice the planes: the fused forward + adjoint pair
+    // carries both inputs through one pass
+    CHK(dalloc(p, &b, static_cast<size_t>(std::max<int64_t>(p->symd.yslots, 1)) * 2 * P * 16));
     p->sym_ypart = b;
-    CHK(dalloc(p, &b, static_cast<size_t>(std::max<int64_t>(p->symd.zslots, 1)) * P * 16));
+    CHK(dalloc(p, &b, static_cast<size_t>(std::max<int64_t>(p->symd.zslots, 1)) * 2 * P * 16));
     p->sym_zpart = b;
   }
   CHK(dalloc(p, &p->sums, static_cast<size_t>(6) * P));
@@ -1336,6 +1476,15 @@ int fftpim_apply(fftpim_plan_t plan, const void* q_dev, void* u_dev, int nrhs, f
 
 int fftpim_apply_adjoint(fftpim_plan_t plan, const void* v_dev, void* w_dev, int nrhs, fftpim_stream_t stream) {
   return apply_common(plan, FFTPIM_PART_ALL, 1, v_dev, w_dev, nrhs, stream, true);
+}
+
+int fftpim_apply_pair(fftpim_plan_t plan, const void* q_dev, void* u_dev, const void* v_dev, void* w_dev, int nrhs,
+                      fftpim_stream_t stream) {
+  if (!plan || !q_dev || !u_dev || !v_dev || !w_dev) return FFTPIM_ERR_INVALID_ARG;
+  if (nrhs < 1 || nrhs > plan->prm.nrhs_max) return FFTPIM_ERR_INVALID_ARG;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (plan->prm.precision == FFTPIM_F32) return run_apply_pair<float>(plan, q_dev, u_dev, v_dev, w_dev, nrhs, st);
+  return run_apply_pair<double>(plan, q_dev, u_dev, v_dev, w_dev, nrhs, st);
 }
 
 int fftpim_apply_parts(fftpim_plan_t plan, int parts, int adjoint, const void* q_dev, void* u_dev, int nrhs,

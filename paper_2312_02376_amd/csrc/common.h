@@ -163,6 +163,17 @@ struct DevBuf {
 
 }  // namespace fftpim
 
+// Work arrays of one near-grid + far-zone pass (all planes-innermost).
+struct WorkSet {
+  void* grid0 = nullptr;     // [nx][ny][nz][planes] near grid
+  void* bufA = nullptr;      // [nx][ny][Mz][planes] after the z pass
+  void* bufB = nullptr;      // [nx][My][Mz][planes] after the y pass
+  void* far_mom = nullptr;   // [far boxes][(qf+1)^3][planes] box moments
+  void* far_q = nullptr;     // [Ngf][planes] far source grid
+  void* far_u = nullptr;     // [Ngf][planes] far observer grid
+  void* far_part = nullptr;  // [splits][Ngf][planes] partial grid sums
+};
+
 struct fftpim_plan_s {
   fftpim::Lattice lat;
   fftpim_problem_t problem;
@@ -240,17 +251,16 @@ struct fftpim_plan_s {
   void* u_int = nullptr;          // [N][planes] complex R: near-grid part
   void* u_corr = nullptr;         // [N][planes] correction part
   void* u_far = nullptr;          // [N][planes] far-zone part
+  void* v_int = nullptr;          // fused pair only: packed adjoint input
+  void* u_int2 = nullptr;         // fused pair only: the three parts of A^H v
+  void* u_corr2 = nullptr;
+  void* u_far2 = nullptr;
   // the correction and the far zone run on their own streams, forked from and
   // joined back into the caller's stream with events (default priority)
   hipStream_t s_corr = nullptr, s_far = nullptr, s_near = nullptr;
   hipEvent_t ev_fork = nullptr, ev_corr = nullptr, ev_far = nullptr, ev_near = nullptr;
-  void* grid0 = nullptr;          // [planes][n^3]
-  void* bufA = nullptr;           // [planes][nx][ny][Mz]
-  void* bufB = nullptr;           // [planes][nx][My][Mz]
-  void* far_mom = nullptr;        // [far boxes][(qf+1)^3][planes]
-  void* far_q = nullptr;          // [planes][Ngf]
-  void* far_u = nullptr;          // [planes][Ngf]
-  void* far_part = nullptr;       // [splits][planes][Ngf] partial grid sums
+  WorkSet ws;                     // near-grid and far-zone work arrays
+  WorkSet ws2;                    // fused pair only: a second set
   double* sums = nullptr;         // [2][planes] neutrality / mean sums
   int* status_dev = nullptr;      // latched device-detected error
 

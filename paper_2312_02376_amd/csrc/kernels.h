@@ -171,8 +171,9 @@ void launch_corr_spmv(bool cplx_vals, const int64_t* rowptr, const int32_t* col,
 int launch_sym_fill(int q, bool cplx_vals, const SymArgs& a, const double* w3, const double* pos3,
                     const void* g0tab, void* vals, hipStream_t st);
 template <typename R>
-void launch_sym_apply(bool cplx_vals, const SymArgs& a, const void* vals, const void* x, int P, bool conj_io,
-                      void* ypart, void* zpart, void* u, bool accumulate, hipStream_t st);
+void launch_sym_apply(bool cplx_vals, const SymArgs& a, const void* vals, const void* x1, const void* x2, int P1,
+                      int P, bool conj1, bool conj2, void* ypart, void* zpart, void* u1, void* u2, bool accumulate,
+                      hipStream_t st);
 
 // far zone
 template <typename R>

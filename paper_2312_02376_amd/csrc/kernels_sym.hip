@@ -105,12 +105,26 @@ __global__ void __launch_bounds__(64) k_sym_fill(SymArgs a, const double* __rest
 
 typedef double dbl2v __attribute__((ext_vector_type(2)));
 
+// Inputs and outputs of one apply: planes [0, P1) come from x1 (stride P1) and
+// go to u1, planes [P1, P) from x2 / to u2 (stride P - P1), each set with its
+// own conjugation (a forward and a conjugate-transpose apply can share one
+// pass over the stored blocks: conj(X conj(v)) is the transpose apply).
 template <typename R>
-__device__ inline void load_planes(const cplx<R>* __restrict__ x, int64_t pt, int P, int p, bool conj_in, double& re,
-                                   double& im) {
-  const cplx<R> v = x[pt * P + p];
+struct SymIO {
+  const cplx<R>* x1;
+  const cplx<R>* x2;
+  cplx<R>* u1;
+  cplx<R>* u2;
+  int P1, P;
+  int conj1, conj2;
+};
+
+template <typename R>
+__device__ inline void load_planes(const SymIO<R>& io, int64_t pt, int p, double& re, double& im) {
+  const bool first = p < io.P1;
+  const cplx<R> v = first ? io.x1[pt * io.P1 + p] : io.x2[pt * (io.P - io.P1) + (p - io.P1)];
   re = static_cast<double>(v.x);
-  im = conj_in ? -static_cast<double>(v.y) : static_cast<double>(v.y);
+  im = (first ? io.conj1 : io.conj2) ? -static_cast<double>(v.y) : static_cast<double>(v.y);
 }
 
 // Reduce-scatter of 8 values per lane over the 64 lanes of a wavefront:
@@ -145,10 +159,11 @@ __device__ inline double wave_reduce_scatter8(double v[8], int lane) {
 // register reduce-scatter.  The group record alone gives every address, so
 // the value and source loads of a group issue without waiting on other
 // tables.  LDS holds x_B and the row accumulators.
-template <typename R, bool CPLX>
+template <typename R, bool CPLX, int PP>
 __device__ inline void sym_rows(const double* __restrict__ vr, const cplx<double>* __restrict__ vc,
-                                const cplx<double>* xb, cplx<double>* yacc, int nB, int P, int p, int lane, bool act,
-                                int64_t voff, int64_t stride, double xsr, double xsi, double& zr, double& zi) {
+                                const cplx<double>* xb, cplx<double>* yacc, int nB, int P, int pg, int lane, bool act,
+                                int64_t voff, int64_t stride, const double (&xsr)[PP], const double (&xsi)[PP],
+                                double (&zr)[PP], double (&zi)[PP]) {
   const int krow = ((lane >> 5) & 1) * 4 + ((lane >> 4) & 1) * 2 + ((lane >> 3) & 1);
   for (int r0 = 0; r0 < nB; r0 += 8) {
     double wr[8], wi[8];
@@ -168,34 +183,43 @@ __device__ inline void sym_rows(const double* __restrict__ vr, const cplx<double
         }
       }
     }
-    double pr_[8], pi_[8];
+    // every plane of the group uses the rows just loaded
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      if (r0 + k < nB) {
-        const cplx<double> xv = xb[(r0 + k) * P + p];
-        zr += wr[k] * xv.x - wi[k] * xv.y;
-        zi += wr[k] * xv.y + wi[k] * xv.x;
+    for (int pp = 0; pp < PP; ++pp) {
+      const int p = pg + pp;
+      if (p >= P) break;
+      double pr_[8], pi_[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        if (r0 + k < nB) {
+          const cplx<double> xv = xb[(r0 + k) * P + p];
+          zr[pp] += wr[k] * xv.x - wi[k] * xv.y;
+          zi[pp] += wr[k] * xv.y + wi[k] * xv.x;
+        }
+        pr_[k] = wr[k] * xsr[pp] - wi[k] * xsi[pp];
+        pi_[k] = wr[k] * xsi[pp] + wi[k] * xsr[pp];
       }
-      pr_[k] = wr[k] * xsr - wi[k] * xsi;
-      pi_[k] = wr[k] * xsi + wi[k] * xsr;
-    }
-    const double sr = wave_reduce_scatter8(pr_, lane);
-    const double si = wave_reduce_scatter8(pi_, lane);
-    if ((lane & 7) == 0 && r0 + krow < nB) {
-      cplx<double> acc = yacc[(r0 + krow) * P + p];
-      acc.x += sr;
-      acc.y += si;
-      yacc[(r0 + krow) * P + p] = acc;
+      const double sr = wave_reduce_scatter8(pr_, lane);
+      const double si = wave_reduce_scatter8(pi_, lane);
+      if ((lane & 7) == 0 && r0 + krow < nB) {
+        cplx<double> acc = yacc[(r0 + krow) * P + p];
+        acc.x += sr;
+        acc.y += si;
+        yacc[(r0 + krow) * P + p] = acc;
+      }
     }
   }
 }
 
-template <typename R, bool CPLX>
+// PP planes are processed per pass over a group's values (all planes when
+// P <= PP, so forward and transpose applies fused into one call read every
+// block once).
+template <typename R, bool CPLX, int PP>
 __global__ void __launch_bounds__(64) k_sym_apply(SymArgs a, const SymGroup* __restrict__ groups,
-                                                  const void* __restrict__ vals, const cplx<R>* __restrict__ x, int P,
-                                                  int conj_in, cplx<double>* __restrict__ ypart,
-                                                  cplx<double>* __restrict__ zpart) {
+                                                  const void* __restrict__ vals, SymIO<R> io,
+                                                  cplx<double>* __restrict__ ypart, cplx<double>* __restrict__ zpart) {
   extern __shared__ unsigned char lds_raw[];
+  const int P = io.P;
   const int item = a.item_order[blockIdx.x];
   const int lane = threadIdx.x;
   const int B = a.ebox[a.item_ebox[item]];
@@ -204,7 +228,7 @@ __global__ void __launch_bounds__(64) k_sym_apply(SymArgs a, const SymGroup* __r
   cplx<double>* yacc = xb + static_cast<int64_t>(a.max_box) * P;         // [nB][P]
   for (int t = lane; t < nB * P; t += 64) {
     double re, im;
-    load_planes<R>(x, m0 + t / P, P, t % P, conj_in, re, im);
+    load_planes<R>(io, m0 + t / P, t % P, re, im);
     xb[t] = cmake<double>(re, im);
     yacc[t] = cmake<double>(0.0, 0.0);
   }
@@ -222,14 +246,22 @@ __global__ void __launch_bounds__(64) k_sym_apply(SymArgs a, const SymGroup* __r
     if (lane >= g.end[0]) n = g.n0[1] + lane - g.end[0];
     if (lane >= g.end[1]) n = g.n0[2] + lane - g.end[1];
     if (lane >= g.end[2]) n = g.n0[3] + lane - g.end[2];
-    for (int p = 0; p < P; ++p) {
-      double xsr = 0.0, xsi = 0.0, zr = 0.0, zi = 0.0;
-      if (act) load_planes<R>(x, n, P, p, conj_in, xsr, xsi);
-      sym_rows<R, CPLX>(vr, vc, xb, yacc, nB, P, p, lane, act, g.voff, g.stride, xsr, xsi, zr, zi);
+    const bool wr = lane < (g.cum + kSymZAlign - 1) / kSymZAlign * kSymZAlign;
+    for (int pg = 0; pg < P; pg += PP) {
+      double xsr[PP], xsi[PP], zr[PP], zi[PP];
+#pragma unroll
+      for (int pp = 0; pp < PP; ++pp) {
+        xsr[pp] = xsi[pp] = zr[pp] = zi[pp] = 0.0;
+        if (act && pg + pp < P) load_planes<R>(io, n, pg + pp, xsr[pp], xsi[pp]);
+      }
+      sym_rows<R, CPLX, PP>(vr, vc, xb, yacc, nB, P, pg, lane, act, g.voff, g.stride, xsr, xsi, zr, zi);
       // the run is written whole, padded to 64-byte segments (padding and
       // diagonal-block columns are never read)
-      if (lane < (g.cum + kSymZAlign - 1) / kSymZAlign * kSymZAlign)
-        zpart[(g.zoff + lane) * P + p] = cmake<double>(zr, zi);
+      if (wr) {
+#pragma unroll
+        for (int pp = 0; pp < PP; ++pp)
+          if (pg + pp < P) zpart[(g.zoff + lane) * P + pg + pp] = cmake<double>(zr[pp], zi[pp]);
+      }
     }
   }
   __syncthreads();
@@ -247,10 +279,10 @@ constexpr int kGatherThreads = 256;
 
 template <typename R>
 __global__ void __launch_bounds__(kGatherThreads) k_sym_gather(SymArgs a, const cplx<double>* __restrict__ ypart,
-                                                               const cplx<double>* __restrict__ zpart, int P,
-                                                               int conj_out, cplx<R>* __restrict__ u,
+                                                               const cplx<double>* __restrict__ zpart, SymIO<R> io,
                                                                int accumulate) {
   __shared__ double sr_[kGatherThreads], si_[kGatherThreads];
+  const int P = io.P;
   const int kb = blockIdx.x;
   const int t = threadIdx.x;
   const int B = a.ebox[kb];
@@ -283,11 +315,15 @@ __global__ void __launch_bounds__(kGatherThreads) k_sym_gather(SymArgs a, const 
         tr += sr_[k * (S > 1 ? run : 0) + t];
         ti += si_[k * (S > 1 ? run : 0) + t];
       }
-      if (conj_out) ti = -ti;
-      const int64_t o = static_cast<int64_t>(m0) * P + (S > 1 ? t : e0 + t);
+      const int e = S > 1 ? t : e0 + t;  // (point, plane) slot within the box
+      const int r = e / P, p = e - (e / P) * P;
+      const bool first = p < io.P1;
+      if (first ? io.conj1 : io.conj2) ti = -ti;
+      cplx<R>* o = first ? io.u1 + static_cast<int64_t>(m0 + r) * io.P1 + p
+                         : io.u2 + static_cast<int64_t>(m0 + r) * (P - io.P1) + (p - io.P1);
       cplx<R> out = cmake<R>(static_cast<R>(tr), static_cast<R>(ti));
-      if (accumulate) out = cadd(u[o], out);
-      u[o] = out;
+      if (accumulate) out = cadd(*o, out);
+      *o = out;
     }
     __syncthreads();
   }
@@ -325,25 +361,37 @@ int launch_sym_fill(int q, bool cplx_vals, const SymArgs& a, const double* w3, c
 }
 
 template <typename R>
-void launch_sym_apply(bool cplx_vals, const SymArgs& a, const void* vals, const void* x, int P, bool conj_io,
-                      void* ypart, void* zpart, void* u, bool accumulate, hipStream_t st) {
+void launch_sym_apply(bool cplx_vals, const SymArgs& a, const void* vals, const void* x1, const void* x2, int P1,
+                      int P, bool conj1, bool conj2, void* ypart, void* zpart, void* u1, void* u2, bool accumulate,
+                      hipStream_t st) {
   const size_t lds = static_cast<size_t>(2) * a.max_box * P * sizeof(cplx<double>);
-  const cplx<R>* xx = static_cast<const cplx<R>*>(x);
+  SymIO<R> io;
+  io.x1 = static_cast<const cplx<R>*>(x1);
+  io.x2 = static_cast<const cplx<R>*>(x2);
+  io.u1 = static_cast<cplx<R>*>(u1);
+  io.u2 = static_cast<cplx<R>*>(u2);
+  io.P1 = P1;
+  io.P = P;
+  io.conj1 = conj1 ? 1 : 0;
+  io.conj2 = conj2 ? 1 : 0;
   cplx<double>* yp = static_cast<cplx<double>*>(ypart);
   cplx<double>* zp = static_cast<cplx<double>*>(zpart);
-  if (cplx_vals)
-    hipLaunchKernelGGL((k_sym_apply<R, true>), dim3(static_cast<unsigned>(a.nitems)), dim3(64), lds, st, a, a.groups,
-                       vals, xx, P, conj_io ? 1 : 0, yp, zp);
-  else
-    hipLaunchKernelGGL((k_sym_apply<R, false>), dim3(static_cast<unsigned>(a.nitems)), dim3(64), lds, st, a, a.groups,
-                       vals, xx, P, conj_io ? 1 : 0, yp, zp);
-  hipLaunchKernelGGL((k_sym_gather<R>), dim3(static_cast<unsigned>(a.nebox)), dim3(kGatherThreads), 0, st, a, yp, zp, P,
-                     conj_io ? 1 : 0, static_cast<cplx<R>*>(u), accumulate ? 1 : 0);
+  const dim3 gr(static_cast<unsigned>(a.nitems));
+#define FFTPIM_SYMAPPLY(C, PPV) \
+  hipLaunchKernelGGL((k_sym_apply<R, C, PPV>), gr, dim3(64), lds, st, a, a.groups, vals, io, yp, zp)
+  if (cplx_vals) {
+    if (P == 1) FFTPIM_SYMAPPLY(true, 1); else if (P == 2) FFTPIM_SYMAPPLY(true, 2); else FFTPIM_SYMAPPLY(true, 4);
+  } else {
+    if (P == 1) FFTPIM_SYMAPPLY(false, 1); else if (P == 2) FFTPIM_SYMAPPLY(false, 2); else FFTPIM_SYMAPPLY(false, 4);
+  }
+#undef FFTPIM_SYMAPPLY
+  hipLaunchKernelGGL((k_sym_gather<R>), dim3(static_cast<unsigned>(a.nebox)), dim3(kGatherThreads), 0, st, a, yp, zp, io,
+                     accumulate ? 1 : 0);
 }
 
-template void launch_sym_apply<double>(bool, const SymArgs&, const void*, const void*, int, bool, void*, void*, void*,
-                                       bool, hipStream_t);
-template void launch_sym_apply<float>(bool, const SymArgs&, const void*, const void*, int, bool, void*, void*, void*,
-                                      bool, hipStream_t);
+template void launch_sym_apply<double>(bool, const SymArgs&, const void*, const void*, const void*, int, int, bool,
+                                       bool, void*, void*, void*, void*, bool, hipStream_t);
+template void launch_sym_apply<float>(bool, const SymArgs&, const void*, const void*, const void*, int, int, bool,
+                                      bool, void*, void*, void*, void*, bool, hipStream_t);
 
 }  // namespace fftpim

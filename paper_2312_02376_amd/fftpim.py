@@ -27,7 +27,7 @@ STATUS = {
 # the entry points declared in include/fftpim.h
 EXPORTS = (
     "fftpim_default_params", "fftpim_plan", "fftpim_apply", "fftpim_apply_adjoint",
-    "fftpim_apply_parts", "fftpim_get_permutation", "fftpim_plan_info", "fftpim_last_status",
+    "fftpim_apply_pair", "fftpim_apply_parts", "fftpim_get_permutation", "fftpim_plan_info", "fftpim_last_status",
     "fftpim_destroy", "fftpim_error_string", "fftpim_eval_pgf", "fftpim_stage_times",
 )
 STAGES = ("pack", "near_spread", "near_fft", "near_interp", "near_corr", "far", "unpack")
@@ -81,6 +81,7 @@ def lib():
                                   i64, vp, vp]
         L.fftpim_apply.argtypes = [vp, vp, vp, ci, vp]
         L.fftpim_apply_adjoint.argtypes = [vp, vp, vp, ci, vp]
+        L.fftpim_apply_pair.argtypes = [vp, vp, vp, vp, vp, ci, vp]
         L.fftpim_apply_parts.argtypes = [vp, ci, ci, vp, vp, ci, vp]
         L.fftpim_get_permutation.argtypes = [vp, ci, vp]
         L.fftpim_plan_info.argtypes = [vp, ctypes.POINTER(Info)]
@@ -205,6 +206,17 @@ class Plan:
         _check(lib().fftpim_apply_adjoint(self._h, ctypes.c_void_p(v2.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                           v2.shape[0], _stream_handle(stream)), "fftpim_apply_adjoint")
         return out[0] if sq else out
+
+    def apply_pair(self, q, v, out_u=None, out_w=None, stream=None):
+        """(A q, A^H v) in one call; q and v of the same shape."""
+        q2, out_u, sq = self._io(q, out_u)
+        v2, out_w, _ = self._io(v, out_w)
+        if v2.shape != q2.shape:
+            raise ValueError("q and v must have the same shape")
+        _check(lib().fftpim_apply_pair(self._h, ctypes.c_void_p(q2.data_ptr()), ctypes.c_void_p(out_u.data_ptr()),
+                                       ctypes.c_void_p(v2.data_ptr()), ctypes.c_void_p(out_w.data_ptr()),
+                                       q2.shape[0], _stream_handle(stream)), "fftpim_apply_pair")
+        return (out_u[0], out_w[0]) if sq else (out_u, out_w)
 
     def apply_parts(self, q, parts, adjoint=False, out=None, stream=None):
         q2, out, sq = self._io(q, out)

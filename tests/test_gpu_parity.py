@@ -283,3 +283,41 @@ def test_autograd_amplitude_gradient(name):
         dre = (L(base + h * e) - L(base - h * e)) / (2 * h)
         dim = (L(base + 1j * h * e) - L(base - 1j * h * e)) / (2 * h)
         assert abs(complex(dre, dim) - g[0, k]) < 1e-9 * max(1.0, abs(g[0, k])), k
+
+
+@pytest.mark.parametrize("name,layout,nrhs,N", [
+    ("helm2_bloch", "sym", 2, 400), ("helm2_bloch", "csr", 2, 400), ("helm2_bloch", "sym", 3, 1500),
+    ("phase3_static", "sym", 1, 400), ("helm3", "auto", 1, 400), ("npsp3_real", "sym", 3, 400),
+    ("npsp3_real", "tile", 19, 400), ("npsp1_real", "csr", 2, 400), ("npsp2_real", "auto", 4, 400)])
+def test_apply_pair(name, layout, nrhs, N):
+    # (A q, A^H v) in one call: each equals the oracle and the two single
+    # calls (the box-pair layout carries q's and v's planes through one pass)
+    print("case", name, layout, nrhs, N, flush=True)
+    lat, ref, plan, qv = _setup(name, N=N, seed=41, nrhs=nrhs, corr_layout=layout)
+    rng = np.random.default_rng(42)
+    if plan.value_type == "real":
+        v = rng.standard_normal(qv.shape)
+    else:
+        v = rng.standard_normal(qv.shape) + 1j * rng.standard_normal(qv.shape)
+    qd, vd = _to_dev(plan, qv), _to_dev(plan, v)
+    want_w = ref.adjoint(v)
+    if lat.npsp:
+        want_w = want_w - want_w.mean(axis=-1, keepdims=True)
+    want_u = ref.apply(qv)
+    for k in (nrhs, 1):
+        u, w = plan.apply_pair(qd[:k], vd[:k])
+        assert plan.last_status() == 0
+        u1 = plan.apply(qd[:k]).cpu().numpy()
+        w1 = plan.adjoint(vd[:k]).cpu().numpy()
+        u, w = u.cpu().numpy(), w.cpu().numpy()
+        assert rel(u, u1) < 1e-14 and rel(w, w1) < 1e-14, (k, rel(u, u1), rel(w, w1))
+        assert rel(u, want_u[:k]) < 1e-11 and rel(w, want_w[:k]) < 1e-11, k
+
+
+def test_apply_pair_fp32():
+    lat, ref, plan, qv = _setup("helm2_bloch", N=400, seed=43, precision="f32", corr_layout="sym")
+    rng = np.random.default_rng(44)
+    v = rng.standard_normal(qv.shape) + 1j * rng.standard_normal(qv.shape)
+    u, w = plan.apply_pair(_to_dev(plan, qv), _to_dev(plan, v))
+    assert rel(u.cpu().numpy(), ref.apply(qv)) < 2e-5
+    assert rel(w.cpu().numpy(), ref.adjoint(v)) < 2e-5
