@@ -15,58 +15,80 @@
 
 namespace fftpim {
 
-// One block per far box, one thread per local stencil node; the box's points
-// are staged through LDS in chunks with their 1D weights, so every thread
-// only multiplies three staged weights per point.
+// One block per far box, one thread per (x, y) pair of local stencil nodes
+// looping over the qf+1 z nodes (the x-y weight product is formed once per
+// point and reused along z).  The box's points are staged through LDS in
+// chunks with their 1D weights.  A block is one or two wavefronts, so the
+// kernel finds room on compute units that the concurrent correction keeps
+// nearly full.
 constexpr int kMomChunk = 64;
 
 template <typename R, int QF, int PB>
-__global__ void k_far_moments(FarArgs f, const int32_t* __restrict__ fbox_start, const int32_t* __restrict__ fperm,
-                              const double* __restrict__ w3, int64_t N, const cplx<R>* __restrict__ qint, int P,
-                              cplx<R>* __restrict__ mom) {
+__global__ void __launch_bounds__(128) k_far_moments(FarArgs f, const int32_t* __restrict__ fbox_start,
+                                                     const int32_t* __restrict__ fperm,
+                                                     const double* __restrict__ w3, int64_t N,
+                                                     const cplx<R>* __restrict__ qint, int P,
+                                                     cplx<R>* __restrict__ mom) {
   constexpr int K1 = QF + 1;
   constexpr int K = K1 * K1 * K1;
   constexpr int CH = kMomChunk;
   __shared__ double sw[CH][3][K1];
   __shared__ cplx<R> sq[CH][PB];
-  const int k = threadIdx.x;
+  const int t = threadIdx.x;
   const int64_t b = blockIdx.x;
   const int p0 = blockIdx.y * PB;
-  const int kx = k / (K1 * K1), ky = (k / K1) % K1, kz = k % K1;
-  double ar[PB], ai[PB];
+  const bool own = t < K1 * K1;
+  const int kx = t / K1, ky = t % K1;
+  double ar[K1][PB], ai[K1][PB];
 #pragma unroll
-  for (int pp = 0; pp < PB; ++pp) ar[pp] = ai[pp] = 0.0;
+  for (int c = 0; c < K1; ++c)
+#pragma unroll
+    for (int pp = 0; pp < PB; ++pp) ar[c][pp] = ai[c][pp] = 0.0;
   const int j0 = fbox_start[b], j1 = fbox_start[b + 1];
   for (int base = j0; base < j1; base += CH) {
     __syncthreads();
-    if (k < CH && base + k < j1) {
-      const int n = fperm[base + k];
+    for (int i = t; i < CH; i += blockDim.x) {
+      if (base + i < j1) {
+        const int n = fperm[base + i];
 #pragma unroll
-      for (int c = 0; c < 3; ++c)
+        for (int c = 0; c < 3; ++c)
 #pragma unroll
-        for (int a = 0; a < K1; ++a) sw[k][c][a] = w3[(c * K1 + a) * N + n];
+          for (int a = 0; a < K1; ++a) sw[i][c][a] = w3[(c * K1 + a) * N + n];
 #pragma unroll
-      for (int pp = 0; pp < PB; ++pp)
-        sq[k][pp] = (p0 + pp < P) ? qint[static_cast<int64_t>(n) * P + p0 + pp] : cmake<R>(R(0), R(0));
+        for (int pp = 0; pp < PB; ++pp)
+          sq[i][pp] = (p0 + pp < P) ? qint[static_cast<int64_t>(n) * P + p0 + pp] : cmake<R>(R(0), R(0));
+      }
     }
     __syncthreads();
     const int cnt = min(CH, j1 - base);
-    if (k < K) {
+    if (own) {
       for (int i = 0; i < cnt; ++i) {
-        const double w = sw[i][0][kx] * sw[i][1][ky] * sw[i][2][kz];
+        const double wxy = sw[i][0][kx] * sw[i][1][ky];
+        double qr[PB], qi[PB];
 #pragma unroll
         for (int pp = 0; pp < PB; ++pp) {
-          ar[pp] += w * static_cast<double>(sq[i][pp].x);
-          ai[pp] += w * static_cast<double>(sq[i][pp].y);
+          qr[pp] = static_cast<double>(sq[i][pp].x);
+          qi[pp] = static_cast<double>(sq[i][pp].y);
+        }
+#pragma unroll
+        for (int c = 0; c < K1; ++c) {
+          const double w = wxy * sw[i][2][c];
+#pragma unroll
+          for (int pp = 0; pp < PB; ++pp) {
+            ar[c][pp] += w * qr[pp];
+            ai[c][pp] += w * qi[pp];
+          }
         }
       }
     }
   }
-  if (k < K) {
+  if (own) {
 #pragma unroll
-    for (int pp = 0; pp < PB; ++pp)
-      if (p0 + pp < P)
-        mom[(b * K + k) * P + p0 + pp] = cmake<R>(static_cast<R>(ar[pp]), static_cast<R>(ai[pp]));
+    for (int c = 0; c < K1; ++c)
+#pragma unroll
+      for (int pp = 0; pp < PB; ++pp)
+        if (p0 + pp < P)
+          mom[(b * K + t * K1 + c) * P + p0 + pp] = cmake<R>(static_cast<R>(ar[c][pp]), static_cast<R>(ai[c][pp]));
   }
 }
 
@@ -472,15 +494,16 @@ void launch_far_table_pgf2(const FarTableArgs& a, void* table, hipStream_t st) {
 template <typename R, int QF>
 static void moments_q(const FarArgs& f, const int32_t* fbox_start, const int32_t* fperm, const double* u3,
                       int64_t N, const void* qint, int P, void* mom, hipStream_t st) {
-  constexpr int K = (QF + 1) * (QF + 1) * (QF + 1);
-  const int bs = ((K + 63) / 64) * 64;
+  constexpr int K1 = QF + 1;
+  const int bs = ((K1 * K1 + 63) / 64) * 64;
 #define FFTPIM_MOM(PBV)                                                                                     \
   do {                                                                                                      \
     dim3 gr(static_cast<unsigned>(f.nboxes), (P + PBV - 1) / PBV);                                          \
     hipLaunchKernelGGL((k_far_moments<R, QF, PBV>), gr, dim3(bs), 0, st, f, fbox_start, fperm, u3, N,       \
                        static_cast<const cplx<R>*>(qint), P, static_cast<cplx<R>*>(mom));                   \
   } while (0)
-  if (P >= 4)
+  // accumulators: (qf+1) z nodes x PB planes per thread
+  if (P >= 4 && K1 <= 6)
     FFTPIM_MOM(4);
   else if (P >= 2)
     FFTPIM_MOM(2);

@@ -299,8 +299,42 @@ __global__ void __launch_bounds__(kGatherThreads) k_sym_gather(SymArgs a, const 
     const bool act = s < S && e < run;
     double xr = 0.0, xi = 0.0;
     if (act) {
-      for (int64_t k = s; k < nruns; k += S) {
-        const cplx<double> v = k < nit ? ypart[y0 + k * run + e] : zpart[a.in_base[ip0 + k - nit] * P + e];
+      // runs s, s + S, ... in increasing order: the row partials of the
+      // box's items, then the column partials; loads are issued kU at a time
+      // (the column runs through their index first) so their latencies
+      // overlap
+      constexpr int kU = 8;
+      int64_t k = s;
+      for (; k + (kU - 1) * S < nit; k += kU * S) {
+        cplx<double> v[kU];
+#pragma unroll
+        for (int j = 0; j < kU; ++j) v[j] = ypart[y0 + (k + j * S) * run + e];
+#pragma unroll
+        for (int j = 0; j < kU; ++j) {
+          xr += v[j].x;
+          xi += v[j].y;
+        }
+      }
+      for (; k < nit; k += S) {
+        const cplx<double> v = ypart[y0 + k * run + e];
+        xr += v.x;
+        xi += v.y;
+      }
+      for (; k + (kU - 1) * S < nruns; k += kU * S) {
+        int64_t zb[kU];
+#pragma unroll
+        for (int j = 0; j < kU; ++j) zb[j] = a.in_base[ip0 + k + j * S - nit];
+        cplx<double> v[kU];
+#pragma unroll
+        for (int j = 0; j < kU; ++j) v[j] = zpart[zb[j] * P + e];
+#pragma unroll
+        for (int j = 0; j < kU; ++j) {
+          xr += v[j].x;
+          xi += v[j].y;
+        }
+      }
+      for (; k < nruns; k += S) {
+        const cplx<double> v = zpart[a.in_base[ip0 + k - nit] * P + e];
         xr += v.x;
         xi += v.y;
       }
