@@ -23,6 +23,11 @@ namespace fftpim {
 // nearly full.
 constexpr int kMomChunk = 64;
 
+// Block size of the elementwise far-zone kernels (gather, dense sum for few
+// planes, split reduction): one wavefront, so they are scheduled on compute
+// units the concurrent correction keeps nearly full.
+constexpr int kFarBlock = 64;
+
 template <typename R, int QF, int PB>
 __global__ void __launch_bounds__(128) k_far_moments(FarArgs f, const int32_t* __restrict__ fbox_start,
                                                      const int32_t* __restrict__ fperm,
@@ -121,12 +126,12 @@ __global__ void k_far_gather(FarArgs f, const cplx<R>* __restrict__ mom, int P, 
 // (conjugate transpose), base(i) = ((ix + nfx - 1) sy + iy + nfy - 1) sz +
 // iz + nfz - 1 and off(j) = (jx sy + jy) sz + jz indexing the (2 nf - 1)^3
 // offset table.  The splits over j are summed in a fixed order afterwards.
-template <typename R, int PB>
-__global__ void __launch_bounds__(256) k_far_apply(FarArgs f, const cplx<R>* __restrict__ table,
-                                                   const cplx<R>* __restrict__ in, cplx<R>* __restrict__ part,
-                                                   int P, int adjoint, int64_t jlen) {
-  __shared__ cplx<R> sh[PB][256];
-  __shared__ int64_t shi[256];
+template <typename R, int PB, int BS>
+__global__ void __launch_bounds__(BS) k_far_apply(FarArgs f, const cplx<R>* __restrict__ table,
+                                                  const cplx<R>* __restrict__ in, cplx<R>* __restrict__ part,
+                                                  int P, int adjoint, int64_t jlen) {
+  __shared__ cplx<R> sh[PB][BS];
+  __shared__ int64_t shi[BS];
   const int64_t sy = 2 * f.nf[1] - 1, sz = 2 * f.nf[2] - 1;
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   const int p0 = blockIdx.y * PB;
@@ -144,7 +149,7 @@ __global__ void __launch_bounds__(256) k_far_apply(FarArgs f, const cplx<R>* __r
   R ar[PB], ai[PB];
 #pragma unroll
   for (int pp = 0; pp < PB; ++pp) ar[pp] = ai[pp] = R(0);
-  for (int64_t jc = jbeg; jc < jend; jc += 256) {
+  for (int64_t jc = jbeg; jc < jend; jc += BS) {
     const int64_t j = jc + threadIdx.x;
     if (j < jend) {
       const int jz = static_cast<int>(j % f.nf[2]);
@@ -157,7 +162,7 @@ __global__ void __launch_bounds__(256) k_far_apply(FarArgs f, const cplx<R>* __r
         sh[pp][threadIdx.x] = (p0 + pp < P) ? in[j * P + p0 + pp] : cmake<R>(R(0), R(0));
     }
     __syncthreads();
-    const int cnt = static_cast<int>(min<int64_t>(256, jend - jc));
+    const int cnt = static_cast<int>(min<int64_t>(BS, jend - jc));
     if (active) {
       for (int jj = 0; jj < cnt; ++jj) {
         const int64_t t = adjoint ? (shi[jj] - off_i) : (base_i - shi[jj]);
@@ -533,8 +538,8 @@ int launch_far_moments(int qf, const FarArgs& f, const int32_t* fbox_start, cons
 template <typename R, int QF>
 static void gather_q(const FarArgs& f, const void* mom, int P, void* grid, hipStream_t st) {
   const int64_t total = f.Ngf * P;
-  hipLaunchKernelGGL((k_far_gather<R, QF>), dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0, st, f,
-                     static_cast<const cplx<R>*>(mom), P, static_cast<cplx<R>*>(grid));
+  hipLaunchKernelGGL((k_far_gather<R, QF>), dim3(static_cast<unsigned>((total + kFarBlock - 1) / kFarBlock)),
+                     dim3(kFarBlock), 0, st, f, static_cast<const cplx<R>*>(mom), P, static_cast<cplx<R>*>(grid));
 }
 
 template <typename R>
@@ -555,8 +560,8 @@ int launch_far_gather(int qf, const FarArgs& f, const void* mom, int P, void* gr
 }
 
 int far_apply_splits(int64_t Ngf, int P) {
-  const int64_t blocks = ((Ngf + 255) / 256) * ((P + 3) / 4);
-  int s = static_cast<int>(std::min<int64_t>(64, std::max<int64_t>(1, (2048 + blocks - 1) / blocks)));
+  const int64_t blocks = ((Ngf + kFarBlock - 1) / kFarBlock) * ((P + 3) / 4);
+  int s = static_cast<int>(std::min<int64_t>(64, std::max<int64_t>(1, (8192 + blocks - 1) / blocks)));
   return static_cast<int>(std::min<int64_t>(s, std::max<int64_t>(1, (Ngf + 255) / 256)));
 }
 
@@ -584,14 +589,15 @@ void launch_far_apply(const FarArgs& f, const void* table, const void* in, void*
                        static_cast<const cplx<R>*>(part), static_cast<cplx<R>*>(out), n, nsplit);
     return;
   }
-  const unsigned nb = static_cast<unsigned>((f.Ngf + 255) / 256);
+  const unsigned nb = static_cast<unsigned>((f.Ngf + kFarBlock - 1) / kFarBlock);
   const int ns = far_apply_splits(f.Ngf, P);
-  const int64_t jlen = (((f.Ngf + ns - 1) / ns + 255) / 256) * 256;
+  const int64_t jlen = (((f.Ngf + ns - 1) / ns + kFarBlock - 1) / kFarBlock) * kFarBlock;
   const int nsplit = static_cast<int>((f.Ngf + jlen - 1) / jlen);
 #define FFTPIM_FARAPPLY(PBV)                                                                               \
   do {                                                                                                     \
     dim3 gr(nb, (P + PBV - 1) / PBV, nsplit);                                                              \
-    hipLaunchKernelGGL((k_far_apply<R, PBV>), gr, dim3(256), 0, st, f, static_cast<const cplx<R>*>(table), \
+    hipLaunchKernelGGL((k_far_apply<R, PBV, kFarBlock>), gr, dim3(kFarBlock), 0, st, f,                   \
+                       static_cast<const cplx<R>*>(table),                                                 \
                        static_cast<const cplx<R>*>(in), static_cast<cplx<R>*>(part), P, adjoint ? 1 : 0,   \
                        jlen);                                                                              \
   } while (0)
@@ -603,8 +609,8 @@ void launch_far_apply(const FarArgs& f, const void* table, const void* in, void*
     FFTPIM_FARAPPLY(1);
 #undef FFTPIM_FARAPPLY
   const int64_t n = f.Ngf * P;
-  hipLaunchKernelGGL((k_far_reduce<R>), dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st,
-                     static_cast<const cplx<R>*>(part), static_cast<cplx<R>*>(out), n, nsplit);
+  hipLaunchKernelGGL((k_far_reduce<R>), dim3(static_cast<unsigned>((n + kFarBlock - 1) / kFarBlock)), dim3(kFarBlock),
+                     0, st, static_cast<const cplx<R>*>(part), static_cast<cplx<R>*>(out), n, nsplit);
 }
 
 #define FFTPIM_INST_FAR(R)                                                                                 \

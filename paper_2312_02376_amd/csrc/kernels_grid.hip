@@ -713,6 +713,11 @@ __global__ void k_scale_convert(const cplx<double>* __restrict__ in, cplx<R>* __
 
 static inline unsigned blocks_for(int64_t n, int bs) { return static_cast<unsigned>((n + bs - 1) / bs); }
 
+// Block size of the per-point / per-node kernels for few planes (projection
+// through the weight CSR, interpolation): one wavefront, so they are
+// scheduled on compute units the concurrent correction keeps nearly full.
+constexpr int kPointBlock = 64;
+
 template <typename R>
 void launch_pack(const void* qu, void* qint, const int32_t* perm, int64_t N, int nrhs, int P,
                  bool real_in, bool use_perm, hipStream_t st) {
@@ -830,8 +835,8 @@ static void spread_q(const GridArgs& g, const int32_t* box_start, const int32_t*
 template <typename R>
 void launch_spread_csr(const int64_t* wrow, const int32_t* widx, const double* wval, int64_t n3, const void* qint,
                        int P, void* grid, hipStream_t st) {
-  hipLaunchKernelGGL((k_spread_csr<R>), dim3(blocks_for(n3 * 16, 256)), dim3(256), 0, st, wrow, widx, wval, n3,
-                     static_cast<const cplx<R>*>(qint), P, static_cast<cplx<R>*>(grid));
+  hipLaunchKernelGGL((k_spread_csr<R>), dim3(blocks_for(n3 * 16, kPointBlock)), dim3(kPointBlock), 0, st, wrow, widx,
+                     wval, n3, static_cast<const cplx<R>*>(qint), P, static_cast<cplx<R>*>(grid));
 }
 
 template <typename R>
@@ -873,8 +878,8 @@ static void interp_q(const GridArgs& g, const int32_t* s3, const double* u3, int
     return;
   }
   FFTPIM_PB_DISPATCH(P, {
-    dim3 gr(blocks_for(N, 256), (P + PB - 1) / PB);
-    hipLaunchKernelGGL((k_interp<R, Q, PB>), gr, dim3(256), 0, st, g, s3, u3, N,
+    dim3 gr(blocks_for(N, kPointBlock), (P + PB - 1) / PB);
+    hipLaunchKernelGGL((k_interp<R, Q, PB>), gr, dim3(kPointBlock), 0, st, g, s3, u3, N,
                        static_cast<const cplx<R>*>(grid), P, static_cast<cplx<R>*>(uint), acc ? 1 : 0);
   });
 }
