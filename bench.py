@@ -50,6 +50,20 @@ SECONDARY = {
                                dims=3, L=(1.0, 1.0, 1.0), precision="f32", value_type="real", nrhs=64,
                                near_n=(128, 128, 128), near_order=4, corr_radius=5, far_n=(14, 14, 14),
                                far_order=5),
+    # the batched workload with the far grid sum on bfloat16 inputs (FP32
+    # accumulation); everything else as above
+    "coulomb_1m_batched_farbf16": dict(name="3D-periodic Coulomb, 1M uniform points, 64 neutral Gaussian right-hand "
+                                            "sides, FP32 bulk, far grid sum with bfloat16 inputs and FP32 "
+                                            "accumulation, FP64 correction",
+                                       dims=3, L=(1.0, 1.0, 1.0), precision="f32_farbf16", value_type="real",
+                                       nrhs=64, near_n=(128, 128, 128), near_order=4, corr_radius=5,
+                                       far_n=(14, 14, 14), far_order=5),
+    "coulomb_1m_batched_farbf16x3": dict(name="3D-periodic Coulomb, 1M uniform points, 64 neutral Gaussian "
+                                              "right-hand sides, FP32 bulk, far grid sum with split (three-product) "
+                                              "bfloat16 inputs and FP32 accumulation, FP64 correction",
+                                         dims=3, L=(1.0, 1.0, 1.0), precision="f32_farbf16x3", value_type="real",
+                                         nrhs=64, near_n=(128, 128, 128), near_order=4, corr_radius=5,
+                                         far_n=(14, 14, 14), far_order=5),
     # the same cell and parameters with one FP64 right-hand side (the first of
     # the batch): the single-RHS side of the batched-versus-single comparison
     "coulomb_1m_single_f64": dict(name="3D-periodic Coulomb, 1M uniform points, one Gaussian right-hand side "

@@ -60,7 +60,14 @@ typedef enum {
   FFTPIM_ERR_UNIMPLEMENTED = 8
 } fftpim_status;
 
-enum { FFTPIM_F64 = 0, FFTPIM_F32 = 1 };          /* precision of the bulk path */
+/* Precision of the bulk path (the correction values and their products stay
+ * FP64 in every mode).  FFTPIM_F32_FARBF16: FP32 everywhere except the far
+ * grid sum of Eq. (8), which rounds the far-kernel table values and the grid
+ * amplitudes to bfloat16 and accumulates in FP32 on the matrix cores (with at
+ * least 8 planes; fewer planes use the FP32 grid sum).  FFTPIM_F32_FARBF16X3:
+ * the same with each input split into two bfloat16 parts and three products
+ * per term (about 16 significant bits). */
+enum { FFTPIM_F64 = 0, FFTPIM_F32 = 1, FFTPIM_F32_FARBF16 = 2, FFTPIM_F32_FARBF16X3 = 3 };
 enum { FFTPIM_REAL = 0, FFTPIM_COMPLEX = 1 };     /* element type of q and u */
 enum { FFTPIM_SELF_IMAGES = 0, FFTPIM_SELF_EXCLUDE = 1 };
 enum { FFTPIM_ORDER_USER = 0, FFTPIM_ORDER_PLAN = 1 };
@@ -91,7 +98,7 @@ typedef struct {
   int far_n[3];      /* far grid nodes per axis */
   int far_order;     /* far projection/interpolation degree */
   int n_images;      /* i_d of Eq. (4): near-zone images per periodic axis */
-  int precision;     /* FFTPIM_F64 or FFTPIM_F32 (correction stays FP64) */
+  int precision;     /* FFTPIM_F64, FFTPIM_F32, FFTPIM_F32_FARBF16(X3) (correction stays FP64) */
   int value_type;    /* FFTPIM_REAL (static no-phase only) or FFTPIM_COMPLEX */
   int self_mode;     /* FFTPIM_SELF_IMAGES or FFTPIM_SELF_EXCLUDE */
   int order_io;      /* FFTPIM_ORDER_USER: q/u indexed like the input points;

@@ -72,7 +72,7 @@ int upload(fftpim_plan_s* p, T** out, const std::vector<T>& host) {
   return FFTPIM_OK;
 }
 
-size_t cbytes(const fftpim_plan_s* p) { return p->prm.precision == FFTPIM_F32 ? 8 : 16; }
+size_t cbytes(const fftpim_plan_s* p) { return p->prm.precision != FFTPIM_F64 ? 8 : 16; }
 
 // Stencil start and offset for one coordinate on a grid (Sec. 3.2, Eq. (grid),
 // with the halo reading): t = (x - origin)/h, s = floor(t - (q-1)/2) clamped
@@ -317,7 +317,9 @@ int far_zone(fftpim_plan_s* p, const WorkSet& ws, bool adjoint, const void* in, 
   const double* fw_out = adjoint ? p->fs_w : p->fo_w;
   CHK(launch_far_moments<R>(qf, fa, fbs, fpm, fw_in, N, in, P, ws.far_mom, sf));
   CHK(launch_far_gather<R>(qf, fa, ws.far_mom, P, ws.far_q, sf));
-  launch_far_apply<R>(fa, p->far_table, ws.far_q, ws.far_u, ws.far_part, P, adjoint, sf);
+  launch_far_apply<R>(fa, p->far_table, ws.far_q, ws.far_u, ws.far_part, P, adjoint,
+                      p->prm.precision == FFTPIM_F32_FARBF16 ? 1 : (p->prm.precision == FFTPIM_F32_FARBF16X3 ? 2 : 0),
+                      sf);
   // interpolation side: observer-grid boxes (forward) or source-grid boxes (adjoint)
   const int32_t* fbs_out = adjoint ? p->fbox_start_s : p->fbox_start_o;
   const int32_t* fpm_out = adjoint ? p->fperm_s : p->fperm_o;
@@ -366,7 +368,7 @@ int run_apply(fftpim_plan_s* p, int parts, bool adjoint, const void* in, void* o
     launch_pack<R>(in, p->q_int, p->perm, N, nrhs, P, real_io, use_perm, st);
     if (finalize && !adjoint && p->lat.npsp()) {
       launch_plane_sums<R>(p->q_int, nullptr, nullptr, N, P, p->sums_work, p->sums, st);
-      launch_check_neutral(p->sums, P, p->prm.precision == FFTPIM_F32 ? 1e-5 : 1e-10, p->status_dev, st);
+      launch_check_neutral(p->sums, P, p->prm.precision != FFTPIM_F64 ? 1e-5 : 1e-10, p->status_dev, st);
     }
   }
   // Fork: the correction (Sec. 3.3 Step 4), the near-grid steps and the far
@@ -492,7 +494,7 @@ int run_apply_pair(fftpim_plan_s* p, const void* q, void* u, const void* v, void
     launch_pack<R>(v, p->v_int, p->perm, N, nrhs, P, real_io, use_perm, st);
     if (p->lat.npsp()) {
       launch_plane_sums<R>(p->q_int, nullptr, nullptr, N, P, p->sums_work, p->sums, st);
-      launch_check_neutral(p->sums, P, p->prm.precision == FFTPIM_F32 ? 1e-5 : 1e-10, p->status_dev, st);
+      launch_check_neutral(p->sums, P, p->prm.precision != FFTPIM_F64 ? 1e-5 : 1e-10, p->status_dev, st);
     }
   }
   HIPCHK(hipEventRecord(p->ev_fork, st));
@@ -563,7 +565,7 @@ int apply_common(fftpim_plan_t plan, int parts, int adjoint, const void* in, voi
   if (nrhs < 1 || nrhs > plan->prm.nrhs_max) return FFTPIM_ERR_INVALID_ARG;
   if (parts < 0 || parts > FFTPIM_PART_ALL) return FFTPIM_ERR_INVALID_ARG;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (plan->prm.precision == FFTPIM_F32)
+  if (plan->prm.precision != FFTPIM_F64)
     return run_apply<float>(plan, parts, adjoint != 0, in, out, nrhs, st, finalize);
   return run_apply<double>(plan, parts, adjoint != 0, in, out, nrhs, st, finalize);
 }
@@ -588,7 +590,7 @@ int validate(const fftpim_problem_t* pr, const fftpim_params_t* pm) {
   }
   if (pm->corr_radius < pm->near_order || pm->corr_radius > kMaxCorrRadius) return FFTPIM_ERR_INVALID_ARG;
   if (pm->n_images < 0 || pm->n_images > 2) return FFTPIM_ERR_INVALID_ARG;
-  if (pm->precision != FFTPIM_F64 && pm->precision != FFTPIM_F32) return FFTPIM_ERR_INVALID_ARG;
+  if (pm->precision < FFTPIM_F64 || pm->precision > FFTPIM_F32_FARBF16X3) return FFTPIM_ERR_INVALID_ARG;
   if (pm->value_type != FFTPIM_REAL && pm->value_type != FFTPIM_COMPLEX) return FFTPIM_ERR_INVALID_ARG;
   if (pm->self_mode != FFTPIM_SELF_IMAGES && pm->self_mode != FFTPIM_SELF_EXCLUDE) return FFTPIM_ERR_INVALID_ARG;
   if (pm->order_io != FFTPIM_ORDER_USER && pm->order_io != FFTPIM_ORDER_PLAN) return FFTPIM_ERR_INVALID_ARG;
@@ -1323,7 +1325,7 @@ int build_plan(fftpim_plan_s* p, int64_t N, const double* src_dev, hipStream_t s
   CHK(upload(p, &dpos, pos_sorted));
 
   plan_log("geometry and sort", t0);
-  if (pm.precision == FFTPIM_F32)
+  if (pm.precision != FFTPIM_F64)
     CHK(build_tables<float>(p, st));
   else
     CHK(build_tables<double>(p, st));
@@ -1483,7 +1485,7 @@ int fftpim_apply_pair(fftpim_plan_t plan, const void* q_dev, void* u_dev, const 
   if (!plan || !q_dev || !u_dev || !v_dev || !w_dev) return FFTPIM_ERR_INVALID_ARG;
   if (nrhs < 1 || nrhs > plan->prm.nrhs_max) return FFTPIM_ERR_INVALID_ARG;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (plan->prm.precision == FFTPIM_F32) return run_apply_pair<float>(plan, q_dev, u_dev, v_dev, w_dev, nrhs, st);
+  if (plan->prm.precision != FFTPIM_F64) return run_apply_pair<float>(plan, q_dev, u_dev, v_dev, w_dev, nrhs, st);
   return run_apply_pair<double>(plan, q_dev, u_dev, v_dev, w_dev, nrhs, st);
 }
 

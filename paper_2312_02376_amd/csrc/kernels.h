@@ -191,6 +191,6 @@ bool launch_far_interp_box(int qf, const FarArgs& f, const int32_t* fbox_start, 
                            hipStream_t st);
 template <typename R>
 void launch_far_apply(const FarArgs& f, const void* table, const void* in, void* out, void* part, int P,
-                      bool adjoint, hipStream_t st);
+                      bool adjoint, int bf16_in, hipStream_t st);
 
 }  // namespace fftpim

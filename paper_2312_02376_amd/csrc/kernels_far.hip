@@ -279,6 +279,138 @@ __global__ void __launch_bounds__(64 * kFarMfmaWaves) k_far_apply_mfma(FarArgs f
   }
 }
 
+// The same GEMM with bfloat16 inputs and FP32 accumulation (16x16x16 bf16
+// MFMA, four k per lane): lane l supplies K(i0 + l % 16, j + 4 (l / 16) + v)
+// and in[j + 4 (l / 16) + v][p0 + l % 16] for v = 0..3; the accumulator layout
+// is the FP32 one above.  Both were checked on the hardware against a host
+// product of small integers.  Inputs are rounded to nearest even on the upper
+// half of their binary32 encoding (the bfloat16 format).  X3: each input is
+// split as hi + lo (hi = bf16(x), lo = bf16(x - hi)) and a product is taken
+// as lo·hi + hi·lo + hi·hi (the three-term bfloat16 splitting of Henry, Tang
+// and Heinecke, 2019), which recovers about 16 significant bits.
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline short bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return static_cast<short>(u >> 16);
+}
+
+__device__ inline float bf16_value(short h) {
+  return __uint_as_float(static_cast<uint32_t>(static_cast<uint16_t>(h)) << 16);
+}
+
+// x = hi + lo to about 16 significant bits
+__device__ inline void bf16_split(float x, short& hi, short& lo) {
+  hi = bf16_rne(x);
+  lo = bf16_rne(x - bf16_value(hi));
+}
+
+__device__ inline mfma_f4 mfma_bf16(bf16x4 a, bf16x4 b, mfma_f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+template <bool X3>
+__global__ void __launch_bounds__(64 * kFarMfmaWaves) k_far_apply_mfma_bf16(FarArgs f,
+                                                                            const cplx<float>* __restrict__ table,
+                                                                            const cplx<float>* __restrict__ in,
+                                                                            cplx<float>* __restrict__ part, int P,
+                                                                            int adjoint, int64_t jlen) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t sy = 2 * f.nf[1] - 1, sz = 2 * f.nf[2] - 1;
+  const int64_t i0 = (static_cast<int64_t>(blockIdx.x) * kFarMfmaWaves + wave) * 16;
+  const int p0 = blockIdx.y * 16;
+  const int split = blockIdx.z;
+  const int64_t jbeg = split * jlen, jend = min<int64_t>(f.Ngf, jbeg + jlen);
+  const int64_t ia = i0 + (lane & 15);
+  const bool row_ok = ia < f.Ngf;
+  const int pb = p0 + (lane & 15);
+  const bool col_ok = pb < P;
+  const int kg = lane >> 4;
+  int64_t base_i = 0, off_i = 0;
+  if (row_ok) {
+    const int iz = static_cast<int>(ia % f.nf[2]);
+    const int iy = static_cast<int>((ia / f.nf[2]) % f.nf[1]);
+    const int ix = static_cast<int>(ia / (static_cast<int64_t>(f.nf[1]) * f.nf[2]));
+    base_i = ((ix + f.nf[0] - 1) * sy + iy + f.nf[1] - 1) * sz + iz + f.nf[2] - 1;
+    off_i = (ix * sy + iy) * sz + iz;
+  }
+  mfma_f4 accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
+  for (int64_t jc = jbeg; jc < jend; jc += 16) {
+    bf16x4 kr, kin, ki, qr, qi;     // hi parts (the only parts without X3)
+    bf16x4 krl, kinl, kil, qrl, qil;  // lo parts
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t j = jc + 4 * kg + v;
+      float a = 0.f, b = 0.f, c = 0.f, d = 0.f;
+      if (j < jend) {
+        const int jz = static_cast<int>(j % f.nf[2]);
+        const int jy = static_cast<int>((j / f.nf[2]) % f.nf[1]);
+        const int jx = static_cast<int>(j / (static_cast<int64_t>(f.nf[1]) * f.nf[2]));
+        if (row_ok) {
+          const int64_t t = adjoint ? (((jx + f.nf[0] - 1) * sy + jy + f.nf[1] - 1) * sz + jz + f.nf[2] - 1) - off_i
+                                    : base_i - ((jx * sy + jy) * sz + jz);
+          const cplx<float> kv = table[t];
+          a = kv.x;
+          b = adjoint ? -kv.y : kv.y;
+        }
+        if (col_ok) {
+          const cplx<float> qv = in[j * P + pb];
+          c = qv.x;
+          d = qv.y;
+        }
+      }
+      if (X3) {
+        short h, l;
+        bf16_split(a, h, l);
+        kr[v] = h;
+        krl[v] = l;
+        bf16_split(b, h, l);
+        ki[v] = h;
+        kil[v] = l;
+        bf16_split(-b, h, l);
+        kin[v] = h;
+        kinl[v] = l;
+        bf16_split(c, h, l);
+        qr[v] = h;
+        qrl[v] = l;
+        bf16_split(d, h, l);
+        qi[v] = h;
+        qil[v] = l;
+      } else {
+        kr[v] = bf16_rne(a);
+        ki[v] = bf16_rne(b);
+        kin[v] = bf16_rne(-b);
+        qr[v] = bf16_rne(c);
+        qi[v] = bf16_rne(d);
+      }
+    }
+    if (X3) {
+      accr = mfma_bf16(krl, qr, accr);
+      accr = mfma_bf16(kr, qrl, accr);
+      accr = mfma_bf16(kinl, qi, accr);
+      accr = mfma_bf16(kin, qil, accr);
+      acci = mfma_bf16(krl, qi, acci);
+      acci = mfma_bf16(kr, qil, acci);
+      acci = mfma_bf16(kil, qr, acci);
+      acci = mfma_bf16(ki, qrl, acci);
+    }
+    accr = mfma_bf16(kr, qr, accr);
+    accr = mfma_bf16(kin, qi, accr);
+    acci = mfma_bf16(kr, qi, acci);
+    acci = mfma_bf16(ki, qr, acci);
+  }
+  const int pc = p0 + (lane & 15);
+  if (pc < P) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t io = i0 + 4 * (lane >> 4) + r;
+      if (io < f.Ngf) part[(static_cast<int64_t>(split) * f.Ngf + io) * P + pc] = cmake<float>(accr[r], acci[r]);
+    }
+  }
+}
+
 // Step 3 with batched planes.  All points of a far box share one stencil
 // (the boxes are keyed by the stencil start), so a block stages the box's
 // (qf+1)^3 nodes x P planes in LDS once and interpolates a chunk of the box's
@@ -570,20 +702,31 @@ constexpr int kFarMfmaMinPlanes = 8;
 
 template <typename R>
 void launch_far_apply(const FarArgs& f, const void* table, const void* in, void* out, void* part, int P,
-                      bool adjoint, hipStream_t st) {
+                      bool adjoint, int bf16_in, hipStream_t st) {
   if (P >= kFarMfmaMinPlanes) {
+    // bfloat16 inputs step j 16 at a time
+    const int64_t kstep = (bf16_in != 0 && sizeof(R) == 4) ? 16 : 4;
     // split j so the launch has a few blocks per compute unit, within the
     // part buffer's split capacity
     const int64_t row_blocks = (f.Ngf + 16 * kFarMfmaWaves - 1) / (16 * kFarMfmaWaves);
     const int64_t col_blocks = (P + 15) / 16;
     int64_t ns = std::max<int64_t>(1, 1024 / std::max<int64_t>(1, row_blocks * col_blocks));
     ns = std::min<int64_t>(ns, std::min<int64_t>(64, std::max<int64_t>(1, (f.Ngf + 255) / 256)));
-    const int64_t jlen = (((f.Ngf + ns - 1) / ns + 3) / 4) * 4;
+    const int64_t jlen = (((f.Ngf + ns - 1) / ns + kstep - 1) / kstep) * kstep;
     const int nsplit = static_cast<int>((f.Ngf + jlen - 1) / jlen);
     dim3 gr(static_cast<unsigned>(row_blocks), static_cast<unsigned>(col_blocks), static_cast<unsigned>(nsplit));
-    hipLaunchKernelGGL((k_far_apply_mfma<R>), gr, dim3(64 * kFarMfmaWaves), 0, st, f,
-                       static_cast<const cplx<R>*>(table), static_cast<const cplx<R>*>(in),
-                       static_cast<cplx<R>*>(part), P, adjoint ? 1 : 0, jlen);
+    if (kstep == 16 && bf16_in == 2)
+      hipLaunchKernelGGL(k_far_apply_mfma_bf16<true>, gr, dim3(64 * kFarMfmaWaves), 0, st, f,
+                         static_cast<const cplx<float>*>(table), static_cast<const cplx<float>*>(in),
+                         static_cast<cplx<float>*>(part), P, adjoint ? 1 : 0, jlen);
+    else if (kstep == 16)
+      hipLaunchKernelGGL(k_far_apply_mfma_bf16<false>, gr, dim3(64 * kFarMfmaWaves), 0, st, f,
+                         static_cast<const cplx<float>*>(table), static_cast<const cplx<float>*>(in),
+                         static_cast<cplx<float>*>(part), P, adjoint ? 1 : 0, jlen);
+    else
+      hipLaunchKernelGGL((k_far_apply_mfma<R>), gr, dim3(64 * kFarMfmaWaves), 0, st, f,
+                         static_cast<const cplx<R>*>(table), static_cast<const cplx<R>*>(in),
+                         static_cast<cplx<R>*>(part), P, adjoint ? 1 : 0, jlen);
     const int64_t n = f.Ngf * P;
     hipLaunchKernelGGL((k_far_reduce<R>), dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st,
                        static_cast<const cplx<R>*>(part), static_cast<cplx<R>*>(out), n, nsplit);
@@ -617,7 +760,7 @@ void launch_far_apply(const FarArgs& f, const void* table, const void* in, void*
   template int launch_far_moments<R>(int, const FarArgs&, const int32_t*, const int32_t*, const double*,   \
                                      int64_t, const void*, int, void*, hipStream_t);                       \
   template int launch_far_gather<R>(int, const FarArgs&, const void*, int, void*, hipStream_t);            \
-  template void launch_far_apply<R>(const FarArgs&, const void*, const void*, void*, void*, int, bool,         \
+  template void launch_far_apply<R>(const FarArgs&, const void*, const void*, void*, void*, int, bool, int,    \
                                     hipStream_t);                                                          \
   template bool launch_far_interp_box<R>(int, const FarArgs&, const int32_t*, const int32_t*, int, const int32_t*, \
                                          const double*, int64_t, const void*, int, void*, bool, hipStream_t);

@@ -13,7 +13,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfftpim.so")
 
-F64, F32 = 0, 1
+F64, F32, F32_FARBF16, F32_FARBF16X3 = 0, 1, 2, 3
 REAL, COMPLEX = 0, 1
 SELF_IMAGES, SELF_EXCLUDE = 0, 1
 ORDER_USER, ORDER_PLAN = 0, 1
@@ -140,7 +140,9 @@ class Plan:
 
     positions: torch CUDA float64 tensor (N, 3) in the zeroth cell.
     The remaining arguments map one-to-one onto fftpim_problem_t and
-    fftpim_params_t (include/fftpim.h).
+    fftpim_params_t (include/fftpim.h); precision is "f64", "f32",
+    "f32_farbf16" (FP32 with a bfloat16-input far grid sum) or
+    "f32_farbf16x3" (the same with split three-product bfloat16 terms).
     """
 
     def __init__(self, positions, periodic_dims, L, k0=0.0, kt=(0.0, 0.0, 0.0), near_n=(16, 16, 16),
@@ -161,7 +163,8 @@ class Plan:
         pm.corr_radius = int(corr_radius)
         pm.far_order = int(far_order)
         pm.n_images = int(n_images)
-        pm.precision = {"f64": F64, "f32": F32}[precision]
+        pm.precision = {"f64": F64, "f32": F32, "f32_farbf16": F32_FARBF16,
+                        "f32_farbf16x3": F32_FARBF16X3}[precision]
         pm.value_type = {"real": REAL, "complex": COMPLEX}[value_type]
         pm.self_mode = {"images": SELF_IMAGES, "exclude": SELF_EXCLUDE}[self_mode]
         pm.order_io = {"user": ORDER_USER, "plan": ORDER_PLAN}[order]

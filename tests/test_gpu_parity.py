@@ -321,3 +321,33 @@ def test_apply_pair_fp32():
     u, w = plan.apply_pair(_to_dev(plan, qv), _to_dev(plan, v))
     assert rel(u.cpu().numpy(), ref.apply(qv)) < 2e-5
     assert rel(w.cpu().numpy(), ref.adjoint(v)) < 2e-5
+
+
+@pytest.mark.parametrize("name", ["npsp3_real", "npsp2_real"])
+def test_far_bf16_modes(name):
+    # the far grid sum on bfloat16 inputs (FP32 accumulation) once planes are
+    # batched.  Rounding K and the grid amplitudes to 8 significant bits
+    # (unit roundoff 2^-8 against 2^-24) may cost up to 2^16 times the FP32
+    # path's error on the same (cancellation-prone, neutral-source) far sum;
+    # the three-product split keeps about 16 bits (2^-16: up to 2^8 times the
+    # FP32 error).  Each result must be worse than FP32 (its path ran) but
+    # within its factor, the split much better than plain bfloat16, and the
+    # whole apply's error the far part's error diluted by the far part's
+    # share of the result
+    lat, ref, plan16, qv = _setup(name, N=400, seed=47, nrhs=19, precision="f32_farbf16")
+    plan3 = _setup(name, N=400, seed=47, nrhs=19, precision="f32_farbf16x3")[2]
+    plan32 = _setup(name, N=400, seed=47, nrhs=19, precision="f32")[2]
+    qd = _to_dev(plan16, qv)
+    for adjoint in (False, True):
+        op = ref.adjoint if adjoint else ref.apply
+        want = op(qv, parts=("far",))
+        whole_want = op(qv)
+        share = np.linalg.norm(want) / np.linalg.norm(whole_want)
+        e = {}
+        for key, pl in (("bf16", plan16), ("bf16x3", plan3), ("fp32", plan32)):
+            e[key] = rel(pl.apply_parts(qd, 4, adjoint=adjoint).cpu().numpy(), want)
+            ew = rel(pl.apply_parts(qd, 7, adjoint=adjoint).cpu().numpy(), whole_want)
+            print(name, adjoint, key, "far rel %.2e whole %.2e (far share %.2f)" % (e[key], ew, share), flush=True)
+            assert ew < 1.5 * e[key] * share + 2e-5, (key, ew, e[key], share)
+        assert 10 * e["fp32"] < e["bf16"] < 2.0 ** 16 * e["fp32"] and e["bf16"] < 0.1, e
+        assert e["bf16x3"] < e["bf16"] / 20 and e["bf16x3"] < 2.0 ** 8 * e["fp32"], e
