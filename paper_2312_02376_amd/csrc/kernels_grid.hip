@@ -660,6 +660,179 @@ __global__ void __launch_bounds__(256) k_fft_pass(const cplx<R>* in,
   }
 }
 
+// Strided passes with the line length M = A B in registers (Cooley-Tukey in
+// four steps): with n = B n1 + n2 and k = k1 + A k2,
+//   X[k1 + A k2] = sum_n2 W_B^(n2 k2) W_M^(n2 k1) sum_n1 W_A^(n1 k1) x[B n1 + n2].
+// A group of TL = min(A, B) threads owns a line: first each thread takes
+// B / TL values of n2 and transforms its A points in registers, applies the
+// twiddles W_M^(n2 k1), and the line is exchanged once through LDS; then each
+// thread takes A / TL values of k1 and transforms the B points.  The inverse
+// runs the same steps backwards (the k1-owned layout after a forward transform
+// is the one the inverse starts from, so the fused pass needs no exchange
+// between the spectrum multiply and the inverse).  Consecutive threads take
+// consecutive lines, so every global load and store is a run of T columns.
+// Natural order in and out, forward exp(-2 pi i / M), unscaled inverse, as the
+// LDS-stage kernel above.
+template <typename R, int L>
+__device__ inline void reg_dft(cplx<R>* v, const cplx<R>* tws, int twstride, bool inverse) {
+  // bit-reversal permutation (compile-time indices)
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    int j = 0;
+#pragma unroll
+    for (int b = 1, m = L >> 1; b < L; b <<= 1, m >>= 1)
+      if (i & b) j |= m;
+    if (j > i) {
+      const cplx<R> tmp = v[i];
+      v[i] = v[j];
+      v[j] = tmp;
+    }
+  }
+#pragma unroll
+  for (int s = 1; s < L; s <<= 1) {
+#pragma unroll
+    for (int k = 0; k < L; k += 2 * s) {
+#pragma unroll
+      for (int j = 0; j < s; ++j) {
+        cplx<R> b = v[k + j + s];
+        if (j != 0) {
+          cplx<R> w = tws[j * (L / (2 * s)) * twstride];
+          if (inverse) w.y = -w.y;
+          b = cmul(b, w);
+        }
+        const cplx<R> a = v[k + j];
+        v[k + j] = cadd(a, b);
+        v[k + j + s] = csub(a, b);
+      }
+    }
+  }
+}
+
+// W_M^e (conjugated for the inverse) from the half table exp(-2 pi i k / M), k < M / 2
+template <typename R, int M>
+__device__ inline cplx<R> tw_full(const cplx<R>* tws, int e, bool inverse) {
+  e &= M - 1;
+  cplx<R> w = tws[e & (M / 2 - 1)];
+  if (e >= M / 2) {
+    w.x = -w.x;
+    w.y = -w.y;
+  }
+  if (inverse) w.y = -w.y;
+  return w;
+}
+
+template <typename R, int MODE, int A, int B, int NTH>
+__global__ void __launch_bounds__(NTH) k_fft_reg(const cplx<R>* in, cplx<R>* out, FftPassDesc d,
+                                                 const cplx<R>* __restrict__ tw, const cplx<R>* __restrict__ spec,
+                                                 int conj_spec) {
+  constexpr int M = A * B;
+  constexpr int TL = A < B ? A : B;  // threads per line
+  constexpr int T = NTH / TL;        // lines per block
+  constexpr int E1 = B / TL;         // length-A transforms per thread
+  constexpr int E3 = A / TL;         // length-B transforms per thread
+  constexpr int E = M / TL;          // values per thread
+  constexpr int LS = M + 1;          // LDS line stride
+  extern __shared__ unsigned char lds_raw[];
+  cplx<R>* xs = reinterpret_cast<cplx<R>*>(lds_raw);  // [T][LS]
+  cplx<R>* tws = xs + T * LS;                         // [M / 2]
+  for (int k = threadIdx.x; k < M / 2; k += NTH) tws[k] = tw[k];
+  const int t = threadIdx.x % T, r = threadIdx.x / T;
+  const int64_t tiles = (d.ncols + T - 1) / T;
+  const int64_t outer = blockIdx.x / tiles;
+  const int64_t col = (blockIdx.x % tiles) * T + t;
+  const bool line_ok = col < d.ncols;
+  const cplx<R>* src = in + outer * d.in_outer + col * d.in_col;
+  cplx<R>* dst = out + outer * d.out_outer + col * d.out_col;
+  cplx<R> v[E];
+  if (MODE == 0 || MODE == 2) {
+    // x[B n1 + n2] for this thread's n2 = r + TL e1
+#pragma unroll
+    for (int e1 = 0; e1 < E1; ++e1)
+#pragma unroll
+      for (int n1 = 0; n1 < A; ++n1) {
+        const int j = B * n1 + r + TL * e1;
+        v[e1 * A + n1] = (line_ok && j < d.n_in) ? src[j * d.in_line] : cmake<R>(R(0), R(0));
+      }
+  } else {
+    // X[k1 + A k2] for this thread's k1 = r + TL e3
+#pragma unroll
+    for (int e3 = 0; e3 < E3; ++e3)
+#pragma unroll
+      for (int k2 = 0; k2 < B; ++k2) {
+        const int k = r + TL * e3 + A * k2;
+        v[e3 * B + k2] = (line_ok && k < d.n_in) ? src[k * d.in_line] : cmake<R>(R(0), R(0));
+      }
+  }
+  __syncthreads();  // twiddle table
+  cplx<R>* xl = xs + t * LS;
+  if (MODE == 0 || MODE == 2) {
+#pragma unroll
+    for (int e1 = 0; e1 < E1; ++e1) {
+      const int n2 = r + TL * e1;
+      reg_dft<R, A>(v + e1 * A, tws, M / A, false);
+#pragma unroll
+      for (int k1 = 0; k1 < A; ++k1) xl[k1 * B + n2] = cmul(v[e1 * A + k1], tw_full<R, M>(tws, n2 * k1, false));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e3 = 0; e3 < E3; ++e3) {
+      const int k1 = r + TL * e3;
+#pragma unroll
+      for (int n2 = 0; n2 < B; ++n2) v[e3 * B + n2] = xl[k1 * B + n2];
+      reg_dft<R, B>(v + e3 * B, tws, M / B, false);
+    }
+    if (MODE == 2) {
+      // spectrum of every k = k1 + A k2 held here; planes share a value
+      const int64_t sc = (col / d.spec_div) * d.spec_col;
+      cplx<R> sv[E];
+#pragma unroll
+      for (int e3 = 0; e3 < E3; ++e3)
+#pragma unroll
+        for (int k2 = 0; k2 < B; ++k2)
+          sv[e3 * B + k2] = line_ok ? spec[static_cast<int64_t>(r + TL * e3 + A * k2) * d.spec_line + sc]
+                                    : cmake<R>(R(0), R(0));
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        cplx<R> w = sv[i];
+        if (conj_spec) w.y = -w.y;
+        v[i] = cmul(v[i], w);
+      }
+      __syncthreads();  // the LDS lines are rewritten below
+    }
+  }
+  if (MODE == 0) {
+#pragma unroll
+    for (int e3 = 0; e3 < E3; ++e3)
+#pragma unroll
+      for (int k2 = 0; k2 < B; ++k2) {
+        const int k = r + TL * e3 + A * k2;
+        if (line_ok && k < d.n_out) dst[k * d.out_line] = v[e3 * B + k2];
+      }
+    return;
+  }
+  // inverse: x[n2 + B n1] = sum_k1 W_A^-(n1 k1) W_M^-(n2 k1) sum_k2 W_B^-(n2 k2) X[k1 + A k2]
+#pragma unroll
+  for (int e3 = 0; e3 < E3; ++e3) {
+    const int k1 = r + TL * e3;
+    reg_dft<R, B>(v + e3 * B, tws, M / B, true);
+#pragma unroll
+    for (int n2 = 0; n2 < B; ++n2) xl[k1 * B + n2] = cmul(v[e3 * B + n2], tw_full<R, M>(tws, n2 * k1, true));
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e1 = 0; e1 < E1; ++e1) {
+    const int n2 = r + TL * e1;
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) v[e1 * A + k1] = xl[k1 * B + n2];
+    reg_dft<R, A>(v + e1 * A, tws, M / A, true);
+#pragma unroll
+    for (int n1 = 0; n1 < A; ++n1) {
+      const int j = n2 + B * n1;
+      if (line_ok && j < d.n_out) dst[j * d.out_line] = v[e1 * A + n1];
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // plan time: near-zone table G^p_near at node offsets, circularly embedded
 // ---------------------------------------------------------------------------
@@ -902,9 +1075,67 @@ int launch_interp(int q, const GridArgs& g, const int32_t* s3, const double* u3,
   return FFTPIM_OK;
 }
 
+template <typename R, int A, int B, int NTH>
+static void fft_reg_n(int mode, const cplx<R>* i, cplx<R>* o, const FftPassDesc& d, const cplx<R>* t,
+                      const cplx<R>* s, bool conj_spec, hipStream_t st) {
+  constexpr int M = A * B, TL = A < B ? A : B, T = NTH / TL;
+  const unsigned nblocks = static_cast<unsigned>(d.nouter * ((d.ncols + T - 1) / T));
+  const size_t lds = (static_cast<size_t>(T) * (M + 1) + M / 2) * sizeof(cplx<R>);
+  if (mode == 0)
+    hipLaunchKernelGGL((k_fft_reg<R, 0, A, B, NTH>), dim3(nblocks), dim3(NTH), lds, st, i, o, d, t, s, 0);
+  else if (mode == 1)
+    hipLaunchKernelGGL((k_fft_reg<R, 1, A, B, NTH>), dim3(nblocks), dim3(NTH), lds, st, i, o, d, t, s, 0);
+  else
+    hipLaunchKernelGGL((k_fft_reg<R, 2, A, B, NTH>), dim3(nblocks), dim3(NTH), lds, st, i, o, d, t, s,
+                       conj_spec ? 1 : 0);
+}
+
+// 256 threads per block, or 128 where the lines of 256 threads would need
+// more than 64 KB of LDS
+template <typename R, int A, int B>
+static bool fft_reg(int mode, const cplx<R>* i, cplx<R>* o, const FftPassDesc& d, const cplx<R>* t,
+                    const cplx<R>* s, bool conj_spec, hipStream_t st) {
+  constexpr int M = A * B, TL = A < B ? A : B;
+  constexpr size_t lds256 = (static_cast<size_t>(256 / TL) * (M + 1) + M / 2) * sizeof(cplx<R>);
+  constexpr size_t lds128 = (static_cast<size_t>(128 / TL) * (M + 1) + M / 2) * sizeof(cplx<R>);
+  if (lds256 <= 65536)
+    fft_reg_n<R, A, B, 256>(mode, i, o, d, t, s, conj_spec, st);
+  else if (lds128 <= 65536)
+    fft_reg_n<R, A, B, 128>(mode, i, o, d, t, s, conj_spec, st);
+  else
+    return false;
+  return true;
+}
+
+// Register transforms for strided FP32 passes of length 16..512; other passes
+// (lines contiguous in memory, FP64) go through the LDS-stage kernel.
+template <typename R>
+static bool launch_fft_reg(int mode, const cplx<R>* i, cplx<R>* o, const FftPassDesc& d, const cplx<R>* t,
+                           const cplx<R>* s, bool conj_spec, hipStream_t st) {
+  if constexpr (sizeof(R) != 4) {
+    // FP64 lines of 16 values per thread cost occupancy; measured slower
+    // than the LDS stages on the FP64 workloads
+    return false;
+  } else {
+  if (d.contig) return false;
+  switch (d.M) {
+    case 16: return fft_reg<R, 4, 4>(mode, i, o, d, t, s, conj_spec, st);
+    case 32: return fft_reg<R, 8, 4>(mode, i, o, d, t, s, conj_spec, st);
+    case 64: return fft_reg<R, 8, 8>(mode, i, o, d, t, s, conj_spec, st);
+    case 128: return fft_reg<R, 16, 8>(mode, i, o, d, t, s, conj_spec, st);
+    case 256: return fft_reg<R, 16, 16>(mode, i, o, d, t, s, conj_spec, st);
+    case 512: return fft_reg<R, 16, 32>(mode, i, o, d, t, s, conj_spec, st);
+    default: return false;
+  }
+  }
+}
+
 template <typename R>
 void launch_fft_pass(int mode, const void* in, void* out, const FftPassDesc& d, const void* tw,
                      const void* spec, bool conj_spec, hipStream_t st) {
+  if (launch_fft_reg<R>(mode, static_cast<const cplx<R>*>(in), static_cast<cplx<R>*>(out), d,
+                        static_cast<const cplx<R>*>(tw), static_cast<const cplx<R>*>(spec), conj_spec, st))
+    return;
   unsigned nblocks = d.contig ? blocks_for(d.nouter, d.T)
                               : static_cast<unsigned>(d.nouter * ((d.ncols + d.T - 1) / d.T));
   size_t lds = (static_cast<size_t>(d.T) * (d.M + 1) + d.M / 2) * sizeof(cplx<R>);
