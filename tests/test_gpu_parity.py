@@ -351,3 +351,29 @@ def test_far_bf16_modes(name):
             assert ew < 1.5 * e[key] * share + 2e-5, (key, ew, e[key], share)
         assert 10 * e["fp32"] < e["bf16"] < 2.0 ** 16 * e["fp32"] and e["bf16"] < 0.1, e
         assert e["bf16x3"] < e["bf16"] / 20 and e["bf16x3"] < 2.0 ** 8 * e["fp32"], e
+
+
+@pytest.mark.parametrize("near_n", [(32, 32, 32), (64, 64, 32), (256, 16, 16)])
+def test_fp32_register_fft_lengths(near_n):
+    # FP32 strided passes run the register transform (line lengths 64, 128
+    # and 512 here; 16, 32 and 256 are covered by the other FP32 tests), FP64
+    # the LDS-stage kernel that the stage tests pin to the oracle: the near
+    # grid parts must agree to FP32 rounding, forward and adjoint, with one
+    # plane and with batched planes
+    fp = _fftpim()
+    rng = np.random.default_rng(53)
+    N = 1500
+    pos = torch.tensor(rng.random((N, 3)), dtype=torch.float64, device="cuda")
+    for nrhs in (1, 12):
+        plans = [fp.Plan(pos, 3, [1.0, 1.0, 1.0], k0=3.0, kt=[0.4, 0.2, 0.1], near_n=near_n, near_order=3,
+                         corr_radius=3, far_n=(8, 8, 8), far_order=3, precision=prec, nrhs_max=nrhs)
+                 for prec in ("f64", "f32")]
+        q = rng.standard_normal((nrhs, N)) + 1j * rng.standard_normal((nrhs, N))
+        for adjoint in (False, True):
+            u64 = plans[0].apply_parts(_to_dev(plans[0], q), 1, adjoint=adjoint).cpu().numpy()
+            u32 = plans[1].apply_parts(_to_dev(plans[1], q), 1, adjoint=adjoint).cpu().numpy()
+            err = rel(u32, u64)
+            print(near_n, nrhs, adjoint, "fp32 vs fp64 near grid rel %.2e" % err, flush=True)
+            assert err < 2e-5, (near_n, nrhs, adjoint, err)
+        for p in plans:
+            p.close()
