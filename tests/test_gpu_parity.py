@@ -377,3 +377,31 @@ def test_fp32_register_fft_lengths(near_n):
             assert err < 2e-5, (near_n, nrhs, adjoint, err)
         for p in plans:
             p.close()
+
+
+def test_far_bf16_modes_fall_back_below_eight_planes():
+    # with fewer than 8 planes the far grid sum is not a GEMM and every mode
+    # uses the FP32 grid sum: the results equal the FP32 mode's bitwise
+    outs = {}
+    for prec in ("f32", "f32_farbf16", "f32_farbf16x3"):
+        lat, ref, plan, qv = _setup("npsp3_real", N=300, seed=59, nrhs=3, precision=prec)
+        outs[prec] = plan.apply_parts(_to_dev(plan, qv), 4).cpu().numpy()
+        plan.close()
+    assert np.array_equal(outs["f32"], outs["f32_farbf16"])
+    assert np.array_equal(outs["f32"], outs["f32_farbf16x3"])
+
+
+def test_apply_pair_rejects_bad_arguments():
+    fp = _fftpim()
+    lat, ref, plan, qv = _setup("helm2_bloch", N=200, seed=61, nrhs=2)
+    qd = _to_dev(plan, qv)
+    big = torch.zeros((plan.params.nrhs_max + 1, plan.N), dtype=plan.dtype, device="cuda")
+    with pytest.raises(fp.FFTPIMError):
+        plan.apply_pair(big, big)
+    with pytest.raises(ValueError):
+        plan.apply_pair(qd, qd[:1])
+    # a valid call after the rejected ones still matches the single calls
+    u, w = plan.apply_pair(qd, qd)
+    assert rel(u.cpu().numpy(), plan.apply(qd).cpu().numpy()) < 1e-14
+    assert rel(w.cpu().numpy(), plan.adjoint(qd).cpu().numpy()) < 1e-14
+    plan.close()
