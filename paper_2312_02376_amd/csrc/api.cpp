@@ -61,7 +61,7 @@ void dfree(fftpim_plan_s* p, void* ptr) {
   auto it = std::find(p->allocations.begin(), p->allocations.end(), ptr);
   if (it != p->allocations.end()) {
     p->allocations.erase(it);
-    hipFree(ptr);
+    (void)hipFree(ptr);
   }
 }
 
@@ -1366,7 +1366,6 @@ int build_plan(fftpim_plan_s* p, int64_t N, const double* src_dev, hipStream_t s
   const int P = planes_for(p, pm.nrhs_max);
   p->nplanes_max = P;
   const size_t es = cbytes(p);
-  const int64_t n3 = static_cast<int64_t>(g.n[0]) * g.n[1] * g.n[2];
   unsigned char* b = nullptr;
   CHK(dalloc(p, &b, static_cast<size_t>(N) * P * es));
   p->q_int = b;
@@ -1557,17 +1556,18 @@ int fftpim_stage_times(fftpim_plan_t plan, int enable, double* ms_out, int64_t* 
 
 int fftpim_destroy(fftpim_plan_t plan) {
   if (!plan) return FFTPIM_OK;
-  // the plan's streams may still be reading its buffers
+  // the plan's streams may still be reading its buffers (teardown goes on
+  // whatever these calls return)
   for (hipStream_t s : {plan->s_corr, plan->s_far, plan->s_near})
-    if (s) hipStreamSynchronize(s);
-  hipStreamSynchronize(plan->last_stream);
-  for (hipEvent_t e : plan->ev_pool) hipEventDestroy(e);
+    if (s) (void)hipStreamSynchronize(s);
+  (void)hipStreamSynchronize(plan->last_stream);
+  for (hipEvent_t e : plan->ev_pool) (void)hipEventDestroy(e);
   plan->ev_pool.clear();
   for (hipEvent_t e : {plan->ev_fork, plan->ev_corr, plan->ev_far, plan->ev_near})
-    if (e) hipEventDestroy(e);
+    if (e) (void)hipEventDestroy(e);
   for (hipStream_t s : {plan->s_corr, plan->s_far, plan->s_near})
-    if (s) hipStreamDestroy(s);
-  for (void* ptr : plan->allocations) hipFree(ptr);
+    if (s) (void)hipStreamDestroy(s);
+  for (void* ptr : plan->allocations) (void)hipFree(ptr);
   plan->allocations.clear();
   delete plan;
   return FFTPIM_OK;

@@ -29,7 +29,7 @@ constexpr int kMomChunk = 64;
 constexpr int kFarBlock = 64;
 
 template <typename R, int QF, int PB>
-__global__ void __launch_bounds__(128) k_far_moments(FarArgs f, const int32_t* __restrict__ fbox_start,
+__global__ void __launch_bounds__(128) k_far_moments(const int32_t* __restrict__ fbox_start,
                                                      const int32_t* __restrict__ fperm,
                                                      const double* __restrict__ w3, int64_t N,
                                                      const cplx<R>* __restrict__ qint, int P,
@@ -636,7 +636,7 @@ static void moments_q(const FarArgs& f, const int32_t* fbox_start, const int32_t
 #define FFTPIM_MOM(PBV)                                                                                     \
   do {                                                                                                      \
     dim3 gr(static_cast<unsigned>(f.nboxes), (P + PBV - 1) / PBV);                                          \
-    hipLaunchKernelGGL((k_far_moments<R, QF, PBV>), gr, dim3(bs), 0, st, f, fbox_start, fperm, u3, N,       \
+    hipLaunchKernelGGL((k_far_moments<R, QF, PBV>), gr, dim3(bs), 0, st, fbox_start, fperm, u3, N,          \
                        static_cast<const cplx<R>*>(qint), P, static_cast<cplx<R>*>(mom));                   \
   } while (0)
   // accumulators: (qf+1) z nodes x PB planes per thread
