@@ -190,7 +190,7 @@ def main():
                     help="only run a plain 1 GiB device copy (scale for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only; multi-GPU runs are not part of it "
+        print("bench.py: measures one GPU only; multi-GPU runs are not supported "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 

@@ -54,7 +54,7 @@ typedef enum {
                                   or outside the given box elsewhere */
   FFTPIM_ERR_NOT_NEUTRAL = 3,  /* static no-phase problem with sum(q) != 0 */
   FFTPIM_ERR_WOOD_ANOMALY = 4, /* a Floquet wavenumber vanishes (Sec. 2) */
-  FFTPIM_ERR_UNSUPPORTED = 5,  /* a combination this build does not handle */
+  FFTPIM_ERR_UNSUPPORTED = 5,  /* a combination the library does not handle */
   FFTPIM_ERR_NO_MEMORY = 6,    /* device or host allocation failed */
   FFTPIM_ERR_DEVICE = 7,       /* a HIP runtime call failed */
   FFTPIM_ERR_UNIMPLEMENTED = 8
@@ -75,7 +75,7 @@ enum { FFTPIM_PART_NEAR_GRID = 1, FFTPIM_PART_NEAR_CORR = 2, FFTPIM_PART_FAR = 4
        FFTPIM_PART_ALL = 7 };
 
 /* The problem of Sec. 2: periodicity, periods, free-space wavenumber k0
- * (0 = static) and phase-shift wavenumbers k_x0, k_y0, k_z0.  This build
+ * (0 = static) and phase-shift wavenumbers k_x0, k_y0, k_z0.  The library
  * takes real k0 and real phase shifts. */
 typedef struct {
   int periodic_dims;   /* 1: x; 2: x, y; 3: x, y, z */

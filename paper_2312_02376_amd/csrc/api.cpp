@@ -1580,7 +1580,7 @@ const char* fftpim_error_string(int status) {
     case FFTPIM_ERR_OUT_OF_CELL: return "a point lies outside the zeroth cell or the given box";
     case FFTPIM_ERR_NOT_NEUTRAL: return "static no-phase problem with a non-neutral right-hand side";
     case FFTPIM_ERR_WOOD_ANOMALY: return "a Floquet wavenumber vanishes (Rayleigh-Wood anomaly)";
-    case FFTPIM_ERR_UNSUPPORTED: return "problem class not supported by this build";
+    case FFTPIM_ERR_UNSUPPORTED: return "problem class not supported by this library";
     case FFTPIM_ERR_NO_MEMORY: return "out of memory";
     case FFTPIM_ERR_DEVICE: return "HIP runtime error";
     case FFTPIM_ERR_UNIMPLEMENTED: return "not implemented";
