@@ -155,14 +155,16 @@ def _brute_force(lat, r, reach):
     return np.sum(terms[order][::-1])
 
 
-@pytest.mark.parametrize("dims,reach", [(3, 14), (2, 40)])
+@pytest.mark.parametrize("dims,reach", [(3, 14), (2, 40), (1, 14)])
 def test_lossy_brute_force_image_sum(dims, reach):
+    # 1D: the Hankel series of Eq. (pgf_1) (the oracle has no Ewald form for
+    # 1D Helmholtz; at these transverse distances the series converges)
     lat = P.Lattice(dims, [1.0, 1.2, 0.9][:dims], k0=2.0 - 3.0j, kt=[0.7, -0.4, 0.3][:dims])
     rng = np.random.default_rng(14 + dims)
     for _ in range(4):
         r = rng.uniform(-0.45, 0.45, 3)
         bf = _brute_force(lat, r, reach)
-        for method in ("series", "ewald"):
+        for method in (("series",) if dims == 1 else ("series", "ewald")):
             val = P.pgf(r[None, :], lat, method)[0]
             assert abs(val - bf) <= 1e-10 * abs(bf), (method, val, bf)
 
