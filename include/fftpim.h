@@ -177,8 +177,11 @@ int fftpim_apply_adjoint(fftpim_plan_t plan, const void* v_dev, void* w_dev, int
  * overwritten and must not overlap each other or the inputs.  The static
  * no-phase case checks q for neutrality and removes the mean of w, as the two
  * single calls do.  The first call on a plan allocates four work arrays of
- * n x planes elements (planes = nrhs_max, or half of it for real values);
- * later calls allocate nothing.  Errors: INVALID_ARG, NO_MEMORY, DEVICE. */
+ * n x planes elements (planes = nrhs_max, or half of it for real values) and a
+ * second set of near-grid and far-zone work buffers of the plan's own sizes
+ * (counted in fftpim_plan_info's device_bytes once made); later calls allocate
+ * nothing.  Enqueued on stream like fftpim_apply.  Errors: INVALID_ARG,
+ * NO_MEMORY, DEVICE. */
 int fftpim_apply_pair(fftpim_plan_t plan, const void* q_dev, void* u_dev, const void* v_dev,
                       void* w_dev, int nrhs, fftpim_stream_t stream);
 
