@@ -30,7 +30,8 @@
  *     non-neutral right-hand side of a static no-phase problem) are latched
  *     and reported by fftpim_last_status.
  *   - Every function returns an fftpim_status (0 = success); no exception or
- *     longjmp crosses the ABI.
+ *     longjmp crosses the ABI (an unexpected internal C++ exception is
+ *     reported as FFTPIM_ERR_DEVICE).
  *   - Applies on one plan share its workspace: enqueue them on one stream, or
  *     use one plan per stream.
  */
@@ -55,7 +56,9 @@ typedef enum {
   FFTPIM_ERR_NOT_NEUTRAL = 3,  /* static no-phase problem with sum(q) != 0 */
   FFTPIM_ERR_WOOD_ANOMALY = 4, /* a Floquet wavenumber vanishes (Sec. 2) */
   FFTPIM_ERR_UNSUPPORTED = 5,  /* a combination the library does not handle */
-  FFTPIM_ERR_NO_MEMORY = 6,    /* device or host allocation failed */
+  FFTPIM_ERR_NO_MEMORY = 6,    /* a device or host allocation failed, a host
+                                  thread could not be started, or the plan
+                                  would exceed params.max_bytes */
   FFTPIM_ERR_DEVICE = 7,       /* a HIP runtime call failed */
   FFTPIM_ERR_UNIMPLEMENTED = 8
 } fftpim_status;
@@ -75,16 +78,21 @@ enum { FFTPIM_PART_NEAR_GRID = 1, FFTPIM_PART_NEAR_CORR = 2, FFTPIM_PART_FAR = 4
        FFTPIM_PART_ALL = 7 };
 
 /* The problem of Sec. 2: periodicity, periods, free-space wavenumber k0
- * (0 = static) and phase-shift wavenumbers k_x0, k_y0, k_z0.  The library
- * takes real k0 and real phase shifts. */
+ * (0 = static) and phase-shift wavenumbers k_x0, k_y0, k_z0, each possibly
+ * complex (Sec. 2 allows a complex phase shift; a lossy medium has
+ * Im k0 < 0 under the exp(-j k0 r) convention).  Complex values are given as
+ * separate real and imaginary parts; zero-initialised imaginary parts give
+ * the real problem. */
 typedef struct {
   int periodic_dims;   /* 1: x; 2: x, y; 3: x, y, z */
   double L[3];         /* periods (entries beyond periodic_dims ignored) */
-  double k0;           /* free-space wavenumber */
-  double kt[3];        /* phase-shift wavenumbers (beyond periodic_dims ignored) */
+  double k0;           /* free-space wavenumber, real part (>= 0) */
+  double kt[3];        /* phase-shift wavenumbers, real parts (beyond periodic_dims ignored) */
   int has_box;         /* 1: use box_lo/box_hi on the non-periodic axes, */
   double box_lo[3];    /* else the bounding box of the points (target region */
   double box_hi[3];    /* D of Sec. 3.2) */
+  double k0_im;        /* imaginary part of k0 (<= 0) */
+  double kt_im[3];     /* imaginary parts of the phase-shift wavenumbers */
 } fftpim_problem_t;
 
 /* Method parameters (Sec. 3.2-3.3).  Grid sizes count the interpolation halo:
@@ -105,6 +113,9 @@ typedef struct {
                         FFTPIM_ORDER_PLAN: indexed in the plan's sorted order */
   int nrhs_max;      /* largest nrhs a single apply may pass */
   int corr_layout;   /* FFTPIM_CORR_AUTO, _CSR, _SYM or _TILE */
+  size_t max_bytes;  /* cap on the device memory the plan may hold, including
+                        what fftpim_apply_pair adds on its first call;
+                        0 = no cap.  Exceeding it returns FFTPIM_ERR_NO_MEMORY. */
 } fftpim_params_t;
 
 /* Storage of the near-zone correction of Eq. (er): one CSR row per observer;

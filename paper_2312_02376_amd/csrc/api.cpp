@@ -5,7 +5,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <new>
 #include <numeric>
+#include <stdexcept>
+#include <system_error>
 #include <thread>
 #include <vector>
 
@@ -45,12 +48,16 @@ int ilog2(int v) {
   return l;
 }
 
+// Device allocation owned by the plan; refused (NO_MEMORY) when it would take
+// the plan's device memory beyond params.max_bytes (0 = no limit).
 template <typename T>
 int dalloc(fftpim_plan_s* p, T** out, size_t count) {
   void* ptr = nullptr;
   size_t bytes = std::max<size_t>(count * sizeof(T), 16);
+  if (p->prm.max_bytes != 0 && static_cast<uint64_t>(p->device_bytes) + bytes > p->prm.max_bytes)
+    return FFTPIM_ERR_NO_MEMORY;
   if (hipMalloc(&ptr, bytes) != hipSuccess) return FFTPIM_ERR_NO_MEMORY;
-  p->allocations.push_back(ptr);
+  p->allocations.push_back(DevBuf{ptr, bytes});
   p->device_bytes += static_cast<int64_t>(bytes);
   *out = static_cast<T*>(ptr);
   return FFTPIM_OK;
@@ -58,8 +65,9 @@ int dalloc(fftpim_plan_s* p, T** out, size_t count) {
 
 void dfree(fftpim_plan_s* p, void* ptr) {
   if (!ptr) return;
-  auto it = std::find(p->allocations.begin(), p->allocations.end(), ptr);
+  auto it = std::find_if(p->allocations.begin(), p->allocations.end(), [&](const DevBuf& b) { return b.p == ptr; });
   if (it != p->allocations.end()) {
+    p->device_bytes -= static_cast<int64_t>(it->bytes);
     p->allocations.erase(it);
     (void)hipFree(ptr);
   }
@@ -427,6 +435,7 @@ int run_apply(fftpim_plan_s* p, int parts, bool adjoint, const void* in, void* o
 }
 
 int alloc_work_set(fftpim_plan_s* p, WorkSet& ws) {
+  ws = WorkSet{};
   const int P = p->nplanes_max;
   const size_t es = cbytes(p);
   const GridGeom& g = p->ng;
@@ -458,14 +467,26 @@ int alloc_work_set(fftpim_plan_s* p, WorkSet& ws) {
 // near/far work set), made on the first pair call of a plan.
 int ensure_pair_buffers(fftpim_plan_s* p) {
   if (p->v_int != nullptr) return FFTPIM_OK;
-  CHK(alloc_work_set(p, p->ws2));
+  // allocate into locals and publish only when every allocation succeeded; a
+  // failure frees what this call made, so a retry starts from scratch
+  WorkSet ws2;
+  void* bufs[4] = {nullptr, nullptr, nullptr, nullptr};
+  auto release = [&]() {
+    for (void* q : {ws2.grid0, ws2.bufA, ws2.bufB, ws2.far_mom, ws2.far_q, ws2.far_u, ws2.far_part}) dfree(p, q);
+    for (void* q : bufs) dfree(p, q);
+  };
+  int s = alloc_work_set(p, ws2);
   const size_t bytes = static_cast<size_t>(p->N) * p->nplanes_max * cbytes(p);
-  unsigned char* b = nullptr;
-  void* bufs[4];
-  for (int k = 0; k < 4; ++k) {
-    CHK(dalloc(p, &b, bytes));
+  for (int k = 0; k < 4 && s == FFTPIM_OK; ++k) {
+    unsigned char* b = nullptr;
+    s = dalloc(p, &b, bytes);
     bufs[k] = b;
   }
+  if (s != FFTPIM_OK) {
+    release();
+    return s;
+  }
+  p->ws2 = ws2;
   p->u_int2 = bufs[1];
   p->u_corr2 = bufs[2];
   p->u_far2 = bufs[3];
@@ -579,8 +600,11 @@ int validate(const fftpim_problem_t* pr, const fftpim_params_t* pm) {
   for (int c = 0; c < pr->periodic_dims; ++c)
     if (!(pr->L[c] > 0.0) || !std::isfinite(pr->L[c])) return FFTPIM_ERR_INVALID_ARG;
   if (!std::isfinite(pr->k0) || pr->k0 < 0.0) return FFTPIM_ERR_INVALID_ARG;
+  if (!std::isfinite(pr->k0_im) || pr->k0_im > 0.0) return FFTPIM_ERR_INVALID_ARG;
   for (int c = 0; c < 3; ++c)
-    if (!std::isfinite(pr->kt[c])) return FFTPIM_ERR_INVALID_ARG;
+    if (!std::isfinite(pr->kt[c]) || !std::isfinite(pr->kt_im[c])) return FFTPIM_ERR_INVALID_ARG;
+  if (pr->k0_im != 0.0 || pr->kt_im[0] != 0.0 || pr->kt_im[1] != 0.0 || pr->kt_im[2] != 0.0)
+    return FFTPIM_ERR_UNSUPPORTED;
   if (pm->near_order < 1 || pm->near_order > kMaxNearOrder) return FFTPIM_ERR_INVALID_ARG;
   if (pm->far_order < 1 || pm->far_order > kMaxFarOrder) return FFTPIM_ERR_INVALID_ARG;
   for (int c = 0; c < 3; ++c) {
@@ -1039,7 +1063,6 @@ int build_tiles(fftpim_plan_s* p, const std::vector<int32_t>& start, const std::
   p->ntiles = ntiles;
   p->tile_nvals = voff[ntiles];
   // the tiles replace the CSR
-  p->device_bytes -= static_cast<int64_t>(p->nnz) * (sizeof(int32_t) + sizeof(double));
   dfree(p, p->col);
   dfree(p, p->val);
   p->col = nullptr;
@@ -1399,178 +1422,218 @@ int build_plan(fftpim_plan_s* p, int64_t N, const double* src_dev, hipStream_t s
   return FFTPIM_OK;
 }
 
+// No C++ exception may cross the C ABI: host allocations (std::vector) and
+// the far-table worker threads can throw on resource exhaustion.
+template <typename F>
+int guarded(F&& f) noexcept {
+  try {
+    return f();
+  } catch (const std::bad_alloc&) {
+    return FFTPIM_ERR_NO_MEMORY;
+  } catch (const std::length_error&) {
+    return FFTPIM_ERR_NO_MEMORY;
+  } catch (const std::system_error&) {
+    return FFTPIM_ERR_NO_MEMORY;  // e.g. no host thread could be started
+  } catch (...) {
+    return FFTPIM_ERR_DEVICE;
+  }
+}
+
 }  // namespace
 
 extern "C" {
 
 int fftpim_default_params(const fftpim_problem_t* problem, fftpim_params_t* params) {
-  if (!problem || !params) return FFTPIM_ERR_INVALID_ARG;
-  fftpim_params_t p{};
-  for (int c = 0; c < 3; ++c) {
-    p.near_n[c] = 16;
-    p.far_n[c] = 16;
-  }
-  p.near_order = 4;
-  p.corr_radius = 6;
-  p.far_order = 7;
-  p.n_images = 1;
-  p.precision = FFTPIM_F64;
-  p.value_type = FFTPIM_COMPLEX;
-  p.self_mode = FFTPIM_SELF_IMAGES;
-  p.order_io = FFTPIM_ORDER_USER;
-  p.nrhs_max = 1;
-  p.corr_layout = FFTPIM_CORR_AUTO;
-  *params = p;
-  return FFTPIM_OK;
+  return guarded([&]() -> int {
+    if (!problem || !params) return FFTPIM_ERR_INVALID_ARG;
+    fftpim_params_t p{};
+    for (int c = 0; c < 3; ++c) {
+      p.near_n[c] = 16;
+      p.far_n[c] = 16;
+    }
+    p.near_order = 4;
+    p.corr_radius = 6;
+    p.far_order = 7;
+    p.n_images = 1;
+    p.precision = FFTPIM_F64;
+    p.value_type = FFTPIM_COMPLEX;
+    p.self_mode = FFTPIM_SELF_IMAGES;
+    p.order_io = FFTPIM_ORDER_USER;
+    p.nrhs_max = 1;
+    p.corr_layout = FFTPIM_CORR_AUTO;
+    *params = p;
+    return FFTPIM_OK;
+  });
 }
 
 int fftpim_plan(fftpim_plan_t* plan, const fftpim_problem_t* problem, const fftpim_params_t* params,
                 int64_t n_src, const double* src_xyz_dev, int64_t n_obs, const double* obs_xyz_dev,
                 fftpim_stream_t stream) {
-  if (!plan || !problem || !params || !src_xyz_dev) return FFTPIM_ERR_INVALID_ARG;
-  *plan = nullptr;
-  if (n_src < 1 || n_src > (int64_t{1} << 30)) return FFTPIM_ERR_INVALID_ARG;
-  if (obs_xyz_dev != nullptr) return FFTPIM_ERR_UNIMPLEMENTED;
-  if (n_obs != n_src && n_obs != 0) return FFTPIM_ERR_INVALID_ARG;
-  CHK(validate(problem, params));
-  Lattice lat{};
-  lat.dims = problem->periodic_dims;
-  for (int c = 0; c < 3; ++c) {
-    lat.L[c] = c < lat.dims ? problem->L[c] : 1.0;
-    lat.kt[c] = c < lat.dims ? problem->kt[c] : 0.0;
-  }
-  lat.k0 = problem->k0;
-  if (params->value_type == FFTPIM_REAL && !lat.npsp()) return FFTPIM_ERR_INVALID_ARG;
-  if (params->self_mode == FFTPIM_SELF_EXCLUDE) return FFTPIM_ERR_UNIMPLEMENTED;
-  if (check_supported(lat)) return FFTPIM_ERR_UNSUPPORTED;
-  if (wood_anomaly(lat)) return FFTPIM_ERR_WOOD_ANOMALY;
-  auto t0 = std::chrono::steady_clock::now();
-  fftpim_plan_s* p = new (std::nothrow) fftpim_plan_s();
-  if (!p) return FFTPIM_ERR_NO_MEMORY;
-  p->lat = lat;
-  p->problem = *problem;
-  p->prm = *params;
-  p->N = n_src;
-  p->complex_kernel = !lat.npsp();
-  p->helmholtz = lat.k0 != 0.0;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  int s = build_plan(p, n_src, src_xyz_dev, st);
-  if (s != FFTPIM_OK) {
-    fftpim_destroy(p);
-    return s;
-  }
-  p->plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  p->last_stream = st;
-  if (std::getenv("FFTPIM_LOG")) {
-    std::fprintf(stderr, "fftpim plan: N=%lld near %dx%dx%d q=%d rc=%d far %dx%dx%d q=%d nnz=%lld bytes=%lld %.3fs\n",
-                 static_cast<long long>(p->N), p->ng.n[0], p->ng.n[1], p->ng.n[2], p->ng.q, p->prm.corr_radius,
-                 p->fg.n[0], p->fg.n[1], p->fg.n[2], p->fg.q, static_cast<long long>(p->nnz),
-                 static_cast<long long>(p->device_bytes), p->plan_seconds);
-  }
-  *plan = p;
-  return FFTPIM_OK;
+  return guarded([&]() -> int {
+    if (!plan || !problem || !params || !src_xyz_dev) return FFTPIM_ERR_INVALID_ARG;
+    *plan = nullptr;
+    if (n_src < 1 || n_src > (int64_t{1} << 30)) return FFTPIM_ERR_INVALID_ARG;
+    if (obs_xyz_dev != nullptr) return FFTPIM_ERR_UNIMPLEMENTED;
+    if (n_obs != n_src && n_obs != 0) return FFTPIM_ERR_INVALID_ARG;
+    CHK(validate(problem, params));
+    Lattice lat{};
+    lat.dims = problem->periodic_dims;
+    for (int c = 0; c < 3; ++c) {
+      lat.L[c] = c < lat.dims ? problem->L[c] : 1.0;
+      lat.kt[c] = c < lat.dims ? problem->kt[c] : 0.0;
+    }
+    lat.k0 = problem->k0;
+    if (params->value_type == FFTPIM_REAL && !lat.npsp()) return FFTPIM_ERR_INVALID_ARG;
+    if (params->self_mode == FFTPIM_SELF_EXCLUDE) return FFTPIM_ERR_UNIMPLEMENTED;
+    if (check_supported(lat)) return FFTPIM_ERR_UNSUPPORTED;
+    if (wood_anomaly(lat)) return FFTPIM_ERR_WOOD_ANOMALY;
+    auto t0 = std::chrono::steady_clock::now();
+    fftpim_plan_s* p = new (std::nothrow) fftpim_plan_s();
+    if (!p) return FFTPIM_ERR_NO_MEMORY;
+    p->lat = lat;
+    p->problem = *problem;
+    p->prm = *params;
+    p->N = n_src;
+    p->complex_kernel = !lat.npsp();
+    p->helmholtz = lat.k0 != 0.0;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // an exception inside the build still frees the partly built plan
+    int s = guarded([&]() -> int { return build_plan(p, n_src, src_xyz_dev, st); });
+    if (s != FFTPIM_OK) {
+      fftpim_destroy(p);
+      return s;
+    }
+    p->plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    p->last_stream = st;
+    if (std::getenv("FFTPIM_LOG")) {
+      std::fprintf(stderr, "fftpim plan: N=%lld near %dx%dx%d q=%d rc=%d far %dx%dx%d q=%d nnz=%lld bytes=%lld %.3fs\n",
+                   static_cast<long long>(p->N), p->ng.n[0], p->ng.n[1], p->ng.n[2], p->ng.q, p->prm.corr_radius,
+                   p->fg.n[0], p->fg.n[1], p->fg.n[2], p->fg.q, static_cast<long long>(p->nnz),
+                   static_cast<long long>(p->device_bytes), p->plan_seconds);
+    }
+    *plan = p;
+    return FFTPIM_OK;
+  });
 }
 
 int fftpim_apply(fftpim_plan_t plan, const void* q_dev, void* u_dev, int nrhs, fftpim_stream_t stream) {
-  return apply_common(plan, FFTPIM_PART_ALL, 0, q_dev, u_dev, nrhs, stream, true);
+  return guarded([&]() -> int {
+    return apply_common(plan, FFTPIM_PART_ALL, 0, q_dev, u_dev, nrhs, stream, true);
+  });
 }
 
 int fftpim_apply_adjoint(fftpim_plan_t plan, const void* v_dev, void* w_dev, int nrhs, fftpim_stream_t stream) {
-  return apply_common(plan, FFTPIM_PART_ALL, 1, v_dev, w_dev, nrhs, stream, true);
+  return guarded([&]() -> int {
+    return apply_common(plan, FFTPIM_PART_ALL, 1, v_dev, w_dev, nrhs, stream, true);
+  });
 }
 
 int fftpim_apply_pair(fftpim_plan_t plan, const void* q_dev, void* u_dev, const void* v_dev, void* w_dev, int nrhs,
                       fftpim_stream_t stream) {
-  if (!plan || !q_dev || !u_dev || !v_dev || !w_dev) return FFTPIM_ERR_INVALID_ARG;
-  if (nrhs < 1 || nrhs > plan->prm.nrhs_max) return FFTPIM_ERR_INVALID_ARG;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  if (plan->prm.precision != FFTPIM_F64) return run_apply_pair<float>(plan, q_dev, u_dev, v_dev, w_dev, nrhs, st);
-  return run_apply_pair<double>(plan, q_dev, u_dev, v_dev, w_dev, nrhs, st);
+  return guarded([&]() -> int {
+    if (!plan || !q_dev || !u_dev || !v_dev || !w_dev) return FFTPIM_ERR_INVALID_ARG;
+    if (nrhs < 1 || nrhs > plan->prm.nrhs_max) return FFTPIM_ERR_INVALID_ARG;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (plan->prm.precision != FFTPIM_F64) return run_apply_pair<float>(plan, q_dev, u_dev, v_dev, w_dev, nrhs, st);
+    return run_apply_pair<double>(plan, q_dev, u_dev, v_dev, w_dev, nrhs, st);
+  });
 }
 
 int fftpim_apply_parts(fftpim_plan_t plan, int parts, int adjoint, const void* q_dev, void* u_dev, int nrhs,
                        fftpim_stream_t stream) {
-  return apply_common(plan, parts, adjoint, q_dev, u_dev, nrhs, stream, false);
+  return guarded([&]() -> int {
+    return apply_common(plan, parts, adjoint, q_dev, u_dev, nrhs, stream, false);
+  });
 }
 
 int fftpim_get_permutation(fftpim_plan_t plan, int which, int32_t* perm_dev) {
-  if (!plan || !perm_dev || (which != 0 && which != 1)) return FFTPIM_ERR_INVALID_ARG;
-  HIPCHK(hipMemcpy(perm_dev, plan->perm, plan->N * sizeof(int32_t), hipMemcpyDeviceToDevice));
-  return FFTPIM_OK;
+  return guarded([&]() -> int {
+    if (!plan || !perm_dev || (which != 0 && which != 1)) return FFTPIM_ERR_INVALID_ARG;
+    HIPCHK(hipMemcpy(perm_dev, plan->perm, plan->N * sizeof(int32_t), hipMemcpyDeviceToDevice));
+    return FFTPIM_OK;
+  });
 }
 
 int fftpim_plan_info(fftpim_plan_t plan, fftpim_info_t* info) {
-  if (!plan || !info) return FFTPIM_ERR_INVALID_ARG;
-  fftpim_info_t r{};
-  r.n_src = plan->N;
-  r.n_obs = plan->N;
-  for (int c = 0; c < 3; ++c) {
-    r.near_n[c] = plan->ng.n[c];
-    r.near_fft[c] = plan->M[c];
-    r.near_cells[c] = plan->ng.nint[c];
-    r.near_h[c] = plan->ng.h[c];
-    r.domain_lo[c] = plan->ng.lo[c];
-    r.domain_hi[c] = plan->ng.lo[c] + plan->ng.h[c] * plan->ng.nint[c];
-    r.far_n[c] = plan->fg.n[c];
-    r.far_cells[c] = plan->fg.nint[c];
-    r.far_h[c] = plan->fg.h[c];
-  }
-  r.corr_nnz = plan->nnz + plan->sym_nvals;
-  r.corr_sym_values = plan->sym_nvals;
-  r.corr_csr_nnz = plan->tile ? 0 : plan->nnz;
-  r.corr_tile_values = plan->tile_nvals;
-  r.corr_value_bytes = plan->complex_kernel ? 16 : 8;
-  r.corr_layout_used = plan->tile ? FFTPIM_CORR_TILE : (plan->sym ? FFTPIM_CORR_SYM : FFTPIM_CORR_CSR);
-  r.device_bytes = plan->device_bytes;
-  r.nplanes_max = plan->nplanes_max;
-  r.plan_seconds = plan->plan_seconds;
-  *info = r;
-  return FFTPIM_OK;
+  return guarded([&]() -> int {
+    if (!plan || !info) return FFTPIM_ERR_INVALID_ARG;
+    fftpim_info_t r{};
+    r.n_src = plan->N;
+    r.n_obs = plan->N;
+    for (int c = 0; c < 3; ++c) {
+      r.near_n[c] = plan->ng.n[c];
+      r.near_fft[c] = plan->M[c];
+      r.near_cells[c] = plan->ng.nint[c];
+      r.near_h[c] = plan->ng.h[c];
+      r.domain_lo[c] = plan->ng.lo[c];
+      r.domain_hi[c] = plan->ng.lo[c] + plan->ng.h[c] * plan->ng.nint[c];
+      r.far_n[c] = plan->fg.n[c];
+      r.far_cells[c] = plan->fg.nint[c];
+      r.far_h[c] = plan->fg.h[c];
+    }
+    r.corr_nnz = plan->nnz + plan->sym_nvals;
+    r.corr_sym_values = plan->sym_nvals;
+    r.corr_csr_nnz = plan->tile ? 0 : plan->nnz;
+    r.corr_tile_values = plan->tile_nvals;
+    r.corr_value_bytes = plan->complex_kernel ? 16 : 8;
+    r.corr_layout_used = plan->tile ? FFTPIM_CORR_TILE : (plan->sym ? FFTPIM_CORR_SYM : FFTPIM_CORR_CSR);
+    r.device_bytes = plan->device_bytes;
+    r.nplanes_max = plan->nplanes_max;
+    r.plan_seconds = plan->plan_seconds;
+    *info = r;
+    return FFTPIM_OK;
+  });
 }
 
 int fftpim_last_status(fftpim_plan_t plan) {
-  if (!plan) return FFTPIM_ERR_INVALID_ARG;
-  HIPCHK(hipStreamSynchronize(plan->last_stream));
-  int v = 0;
-  HIPCHK(hipMemcpy(&v, plan->status_dev, sizeof(int), hipMemcpyDeviceToHost));
-  HIPCHK(hipMemset(plan->status_dev, 0, sizeof(int)));
-  return v;
+  return guarded([&]() -> int {
+    if (!plan) return FFTPIM_ERR_INVALID_ARG;
+    HIPCHK(hipStreamSynchronize(plan->last_stream));
+    int v = 0;
+    HIPCHK(hipMemcpy(&v, plan->status_dev, sizeof(int), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemset(plan->status_dev, 0, sizeof(int)));
+    return v;
+  });
 }
 
 int fftpim_stage_times(fftpim_plan_t plan, int enable, double* ms_out, int64_t* calls_out) {
-  if (!plan) return FFTPIM_ERR_INVALID_ARG;
-  resolve_timers(plan);
-  if (ms_out)
-    for (int s = 0; s < FFTPIM_NSTAGES; ++s) ms_out[s] = plan->stage_ms[s];
-  if (calls_out)
-    for (int s = 0; s < FFTPIM_NSTAGES; ++s) calls_out[s] = plan->stage_calls[s];
-  if (enable) {
-    for (int s = 0; s < FFTPIM_NSTAGES; ++s) {
-      plan->stage_ms[s] = 0.0;
-      plan->stage_calls[s] = 0;
+  return guarded([&]() -> int {
+    if (!plan) return FFTPIM_ERR_INVALID_ARG;
+    resolve_timers(plan);
+    if (ms_out)
+      for (int s = 0; s < FFTPIM_NSTAGES; ++s) ms_out[s] = plan->stage_ms[s];
+    if (calls_out)
+      for (int s = 0; s < FFTPIM_NSTAGES; ++s) calls_out[s] = plan->stage_calls[s];
+    if (enable) {
+      for (int s = 0; s < FFTPIM_NSTAGES; ++s) {
+        plan->stage_ms[s] = 0.0;
+        plan->stage_calls[s] = 0;
+      }
     }
-  }
-  plan->timing = enable != 0;
-  return FFTPIM_OK;
+    plan->timing = enable != 0;
+    return FFTPIM_OK;
+  });
 }
 
 int fftpim_destroy(fftpim_plan_t plan) {
-  if (!plan) return FFTPIM_OK;
-  // the plan's streams may still be reading its buffers (teardown goes on
-  // whatever these calls return)
-  for (hipStream_t s : {plan->s_corr, plan->s_far, plan->s_near})
-    if (s) (void)hipStreamSynchronize(s);
-  (void)hipStreamSynchronize(plan->last_stream);
-  for (hipEvent_t e : plan->ev_pool) (void)hipEventDestroy(e);
-  plan->ev_pool.clear();
-  for (hipEvent_t e : {plan->ev_fork, plan->ev_corr, plan->ev_far, plan->ev_near})
-    if (e) (void)hipEventDestroy(e);
-  for (hipStream_t s : {plan->s_corr, plan->s_far, plan->s_near})
-    if (s) (void)hipStreamDestroy(s);
-  for (void* ptr : plan->allocations) (void)hipFree(ptr);
-  plan->allocations.clear();
-  delete plan;
-  return FFTPIM_OK;
+  return guarded([&]() -> int {
+    if (!plan) return FFTPIM_OK;
+    // the plan's streams may still be reading its buffers (teardown goes on
+    // whatever these calls return)
+    for (hipStream_t s : {plan->s_corr, plan->s_far, plan->s_near})
+      if (s) (void)hipStreamSynchronize(s);
+    (void)hipStreamSynchronize(plan->last_stream);
+    for (hipEvent_t e : plan->ev_pool) (void)hipEventDestroy(e);
+    plan->ev_pool.clear();
+    for (hipEvent_t e : {plan->ev_fork, plan->ev_corr, plan->ev_far, plan->ev_near})
+      if (e) (void)hipEventDestroy(e);
+    for (hipStream_t s : {plan->s_corr, plan->s_far, plan->s_near})
+      if (s) (void)hipStreamDestroy(s);
+    for (const DevBuf& b : plan->allocations) (void)hipFree(b.p);
+    plan->allocations.clear();
+    delete plan;
+    return FFTPIM_OK;
+  });
 }
 
 const char* fftpim_error_string(int status) {
@@ -1589,22 +1652,24 @@ const char* fftpim_error_string(int status) {
 }
 
 int fftpim_eval_pgf(const fftpim_problem_t* problem, int64_t n, const double* r_xyz, double* out) {
-  if (!problem || !r_xyz || !out || n < 0) return FFTPIM_ERR_INVALID_ARG;
-  if (problem->periodic_dims < 1 || problem->periodic_dims > 3) return FFTPIM_ERR_INVALID_ARG;
-  Lattice lat{};
-  lat.dims = problem->periodic_dims;
-  for (int c = 0; c < 3; ++c) {
-    lat.L[c] = c < lat.dims ? problem->L[c] : 1.0;
-    lat.kt[c] = c < lat.dims ? problem->kt[c] : 0.0;
-  }
-  lat.k0 = problem->k0;
-  if (check_supported(lat)) return FFTPIM_ERR_UNSUPPORTED;
-  for (int64_t i = 0; i < n; ++i) {
-    cd v = pgf(lat, r_xyz + 3 * i);
-    out[2 * i] = v.real();
-    out[2 * i + 1] = v.imag();
-  }
-  return FFTPIM_OK;
+  return guarded([&]() -> int {
+    if (!problem || !r_xyz || !out || n < 0) return FFTPIM_ERR_INVALID_ARG;
+    if (problem->periodic_dims < 1 || problem->periodic_dims > 3) return FFTPIM_ERR_INVALID_ARG;
+    Lattice lat{};
+    lat.dims = problem->periodic_dims;
+    for (int c = 0; c < 3; ++c) {
+      lat.L[c] = c < lat.dims ? problem->L[c] : 1.0;
+      lat.kt[c] = c < lat.dims ? problem->kt[c] : 0.0;
+    }
+    lat.k0 = problem->k0;
+    if (check_supported(lat)) return FFTPIM_ERR_UNSUPPORTED;
+    for (int64_t i = 0; i < n; ++i) {
+      cd v = pgf(lat, r_xyz + 3 * i);
+      out[2 * i] = v.real();
+      out[2 * i + 1] = v.imag();
+    }
+    return FFTPIM_OK;
+  });
 }
 
 }  // extern "C"

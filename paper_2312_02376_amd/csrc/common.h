@@ -212,7 +212,6 @@ struct fftpim_plan_s {
   void* near_hat = nullptr;       // [Mx][My][Mz] complex R, scaled by 1/(Mx My Mz)
   void* twiddle[3] = {nullptr, nullptr, nullptr};  // per axis, M/2 complex R
   void* far_table = nullptr;      // [(2nf-1)^3] complex R
-  double self_value[2] = {0.0, 0.0};
 
   // in-cell correction as symmetric box-pair blocks (when sym is set), the
   // CSR below then holds only the close-image part
@@ -272,7 +271,7 @@ struct fftpim_plan_s {
   double stage_ms[8] = {0};
   int64_t stage_calls[8] = {0};
 
-  std::vector<void*> allocations;
+  std::vector<fftpim::DevBuf> allocations;
   int64_t device_bytes = 0;
   double plan_seconds = 0.0;
   hipStream_t last_stream = nullptr;

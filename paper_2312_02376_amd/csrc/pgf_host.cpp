@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <system_error>
 #include <thread>
 #include <vector>
 
@@ -298,20 +299,28 @@ void far_table(const Lattice& lat, int i_d, const int nf[3], const double delta[
   const int sx = 2 * nf[0] - 1, sy = 2 * nf[1] - 1, sz = 2 * nf[2] - 1;
   const int64_t total = static_cast<int64_t>(sx) * sy * sz;
   table.assign(total, cd(0.0, 0.0));
-  unsigned nthreads = std::max(1u, std::min(64u, std::thread::hardware_concurrency()));
+  const unsigned nthreads = std::max(1u, std::min(64u, std::thread::hardware_concurrency()));
+  auto work = [&](unsigned t) {
+    for (int64_t e = t; e < total; e += nthreads) {
+      int dz = static_cast<int>(e % sz);
+      int dy = static_cast<int>((e / sz) % sy);
+      int dx = static_cast<int>(e / (static_cast<int64_t>(sz) * sy));
+      double r[3] = {(dx - (nf[0] - 1) - 0.5) * delta[0], (dy - (nf[1] - 1) - 0.5) * delta[1],
+                     (dz - (nf[2] - 1) - 0.5) * delta[2]};
+      table[e] = pgf(lat, r) - g_near(lat, r, i_d);
+    }
+  };
   std::vector<std::thread> pool;
-  for (unsigned t = 0; t < nthreads; ++t) {
-    pool.emplace_back([&, t]() {
-      for (int64_t e = t; e < total; e += nthreads) {
-        int dz = static_cast<int>(e % sz);
-        int dy = static_cast<int>((e / sz) % sy);
-        int dx = static_cast<int>(e / (static_cast<int64_t>(sz) * sy));
-        double r[3] = {(dx - (nf[0] - 1) - 0.5) * delta[0], (dy - (nf[1] - 1) - 0.5) * delta[1],
-                       (dz - (nf[2] - 1) - 0.5) * delta[2]};
-        table[e] = pgf(lat, r) - g_near(lat, r, i_d);
-      }
-    });
+  pool.reserve(nthreads);
+  unsigned started = 0;
+  for (; started < nthreads; ++started) {
+    try {
+      pool.emplace_back(work, started);
+    } catch (const std::system_error&) {
+      break;  // no more host threads: the calling thread takes the rest
+    }
   }
+  for (unsigned t = started; t < nthreads; ++t) work(t);
   for (auto& th : pool) th.join();
 }
 

@@ -43,14 +43,15 @@ class FFTPIMError(RuntimeError):
 class Problem(ctypes.Structure):
     _fields_ = [("periodic_dims", ctypes.c_int), ("L", ctypes.c_double * 3), ("k0", ctypes.c_double),
                 ("kt", ctypes.c_double * 3), ("has_box", ctypes.c_int), ("box_lo", ctypes.c_double * 3),
-                ("box_hi", ctypes.c_double * 3)]
+                ("box_hi", ctypes.c_double * 3), ("k0_im", ctypes.c_double), ("kt_im", ctypes.c_double * 3)]
 
 
 class Params(ctypes.Structure):
     _fields_ = [("near_n", ctypes.c_int * 3), ("near_order", ctypes.c_int), ("corr_radius", ctypes.c_int),
                 ("far_n", ctypes.c_int * 3), ("far_order", ctypes.c_int), ("n_images", ctypes.c_int),
                 ("precision", ctypes.c_int), ("value_type", ctypes.c_int), ("self_mode", ctypes.c_int),
-                ("order_io", ctypes.c_int), ("nrhs_max", ctypes.c_int), ("corr_layout", ctypes.c_int)]
+                ("order_io", ctypes.c_int), ("nrhs_max", ctypes.c_int), ("corr_layout", ctypes.c_int),
+                ("max_bytes", ctypes.c_size_t)]
 
 
 class Info(ctypes.Structure):
@@ -109,8 +110,11 @@ def make_problem(periodic_dims, L, k0=0.0, kt=(0.0, 0.0, 0.0), box=None):
     Lv = list(np.broadcast_to(np.asarray(L, float), (3,))) if np.ndim(L) == 0 else list(L) + [1.0] * (3 - len(L))
     for c in range(3):
         pr.L[c] = float(Lv[c])
-        pr.kt[c] = float(kt[c]) if c < len(kt) else 0.0
-    pr.k0 = float(k0)
+        k = complex(kt[c]) if c < len(kt) else 0j
+        pr.kt[c] = k.real
+        pr.kt_im[c] = k.imag
+    pr.k0 = complex(k0).real
+    pr.k0_im = complex(k0).imag
     if box is not None:
         pr.has_box = 1
         for c in range(3):
@@ -127,6 +131,16 @@ def eval_pgf(r, periodic_dims, L, k0=0.0, kt=(0.0, 0.0, 0.0)):
     pr = make_problem(periodic_dims, L, k0, kt)
     _check(lib().fftpim_eval_pgf(ctypes.byref(pr), r.shape[0], r.ctypes.data, out.ctypes.data), "fftpim_eval_pgf")
     return out[:, 0] + 1j * out[:, 1]
+
+
+def _overlap(a, b):
+    """True when the memory spans of two dense tensors intersect."""
+    if a.device != b.device:
+        return False
+    a0, b0 = a.data_ptr(), b.data_ptr()
+    a1 = a0 + a.numel() * a.element_size()
+    b1 = b0 + b.numel() * b.element_size()
+    return a0 < b1 and b0 < a1
 
 
 def _stream_handle(stream):
@@ -148,7 +162,7 @@ class Plan:
     def __init__(self, positions, periodic_dims, L, k0=0.0, kt=(0.0, 0.0, 0.0), near_n=(16, 16, 16),
                  near_order=4, corr_radius=6, far_n=(16, 16, 16), far_order=7, n_images=1, precision="f64",
                  value_type="complex", order="user", nrhs_max=1, box=None, self_mode="images",
-                 corr_layout="auto", stream=None):
+                 corr_layout="auto", max_bytes=0, stream=None):
         import torch
         if not (isinstance(positions, torch.Tensor) and positions.is_cuda and positions.dtype == torch.float64):
             raise TypeError("positions must be a CUDA float64 tensor of shape (N, 3)")
@@ -170,6 +184,7 @@ class Plan:
         pm.order_io = {"user": ORDER_USER, "plan": ORDER_PLAN}[order]
         pm.nrhs_max = int(nrhs_max)
         pm.corr_layout = {"auto": 0, "csr": 1, "sym": 2, "tile": 3}[corr_layout]
+        pm.max_bytes = int(max_bytes)
         self.params = pm
         self.precision = precision
         self.value_type = value_type
@@ -185,8 +200,8 @@ class Plan:
 
     def _io(self, x, out):
         import torch
-        if x.dtype != self.dtype or not x.is_cuda:
-            raise TypeError("expected a CUDA %s tensor" % self.dtype)
+        if not isinstance(x, torch.Tensor) or x.dtype != self.dtype or x.device != self.device:
+            raise TypeError("expected a %s tensor on %s" % (self.dtype, self.device))
         squeeze = x.dim() == 1
         x2 = x.reshape(1, -1) if squeeze else x
         if x2.shape[1] != self.N:
@@ -194,6 +209,21 @@ class Plan:
         x2 = x2.contiguous()
         if out is None:
             out = torch.empty_like(x2)
+        else:
+            # the library writes nrhs x N elements through out's pointer:
+            # accept only a tensor that holds exactly that, densely
+            if not isinstance(out, torch.Tensor) or out.dtype != self.dtype:
+                raise TypeError("out must be a %s tensor" % self.dtype)
+            if out.device != self.device:
+                raise ValueError("out is on %s, the plan on %s" % (out.device, self.device))
+            o2 = out.reshape(1, -1) if (squeeze and out.dim() == 1) else out
+            if tuple(o2.shape) != tuple(x2.shape):
+                raise ValueError("out has shape %s, expected %s" % (tuple(out.shape), tuple(x.shape)))
+            if not out.is_contiguous():
+                raise ValueError("out must be contiguous")
+            if _overlap(out, x2):
+                raise ValueError("out must not overlap the input")
+            out = o2
         return x2, out, squeeze
 
     def apply(self, q, out=None, stream=None):
@@ -216,6 +246,8 @@ class Plan:
         v2, out_w, _ = self._io(v, out_w)
         if v2.shape != q2.shape:
             raise ValueError("q and v must have the same shape")
+        if _overlap(out_u, out_w) or _overlap(out_u, v2) or _overlap(out_w, q2):
+            raise ValueError("out_u and out_w must not overlap each other or the inputs")
         _check(lib().fftpim_apply_pair(self._h, ctypes.c_void_p(q2.data_ptr()), ctypes.c_void_p(out_u.data_ptr()),
                                        ctypes.c_void_p(v2.data_ptr()), ctypes.c_void_p(out_w.data_ptr()),
                                        q2.shape[0], _stream_handle(stream)), "fftpim_apply_pair")
