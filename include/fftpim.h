@@ -72,6 +72,12 @@ typedef enum {
  * per term (about 16 significant bits). */
 enum { FFTPIM_F64 = 0, FFTPIM_F32 = 1, FFTPIM_F32_FARBF16 = 2, FFTPIM_F32_FARBF16X3 = 3 };
 enum { FFTPIM_REAL = 0, FFTPIM_COMPLEX = 1 };     /* element type of q and u */
+/* Self term (Eq. (1) sums over every n, Eq. (5) writes n != m):
+ * FFTPIM_SELF_IMAGES drops only the singular zeroth image of the n = m term,
+ * so the images of a point act on itself (what the grid pipeline computes);
+ * FFTPIM_SELF_EXCLUDE drops the whole n = m term: every apply (and every
+ * part mask of fftpim_apply_parts) also subtracts C_self q_m, with C_self =
+ * fftpim_eval_pgf_self, and the conjugate transpose conj(C_self) v_m. */
 enum { FFTPIM_SELF_IMAGES = 0, FFTPIM_SELF_EXCLUDE = 1 };
 enum { FFTPIM_ORDER_USER = 0, FFTPIM_ORDER_PLAN = 1 };
 enum { FFTPIM_PART_NEAR_GRID = 1, FFTPIM_PART_NEAR_CORR = 2, FFTPIM_PART_FAR = 4,
@@ -238,6 +244,15 @@ const char* fftpim_error_string(int status);
  * vectors.  Exposed so the evaluator can be checked on its own. */
 int fftpim_eval_pgf(const fftpim_problem_t* problem, int64_t n, const double* r_xyz,
                     double* out);
+
+/* lim_{r->0} [G^p(r) - G0(r)] for the problem (Sec. 2): the coefficient
+ * with which the images of a point act on the point itself, i.e. the n = m
+ * term of Eq. (1) without its singular zeroth image, in the gauge of
+ * fftpim_eval_pgf for the neutral static case.  The apply subtracts
+ * C_self q_m when params.self_mode is FFTPIM_SELF_EXCLUDE (Eq. (5), n != m).
+ * out [2] receives (re, im).  Host only.  Errors: INVALID_ARG, UNSUPPORTED,
+ * WOOD_ANOMALY. */
+int fftpim_eval_pgf_self(const fftpim_problem_t* problem, double* out);
 
 #ifdef __cplusplus
 }

@@ -12,9 +12,10 @@ Conventions (Sec. 2, Eq. (1)-(2)):
 Representations used, per periodicity:
   * the paper's Floquet series, Eq. (pgf_1)-(pgf_3);
   * the paper's neutral static series, Eq. (lgf_1)-(lgf_3);
-  * textbook Ewald splittings (3D and 2D, static and Helmholtz, with phase)
-    and, for the 1D static case at small transverse distance, the real-space
-    series that follows from Gradshteyn & Ryzhik 8.526.1.
+  * textbook Ewald splittings (3D, 2D and 1D, static and Helmholtz, with
+    phase; the 1D spectral part in incomplete-gamma form) and, for the neutral
+    1D static case at small transverse distance, the real-space series that
+    follows from Gradshteyn & Ryzhik 8.526.1.
 The paper's series converge exponentially only when the transverse distance is
 not small (end of Sec. 2); the dispatcher `pgf` picks the paper's series when
 it converges quickly and an Ewald splitting otherwise.  The test suite checks
@@ -423,6 +424,57 @@ def ewald2(r, lat, E=None, self_term=False):
     return out
 
 
+def _expint1(z):
+    """E1(z) on the principal branch; on the negative real axis the value
+    reached from above (the limit of a lossy k0 with Im k0 -> 0-)."""
+    z = complex(z)
+    if z.imag == 0.0 and z.real < 0.0:
+        return -float(sp.expi(-z.real)) - 1j * math.pi
+    return complex(sp.exp1(z))
+
+
+def ewald1(r, lat, E=None, self_term=False):
+    """1D-periodic (x) Ewald splitting (static with a phase shift, or
+    Helmholtz, any phase; not the neutral static case).
+
+    Spatial part: sum_R phi_R S(|r - R|) as in 3D.  Spectral part
+      (1/(4 pi Lx)) sum_m e^{-j kxm x} sum_{q>=0} ((-1)^q/q!) (rho E)^{2q} E_{q+1}(-krho_m^2/(4 E^2)),
+    krho_m^2 = k0^2 - kxm^2, with E_{q+1} on the principal branch (the branch
+    that matches Im krho_m <= 0) and E_{q+1}(z) = (e^{-z} - z E_q(z))/q.
+    Valid at any rho, including rho = 0 (x not a lattice point)."""
+    if lat.npsp:
+        raise ValueError("the neutral static 1D case has no E1 spectral form (divergent m = 0 term)")
+    r = np.atleast_2d(np.asarray(r, dtype=float))
+    Lx = lat.L[0]
+    k0 = lat.k0
+    if E is None:
+        E = max(math.sqrt(math.pi) / Lx, abs(k0) / 6.0)
+    out = _spatial_part(r, lat, E, self_term)
+    x = r[:, 0]
+    t2 = (r[:, 1] ** 2 + r[:, 2] ** 2) * E * E
+    kmax = 2 * E * math.sqrt(42.0 + max(0.0, (k0 * k0).real) / (4 * E * E)) + abs(lat.kt[0])
+    mmax = int(math.ceil(kmax * Lx / (2 * math.pi))) + 1
+    qmax = 0
+    coef = 1.0
+    tmax = float(t2.max()) if t2.size else 0.0
+    while coef > 1e-19 and qmax < 200:
+        qmax += 1
+        coef *= tmax / qmax
+    for m in range(-mmax, mmax + 1):
+        kx = lat.kt[0] + 2 * math.pi * m / Lx
+        z = -(k0 * k0 - kx * kx) / (4 * E * E)
+        En = _expint1(z)
+        ez = np.exp(-z)
+        acc = np.full(x.size, En, dtype=complex)
+        c = np.ones(x.size)
+        for q in range(1, qmax + 1):
+            En = (ez - z * En) / q
+            c = c * (-t2) / q
+            acc += c * En
+        out += np.exp(-1j * kx * x) * acc / (4 * math.pi * Lx)
+    return out
+
+
 # ----------------------------------------------------------------------------
 # dispatcher
 # ----------------------------------------------------------------------------
@@ -497,7 +549,7 @@ def _pgf_reduced(r, lat, method):
         elif lat.npsp:
             out[idx_e] = lgf1_realspace(re[:, 0], re[:, 1], re[:, 2], L[0])
         else:
-            raise NotImplementedError("1D Helmholtz at small transverse distance")
+            out[idx_e] = ewald1(re, lat)
     return out
 
 
@@ -531,7 +583,7 @@ def pgf_self(lat):
         return complex(ewald2(z, lat, self_term=True)[0])
     if lat.npsp:
         return (EULER_GAMMA - math.log(2 * lat.L[0])) / (2 * math.pi * lat.L[0])
-    raise NotImplementedError("1D Helmholtz self term")
+    return complex(ewald1(z, lat, self_term=True)[0])
 
 
 def g_near(r, lat, i_d):

@@ -205,7 +205,8 @@ SymArgs sym_args(const fftpim_plan_s* p) {
   for (int c = 0; c < 3; ++c) a.nb[c] = p->nb[c];
   a.R = p->prm.corr_radius + p->ng.q;
   a.W = 2 * a.R + 1;
-  a.k0 = p->lat.k0;
+  a.k0 = p->lat.k0.real();
+  a.k0_im = p->lat.k0.imag();
   a.max_box = d.max_box;
   a.npairs = d.npairs;
   a.nitems = d.nitems;
@@ -291,7 +292,7 @@ void resolve_timers(fftpim_plan_s* p) {
 template <typename R>
 void correction_zone(fftpim_plan_s* p, bool adjoint, const void* in, int P, void* out, hipStream_t sc) {
   const int64_t N = p->N;
-  const void* v = (adjoint && p->helmholtz) ? p->val_adj : p->val;
+  const void* v = (adjoint && p->nonhermitian) ? p->val_adj : p->val;
   if (p->tile) {
     // real correction values: the operator is symmetric, so the conjugate
     // transpose uses the same tiles
@@ -362,6 +363,18 @@ int near_grid_zone(fftpim_plan_s* p, const WorkSet& ws, bool adjoint, const void
   return FFTPIM_OK;
 }
 
+// The "exclude self" option (Eq. (5) read literally, n != m): the apply
+// subtracts C_self q_m, C_self = lim_{r->0}[G^p(r) - G0(r)], and its
+// conjugate transpose conj(C_self) v_m.
+DiagTerm self_term(const fftpim_plan_s* p, const void* packed_in, bool adjoint) {
+  DiagTerm d;
+  if (p->prm.self_mode != FFTPIM_SELF_EXCLUDE) return d;
+  d.in = packed_in;
+  d.re = -p->self_coef.real();
+  d.im = adjoint ? p->self_coef.imag() : -p->self_coef.imag();
+  return d;
+}
+
 template <typename R>
 int run_apply(fftpim_plan_s* p, int parts, bool adjoint, const void* in, void* out, int nrhs, hipStream_t st,
               bool finalize) {
@@ -419,78 +432,115 @@ int run_apply(fftpim_plan_s* p, int parts, bool adjoint, const void* in, void* o
   const void* un = do_near ? p->u_int : nullptr;
   const void* uc = do_corr ? p->u_corr : nullptr;
   const void* uf = do_far ? p->u_far : nullptr;
+  const DiagTerm diag = self_term(p, p->q_int, adjoint);
   const double* mean = nullptr;
   if (finalize && adjoint && p->lat.npsp()) {
     // only the zero-mean part of A^H v is defined for the neutral static case
-    launch_plane_sums<R>(un, uc, uf, N, P, p->sums_work, p->sums, st);
+    launch_plane_sums<R>(un, uc, uf, N, P, p->sums_work, p->sums, st, diag);
     launch_mean_from_sums(p->sums, P, N, p->sums + 4 * p->nplanes_max, st);
     mean = p->sums + 4 * p->nplanes_max;
   }
   {
     StageTimer t(p, st, FFTPIM_STAGE_UNPACK);
-    launch_unpack<R>(un, uc, uf, out, p->perm, N, nrhs, P, real_io, use_perm, mean, st);
+    launch_unpack<R>(un, uc, uf, out, p->perm, N, nrhs, P, real_io, use_perm, mean, st, diag);
   }
   if (hipPeekAtLastError() != hipSuccess) return FFTPIM_ERR_DEVICE;
   return FFTPIM_OK;
 }
 
-int alloc_work_set(fftpim_plan_s* p, WorkSet& ws) {
-  ws = WorkSet{};
-  const int P = p->nplanes_max;
+// Byte sizes of the arrays of one near-grid + far-zone work set (for the
+// plan's largest plane count), in WorkSet field order.
+constexpr int kWorkArrays = 7;
+void work_set_sizes(const fftpim_plan_s* p, size_t sz[kWorkArrays]) {
+  const size_t P = static_cast<size_t>(p->nplanes_max);
   const size_t es = cbytes(p);
   const GridGeom& g = p->ng;
   const GridGeom& f = p->fg;
-  unsigned char* b = nullptr;
-  CHK(dalloc(p, &b, static_cast<size_t>(g.n[0]) * g.n[1] * g.n[2] * P * es));
-  ws.grid0 = b;
-  CHK(dalloc(p, &b, static_cast<size_t>(g.n[0]) * g.n[1] * p->M[2] * P * es));
-  ws.bufA = b;
-  CHK(dalloc(p, &b, static_cast<size_t>(g.n[0]) * p->M[1] * p->M[2] * P * es));
-  ws.bufB = b;
-  const int K1 = f.q + 1;
-  const int64_t fboxes = static_cast<int64_t>(p->fnb[0]) * p->fnb[1] * p->fnb[2];
-  CHK(dalloc(p, &b, static_cast<size_t>(fboxes) * K1 * K1 * K1 * P * es));
-  ws.far_mom = b;
-  const int64_t Ngf = static_cast<int64_t>(f.n[0]) * f.n[1] * f.n[2];
-  CHK(dalloc(p, &b, static_cast<size_t>(Ngf) * P * es));
-  ws.far_q = b;
-  CHK(dalloc(p, &b, static_cast<size_t>(Ngf) * P * es));
-  ws.far_u = b;
+  const size_t K1 = static_cast<size_t>(f.q + 1);
+  const size_t fboxes = static_cast<size_t>(p->fnb[0]) * p->fnb[1] * p->fnb[2];
+  const size_t Ngf = static_cast<size_t>(f.n[0]) * f.n[1] * f.n[2];
   // the split count never exceeds min(64, ceil(Ngf / 256)) for any nrhs
-  const int64_t max_splits = std::min<int64_t>(64, std::max<int64_t>(1, (Ngf + 255) / 256));
-  CHK(dalloc(p, &b, static_cast<size_t>(max_splits) * Ngf * P * es));
-  ws.far_part = b;
+  const size_t max_splits = std::min<size_t>(64, std::max<size_t>(1, (Ngf + 255) / 256));
+  sz[0] = static_cast<size_t>(g.n[0]) * g.n[1] * g.n[2] * P * es;        // grid0
+  sz[1] = static_cast<size_t>(g.n[0]) * g.n[1] * p->M[2] * P * es;       // bufA
+  sz[2] = static_cast<size_t>(g.n[0]) * p->M[1] * p->M[2] * P * es;      // bufB
+  sz[3] = fboxes * K1 * K1 * K1 * P * es;                                // far_mom
+  sz[4] = Ngf * P * es;                                                  // far_q
+  sz[5] = Ngf * P * es;                                                  // far_u
+  sz[6] = max_splits * Ngf * P * es;                                     // far_part
+}
+
+void** work_set_slots(WorkSet& ws, int k) {
+  void** slots[kWorkArrays] = {&ws.grid0, &ws.bufA, &ws.bufB, &ws.far_mom, &ws.far_q, &ws.far_u, &ws.far_part};
+  return slots[k];
+}
+
+int alloc_work_set(fftpim_plan_s* p, WorkSet& ws) {
+  ws = WorkSet{};
+  size_t sz[kWorkArrays];
+  work_set_sizes(p, sz);
+  for (int k = 0; k < kWorkArrays; ++k) {
+    unsigned char* b = nullptr;
+    CHK(dalloc(p, &b, sz[k]));
+    *work_set_slots(ws, k) = b;
+  }
   return FFTPIM_OK;
 }
 
-// Work arrays of the fused pair (packed v, the three parts of w and a second
-// near/far work set), made on the first pair call of a plan.
+// Bytes of the fused pair's own arrays (a second work set, packed v and the
+// three parts of w), each rounded up to 256 bytes as laid out by
+// carve_pair_buffers.
+size_t pair_buffer_bytes(const fftpim_plan_s* p) {
+  size_t sz[kWorkArrays];
+  work_set_sizes(p, sz);
+  auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  size_t total = 0;
+  for (int k = 0; k < kWorkArrays; ++k) total += up(sz[k]);
+  total += 4 * up(static_cast<size_t>(p->N) * p->nplanes_max * cbytes(p));
+  return total;
+}
+
+// Lays the fused pair's arrays out in one caller-provided device region of at
+// least pair_buffer_bytes(p) bytes (256-byte aligned); allocates nothing.
+PairBufs carve_pair_buffers(const fftpim_plan_s* p, unsigned char* base) {
+  size_t sz[kWorkArrays];
+  work_set_sizes(p, sz);
+  auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  PairBufs pb;
+  size_t off = 0;
+  for (int k = 0; k < kWorkArrays; ++k) {
+    *work_set_slots(pb.ws2, k) = base + off;
+    off += up(sz[k]);
+  }
+  const size_t nb = up(static_cast<size_t>(p->N) * p->nplanes_max * cbytes(p));
+  void** arr[4] = {&pb.v_int, &pb.u_int2, &pb.u_corr2, &pb.u_far2};
+  for (int k = 0; k < 4; ++k) {
+    *arr[k] = base + off;
+    off += nb;
+  }
+  return pb;
+}
+
+// The fused pair's arrays owned by the plan, made on its first pair call.
 int ensure_pair_buffers(fftpim_plan_s* p) {
-  if (p->v_int != nullptr) return FFTPIM_OK;
+  if (p->pair.v_int != nullptr) return FFTPIM_OK;
   // allocate into locals and publish only when every allocation succeeded; a
   // failure frees what this call made, so a retry starts from scratch
-  WorkSet ws2;
-  void* bufs[4] = {nullptr, nullptr, nullptr, nullptr};
-  auto release = [&]() {
-    for (void* q : {ws2.grid0, ws2.bufA, ws2.bufB, ws2.far_mom, ws2.far_q, ws2.far_u, ws2.far_part}) dfree(p, q);
-    for (void* q : bufs) dfree(p, q);
-  };
-  int s = alloc_work_set(p, ws2);
+  PairBufs pb;
+  int s = alloc_work_set(p, pb.ws2);
   const size_t bytes = static_cast<size_t>(p->N) * p->nplanes_max * cbytes(p);
+  void** arr[4] = {&pb.v_int, &pb.u_int2, &pb.u_corr2, &pb.u_far2};
   for (int k = 0; k < 4 && s == FFTPIM_OK; ++k) {
     unsigned char* b = nullptr;
     s = dalloc(p, &b, bytes);
-    bufs[k] = b;
+    *arr[k] = b;
   }
   if (s != FFTPIM_OK) {
-    release();
+    for (int k = 0; k < kWorkArrays; ++k) dfree(p, *work_set_slots(pb.ws2, k));
+    for (int k = 0; k < 4; ++k) dfree(p, *arr[k]);
     return s;
   }
-  p->ws2 = ws2;
-  p->u_int2 = bufs[1];
-  p->u_corr2 = bufs[2];
-  p->u_far2 = bufs[3];
-  p->v_int = bufs[0];
+  p->pair = pb;
   return FFTPIM_OK;
 }
 
@@ -501,18 +551,18 @@ int ensure_pair_buffers(fftpim_plan_s* p) {
 // far of A^H v on one, far of A q then near of A^H v on the other), each
 // product with its own work set, so both streams carry about the same work.
 template <typename R>
-int run_apply_pair(fftpim_plan_s* p, const void* q, void* u, const void* v, void* w, int nrhs, hipStream_t st) {
+int run_apply_pair(fftpim_plan_s* p, const PairBufs& pb, const void* q, void* u, const void* v, void* w, int nrhs,
+                   hipStream_t st) {
   const int64_t N = p->N;
   const int P = planes_for(p, nrhs);
   const bool real_io = p->prm.value_type == FFTPIM_REAL;
   const bool use_perm = p->prm.order_io == FFTPIM_ORDER_USER;
-  CHK(ensure_pair_buffers(p));
   p->last_stream = st;
   if (p->timing && p->ev_used > 4096) resolve_timers(p);
   {
     StageTimer t(p, st, FFTPIM_STAGE_PACK);
     launch_pack<R>(q, p->q_int, p->perm, N, nrhs, P, real_io, use_perm, st);
-    launch_pack<R>(v, p->v_int, p->perm, N, nrhs, P, real_io, use_perm, st);
+    launch_pack<R>(v, pb.v_int, p->perm, N, nrhs, P, real_io, use_perm, st);
     if (p->lat.npsp()) {
       launch_plane_sums<R>(p->q_int, nullptr, nullptr, N, P, p->sums_work, p->sums, st);
       launch_check_neutral(p->sums, P, p->prm.precision != FFTPIM_F64 ? 1e-5 : 1e-10, p->status_dev, st);
@@ -527,17 +577,17 @@ int run_apply_pair(fftpim_plan_s* p, const void* q, void* u, const void* v, void
       // the fused box-pair pass stages both inputs in LDS (at most 64 KB, as
       // the single apply)
       if (p->sym && static_cast<int64_t>(p->symd.max_box) * 2 * P <= 2048) {
-        launch_sym_apply<R>(p->complex_kernel, sym_args(p), p->sym_vals, p->q_int, p->v_int, P, 2 * P, false, true,
-                            p->sym_ypart, p->sym_zpart, p->u_corr, p->u_corr2, false, sc);
+        launch_sym_apply<R>(p->complex_kernel, sym_args(p), p->sym_vals, p->q_int, pb.v_int, P, 2 * P, false, true,
+                            p->sym_ypart, p->sym_zpart, p->u_corr, pb.u_corr2, false, sc);
         if (p->nnz > 0) {
           launch_corr_spmv<R>(p->complex_kernel, p->rowptr, p->col, p->val, N, p->corr_order, p->corr_slots, p->q_int,
                               P, p->u_corr, true, sc);
-          launch_corr_spmv<R>(p->complex_kernel, p->rowptr, p->col, p->helmholtz ? p->val_adj : p->val, N,
-                              p->corr_order, p->corr_slots, p->v_int, P, p->u_corr2, true, sc);
+          launch_corr_spmv<R>(p->complex_kernel, p->rowptr, p->col, p->nonhermitian ? p->val_adj : p->val, N,
+                              p->corr_order, p->corr_slots, pb.v_int, P, pb.u_corr2, true, sc);
         }
       } else {
         correction_zone<R>(p, false, p->q_int, P, p->u_corr, sc);
-        correction_zone<R>(p, true, p->v_int, P, p->u_corr2, sc);
+        correction_zone<R>(p, true, pb.v_int, P, pb.u_corr2, sc);
       }
     }
     HIPCHK(hipEventRecord(p->ev_corr, sc));
@@ -549,7 +599,7 @@ int run_apply_pair(fftpim_plan_s* p, const void* q, void* u, const void* v, void
       StageTimer t(p, sf, FFTPIM_STAGE_FAR);
       CHK(far_zone<R>(p, p->ws, false, p->q_int, P, p->u_far, sf));
     }
-    CHK(near_grid_zone<R>(p, p->ws2, true, p->v_int, P, p->u_int2, sf));
+    CHK(near_grid_zone<R>(p, pb.ws2, true, pb.v_int, P, pb.u_int2, sf));
     HIPCHK(hipEventRecord(p->ev_far, sf));
   }
   {
@@ -558,23 +608,24 @@ int run_apply_pair(fftpim_plan_s* p, const void* q, void* u, const void* v, void
     CHK(near_grid_zone<R>(p, p->ws, false, p->q_int, P, p->u_int, sn));
     {
       StageTimer t(p, sn, FFTPIM_STAGE_FAR);
-      CHK(far_zone<R>(p, p->ws2, true, p->v_int, P, p->u_far2, sn));
+      CHK(far_zone<R>(p, pb.ws2, true, pb.v_int, P, pb.u_far2, sn));
     }
     HIPCHK(hipEventRecord(p->ev_near, sn));
   }
   HIPCHK(hipStreamWaitEvent(st, p->ev_corr, 0));
   HIPCHK(hipStreamWaitEvent(st, p->ev_far, 0));
   HIPCHK(hipStreamWaitEvent(st, p->ev_near, 0));
+  const DiagTerm diag_u = self_term(p, p->q_int, false), diag_w = self_term(p, pb.v_int, true);
   const double* mean = nullptr;
   if (p->lat.npsp()) {
-    launch_plane_sums<R>(p->u_int2, p->u_corr2, p->u_far2, N, P, p->sums_work, p->sums, st);
+    launch_plane_sums<R>(pb.u_int2, pb.u_corr2, pb.u_far2, N, P, p->sums_work, p->sums, st, diag_w);
     launch_mean_from_sums(p->sums, P, N, p->sums + 4 * p->nplanes_max, st);
     mean = p->sums + 4 * p->nplanes_max;
   }
   {
     StageTimer t(p, st, FFTPIM_STAGE_UNPACK);
-    launch_unpack<R>(p->u_int, p->u_corr, p->u_far, u, p->perm, N, nrhs, P, real_io, use_perm, nullptr, st);
-    launch_unpack<R>(p->u_int2, p->u_corr2, p->u_far2, w, p->perm, N, nrhs, P, real_io, use_perm, mean, st);
+    launch_unpack<R>(p->u_int, p->u_corr, p->u_far, u, p->perm, N, nrhs, P, real_io, use_perm, nullptr, st, diag_u);
+    launch_unpack<R>(pb.u_int2, pb.u_corr2, pb.u_far2, w, p->perm, N, nrhs, P, real_io, use_perm, mean, st, diag_w);
   }
   if (hipPeekAtLastError() != hipSuccess) return FFTPIM_ERR_DEVICE;
   return FFTPIM_OK;
@@ -603,8 +654,6 @@ int validate(const fftpim_problem_t* pr, const fftpim_params_t* pm) {
   if (!std::isfinite(pr->k0_im) || pr->k0_im > 0.0) return FFTPIM_ERR_INVALID_ARG;
   for (int c = 0; c < 3; ++c)
     if (!std::isfinite(pr->kt[c]) || !std::isfinite(pr->kt_im[c])) return FFTPIM_ERR_INVALID_ARG;
-  if (pr->k0_im != 0.0 || pr->kt_im[0] != 0.0 || pr->kt_im[1] != 0.0 || pr->kt_im[2] != 0.0)
-    return FFTPIM_ERR_UNSUPPORTED;
   if (pm->near_order < 1 || pm->near_order > kMaxNearOrder) return FFTPIM_ERR_INVALID_ARG;
   if (pm->far_order < 1 || pm->far_order > kMaxFarOrder) return FFTPIM_ERR_INVALID_ARG;
   for (int c = 0; c < 3; ++c) {
@@ -654,9 +703,9 @@ int build_tables(fftpim_plan_s* p, hipStream_t st) {
         img.push_back(ix);
         img.push_back(iy);
         img.push_back(iz);
-        double a = p->lat.kt[0] * ix * p->lat.L[0] + p->lat.kt[1] * iy * p->lat.L[1] + p->lat.kt[2] * iz * p->lat.L[2];
-        ph.push_back(std::cos(a));
-        ph.push_back(-std::sin(a));
+        const cd f = p->lat.phase(ix, iy, iz);
+        ph.push_back(f.real());
+        ph.push_back(f.imag());
       }
   int* dimg = nullptr;
   double* dph = nullptr;
@@ -669,7 +718,8 @@ int build_tables(fftpim_plan_s* p, hipStream_t st) {
     na.nint[c] = p->ng.nint[c];
     na.h[c] = p->ng.h[c];
   }
-  na.k0 = p->lat.k0;
+  na.k0 = p->lat.k0.real();
+  na.k0_im = p->lat.k0.imag();
   na.nimg = static_cast<int>(img.size() / 3);
   na.img = dimg;
   na.phase = dph;
@@ -712,9 +762,11 @@ int build_tables(fftpim_plan_s* p, hipStream_t st) {
       ta.nf[c] = nf[c];
       ta.delta[c] = p->fg.h[c];
       ta.L[c] = p->lat.L[c];
-      ta.kt[c] = p->lat.kt[c];
+      ta.kt[c] = p->lat.kt[c].real();
+      ta.kt_im[c] = p->lat.kt[c].imag();
     }
-    ta.k0 = p->lat.k0;
+    ta.k0 = p->lat.k0.real();
+    ta.k0_im = p->lat.k0.imag();
     ta.id = id;
     const int64_t total = static_cast<int64_t>(2 * nf[0] - 1) * (2 * nf[1] - 1) * (2 * nf[2] - 1);
     cplx<double>* dt = nullptr;
@@ -1091,24 +1143,30 @@ int build_correction(fftpim_plan_s* p, const std::vector<int32_t>& start, const 
   ca.R = rc + q;
   ca.W = 2 * ca.R + 1;
   ca.N = p->N;
-  ca.k0 = p->lat.k0;
+  ca.k0 = p->lat.k0.real();
+  ca.k0_im = p->lat.k0.imag();
   ca.nimg_axis = A;
   ca.images_only = p->sym ? 1 : 0;
-  // image phases indexed by (gx, gy, gz), image g - id on periodic axes
-  std::vector<double> ph(2 * A * A * A, 0.0);
+  // image phases indexed by (gx, gy, gz), image g - id on periodic axes; the
+  // conjugate-transpose values use conj(phase of image -i) (the same as the
+  // phase of image i for a real phase shift)
+  std::vector<double> ph(4 * A * A * A, 0.0);
   for (int gx = 0; gx < A; ++gx)
     for (int gy = 0; gy < A; ++gy)
       for (int gz = 0; gz < A; ++gz) {
         int im[3] = {gx - id * ca.per[0], gy - id * ca.per[1], gz - id * ca.per[2]};
-        double a = 0.0;
-        for (int c = 0; c < 3; ++c) a += p->lat.kt[c] * im[c] * p->lat.L[c];
+        const cd f = p->lat.phase(im[0], im[1], im[2]);
+        const cd fa = std::conj(p->lat.phase(-im[0], -im[1], -im[2]));
         int k = (gx * A + gy) * A + gz;
-        ph[2 * k] = std::cos(a);
-        ph[2 * k + 1] = -std::sin(a);
+        ph[2 * k] = f.real();
+        ph[2 * k + 1] = f.imag();
+        ph[2 * A * A * A + 2 * k] = fa.real();
+        ph[2 * A * A * A + 2 * k + 1] = fa.imag();
       }
   double* dph = nullptr;
   CHK(upload(p, &dph, ph));
   ca.phase = dph;
+  ca.phase_adj = dph + 2 * A * A * A;
   // per-axis candidate source boxes for every observer box
   int32_t* doff[3];
   int32_t* dent[3];
@@ -1177,13 +1235,13 @@ int build_correction(fftpim_plan_s* p, const std::vector<int32_t>& start, const 
     unsigned char* v = nullptr;
     CHK(dalloc(p, &v, p->nnz * vb));
     p->val = v;
-    if (p->helmholtz) {
+    if (p->nonhermitian) {
       unsigned char* va = nullptr;
       CHK(dalloc(p, &va, p->nnz * vb));
       p->val_adj = va;
     }
   }
-  CHK(launch_corr_fill(q, cv, p->helmholtz, ca, p->near_s, p->near_u, pos3_dev, p->box_start, dg0, p->rowptr,
+  CHK(launch_corr_fill(q, cv, p->nonhermitian, ca, p->near_s, p->near_u, pos3_dev, p->box_start, dg0, p->rowptr,
                        p->col, p->val, p->val_adj, st));
   HIPCHK(hipStreamSynchronize(st));
   HIPCHK(hipGetLastError());
@@ -1422,6 +1480,17 @@ int build_plan(fftpim_plan_s* p, int64_t N, const double* src_dev, hipStream_t s
   return FFTPIM_OK;
 }
 
+Lattice lattice_of(const fftpim_problem_t& pr) {
+  Lattice lat{};
+  lat.dims = pr.periodic_dims;
+  for (int c = 0; c < 3; ++c) {
+    lat.L[c] = c < lat.dims ? pr.L[c] : 1.0;
+    lat.kt[c] = c < lat.dims ? cd(pr.kt[c], pr.kt_im[c]) : cd(0.0, 0.0);
+  }
+  lat.k0 = cd(pr.k0, pr.k0_im);
+  return lat;
+}
+
 // No C++ exception may cross the C ABI: host allocations (std::vector) and
 // the far-table worker threads can throw on resource exhaustion.
 template <typename F>
@@ -1476,15 +1545,8 @@ int fftpim_plan(fftpim_plan_t* plan, const fftpim_problem_t* problem, const fftp
     if (obs_xyz_dev != nullptr) return FFTPIM_ERR_UNIMPLEMENTED;
     if (n_obs != n_src && n_obs != 0) return FFTPIM_ERR_INVALID_ARG;
     CHK(validate(problem, params));
-    Lattice lat{};
-    lat.dims = problem->periodic_dims;
-    for (int c = 0; c < 3; ++c) {
-      lat.L[c] = c < lat.dims ? problem->L[c] : 1.0;
-      lat.kt[c] = c < lat.dims ? problem->kt[c] : 0.0;
-    }
-    lat.k0 = problem->k0;
+    const Lattice lat = lattice_of(*problem);
     if (params->value_type == FFTPIM_REAL && !lat.npsp()) return FFTPIM_ERR_INVALID_ARG;
-    if (params->self_mode == FFTPIM_SELF_EXCLUDE) return FFTPIM_ERR_UNIMPLEMENTED;
     if (check_supported(lat)) return FFTPIM_ERR_UNSUPPORTED;
     if (wood_anomaly(lat)) return FFTPIM_ERR_WOOD_ANOMALY;
     auto t0 = std::chrono::steady_clock::now();
@@ -1495,7 +1557,8 @@ int fftpim_plan(fftpim_plan_t* plan, const fftpim_problem_t* problem, const fftp
     p->prm = *params;
     p->N = n_src;
     p->complex_kernel = !lat.npsp();
-    p->helmholtz = lat.k0 != 0.0;
+    p->nonhermitian = !lat.hermitian();
+    if (params->self_mode == FFTPIM_SELF_EXCLUDE) p->self_coef = pgf_self(lat);
     hipStream_t st = static_cast<hipStream_t>(stream);
     // an exception inside the build still frees the partly built plan
     int s = guarded([&]() -> int { return build_plan(p, n_src, src_xyz_dev, st); });
@@ -1534,8 +1597,10 @@ int fftpim_apply_pair(fftpim_plan_t plan, const void* q_dev, void* u_dev, const 
     if (!plan || !q_dev || !u_dev || !v_dev || !w_dev) return FFTPIM_ERR_INVALID_ARG;
     if (nrhs < 1 || nrhs > plan->prm.nrhs_max) return FFTPIM_ERR_INVALID_ARG;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (plan->prm.precision != FFTPIM_F64) return run_apply_pair<float>(plan, q_dev, u_dev, v_dev, w_dev, nrhs, st);
-    return run_apply_pair<double>(plan, q_dev, u_dev, v_dev, w_dev, nrhs, st);
+    CHK(ensure_pair_buffers(plan));
+    if (plan->prm.precision != FFTPIM_F64)
+      return run_apply_pair<float>(plan, plan->pair, q_dev, u_dev, v_dev, w_dev, nrhs, st);
+    return run_apply_pair<double>(plan, plan->pair, q_dev, u_dev, v_dev, w_dev, nrhs, st);
   });
 }
 
@@ -1655,19 +1720,27 @@ int fftpim_eval_pgf(const fftpim_problem_t* problem, int64_t n, const double* r_
   return guarded([&]() -> int {
     if (!problem || !r_xyz || !out || n < 0) return FFTPIM_ERR_INVALID_ARG;
     if (problem->periodic_dims < 1 || problem->periodic_dims > 3) return FFTPIM_ERR_INVALID_ARG;
-    Lattice lat{};
-    lat.dims = problem->periodic_dims;
-    for (int c = 0; c < 3; ++c) {
-      lat.L[c] = c < lat.dims ? problem->L[c] : 1.0;
-      lat.kt[c] = c < lat.dims ? problem->kt[c] : 0.0;
-    }
-    lat.k0 = problem->k0;
+    const Lattice lat = lattice_of(*problem);
     if (check_supported(lat)) return FFTPIM_ERR_UNSUPPORTED;
     for (int64_t i = 0; i < n; ++i) {
       cd v = pgf(lat, r_xyz + 3 * i);
       out[2 * i] = v.real();
       out[2 * i + 1] = v.imag();
     }
+    return FFTPIM_OK;
+  });
+}
+
+int fftpim_eval_pgf_self(const fftpim_problem_t* problem, double* out) {
+  return guarded([&]() -> int {
+    if (!problem || !out) return FFTPIM_ERR_INVALID_ARG;
+    if (problem->periodic_dims < 1 || problem->periodic_dims > 3) return FFTPIM_ERR_INVALID_ARG;
+    const Lattice lat = lattice_of(*problem);
+    if (check_supported(lat)) return FFTPIM_ERR_UNSUPPORTED;
+    if (wood_anomaly(lat)) return FFTPIM_ERR_WOOD_ANOMALY;
+    const cd v = pgf_self(lat);
+    out[0] = v.real();
+    out[1] = v.imag();
     return FFTPIM_OK;
   });
 }

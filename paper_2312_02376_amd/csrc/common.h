@@ -174,13 +174,24 @@ struct WorkSet {
   void* far_part = nullptr;  // [splits][Ngf][planes] partial grid sums
 };
 
+// Arrays of the fused forward + adjoint pair beyond the plan's own workspace:
+// a second work set, the packed adjoint input and the three parts of A^H v.
+struct PairBufs {
+  WorkSet ws2;
+  void* v_int = nullptr;
+  void* u_int2 = nullptr;
+  void* u_corr2 = nullptr;
+  void* u_far2 = nullptr;
+};
+
 struct fftpim_plan_s {
   fftpim::Lattice lat;
   fftpim_problem_t problem;
   fftpim_params_t prm;
   int64_t N = 0;
   bool complex_kernel = true;  // G0 or the phases are complex
-  bool helmholtz = false;      // k0 != 0 (correction values not Hermitian)
+  bool nonhermitian = false;   // k0 != 0 or a complex phase shift: C^H needs its own values
+  std::complex<double> self_coef = 0.0;  // lim_{r->0}[G^p - G0] (self_mode exclude)
 
   // near grid
   fftpim::GridGeom ng;
@@ -250,16 +261,12 @@ struct fftpim_plan_s {
   void* u_int = nullptr;          // [N][planes] complex R: near-grid part
   void* u_corr = nullptr;         // [N][planes] correction part
   void* u_far = nullptr;          // [N][planes] far-zone part
-  void* v_int = nullptr;          // fused pair only: packed adjoint input
-  void* u_int2 = nullptr;         // fused pair only: the three parts of A^H v
-  void* u_corr2 = nullptr;
-  void* u_far2 = nullptr;
   // the correction and the far zone run on their own streams, forked from and
   // joined back into the caller's stream with events (default priority)
   hipStream_t s_corr = nullptr, s_far = nullptr, s_near = nullptr;
   hipEvent_t ev_fork = nullptr, ev_corr = nullptr, ev_far = nullptr, ev_near = nullptr;
   WorkSet ws;                     // near-grid and far-zone work arrays
-  WorkSet ws2;                    // fused pair only: a second set
+  PairBufs pair;                  // fused pair only, made on its first call
   double* sums = nullptr;         // [2][planes] neutrality / mean sums
   int* status_dev = nullptr;      // latched device-detected error
 

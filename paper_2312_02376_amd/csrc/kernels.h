@@ -38,7 +38,7 @@ struct FftPassDesc {
 struct NearTableArgs {
   int M[3], n[3], nint[3];
   double h[3];
-  double k0;
+  double k0, k0_im;
   int nimg;
   const int* img;        // device [nimg][3] image offsets
   const double* phase;   // device [nimg][2] image phases
@@ -50,9 +50,10 @@ struct CorrArgs {
   int R, W;            // g0 table covers offsets [-R, R]^3, W = 2R + 1
   int64_t N;
   double L[3];
-  double k0;
+  double k0, k0_im;
   int nimg_axis;       // 2 id + 1
   const double* phase;    // device image phases (re, im), index (gx * A + gy) * A + gz, image g - id
+  const double* phase_adj;  // conj(phase of image -i) at the index of image i (the C^H values)
   // per-axis candidate source boxes of an observer box S: entries
   // lent[c][loff[c][S] .. loff[c][S+1]) = b | (mask << 16), bit g of mask
   // marking image g - id (g = 0 only on non-periodic axes) as close
@@ -67,7 +68,7 @@ struct SymArgs {
   int64_t N;
   int nb[3];
   int R, W;             // g0 table geometry (as in CorrArgs)
-  double k0;
+  double k0, k0_im;
   int max_box;          // largest point count of a box
   int64_t npairs, nitems, nebox;
   const int32_t* box_start;      // [nb^3 + 1]
@@ -92,8 +93,8 @@ struct FarTableArgs {
   int nf[3];        // far grid nodes per axis
   double delta[3];  // far grid spacing
   double L[3];
-  double k0;
-  double kt[3];
+  double k0, k0_im;
+  double kt[3], kt_im[3];
   int id;           // near-zone images per periodic axis
 };
 void launch_far_table_pgf2(const FarTableArgs& a, void* table, hipStream_t st);
@@ -113,23 +114,34 @@ struct PartPtrs {
   const cplx<R>* a;
   const cplx<R>* b;
   const cplx<R>* c;
+  const cplx<R>* self;  // packed input of a diagonal term coef * input (null: none)
+  R cr, ci;             // its coefficient
   __device__ cplx<R> sum(int64_t i) const {
     cplx<R> s = cmake<R>(R(0), R(0));
     if (a) s = cadd(s, a[i]);
     if (b) s = cadd(s, b[i]);
     if (c) s = cadd(s, c[i]);
+    if (self) s = cadd(s, cmul(cmake<R>(cr, ci), self[i]));
     return s;
   }
 };
 
+// A diagonal term coef * x (x the packed input of the apply) added after the
+// parts: the "exclude self" option subtracts lim_{r->0}[G^p - G0] q_m.
+struct DiagTerm {
+  const void* in = nullptr;
+  double re = 0.0, im = 0.0;
+};
+
 template <typename R>
 void launch_unpack(const void* u_near, const void* u_corr, const void* u_far, void* uu, const int32_t* perm,
-                   int64_t N, int nrhs, int P, bool real_out, bool use_perm, const double* mean, hipStream_t st);
+                   int64_t N, int nrhs, int P, bool real_out, bool use_perm, const double* mean, hipStream_t st,
+                   DiagTerm diag = DiagTerm());
 // work: plane_sums_chunks(N) * P * 4 doubles of scratch
 int64_t plane_sums_chunks(int64_t N);
 template <typename R>
 void launch_plane_sums(const void* a, const void* b, const void* c, int64_t N, int P, double* work, double* out,
-                       hipStream_t st);
+                       hipStream_t st, DiagTerm diag = DiagTerm());
 void launch_check_neutral(const double* sums, int P, double tol, int* status, hipStream_t st);
 void launch_mean_from_sums(const double* sums, int P, int64_t N, double* mean, hipStream_t st);
 // Projection through the node-major weight CSR (few planes).

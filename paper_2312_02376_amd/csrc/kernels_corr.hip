@@ -119,7 +119,7 @@ __global__ void __launch_bounds__(64) k_corr_fill(
                   double dy = rm[1] - rn[1] - imy * a.L[1];
                   double dz = rm[2] - rn[2] - imz * a.L[2];
                   double r = sqrt(dx * dx + dy * dy + dz * dz);
-                  double inv = 1.0 / (4.0 * M_PI * r);
+                  double inv = (a.k0_im != 0.0 ? exp(a.k0_im * r) : 1.0) / (4.0 * M_PI * r);
                   if (CPLX) {
                     double s, c;
                     sincos(a.k0 * r, &s, &c);
@@ -155,8 +155,10 @@ __global__ void __launch_bounds__(64) k_corr_fill(
                   fr += pr * xr - pi * xi;
                   fi += pr * xi + pi * xr;
                   if (ADJ) {
-                    ar += pr * xr + pi * xi;
-                    ai += pi * xr - pr * xi;
+                    // entry (m, n) of C^H: psi_i conj(X), psi_i = conj(phase_{-i})
+                    const double qr = a.phase_adj[2 * pidx], qi = a.phase_adj[2 * pidx + 1];
+                    ar += qr * xr + qi * xi;
+                    ai += qi * xr - qr * xi;
                   }
                 } else {
                   fr += xr;

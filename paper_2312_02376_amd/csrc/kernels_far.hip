@@ -536,6 +536,41 @@ __global__ void k_far_reduce(const cplx<R>* __restrict__ part, cplx<R>* __restri
 
 constexpr int kTableThreads = 256;
 
+__device__ inline cplx<double> cexp_d(cplx<double> z) {
+  double sn, cs;
+  sincos(z.y, &sn, &cs);
+  const double e = exp(z.x);
+  return cmake<double>(e * cs, e * sn);
+}
+
+__device__ inline cplx<double> cdiv_d(cplx<double> a, cplx<double> b) {
+  const double d = 1.0 / (b.x * b.x + b.y * b.y);
+  return cmake<double>((a.x * b.x + a.y * b.y) * d, (a.y * b.x - a.x * b.y) * d);
+}
+
+// square root with Im <= 0 (and Re >= 0 on the real axis), computed without
+// cancellation from the principal root
+__device__ inline cplx<double> csqrt_im_nonpos_d(cplx<double> w) {
+  const double a = hypot(w.x, w.y);
+  if (a == 0.0) return cmake<double>(0.0, 0.0);
+  double re, im;
+  if (w.x >= 0.0) {
+    re = sqrt(0.5 * (a + w.x));
+    im = w.y / (2.0 * re);
+  } else {
+    im = copysign(sqrt(0.5 * (a - w.x)), w.y);
+    re = w.y / (2.0 * im);
+  }
+  if (im > 0.0) {
+    re = -re;
+    im = -im;
+  }
+  return cmake<double>(re, im);
+}
+
+// CW: complex wavenumbers (a lossy k0 or a complex phase shift); the real
+// instantiation keeps the propagating / evanescent split in real arithmetic.
+template <bool CW>
 __global__ void __launch_bounds__(kTableThreads) k_far_table_pgf2(FarTableArgs a, cplx<double>* __restrict__ table) {
   __shared__ double shr[kTableThreads], shi[kTableThreads];
   const double pi = 3.14159265358979323846;
@@ -545,45 +580,65 @@ __global__ void __launch_bounds__(kTableThreads) k_far_table_pgf2(FarTableArgs a
             dx = static_cast<int>(e / (static_cast<int64_t>(sz) * sy));
   const double r0[3] = {(dx - (a.nf[0] - 1) - 0.5) * a.delta[0], (dy - (a.nf[1] - 1) - 0.5) * a.delta[1],
                         (dz - (a.nf[2] - 1) - 0.5) * a.delta[2]};
-  // reduce x, y into the cell; Bloch phase of the shift
+  const cplx<double> k0 = cmake<double>(a.k0, a.k0_im);
+  const cplx<double> kt0 = cmake<double>(a.kt[0], a.kt_im[0]), kt1 = cmake<double>(a.kt[1], a.kt_im[1]);
+  // reduce x, y into the cell; Bloch phase of the shift, exp(-j arg)
   double r[3] = {r0[0], r0[1], r0[2]};
-  double arg = 0.0;
+  cplx<double> arg = cmake<double>(0.0, 0.0);
   for (int c = 0; c < 2; ++c) {
     const double n = round(r[c] / a.L[c]);
     r[c] -= n * a.L[c];
-    arg += a.kt[c] * n * a.L[c];
+    arg = cadd(arg, cscale(c == 0 ? kt0 : kt1, n * a.L[c]));
   }
   const double az = fabs(r[2]);
-  const double kreach = 41.0 / az + fabs(a.k0) + fabs(a.kt[0]) + fabs(a.kt[1]);
+  const double kreach = 41.0 / az + hypot(a.k0, a.k0_im) + hypot(a.kt[0], a.kt_im[0]) + hypot(a.kt[1], a.kt_im[1]);
   const int mmax = static_cast<int>(ceil(kreach * a.L[0] / (2.0 * pi))) + 1;
   const int nmax = static_cast<int>(ceil(kreach * a.L[1] / (2.0 * pi))) + 1;
   double sr = 0.0, si = 0.0;
   for (int m = -mmax + static_cast<int>(threadIdx.x); m <= mmax; m += kTableThreads) {
-    const double kx = a.kt[0] + 2.0 * pi * m / a.L[0];
-    double pr = 0.0, pim = 0.0;
-    for (int n = -nmax; n <= nmax; ++n) {
-      const double ky = a.kt[1] + 2.0 * pi * n / a.L[1];
-      const double w = a.k0 * a.k0 - kx * kx - ky * ky;
-      double s, c;
-      if (w >= 0.0) {
-        // propagating: exp(-j (ky y + kz |z|)) / kz
-        const double kz = sqrt(w);
-        sincos(-(ky * r[1] + kz * az), &s, &c);
-        pr += c / kz;
-        pim += s / kz;
-      } else {
-        // evanescent, kz = -j kappa: j exp(-kappa |z|) exp(-j ky y) / kappa
-        const double kap = sqrt(-w);
-        sincos(-ky * r[1], &s, &c);
-        const double fct = exp(-kap * az) / kap;
-        pr -= s * fct;
-        pim += c * fct;
+    if (CW) {
+      const cplx<double> kx = cadd(kt0, cmake<double>(2.0 * pi * m / a.L[0], 0.0));
+      const cplx<double> kx2 = cmul(kx, kx);
+      cplx<double> part = cmake<double>(0.0, 0.0);
+      for (int n = -nmax; n <= nmax; ++n) {
+        const cplx<double> ky = cadd(kt1, cmake<double>(2.0 * pi * n / a.L[1], 0.0));
+        const cplx<double> w = csub(csub(cmul(k0, k0), kx2), cmul(ky, ky));
+        const cplx<double> kz = csqrt_im_nonpos_d(w);
+        // exp(-j (ky y + kz |z|)) / kz
+        const cplx<double> ex = cadd(cscale(ky, r[1]), cscale(kz, az));
+        part = cadd(part, cdiv_d(cexp_d(cmake<double>(ex.y, -ex.x)), kz));
       }
+      const cplx<double> exx = cexp_d(cmake<double>(kx.y * r[0], -kx.x * r[0]));
+      const cplx<double> t = cmul(exx, part);
+      sr += t.x;
+      si += t.y;
+    } else {
+      const double kx = a.kt[0] + 2.0 * pi * m / a.L[0];
+      double pr = 0.0, pim = 0.0;
+      for (int n = -nmax; n <= nmax; ++n) {
+        const double ky = a.kt[1] + 2.0 * pi * n / a.L[1];
+        const double w = a.k0 * a.k0 - kx * kx - ky * ky;
+        double s, c;
+        if (w >= 0.0) {
+          // propagating: exp(-j (ky y + kz |z|)) / kz
+          const double kz = sqrt(w);
+          sincos(-(ky * r[1] + kz * az), &s, &c);
+          pr += c / kz;
+          pim += s / kz;
+        } else {
+          // evanescent, kz = -j kappa: j exp(-kappa |z|) exp(-j ky y) / kappa
+          const double kap = sqrt(-w);
+          sincos(-ky * r[1], &s, &c);
+          const double fct = exp(-kap * az) / kap;
+          pr -= s * fct;
+          pim += c * fct;
+        }
+      }
+      double s, c;
+      sincos(-kx * r[0], &s, &c);
+      sr += c * pr - s * pim;
+      si += c * pim + s * pr;
     }
-    double s, c;
-    sincos(-kx * r[0], &s, &c);
-    sr += c * pr - s * pim;
-    si += c * pim + s * pr;
   }
   shr[threadIdx.x] = sr;
   shi[threadIdx.x] = si;
@@ -598,30 +653,30 @@ __global__ void __launch_bounds__(kTableThreads) k_far_table_pgf2(FarTableArgs a
   if (threadIdx.x != 0) return;
   // divide by 2 j Lx Ly, apply the Bloch phase exp(-j arg)
   const double inv = 1.0 / (2.0 * a.L[0] * a.L[1]);
-  const double gr = shi[0] * inv, gi = -shr[0] * inv;
-  double ps, pc;
-  sincos(-arg, &ps, &pc);
-  double outr = pc * gr - ps * gi, outi = pc * gi + ps * gr;
+  const cplx<double> g = cmake<double>(shi[0] * inv, -shr[0] * inv);
+  cplx<double> out = cmul(cexp_d(cmake<double>(arg.y, -arg.x)), g);
   // minus the near-zone images (unreduced offset)
   for (int ix = -a.id; ix <= a.id; ++ix)
     for (int iy = -a.id; iy <= a.id; ++iy) {
       const double Rx = ix * a.L[0], Ry = iy * a.L[1];
       const double ddx = r0[0] - Rx, ddy = r0[1] - Ry, ddz = r0[2];
       const double dist = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
-      double s1, c1, s2, c2;
-      sincos(-(a.kt[0] * Rx + a.kt[1] * Ry), &s1, &c1);
-      sincos(-a.k0 * dist, &s2, &c2);
-      const double g = 1.0 / (4.0 * pi * dist);
-      outr -= (c1 * c2 - s1 * s2) * g;
-      outi -= (c1 * s2 + s1 * c2) * g;
+      // phase exp(-j (kt . R)) times exp(-j k0 dist) / (4 pi dist)
+      const cplx<double> ph = cadd(cadd(cscale(kt0, Rx), cscale(kt1, Ry)), cscale(k0, dist));
+      out = csub(out, cscale(cexp_d(cmake<double>(ph.y, -ph.x)), 1.0 / (4.0 * pi * dist)));
     }
-  table[e] = cmake<double>(outr, outi);
+  table[e] = out;
 }
 
 void launch_far_table_pgf2(const FarTableArgs& a, void* table, hipStream_t st) {
   const int64_t total = static_cast<int64_t>(2 * a.nf[0] - 1) * (2 * a.nf[1] - 1) * (2 * a.nf[2] - 1);
-  hipLaunchKernelGGL(k_far_table_pgf2, dim3(static_cast<unsigned>(total)), dim3(kTableThreads), 0, st, a,
-                     static_cast<cplx<double>*>(table));
+  const bool cw = a.k0_im != 0.0 || a.kt_im[0] != 0.0 || a.kt_im[1] != 0.0;
+  if (cw)
+    hipLaunchKernelGGL(k_far_table_pgf2<true>, dim3(static_cast<unsigned>(total)), dim3(kTableThreads), 0, st, a,
+                       static_cast<cplx<double>*>(table));
+  else
+    hipLaunchKernelGGL(k_far_table_pgf2<false>, dim3(static_cast<unsigned>(total)), dim3(kTableThreads), 0, st, a,
+                       static_cast<cplx<double>*>(table));
 }
 
 // ---------------------------------------------------------------------------

@@ -861,7 +861,8 @@ __global__ void k_near_table(cplx<double>* __restrict__ T, NearTableArgs a) {
       double r = sqrt(dx * dx + dy * dy + dz * dz);
       double s, c;
       sincos(a.k0 * r, &s, &c);
-      double inv = 1.0 / (4.0 * M_PI * r);
+      // a lossy k0 = k0 + j k0_im adds the factor exp(k0_im r)
+      double inv = (a.k0_im != 0.0 ? exp(a.k0_im * r) : 1.0) / (4.0 * M_PI * r);
       // phase * exp(-j k0 r) / (4 pi r)
       double gr = c * inv, gi = -s * inv;
       sr += a.phase[2 * k] * gr - a.phase[2 * k + 1] * gi;
@@ -914,18 +915,22 @@ void launch_pack(const void* qu, void* qint, const int32_t* perm, int64_t N, int
 }
 
 template <typename R>
-static PartPtrs<R> part_ptrs(const void* a, const void* b, const void* c) {
+static PartPtrs<R> part_ptrs(const void* a, const void* b, const void* c, DiagTerm diag = DiagTerm()) {
   PartPtrs<R> s;
   s.a = static_cast<const cplx<R>*>(a);
   s.b = static_cast<const cplx<R>*>(b);
   s.c = static_cast<const cplx<R>*>(c);
+  s.self = static_cast<const cplx<R>*>(diag.in);
+  s.cr = static_cast<R>(diag.re);
+  s.ci = static_cast<R>(diag.im);
   return s;
 }
 
 template <typename R>
 void launch_unpack(const void* u_near, const void* u_corr, const void* u_far, void* uu, const int32_t* perm,
-                   int64_t N, int nrhs, int P, bool real_out, bool use_perm, const double* mean, hipStream_t st) {
-  PartPtrs<R> s = part_ptrs<R>(u_near, u_corr, u_far);
+                   int64_t N, int nrhs, int P, bool real_out, bool use_perm, const double* mean, hipStream_t st,
+                   DiagTerm diag) {
+  PartPtrs<R> s = part_ptrs<R>(u_near, u_corr, u_far, diag);
   if (P >= 4) {
     dim3 gr(static_cast<unsigned>((N + kTpPts - 1) / kTpPts), static_cast<unsigned>((P + kTpPl - 1) / kTpPl));
     if (real_out)
@@ -949,10 +954,10 @@ int64_t plane_sums_chunks(int64_t N) { return (N + kPlaneSumChunk - 1) / kPlaneS
 
 template <typename R>
 void launch_plane_sums(const void* a, const void* b, const void* c, int64_t N, int P, double* work, double* out,
-                       hipStream_t st) {
+                       hipStream_t st, DiagTerm diag) {
   const int64_t nch = plane_sums_chunks(N);
   hipLaunchKernelGGL((k_plane_sums_part<R>), dim3(static_cast<unsigned>(nch), static_cast<unsigned>((P + 63) / 64)),
-                     dim3(256), 0, st, part_ptrs<R>(a, b, c), N, P, work);
+                     dim3(256), 0, st, part_ptrs<R>(a, b, c, diag), N, P, work);
   hipLaunchKernelGGL(k_plane_sums_final, dim3(static_cast<unsigned>((P + 63) / 64)), dim3(64), 0, st, work, nch, P,
                      out);
 }
@@ -1169,9 +1174,9 @@ void launch_scale_convert(const void* in, void* out, int64_t n, double s, hipStr
   template void launch_pack<R>(const void*, void*, const int32_t*, int64_t, int, int, bool, bool,        \
                                hipStream_t);                                                             \
   template void launch_unpack<R>(const void*, const void*, const void*, void*, const int32_t*, int64_t,  \
-                                 int, int, bool, bool, const double*, hipStream_t);                      \
+                                 int, int, bool, bool, const double*, hipStream_t, DiagTerm);            \
   template void launch_plane_sums<R>(const void*, const void*, const void*, int64_t, int, double*, double*, \
-                                     hipStream_t);                                                       \
+                                     hipStream_t, DiagTerm);                                             \
   template void launch_spread_csr<R>(const int64_t*, const int32_t*, const double*, int64_t, const void*, int, \
                                      void*, hipStream_t);                                                \
   template int launch_spread_near<R>(int, const GridArgs&, const int32_t*, const int32_t*, const double*, \

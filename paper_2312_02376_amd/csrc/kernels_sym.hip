@@ -81,7 +81,7 @@ __global__ void __launch_bounds__(64) k_sym_fill(SymArgs a, const double* __rest
     if (m != n) {
       const double dx = pos3[m] - pos3[n], dy = pos3[N + m] - pos3[N + n], dz = pos3[2 * N + m] - pos3[2 * N + n];
       const double rr = sqrt(dx * dx + dy * dy + dz * dz);
-      const double inv = 1.0 / (4.0 * M_PI * rr);
+      const double inv = (a.k0_im != 0.0 ? exp(a.k0_im * rr) : 1.0) / (4.0 * M_PI * rr);
       if (CPLX) {
         double s, c2;
         sincos(a.k0 * rr, &s, &c2);

@@ -13,21 +13,33 @@ using cd = std::complex<double>;
 struct Lattice {
   int dims;       // periodic axes: x (1), x,y (2), x,y,z (3)
   double L[3];    // periods
-  double k0;      // free-space wavenumber (real)
-  double kt[3];   // phase-shift wavenumbers (real)
+  cd k0;          // free-space wavenumber (Im <= 0)
+  cd kt[3];       // phase-shift wavenumbers (possibly complex, Sec. 2)
   bool npsp() const { return k0 == 0.0 && kt[0] == 0.0 && kt[1] == 0.0 && kt[2] == 0.0; }
+  // the correction operator is Hermitian only for a real static kernel with
+  // a real phase shift
+  bool hermitian() const {
+    return k0 == 0.0 && kt[0].imag() == 0.0 && kt[1].imag() == 0.0 && kt[2].imag() == 0.0;
+  }
+  // phase exp(-j k_t . R) of the image i (integer offsets on the periodic axes)
+  cd phase(int ix, int iy, int iz) const;
 };
 
 double bessel_k0(double x);
-cd g0(double r, double k0);
+// K0(w) for complex w with Re w >= 0, w != 0.
+cd bessel_k0c(cd w);
+cd g0(double r, cd k0);
 double lgf3(double x, double y, double z, double Lx, double Ly, double Lz);
 double lgf2(double x, double y, double z, double Lx, double Ly);
 double lgf1(double x, double rho, double Lx);
-cd pgf2(double x, double y, double z, double Lx, double Ly, double k0, double kx0, double ky0);
-cd pgf3(double x, double y, double z, const double L[3], double k0, const double kt[3]);
+cd pgf1(double x, double rho, double Lx, cd k0, cd kx0);
+cd pgf2(double x, double y, double z, double Lx, double Ly, cd k0, cd kx0, cd ky0);
+cd pgf3(double x, double y, double z, const double L[3], cd k0, const cd kt[3]);
 cd pgf_reduced(const Lattice& lat, const double r[3]);
 // Full G^p (Bloch factor included); r must not be a lattice vector.
 cd pgf(const Lattice& lat, const double r[3]);
+// lim_{r->0} [G^p(r) - G0(r)] (the images of a point acting on itself).
+cd pgf_self(const Lattice& lat);
 // Eq. (4): images |i_c| <= i_d on the periodic axes.
 cd g_near(const Lattice& lat, const double r[3], int i_d);
 // Nonzero when this evaluator does not cover the problem class.

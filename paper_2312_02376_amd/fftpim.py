@@ -28,7 +28,7 @@ STATUS = {
 EXPORTS = (
     "fftpim_default_params", "fftpim_plan", "fftpim_apply", "fftpim_apply_adjoint",
     "fftpim_apply_pair", "fftpim_apply_parts", "fftpim_get_permutation", "fftpim_plan_info", "fftpim_last_status",
-    "fftpim_destroy", "fftpim_error_string", "fftpim_eval_pgf", "fftpim_stage_times",
+    "fftpim_destroy", "fftpim_error_string", "fftpim_eval_pgf", "fftpim_stage_times", "fftpim_eval_pgf_self",
 )
 STAGES = ("pack", "near_spread", "near_fft", "near_interp", "near_corr", "far", "unpack")
 
@@ -92,6 +92,7 @@ def lib():
         L.fftpim_error_string.restype = ctypes.c_char_p
         L.fftpim_eval_pgf.argtypes = [ctypes.POINTER(Problem), i64, vp, vp]
         L.fftpim_stage_times.argtypes = [vp, ci, vp, vp]
+        L.fftpim_eval_pgf_self.argtypes = [ctypes.POINTER(Problem), vp]
         for name in EXPORTS:
             if name != "fftpim_error_string":
                 getattr(L, name).restype = ci
@@ -131,6 +132,14 @@ def eval_pgf(r, periodic_dims, L, k0=0.0, kt=(0.0, 0.0, 0.0)):
     pr = make_problem(periodic_dims, L, k0, kt)
     _check(lib().fftpim_eval_pgf(ctypes.byref(pr), r.shape[0], r.ctypes.data, out.ctypes.data), "fftpim_eval_pgf")
     return out[:, 0] + 1j * out[:, 1]
+
+
+def eval_pgf_self(periodic_dims, L, k0=0.0, kt=(0.0, 0.0, 0.0)):
+    """The library's lim_{r->0}[G^p(r) - G0(r)] (host only)."""
+    out = np.empty(2)
+    pr = make_problem(periodic_dims, L, k0, kt)
+    _check(lib().fftpim_eval_pgf_self(ctypes.byref(pr), out.ctypes.data), "fftpim_eval_pgf_self")
+    return complex(out[0], out[1])
 
 
 def _overlap(a, b):

@@ -119,3 +119,47 @@ def coulomb_cube_1m_batched(n=1_000_000, nrhs=64):
     """3D-periodic static Coulomb, 1M uniform points, 64 neutral Gaussian
     right-hand sides (float32)."""
     return uniform_cube(n, 3), gaussian_neutral(nrhs, n, 3, np.float32)
+
+
+# ---------------------------------------------------------------------------
+# coaxial shells in a 1D-periodic cell (the potential figure of Sec. 4)
+# ---------------------------------------------------------------------------
+
+def coax_shells_random(n, seed, r1=1.0, r2=2.0, L=1.0):
+    """n points on two coaxial cylinders around the x axis (a third on the
+    inner radius r1, the rest on r2), x uniform in [0, L)."""
+    rng = np.random.default_rng(seed)
+    n1 = n // 3
+    rad = np.where(np.arange(n) < n1, r1, r2)
+    th = rng.uniform(0.0, 2 * np.pi, n)
+    return np.c_[rng.random(n) * L, rad * np.cos(th), rad * np.sin(th)]
+
+
+def coax_shells(nx, ntheta, n_axis, r1=1.0, r2=2.0, sigma1=-1.0, sigma2=0.5, L=1.0):
+    """Uniform surface charge on two coaxial cylinders (densities sigma1 on
+    radius r1 and sigma2 on r2; the defaults make the cell neutral) sampled
+    on an nx x ntheta midpoint grid per shell, plus n_axis zero-charge points
+    on the x axis where the potential is observed.
+
+    Returns (positions [N][3], charges [N], slice of the axis points)."""
+    x = (np.arange(nx) + 0.5) / nx * L
+    th = 2 * np.pi * (np.arange(ntheta) + 0.5) / ntheta
+    X, T = np.meshgrid(x, th, indexing="ij")
+    pts, q = [], []
+    for rad, sig in ((r1, sigma1), (r2, sigma2)):
+        pts.append(np.c_[X.ravel(), rad * np.cos(T.ravel()), rad * np.sin(T.ravel())])
+        q.append(np.full(X.size, sig * (L / nx) * (2 * np.pi * rad / ntheta)))
+    xa = (np.arange(n_axis) + 0.25) / n_axis * L
+    pts.append(np.c_[xa, np.zeros(n_axis), np.zeros(n_axis)])
+    q.append(np.zeros(n_axis))
+    P = np.concatenate(pts)
+    return P, np.concatenate(q), slice(P.shape[0] - n_axis, P.shape[0])
+
+
+def dynamic_cube(n, seed, D=100.0):
+    """n points uniform in a cube of side D centred in a 3D-periodic cell of
+    period D + 1 (the dynamic 3D timing runs of Sec. 4.2); complex64 N(0,1)
+    strengths."""
+    rng = np.random.default_rng(seed)
+    pos = 0.5 + rng.random((n, 3)) * D
+    return pos, gaussian_complex(1, n, seed)[0]

@@ -61,7 +61,7 @@ CUBE = dict(periodic_dims=3, L=[1.0, 1.0, 1.0])
     (dict(near_n=(12, 16, 16)), 1),          # 2n must be a power of two
     (dict(corr_radius=2), 1),                 # r_c >= q is required
     (dict(n_images=3), 1), (dict(precision=5), 1), (dict(nrhs_max=0), 1),
-    (dict(self_mode=1), 8),
+    (dict(self_mode=2), 1),
 ])
 def test_parameter_validation(kw, code):
     assert _plan_status(CUBE, **kw) == code
@@ -73,7 +73,9 @@ def test_real_values_need_static_no_phase():
 
 
 def test_unsupported_and_anomaly():
-    assert _plan_status(dict(periodic_dims=1, L=[1.0], k0=3.0)) == 5      # 1D Helmholtz
+    # static with a phase that is a whole multiple of 2 pi / L on every axis:
+    # every lateral Floquet wavenumber pair of Eq. (pgf_3) has a 0/0 term
+    assert _plan_status(dict(periodic_dims=3, L=[1.0, 1.0, 1.0], kt=[2 * math.pi, 0.0, 0.0])) == 5
     k = 2 * math.pi
     # k0 = 2 pi / L with no phase: the (+-1, 0) Floquet modes are grazing
     assert _plan_status(dict(periodic_dims=2, L=[1.0, 1.0], k0=k)) == 4
@@ -100,6 +102,40 @@ def test_host_evaluator_matches_oracle(dims, k0, kt):
     np.testing.assert_allclose(a, b, rtol=1e-12)
 
 
+def test_wavenumber_validation():
+    assert _plan_status(dict(periodic_dims=3, L=[1.0, 1.0, 1.0], k0=2.0 + 0.5j)) == 1   # Im k0 > 0
+    assert _plan_status(dict(periodic_dims=3, L=[1.0, 1.0, 1.0], k0=-1.0)) == 1         # Re k0 < 0
+    assert _plan_status(dict(periodic_dims=2, L=[1.0, 1.0], kt=[float("nan"), 0.0])) == 1
+
+
+@pytest.mark.parametrize("dims,k0,kt", [
+    (1, 2 * math.pi * 0.8, [0.3]),            # lossless 1D Helmholtz: propagating Hankel terms
+    (1, 7.0, [1.1]),                          # two propagating orders, |k_rho rho| up to ~10
+    (1, 3.0 - 0.5j, [0.7]),                   # lossy k0
+    (1, 1.0, [1 - 1j]),                       # the coax case of the paper's potential figure
+    (1, 0.0, [0.9]),                          # static with a phase (K0 of real argument)
+    (1, 0.0, [0.9 - 0.4j]),                   # static with a complex phase
+    (2, 2 * math.pi, [0.6 * math.pi + 0.2j, 0.2 * math.pi - 0.1j]),
+    (2, 4.0 - 1.0j, [0.5, -0.3]),
+    (3, 0.311, [0.01 - 0.01j] * 3),           # complex phase of the dynamic 3D timing runs, L = 1
+    (3, 3.0 - 0.7j, [0.4, 0.0, -0.2]),
+])
+def test_host_evaluator_complex_wavenumbers(dims, k0, kt):
+    from oracle import pgf as P
+    rng = np.random.default_rng(40 + dims)
+    r = rng.uniform(-0.5, 0.5, (30, 3)) + rng.integers(-1, 2, (30, 3)) * (np.arange(3) < dims)
+    if dims == 1:
+        # transverse distances from the far-grid scale up to several periods
+        rho = np.exp(rng.uniform(np.log(0.02), np.log(3.0), 30))
+        ang = rng.uniform(0, 2 * np.pi, 30)
+        r[:, 1], r[:, 2] = rho * np.cos(ang), rho * np.sin(ang)
+    else:
+        r[:, 2] = np.where(np.abs(r[:, 2]) < 0.04, 0.04, r[:, 2])
+    a = fp.eval_pgf(r, dims, [1, 1, 1], k0, kt)
+    b = P.pgf(r, P.Lattice(dims, [1, 1, 1], k0, kt))
+    np.testing.assert_allclose(a, b, rtol=1e-11, atol=1e-13 * np.abs(b).max())
+
+
 @pytest.mark.parametrize("x", [1e-3, 0.1, 0.7, 1.9, 2.0, 2.1, 5.0, 17.0, 40.0])
 def test_host_bessel_k0_through_1d_series(x):
     # lgf_1 at x-offset 0 probes sum_m K0(2 pi m rho): compare with SciPy's K0
@@ -109,3 +145,21 @@ def test_host_bessel_k0_through_1d_series(x):
     m = np.arange(1, int(60.0 / x) + 2)
     want = -math.log(rho) / (2 * math.pi) + np.sum(k0(m * x)[::-1]) / math.pi
     assert got == pytest.approx(want, rel=1e-13, abs=1e-15)
+
+
+@pytest.mark.parametrize("dims,L,k0,kt", [
+    (3, [1, 1.2, 0.9], 0.0, [0, 0, 0]), (2, [1, 1.3], 0.0, [0, 0]), (1, [1.3], 0.0, [0]),
+    (3, [1, 1, 1], 5.0, [0, 0, 0]), (3, [1, 1.2, 0.9], 2.0 - 3.0j, [0.7, -1.1, 0.5]),
+    (3, [1, 1, 1], 3.0, [0.3 - 0.2j, 0.1 + 0.1j, -0.2 - 0.1j]), (3, [1, 1.2, 0.9], 0.0, [0.5, 0.3, 0.2]),
+    (2, [1, 1], 2 * math.pi, [0.6 * math.pi, 0.2 * math.pi]), (2, [1, 1.2], 2.5 - 3.0j, [0.9, -1.3]),
+    (2, [1, 1], 2 * math.pi, [0.6 * math.pi + 0.2j, 0.2 * math.pi - 0.1j]),
+    (1, [1.0], 0.8 * 2 * math.pi, [1.1]), (1, [1.0], 1.0, [1 - 1j]), (1, [1.0], 0.0, [0.9 - 0.4j]),
+    (1, [1.0], 2.0 - 3.0j, [0.7]),
+])
+def test_self_evaluator_matches_oracle(dims, L, k0, kt):
+    # the library's Ewald-at-zero self coefficient (splitting parameter
+    # E L >= 6.8) against the oracle's (E ~ sqrt(pi)/L, different terms)
+    from oracle import pgf as P
+    got = fp.eval_pgf_self(dims, L, k0, kt)
+    want = P.pgf_self(P.Lattice(dims, L, k0, kt))
+    assert abs(got - want) <= 2e-12 * abs(want), (got, want)

@@ -35,6 +35,17 @@ CASES = {
               (10, 10, 10), 5),
     "npsp2_real": (dict(dims=2, L=[1, 1.3]), "slab", 2, "real", (16, 16, 8), 4, 4, (10, 10, 8), 5),
     "npsp1_real": (dict(dims=1, L=[1.0]), "rod", 2, "real", (16, 8, 8), 2, 3, (10, 8, 8), 3),
+    # complex wavenumbers and 1D Helmholtz (Sec. 2: possibly complex phase shifts)
+    "helm1_bloch": (dict(dims=1, L=[1.0], k0=0.8 * TWO_PI, kt=[1.1]), "rod", 2, "complex", (16, 8, 8), 4, 4,
+                    (10, 8, 8), 5),
+    "coax_dyn": (dict(dims=1, L=[1.0], k0=1.0, kt=[1 - 1j]), "coax", 1, "complex", (16, 16, 16), 4, 4,
+                 (9, 10, 10), 5),
+    "helm3_cphase": (dict(dims=3, L=[1, 1, 1], k0=3.0, kt=[0.3 - 0.2j, 0.1 + 0.1j, -0.2 - 0.1j]), "cube", 1,
+                     "complex", (16, 16, 16), 4, 4, (10, 10, 10), 5),
+    "helm2_lossy": (dict(dims=2, L=[1, 1], k0=5.0 - 1.0j, kt=[0.4, -0.2]), "surface", 1, "complex",
+                    (16, 16, 8), 4, 4, (10, 10, 8), 5),
+    "phase1_cstatic": (dict(dims=1, L=[1.0], k0=0.0, kt=[0.9 - 0.4j]), "rod", 1, "complex", (16, 8, 8), 3, 3,
+                       (10, 8, 8), 4),
 }
 
 
@@ -50,17 +61,19 @@ def _points(kind, N, seed):
     if kind == "rod":
         p = rng.random((N, 3)) * np.array([1.0, 0.5, 0.3])
         return p
+    if kind == "coax":
+        return W.coax_shells_random(N, seed)
     raise ValueError(kind)
 
 
-def _setup(name, N=257, seed=31, precision="f64", nrhs=None, corr_layout="auto"):
+def _setup(name, N=257, seed=31, precision="f64", nrhs=None, corr_layout="auto", self_mode="images"):
     latkw, kind, nrhs0, vt, nn, q, rc, nf, qf = CASES[name]
     nrhs = nrhs0 if nrhs is None else nrhs
     lat = P.Lattice(latkw["dims"], latkw["L"], latkw.get("k0", 0.0), latkw.get("kt", [0, 0, 0]))
     src = _points(kind, N, seed)
     if kind == "cube":
         src = src * np.asarray((latkw["L"] + [1, 1, 1])[:3])
-    ref = S.FFTPIM(lat, S.Params(nn, q, rc, nf, qf, 1), src)
+    ref = S.FFTPIM(lat, S.Params(nn, q, rc, nf, qf, 1), src, self_mode=self_mode)
     rng = np.random.default_rng(seed + 1)
     if vt == "real":
         qv = rng.standard_normal((nrhs, N))
@@ -71,7 +84,8 @@ def _setup(name, N=257, seed=31, precision="f64", nrhs=None, corr_layout="auto")
     pos = torch.tensor(src, dtype=torch.float64, device="cuda")
     plan = fp.Plan(pos, latkw["dims"], latkw["L"], k0=latkw.get("k0", 0.0), kt=latkw.get("kt", [0, 0, 0]),
                    near_n=nn, near_order=q, corr_radius=rc, far_n=nf, far_order=qf, n_images=1,
-                   precision=precision, value_type=vt, nrhs_max=max(4, nrhs), corr_layout=corr_layout)
+                   precision=precision, value_type=vt, nrhs_max=max(4, nrhs), corr_layout=corr_layout,
+                   self_mode=self_mode)
     return lat, ref, plan, qv
 
 
@@ -99,7 +113,7 @@ def test_stage_parity_fp64(name, adjoint):
     assert rel(got, want) < 1e-11
 
 
-@pytest.mark.parametrize("name", ["npsp3_real", "helm2_bloch"])
+@pytest.mark.parametrize("name", ["npsp3_real", "helm2_bloch", "helm1_bloch", "coax_dyn", "helm3_cphase"])
 def test_full_apply_and_adjoint(name):
     lat, ref, plan, qv = _setup(name)
     qd = _to_dev(plan, qv)
@@ -405,3 +419,31 @@ def test_apply_pair_rejects_bad_arguments():
     assert rel(u.cpu().numpy(), plan.apply(qd).cpu().numpy()) < 1e-14
     assert rel(w.cpu().numpy(), plan.adjoint(qd).cpu().numpy()) < 1e-14
     plan.close()
+
+
+@pytest.mark.parametrize("name", ["npsp3_real", "helm2_bloch", "helm1_bloch", "coax_dyn", "npsp1_real"])
+def test_self_exclude(name):
+    # Eq. (5) read literally (n != m): the library subtracts its own
+    # lim_{r->0}[G^p - G0] q_m, the oracle its own; forward, conjugate
+    # transpose, one stage alone and the fused pair
+    print("case", name, flush=True)
+    lat, ref, plan, qv = _setup(name, self_mode="exclude")
+    qd = _to_dev(plan, qv)
+    u = plan.apply(qd).cpu().numpy()
+    assert rel(u, ref.apply(qv)) < 1e-11
+    want_w = ref.adjoint(qv)
+    if lat.npsp:
+        want_w = want_w - want_w.mean(axis=-1, keepdims=True)
+    w = plan.adjoint(qd).cpu().numpy()
+    assert rel(w, want_w) < 1e-11
+    got = plan.apply_parts(qd, PARTS["far"]).cpu().numpy()
+    assert rel(got, ref.apply(qv, parts=("far",))) < 1e-11
+    up, wp = plan.apply_pair(qd, qd)
+    assert rel(up.cpu().numpy(), ref.apply(qv)) < 1e-11
+    assert rel(wp.cpu().numpy(), want_w) < 1e-11
+    # the difference from the default mode is exactly C_self q_m
+    lat2, ref2, plan2, _ = _setup(name)
+    d = plan2.apply(qd).cpu().numpy() - u
+    cs = _fftpim().eval_pgf_self(lat.dims, lat.L[:lat.dims], lat.k0, lat.kt[:lat.dims])
+    np.testing.assert_allclose(d, cs * qv if plan.value_type == "complex" else cs.real * qv,
+                               rtol=1e-9, atol=1e-12 * np.abs(u).max())

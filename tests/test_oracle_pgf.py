@@ -157,14 +157,12 @@ def _brute_force(lat, r, reach):
 
 @pytest.mark.parametrize("dims,reach", [(3, 14), (2, 40), (1, 14)])
 def test_lossy_brute_force_image_sum(dims, reach):
-    # 1D: the Hankel series of Eq. (pgf_1) (the oracle has no Ewald form for
-    # 1D Helmholtz; at these transverse distances the series converges)
     lat = P.Lattice(dims, [1.0, 1.2, 0.9][:dims], k0=2.0 - 3.0j, kt=[0.7, -0.4, 0.3][:dims])
     rng = np.random.default_rng(14 + dims)
     for _ in range(4):
         r = rng.uniform(-0.45, 0.45, 3)
         bf = _brute_force(lat, r, reach)
-        for method in (("series",) if dims == 1 else ("series", "ewald")):
+        for method in ("series", "ewald"):
             val = P.pgf(r[None, :], lat, method)[0]
             assert abs(val - bf) <= 1e-10 * abs(bf), (method, val, bf)
 
@@ -195,17 +193,13 @@ def test_fig2_parameters_two_representations(dims):
     # Fig. 2 of the paper: L = 1, k0 = -1-j, k_t = (1-j, 1+j, -1+j), r = (1/2, 1/2, 1/2)
     lat = P.Lattice(dims, [1, 1, 1], k0=-1 - 1j, kt=[1 - 1j, 1 + 1j, -1 + 1j][:dims])
     r = np.array([[0.5, 0.5, 0.5]])
+    a = P.pgf(r, lat, "series")[0]
+    b = P.pgf(r, lat, "ewald")[0]
+    assert a == pytest.approx(b, rel=1e-12)
     if dims == 1:
-        a = P.pgf1_series(r[:, 0], np.hypot(r[:, 1], r[:, 2]), 1.0, lat.k0, lat.kt[0])[0]
-        # independent check for 1D: Ewald is not provided, use the 3D-embedded
-        # Floquet identity through the 2D series limit is not available either;
-        # the spectral sum must at least be Bloch-consistent
-        b = P.pgf1_series(r[:, 0] + 1.0, np.hypot(r[:, 1], r[:, 2]), 1.0, lat.k0, lat.kt[0])[0]
-        assert b == pytest.approx(np.exp(-1j * lat.kt[0]) * a, rel=1e-12)
-    else:
-        a = P.pgf(r, lat, "series")[0]
-        b = P.pgf(r, lat, "ewald")[0]
-        assert a == pytest.approx(b, rel=1e-12)
+        # the spectral sum is also Bloch-consistent
+        c = P.pgf1_series(r[:, 0] + 1.0, np.hypot(r[:, 1], r[:, 2]), 1.0, lat.k0, lat.kt[0])[0]
+        assert c == pytest.approx(np.exp(-1j * lat.kt[0]) * a, rel=1e-12)
 
 
 def test_reciprocity():
