@@ -60,7 +60,9 @@ typedef enum {
                                   thread could not be started, or the plan
                                   would exceed params.max_bytes */
   FFTPIM_ERR_DEVICE = 7,       /* a HIP runtime call failed */
-  FFTPIM_ERR_UNIMPLEMENTED = 8
+  FFTPIM_ERR_UNIMPLEMENTED = 8,
+  FFTPIM_ERR_SCRATCH_LIMIT = 9 /* fftpim_apply_pair_noalloc: the plan needs more
+                                  than its fixed per-device array */
 } fftpim_status;
 
 /* Precision of the bulk path (the correction values and their products stay
@@ -201,6 +203,22 @@ int fftpim_apply_adjoint(fftpim_plan_t plan, const void* v_dev, void* w_dev, int
  * NO_MEMORY, DEVICE. */
 int fftpim_apply_pair(fftpim_plan_t plan, const void* q_dev, void* u_dev, const void* v_dev,
                       void* w_dev, int nrhs, fftpim_stream_t stream);
+
+/* fftpim_apply_pair for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, results and stream semantics as
+ * fftpim_apply_pair; the pair's own work arrays (a second near-grid/far-zone
+ * work set, the packed v and the three parts of w) live in a fixed array of
+ * 64 MiB per device, held from library load until the process ends, instead
+ * of plan-owned allocations, so no call allocates (stage timing is not
+ * recorded for this call).  Every call on a device shares that device's
+ * array and leaves it holding its last contents: calls that overlap in time
+ * on one device (on different streams, or from different plans or host
+ * threads) race and must be serialised by the caller.
+ * Errors: INVALID_ARG; SCRATCH_LIMIT when the plan's pair arrays exceed the
+ * array (nothing is enqueued); DEVICE. */
+int fftpim_apply_pair_noalloc(fftpim_plan_t plan, const void* q_dev, void* u_dev, const void* v_dev,
+                              void* w_dev, int nrhs, fftpim_stream_t stream);
 
 /* Apply only some parts of the operator (FFTPIM_PART_* mask) - forward
  * (adjoint = 0) or conjugate transpose (adjoint = 1).  PART_ALL equals

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <stdexcept>
@@ -1491,6 +1492,39 @@ Lattice lattice_of(const fftpim_problem_t& pr) {
   return lat;
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free fused pair: the pair's own arrays (a second work set, the
+// packed adjoint input, the three parts of A^H v) are laid out in a fixed
+// per-device array instead of plan-owned allocations.
+// ---------------------------------------------------------------------------
+
+constexpr size_t kScratchBytes = size_t{64} << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the given device, looked up once per device
+// with that device current (each device holds its own copy of the array; in
+// host code the array's name is not a device address).
+int scratch_address(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return FFTPIM_ERR_DEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device] == nullptr) {
+    int cur = -1;
+    HIPCHK(hipGetDevice(&cur));
+    if (cur != device) HIPCHK(hipSetDevice(device));
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess || ptr == nullptr) return FFTPIM_ERR_DEVICE;
+    g_scratch_ptr[device] = ptr;
+  }
+  *out = g_scratch_ptr[device];
+  return FFTPIM_OK;
+}
+
 // No C++ exception may cross the C ABI: host allocations (std::vector) and
 // the far-table worker threads can throw on resource exhaustion.
 template <typename F>
@@ -1556,6 +1590,7 @@ int fftpim_plan(fftpim_plan_t* plan, const fftpim_problem_t* problem, const fftp
     p->problem = *problem;
     p->prm = *params;
     p->N = n_src;
+    HIPCHK(hipGetDevice(&p->device));
     p->complex_kernel = !lat.npsp();
     p->nonhermitian = !lat.hermitian();
     if (params->self_mode == FFTPIM_SELF_EXCLUDE) p->self_coef = pgf_self(lat);
@@ -1601,6 +1636,27 @@ int fftpim_apply_pair(fftpim_plan_t plan, const void* q_dev, void* u_dev, const 
     if (plan->prm.precision != FFTPIM_F64)
       return run_apply_pair<float>(plan, plan->pair, q_dev, u_dev, v_dev, w_dev, nrhs, st);
     return run_apply_pair<double>(plan, plan->pair, q_dev, u_dev, v_dev, w_dev, nrhs, st);
+  });
+}
+
+int fftpim_apply_pair_noalloc(fftpim_plan_t plan, const void* q_dev, void* u_dev, const void* v_dev, void* w_dev,
+                              int nrhs, fftpim_stream_t stream) {
+  return guarded([&]() -> int {
+    if (!plan || !q_dev || !u_dev || !v_dev || !w_dev) return FFTPIM_ERR_INVALID_ARG;
+    if (nrhs < 1 || nrhs > plan->prm.nrhs_max) return FFTPIM_ERR_INVALID_ARG;
+    if (pair_buffer_bytes(plan) > kScratchBytes) return FFTPIM_ERR_SCRATCH_LIMIT;
+    void* base = nullptr;
+    CHK(scratch_address(plan->device, &base));
+    const PairBufs pb = carve_pair_buffers(plan, static_cast<unsigned char*>(base));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // stage timing may grow its event pool: it is off for this call
+    const bool timing = plan->timing;
+    plan->timing = false;
+    const int s = plan->prm.precision != FFTPIM_F64
+                      ? run_apply_pair<float>(plan, pb, q_dev, u_dev, v_dev, w_dev, nrhs, st)
+                      : run_apply_pair<double>(plan, pb, q_dev, u_dev, v_dev, w_dev, nrhs, st);
+    plan->timing = timing;
+    return s;
   });
 }
 
@@ -1712,6 +1768,8 @@ const char* fftpim_error_string(int status) {
     case FFTPIM_ERR_NO_MEMORY: return "out of memory";
     case FFTPIM_ERR_DEVICE: return "HIP runtime error";
     case FFTPIM_ERR_UNIMPLEMENTED: return "not implemented";
+    case FFTPIM_ERR_SCRATCH_LIMIT:
+      return "the plan's pair work arrays exceed the 64 MiB per-device array of fftpim_apply_pair_noalloc";
     default: return "unknown status";
   }
 }

@@ -189,6 +189,7 @@ struct fftpim_plan_s {
   fftpim_problem_t problem;
   fftpim_params_t prm;
   int64_t N = 0;
+  int device = 0;              // HIP device current when the plan was made
   bool complex_kernel = true;  // G0 or the phases are complex
   bool nonhermitian = false;   // k0 != 0 or a complex phase shift: C^H needs its own values
   std::complex<double> self_coef = 0.0;  // lim_{r->0}[G^p - G0] (self_mode exclude)

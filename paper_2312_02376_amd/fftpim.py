@@ -21,7 +21,7 @@ PART_NEAR_GRID, PART_NEAR_CORR, PART_FAR, PART_ALL = 1, 2, 4, 7
 
 STATUS = {
     0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_CELL", 3: "NOT_NEUTRAL", 4: "WOOD_ANOMALY",
-    5: "UNSUPPORTED", 6: "NO_MEMORY", 7: "DEVICE", 8: "UNIMPLEMENTED",
+    5: "UNSUPPORTED", 6: "NO_MEMORY", 7: "DEVICE", 8: "UNIMPLEMENTED", 9: "SCRATCH_LIMIT",
 }
 
 # the entry points declared in include/fftpim.h
@@ -29,6 +29,7 @@ EXPORTS = (
     "fftpim_default_params", "fftpim_plan", "fftpim_apply", "fftpim_apply_adjoint",
     "fftpim_apply_pair", "fftpim_apply_parts", "fftpim_get_permutation", "fftpim_plan_info", "fftpim_last_status",
     "fftpim_destroy", "fftpim_error_string", "fftpim_eval_pgf", "fftpim_stage_times", "fftpim_eval_pgf_self",
+    "fftpim_apply_pair_noalloc",
 )
 STAGES = ("pack", "near_spread", "near_fft", "near_interp", "near_corr", "far", "unpack")
 
@@ -83,6 +84,7 @@ def lib():
         L.fftpim_apply.argtypes = [vp, vp, vp, ci, vp]
         L.fftpim_apply_adjoint.argtypes = [vp, vp, vp, ci, vp]
         L.fftpim_apply_pair.argtypes = [vp, vp, vp, vp, vp, ci, vp]
+        L.fftpim_apply_pair_noalloc.argtypes = [vp, vp, vp, vp, vp, ci, vp]
         L.fftpim_apply_parts.argtypes = [vp, ci, ci, vp, vp, ci, vp]
         L.fftpim_get_permutation.argtypes = [vp, ci, vp]
         L.fftpim_plan_info.argtypes = [vp, ctypes.POINTER(Info)]
@@ -260,6 +262,24 @@ class Plan:
         _check(lib().fftpim_apply_pair(self._h, ctypes.c_void_p(q2.data_ptr()), ctypes.c_void_p(out_u.data_ptr()),
                                        ctypes.c_void_p(v2.data_ptr()), ctypes.c_void_p(out_w.data_ptr()),
                                        q2.shape[0], _stream_handle(stream)), "fftpim_apply_pair")
+        return (out_u[0], out_w[0]) if sq else (out_u, out_w)
+
+    def apply_pair_noalloc(self, q, v, out_u, out_w, stream=None):
+        """apply_pair through the entry point that allocates nothing: the
+        outputs must be given, and the pair's work arrays come from the
+        library's fixed per-device array."""
+        if out_u is None or out_w is None:
+            raise ValueError("apply_pair_noalloc needs out_u and out_w")
+        q2, out_u, sq = self._io(q, out_u)
+        v2, out_w, _ = self._io(v, out_w)
+        if v2.shape != q2.shape:
+            raise ValueError("q and v must have the same shape")
+        if _overlap(out_u, out_w) or _overlap(out_u, v2) or _overlap(out_w, q2):
+            raise ValueError("out_u and out_w must not overlap each other or the inputs")
+        _check(lib().fftpim_apply_pair_noalloc(self._h, ctypes.c_void_p(q2.data_ptr()),
+                                               ctypes.c_void_p(out_u.data_ptr()), ctypes.c_void_p(v2.data_ptr()),
+                                               ctypes.c_void_p(out_w.data_ptr()), q2.shape[0],
+                                               _stream_handle(stream)), "fftpim_apply_pair_noalloc")
         return (out_u[0], out_w[0]) if sq else (out_u, out_w)
 
     def apply_parts(self, q, parts, adjoint=False, out=None, stream=None):

@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_error_strings():
     L = fp.lib()
-    for code in range(9):
+    for code in range(10):
         assert L.fftpim_error_string(code)
 
 
