@@ -6,19 +6,29 @@ Workload (the paper's Helmholtz case with a phase shift, synthetic): a
 k_x0 = 0.3 k0 and k_y0 = 0.1 k0, 100,000 points area-uniform on a random smooth
 closed surface inside the cell (z in [0, 0.5]), complex N(0,1) strengths
 (drawn as complex64, computed in FP64).  Near grid 64 x 64 x 32, Lagrange
-degree 4, correction radius 10 boxes; far grid 24 x 24 x 16, degree 7; one
-near image layer.  Inputs and outputs stay in the plan's point order (the
+degree 4, correction region the ball of Eq. (er) of radius 10.5 times the
+largest near-grid spacing; far grid 24 x 24 x 16, degree 7; one near image
+layer.  Inputs and outputs stay in the plan's point order (the
 iterative-solver use case) and are resident in HBM before timing starts.
 
 One step = u = A q and w = A^H v for two different inputs, both computed in
 full by one fftpim_apply_pair call (the box-pair correction reads each stored
-block once for both products).  value = N / (time per step).  The same step
-made of the two single calls (fftpim_apply, then fftpim_apply_adjoint) is timed
-too and reported under "separate_calls".
+block once for both products).  value = N / (time per step), the time per step
+being the host wall time of exactly `steps` steps between two device
+synchronisations; the median of per-step HIP event times is reported beside
+it.  The per-stage HIP-event times behind the roofline entry come from a second
+pass of the same steps with stage timing switched on, so the events never sit
+inside the timed pass.  The same step made of the two single calls
+(fftpim_apply, then fftpim_apply_adjoint) is timed too and reported under
+"separate_calls".
 The accuracy of the timed configuration is measured in the same run: the
 CPU-baseline leg evaluates the direct FP64 pair sum (the oracle) on a sample of
 observers, and the relative L2 error of the GPU result on that sample is
 reported.
+A nested "batched" record times the 1M-point, 64-right-hand-side Coulomb cell
+(FP32 bulk, FP64 correction) the same way, with its dominant kernel's roofline,
+its error on the stored exact rows, and the same cell with one FP64
+right-hand side for the batched-versus-single comparison.
 """
 import argparse
 import json
@@ -37,7 +47,8 @@ HBM_PEAK_GBS = 8000.0
 WORKLOAD = dict(
     name="2D-periodic Helmholtz with phase shift, 100k points on a closed surface",
     N=100_000, k0=2 * math.pi, kt=(0.3 * 2 * math.pi, 0.1 * 2 * math.pi), L=(1.0, 1.0),
-    near_n=(64, 64, 32), near_order=4, corr_radius=10, far_n=(24, 24, 16), far_order=7, n_images=1,
+    near_n=(64, 64, 32), near_order=4, corr_radius=10, corr_ball=10.5, far_n=(24, 24, 16), far_order=7,
+    n_images=1,
 )
 
 # secondary workloads (--workload): timed the same way, without the oracle leg
@@ -73,6 +84,48 @@ SECONDARY = {
                                   far_order=5),
 }
 GOLD_1M = os.path.join(ROOT, "tests", "golden", "coulomb_cube_1m_rows.txt")
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def time_steps(step, steps, warmup):
+    """Wall time of exactly `steps` calls of step() between two device
+    synchronisations (ms per step), and the median of per-step HIP event
+    times on the current stream (ms)."""
+    import torch
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    t0 = time.perf_counter()
+    ev[0].record()
+    for k in range(steps):
+        step()
+        ev[k + 1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = sorted(ev[k].elapsed_time(ev[k + 1]) for k in range(steps))
+    return 1e3 * wall / steps, per[len(per) // 2]
+
+
+def staged_pass(plan, step, steps):
+    """Per-stage HIP-event times over `steps` more steps (a pass of its own)."""
+    import torch
+    torch.cuda.synchronize()
+    plan.stage_times(True)
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    return plan.stage_times(False)
 
 
 def run_secondary(args, key):
@@ -179,11 +232,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--corr-radius", type=int, default=WORKLOAD["corr_radius"])
+    ap.add_argument("--corr-ball", type=float, default=WORKLOAD["corr_ball"],
+                    help="radius of the ball correction region in near-grid spacings (0: the cube of 10 boxes)")
     ap.add_argument("--oracle-rows", type=int, default=24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="helmholtz_100k",
                     choices=["helmholtz_100k"] + sorted(SECONDARY))
+    ap.add_argument("--no-batched", action="store_true", help="skip the nested 1M-point batched record")
     ap.add_argument("--no-separate", action="store_true",
                     help="skip the timing of the step made of two single calls")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -216,7 +271,7 @@ def main():
 
     fp.lib()  # fail loudly if the HIP library is not built
     wl = dict(WORKLOAD)
-    wl["corr_radius"] = args.corr_radius
+    wl["corr_ball"] = args.corr_ball
     N = wl["N"]
     src, q64 = W.helmholtz_surface_100k(N)
     q = q64.astype(np.complex128)
@@ -227,7 +282,7 @@ def main():
     plan = fp.Plan(pos, 2, list(wl["L"]), k0=wl["k0"], kt=wl["kt"], near_n=wl["near_n"],
                    near_order=wl["near_order"], corr_radius=wl["corr_radius"], far_n=wl["far_n"],
                    far_order=wl["far_order"], n_images=wl["n_images"], precision="f64",
-                   value_type="complex", order="plan", nrhs_max=1)
+                   value_type="complex", order="plan", nrhs_max=1, corr_ball=wl["corr_ball"])
     torch.cuda.synchronize()
     plan_s = time.perf_counter() - t0
     info = plan.info()
@@ -257,21 +312,14 @@ def main():
                     "calls": "fftpim_apply + fftpim_apply_adjoint"}
         print("separate calls: %.3f ms per step" % sep_ms, file=sys.stderr, flush=True)
 
-    for _ in range(args.warmup):
+    def pair_step():
         plan.apply_pair(qd, vd, out_u=u, out_w=w)
-    torch.cuda.synchronize()
-    plan.stage_times(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        plan.apply_pair(qd, vd, out_u=u, out_w=w)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    stages = plan.stage_times(False)
+
+    ms_per_step, ms_median = time_steps(pair_step, args.steps, args.warmup)
     if plan.last_status() != 0:
         raise RuntimeError("device-reported error during the timed applies")
-    ms_per_step = 1e3 * elapsed / args.steps
     value = N * 1 / (ms_per_step * 1e-3)
+    stages = staged_pass(plan, pair_step, args.steps)
     print("stages (ms per launch): " + ", ".join(
         "%s %.4f" % (k, t / c) for k, (t, c) in stages.items() if c), file=sys.stderr, flush=True)
 
@@ -304,6 +352,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_per_step,
+        "ms_per_step_median": ms_median,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -312,13 +361,16 @@ def main():
         "config": {
             "workload": wl["name"],
             "N": N, "nrhs": 1, "periodicity": "2D (x, y)", "k0": wl["k0"], "kt": list(wl["kt"]),
-            "near_grid": list(wl["near_n"]), "near_order": wl["near_order"], "corr_radius": wl["corr_radius"],
+            "near_grid": list(wl["near_n"]), "near_order": wl["near_order"],
+            "corr_region": ("ball, radius %g near-grid spacings" % wl["corr_ball"]) if wl["corr_ball"] > 0
+            else "cube, %d boxes" % wl["corr_radius"],
             "far_grid": list(wl["far_n"]), "far_order": wl["far_order"], "n_images": wl["n_images"],
             "corr_nnz": nnz, "plan_seconds": plan_s, "io_order": "plan",
         },
         "roofline": roofline,
         "step": "fftpim_apply_pair (A q and A^H v, both in full)",
         "separate_calls": separate,
+        "stage_pass": "roofline launch times from a second pass of %d steps with stage events on" % args.steps,
     }
 
     if not args.no_cpu_baseline:
@@ -343,13 +395,93 @@ def main():
             "value": len(rows) / cpu_s,
             "unit": "observer points/s",
             "cores": workers,
+            "cpu": cpu_model(),
             "kind": "oracle",
             "sample": "%d observers (forward) and %d sources (conjugate transpose) of the same workload, "
                       "direct FP64 pair sum over images (Ewald / Floquet series), %.1f s" % (len(rows), len(rows), cpu_s),
         }
         result["rel_l2_vs_oracle"] = {"forward": e_fwd, "adjoint": e_adj, "sample_rows": len(rows)}
-    print(json.dumps(result), flush=True)
     plan.close()
+    if not args.no_batched:
+        result["batched"] = batched_record(args)
+    print(json.dumps(result), flush=True)
+
+
+def batched_record(args):
+    """The 1M-point, 64-right-hand-side Coulomb cell (FP32 bulk, FP64
+    correction), one step = fftpim_apply_pair over all right-hand sides, and
+    the same cell with one FP64 right-hand side; errors on the stored exact
+    rows."""
+    import numpy as np
+    import torch
+
+    from paper_2312_02376_amd import fftpim as fp
+    from paper_2312_02376_amd import workloads as W
+    dev = torch.device("cuda:0")
+    src, q = W.coulomb_cube_1m_batched()
+    N = src.shape[0]
+    gold = np.loadtxt(GOLD_1M) if os.path.exists(GOLD_1M) else None
+    out = {}
+    for key in ("coulomb_1m_batched", "coulomb_1m_single_f64"):
+        wl = SECONDARY[key]
+        qq = q if wl["nrhs"] > 1 else q[:1].astype(np.float64)
+        nrhs = qq.shape[0]
+        t0 = time.perf_counter()
+        plan = fp.Plan(torch.tensor(src, device=dev), 3, [1.0, 1.0, 1.0], near_n=wl["near_n"],
+                       near_order=wl["near_order"], corr_radius=wl["corr_radius"], far_n=wl["far_n"],
+                       far_order=wl["far_order"], n_images=1, precision=wl["precision"],
+                       value_type=wl["value_type"], order="plan", nrhs_max=nrhs)
+        torch.cuda.synchronize()
+        plan_s = time.perf_counter() - t0
+        info = plan.info()
+        perm = plan.permutation().long()
+        qd = torch.tensor(qq, device=dev)[:, perm].contiguous()
+        vd = torch.roll(qd, 1, dims=0).contiguous() if nrhs > 1 else (-qd).contiguous()
+        u, w = torch.empty_like(qd), torch.empty_like(vd)
+
+        def step():
+            plan.apply_pair(qd, vd, out_u=u, out_w=w)
+
+        steps = max(5, args.steps // 2)
+        ms, med = time_steps(step, steps, 2)
+        if plan.last_status() != 0:
+            raise RuntimeError("device-reported error during the batched applies")
+        rec = {"workload": wl["name"], "value": N * nrhs / (ms * 1e-3), "unit": "observer points/s",
+               "ms_per_step": ms, "ms_per_step_median": med, "steps": steps, "N": N, "nrhs": nrhs,
+               "dtype": "f32 (FP64 correction)" if wl["precision"] == "f32" else "f64",
+               "corr_layout_used": info["corr_layout_used"], "corr_tile_values": info["corr_tile_values"],
+               "plan_seconds": plan_s, "step": "fftpim_apply_pair over all right-hand sides"}
+        if gold is not None:
+            rows = np.unique(gold[:, 0].astype(np.int64))
+            g = gold[:, 2].reshape(len(rows), -1).T[:nrhs]
+            inv = torch.empty_like(perm)
+            inv[perm] = torch.arange(N, device=dev)
+            got = u[:, inv[torch.tensor(rows, device=dev)]].double().cpu().numpy()
+            rec["rel_l2_vs_oracle_rows"] = float(np.linalg.norm(got - g) / np.linalg.norm(g))
+            rec["max_rel_elem_vs_oracle_rows"] = float(np.abs(got - g).max() / np.abs(g).max())
+            rec["oracle_rows"] = int(len(rows))
+        if key == "coulomb_1m_batched":
+            stages = staged_pass(plan, step, steps)
+            rec["stages_ms"] = {k: t / c for k, (t, c) in stages.items() if c}
+            # dominant kernel: the dense FP64 correction tiles on the matrix
+            # cores, two launches (A q, A^H v) inside the correction stage
+            corr_ms, calls = stages["near_corr"]
+            launch_s = corr_ms / max(calls, 1) / 2 * 1e-3
+            flops = 2.0 * info["corr_tile_values"] * nrhs
+            tbytes = info["corr_tile_values"] * 8.0
+            rec["roofline"] = {"kernel": "k_corr_tile (FP64 MFMA 16x16x4, dense 16-observer tiles)",
+                               "bound": "mfma", "achieved": flops / launch_s / 1e12, "peak": 78.6,
+                               "unit": "TFLOP/s", "frac": flops / launch_s / 1e12 / 78.6, "traffic": None,
+                               "flops_per_launch": flops, "avg_launch_ms": launch_s * 1e3,
+                               "hbm_GBps_stored_values": tbytes / launch_s / 1e9}
+        out[key] = rec
+        plan.close()
+        del qd, vd, u, w
+        torch.cuda.empty_cache()
+    b, s1 = out["coulomb_1m_batched"], out["coulomb_1m_single_f64"]
+    b["single_rhs_f64"] = s1
+    b["batched_over_single_per_rhs"] = b["value"] / s1["value"]
+    return b
 
 
 if __name__ == "__main__":

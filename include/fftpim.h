@@ -124,6 +124,13 @@ typedef struct {
   size_t max_bytes;  /* cap on the device memory the plan may hold, including
                         what fftpim_apply_pair adds on its first call;
                         0 = no cap.  Exceeding it returns FFTPIM_ERR_NO_MEMORY. */
+  double corr_ball;  /* shape of the correction region of Eq. (er): 0 = the cube
+                        of Chebyshev box distance <= corr_radius; > 0 = the
+                        ball |r - r_m| <= D^ER of Eq. (er) over box offsets d,
+                        sum_c (d_c h_c / h_max)^2 <= corr_ball^2 (h_c the near
+                        grid spacings), corr_radius then unused.  The ball
+                        must hold every offset with max_c |d_c| <= near_order
+                        (overlapping stencils), else INVALID_ARG. */
 } fftpim_params_t;
 
 /* Storage of the near-zone correction of Eq. (er): one CSR row per observer;
@@ -219,6 +226,26 @@ int fftpim_apply_pair(fftpim_plan_t plan, const void* q_dev, void* u_dev, const 
  * array (nothing is enqueued); DEVICE. */
 int fftpim_apply_pair_noalloc(fftpim_plan_t plan, const void* q_dev, void* u_dev, const void* v_dev,
                               void* w_dev, int nrhs, fftpim_stream_t stream);
+
+/* Position gradient (forces) of the discrete operator A that fftpim_apply
+ * applies: its entries depend on the positions through the Lagrange weights
+ * of the projections and interpolations (Eq. (projection),
+ * Eq. (interpolation)) and through the correction entries of Eq. (er), all
+ * differentiated here.  For amplitudes q_dev and an upstream gradient g_dev
+ * = dL/du (both [nrhs][n], element type as for fftpim_apply), grad_dev
+ * (device double [n][3], overwritten) receives
+ *     dL/dr_k = sum over right-hand sides of
+ *               Re(conj(g_k) sum_n dA[k,n]/dr_k q_n) + Re(sum_m conj(g_m) dA[m,k]/dr_k q_k),
+ * the gradient of L = Re sum_m conj(g_m) (A q)_m (for real values,
+ * L = sum_m g_m (A q)_m; with g = q / 2 and a real static kernel, L is the
+ * electrostatic energy and -grad the forces).  Rows follow the caller's
+ * order (FFTPIM_ORDER_PLAN: the plan's order).  A is piecewise smooth: a
+ * point exactly on a stencil switch gets the derivative of the stencil it
+ * uses.  The first call on a plan allocates the fused pair's work arrays (as
+ * fftpim_apply_pair does) and an [n][3] accumulator.  Enqueued on stream.
+ * Errors: INVALID_ARG, NO_MEMORY, DEVICE. */
+int fftpim_grad_positions(fftpim_plan_t plan, const void* q_dev, const void* g_dev, int nrhs, double* grad_dev,
+                          fftpim_stream_t stream);
 
 /* Apply only some parts of the operator (FFTPIM_PART_* mask) - forward
  * (adjoint = 0) or conjugate transpose (adjoint = 1).  PART_ALL equals

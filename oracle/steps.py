@@ -35,8 +35,11 @@ library implements):
              the near grid is exactly n_int nodes (L = n_int h).  "Doubling
              its size" means zero padding to 2n on every axis.
   correction The triple (observer m, source n, image i) is corrected when
-             the Chebyshev distance between the observer's box and the image
-             box s_n + i n_int is at most r_c.  Its entry is
+             its box offset d = s_m - s_n - i n_int (in boxes) is close: the
+             Chebyshev distance max_c |d_c| <= r_c (the cube), or, for the
+             ball |r - r_m| <= D^ER of Eq. (er) with D^ER = corr_ball h_max,
+             when sum_c (d_c h_c / h_max)^2 <= corr_ball^2 (a relative slack
+             of 1e-9 settles offsets on the sphere).  Its entry is
              phi_i [G0(r_m - r_n - R_i) - G_grid,i(m, n)], the G0 term being
              dropped for the singular self pair (n = m, i = 0).  The weights in
              Eq. (er_2) are those of near Steps 1 and 3.
@@ -54,15 +57,19 @@ from . import pgf as _pgf
 
 class Params:
     """Method parameters: near grid nodes and order, correction radius (in
-    boxes), far grid nodes and order, near image range i_d (Eq. (4))."""
+    boxes), far grid nodes and order, near image range i_d (Eq. (4)), and the
+    correction region: the cube of Chebyshev box distance <= r_c
+    (corr_ball = 0) or the ball of Eq. (er) over box offsets, of radius
+    corr_ball h_max (corr_ball > 0; r_c is then unused)."""
 
-    def __init__(self, near_n, near_q, r_c, far_n, far_q, i_d=1):
+    def __init__(self, near_n, near_q, r_c, far_n, far_q, i_d=1, corr_ball=0.0):
         self.near_n = np.broadcast_to(np.asarray(near_n, dtype=int), (3,)).copy()
         self.near_q = int(near_q)
         self.r_c = int(r_c)
         self.far_n = np.broadcast_to(np.asarray(far_n, dtype=int), (3,)).copy()
         self.far_q = int(far_q)
         self.i_d = int(i_d)
+        self.corr_ball = float(corr_ball)
 
 
 def domain_bounds(lat, pts):
@@ -281,7 +288,7 @@ class FFTPIM:
         ss = self.st_src.s[src_cols]
         for img, ph in zip(self.images, self.img_phase):
             delta = so[:, None, :] - ss[None, :, :] - img * self.n_int
-            jj, nn = np.nonzero(np.max(np.abs(delta), axis=2) <= self.prm.r_c)
+            jj, nn = np.nonzero(self._close(delta))
             if jj.size == 0:
                 continue
             m = obs_rows[jj]
@@ -308,6 +315,14 @@ class FFTPIM:
                 gg[sel] = np.sum((wm @ M) * wn, axis=1)
             np.add.at(C, (jj, nn), ph * (ex - gg))
         return C
+
+    def _close(self, delta):
+        """Close box offsets (last axis: x, y, z) of the correction region."""
+        if self.prm.corr_ball <= 0:
+            return np.max(np.abs(delta), axis=-1) <= self.prm.r_c
+        wgt = self.h / self.h.max()
+        s = np.sum((delta * wgt) ** 2, axis=-1)
+        return s <= self.prm.corr_ball ** 2 * (1.0 + 1e-9)
 
     @staticmethod
     def _tensor_w(st, idx):

@@ -27,6 +27,8 @@ SOURCES = [
     ("kernels_corr.hip", []),
     ("kernels_far.hip", []),
     ("kernels_sym.hip", []),
+    ("kernels_table.hip", []),
+    ("kernels_grad.hip", []),
     ("api.cpp", ["-x", "hip"]),
     ("pgf_host.cpp", []),
 ]

@@ -83,6 +83,28 @@ int upload(fftpim_plan_s* p, T** out, const std::vector<T>& host) {
 
 size_t cbytes(const fftpim_plan_s* p) { return p->prm.precision != FFTPIM_F64 ? 8 : 16; }
 
+// The correction region of Eq. (er) over box offsets: its per-axis reach (in
+// boxes) and, for the ball, the weights h_c / h_max and the squared radius
+// (with a relative slack of 1e-9 that settles offsets on the sphere).
+struct CorrRegion {
+  int reach[3];
+  int ball;
+  double bw[3], br2;
+};
+
+CorrRegion corr_region(const fftpim_plan_s* p) {
+  CorrRegion r{};
+  const double rb = p->prm.corr_ball;
+  r.ball = rb > 0.0 ? 1 : 0;
+  const double hmax = std::max(p->ng.h[0], std::max(p->ng.h[1], p->ng.h[2]));
+  for (int c = 0; c < 3; ++c) {
+    r.bw[c] = p->ng.h[c] / hmax;
+    r.reach[c] = r.ball ? static_cast<int>(std::floor(rb / r.bw[c] * (1.0 + 1e-9))) : p->prm.corr_radius;
+  }
+  r.br2 = rb * rb * (1.0 + 1e-9);
+  return r;
+}
+
 // Stencil start and offset for one coordinate on a grid (Sec. 3.2, Eq. (grid),
 // with the halo reading): t = (x - origin)/h, s = floor(t - (q-1)/2) clamped
 // to [0, n-1-q], u = t - s.
@@ -204,7 +226,8 @@ SymArgs sym_args(const fftpim_plan_s* p) {
   const SymDev& d = p->symd;
   a.N = p->N;
   for (int c = 0; c < 3; ++c) a.nb[c] = p->nb[c];
-  a.R = p->prm.corr_radius + p->ng.q;
+  const CorrRegion reg = corr_region(p);
+  a.R = std::max(reg.reach[0], std::max(reg.reach[1], reg.reach[2])) + p->ng.q;
   a.W = 2 * a.R + 1;
   a.k0 = p->lat.k0.real();
   a.k0_im = p->lat.k0.imag();
@@ -314,22 +337,33 @@ void correction_zone(fftpim_plan_s* p, bool adjoint, const void* in, int P, void
 // Steps 1-3 of Sec. 3.2 for one input, on stream sf.  The adjoint projects
 // with the observer-grid weights, applies K^H and interpolates from the
 // source grid.
+// Far Steps 1-2 (Sec. 3.2): projection onto the source grid (observer grid
+// for the adjoint) and the grid sum with K (K^H); the result is in ws.far_u.
 template <typename R>
-int far_zone(fftpim_plan_s* p, const WorkSet& ws, bool adjoint, const void* in, int P, void* out,
-             hipStream_t sf) {
+int far_field(fftpim_plan_s* p, const WorkSet& ws, bool adjoint, const void* in, int P, hipStream_t sf) {
   const int64_t N = p->N;
   const FarArgs fa = far_args(p);
   const int qf = p->fg.q;
   const int32_t* fbs = adjoint ? p->fbox_start_o : p->fbox_start_s;
   const int32_t* fpm = adjoint ? p->fperm_o : p->fperm_s;
   const double* fw_in = adjoint ? p->fo_w : p->fs_w;
-  const int32_t* fs_out = adjoint ? p->fs_s : p->fo_s;
-  const double* fw_out = adjoint ? p->fs_w : p->fo_w;
   CHK(launch_far_moments<R>(qf, fa, fbs, fpm, fw_in, N, in, P, ws.far_mom, sf));
   CHK(launch_far_gather<R>(qf, fa, ws.far_mom, P, ws.far_q, sf));
   launch_far_apply<R>(fa, p->far_table, ws.far_q, ws.far_u, ws.far_part, P, adjoint,
                       p->prm.precision == FFTPIM_F32_FARBF16 ? 1 : (p->prm.precision == FFTPIM_F32_FARBF16X3 ? 2 : 0),
                       sf);
+  return FFTPIM_OK;
+}
+
+template <typename R>
+int far_zone(fftpim_plan_s* p, const WorkSet& ws, bool adjoint, const void* in, int P, void* out,
+             hipStream_t sf) {
+  const int64_t N = p->N;
+  const FarArgs fa = far_args(p);
+  const int qf = p->fg.q;
+  const int32_t* fs_out = adjoint ? p->fs_s : p->fo_s;
+  const double* fw_out = adjoint ? p->fs_w : p->fo_w;
+  CHK(far_field<R>(p, ws, adjoint, in, P, sf));
   // interpolation side: observer-grid boxes (forward) or source-grid boxes (adjoint)
   const int32_t* fbs_out = adjoint ? p->fbox_start_s : p->fbox_start_o;
   const int32_t* fpm_out = adjoint ? p->fperm_s : p->fperm_o;
@@ -341,9 +375,10 @@ int far_zone(fftpim_plan_s* p, const WorkSet& ws, bool adjoint, const void* in, 
 
 // Steps 1-3 of Sec. 3.3 for one input, on stream sn (the same grid serves
 // sources and observers).
+// Near Steps 1-2 (Sec. 3.3): projection and the zero-padded FFT convolution
+// (with conj(G^hat) for the adjoint); the result is in ws.grid0.
 template <typename R>
-int near_grid_zone(fftpim_plan_s* p, const WorkSet& ws, bool adjoint, const void* in, int P, void* out,
-                   hipStream_t sn) {
+int near_field(fftpim_plan_s* p, const WorkSet& ws, bool adjoint, const void* in, int P, hipStream_t sn) {
   const GridArgs ga = grid_args(p->ng);
   {
     StageTimer t(p, sn, FFTPIM_STAGE_NEAR_SPREAD);
@@ -357,6 +392,14 @@ int near_grid_zone(fftpim_plan_s* p, const WorkSet& ws, bool adjoint, const void
     StageTimer t(p, sn, FFTPIM_STAGE_NEAR_FFT);
     near_convolution<R>(p, ws, P, adjoint, sn);
   }
+  return FFTPIM_OK;
+}
+
+template <typename R>
+int near_grid_zone(fftpim_plan_s* p, const WorkSet& ws, bool adjoint, const void* in, int P, void* out,
+                   hipStream_t sn) {
+  const GridArgs ga = grid_args(p->ng);
+  CHK(near_field<R>(p, ws, adjoint, in, P, sn));
   {
     StageTimer t(p, sn, FFTPIM_STAGE_NEAR_INTERP);
     CHK(launch_interp<R>(p->ng.q, ga, p->near_s, p->near_w, p->N, ws.grid0, P, out, false, sn));
@@ -632,6 +675,44 @@ int run_apply_pair(fftpim_plan_s* p, const PairBufs& pb, const void* q, void* u,
   return FFTPIM_OK;
 }
 
+// Position gradient (see kernels_grad.hip): the forward near and far fields of
+// q and the conjugate-transposed ones of g, differentiated interpolation at
+// every point, and the correction entries differentiated on the fly.  All
+// on the caller's stream; the [N][3] accumulator is added to in a fixed
+// kernel order.
+template <typename R>
+int run_grad(fftpim_plan_s* p, const void* q, const void* g, int nrhs, double* grad, hipStream_t st) {
+  const int64_t N = p->N;
+  const int P = planes_for(p, nrhs);
+  const bool real_io = p->prm.value_type == FFTPIM_REAL;
+  const bool use_perm = p->prm.order_io == FFTPIM_ORDER_USER;
+  CHK(ensure_pair_buffers(p));
+  if (p->grad_acc == nullptr) CHK(dalloc(p, &p->grad_acc, static_cast<size_t>(N) * 3));
+  p->last_stream = st;
+  const PairBufs& pb = p->pair;
+  launch_pack<R>(q, p->q_int, p->perm, N, nrhs, P, real_io, use_perm, st);
+  launch_pack<R>(g, pb.v_int, p->perm, N, nrhs, P, real_io, use_perm, st);
+  HIPCHK(hipMemsetAsync(p->grad_acc, 0, static_cast<size_t>(N) * 3 * sizeof(double), st));
+  const GridArgs ga = grid_args(p->ng), fa = grid_args(p->fg);
+  // near grid: forward field of q, adjoint field of g
+  CHK(near_field<R>(p, p->ws, false, p->q_int, P, st));
+  CHK(launch_interp_grad<R>(p->ng.q, ga, p->ng.h, p->near_s, p->near_u, N, p->ws.grid0, P, pb.v_int, p->grad_acc, st));
+  CHK(near_field<R>(p, pb.ws2, true, pb.v_int, P, st));
+  CHK(launch_interp_grad<R>(p->ng.q, ga, p->ng.h, p->near_s, p->near_u, N, pb.ws2.grid0, P, p->q_int, p->grad_acc,
+                            st));
+  // far zone: observer-grid weights on K W_s q, source-grid weights on K^H W_o g
+  CHK(far_field<R>(p, p->ws, false, p->q_int, P, st));
+  CHK(launch_interp_grad<R>(p->fg.q, fa, p->fg.h, p->fo_s, p->fo_u, N, p->ws.far_u, P, pb.v_int, p->grad_acc, st));
+  CHK(far_field<R>(p, pb.ws2, true, pb.v_int, P, st));
+  CHK(launch_interp_grad<R>(p->fg.q, fa, p->fg.h, p->fs_s, p->fs_u, N, pb.ws2.far_u, P, p->q_int, p->grad_acc, st));
+  // correction entries of Eq. (er)
+  CHK(launch_corr_grad(p->ng.q, p->complex_kernel, p->grad_ca, p->near_s, p->near_u, p->ng.h, p->pos3, p->box_start,
+                       p->g0tab, P, p->q_int, pb.v_int, sizeof(R) == 4, p->grad_acc, st));
+  launch_unpermute3(p->grad_acc, p->perm, N, use_perm, grad, st);
+  if (hipPeekAtLastError() != hipSuccess) return FFTPIM_ERR_DEVICE;
+  return FFTPIM_OK;
+}
+
 int apply_common(fftpim_plan_t plan, int parts, int adjoint, const void* in, void* out, int nrhs,
                  fftpim_stream_t stream, bool finalize) {
   if (!plan || !in || !out) return FFTPIM_ERR_INVALID_ARG;
@@ -662,7 +743,10 @@ int validate(const fftpim_problem_t* pr, const fftpim_params_t* pm) {
       return FFTPIM_ERR_INVALID_ARG;
     if (pm->far_n[c] < pm->far_order + 2 || pm->far_n[c] > 512) return FFTPIM_ERR_INVALID_ARG;
   }
-  if (pm->corr_radius < pm->near_order || pm->corr_radius > kMaxCorrRadius) return FFTPIM_ERR_INVALID_ARG;
+  if (!std::isfinite(pm->corr_ball) || pm->corr_ball < 0.0 || pm->corr_ball > kMaxCorrRadius)
+    return FFTPIM_ERR_INVALID_ARG;
+  if (pm->corr_ball == 0.0 && (pm->corr_radius < pm->near_order || pm->corr_radius > kMaxCorrRadius))
+    return FFTPIM_ERR_INVALID_ARG;
   if (pm->n_images < 0 || pm->n_images > 2) return FFTPIM_ERR_INVALID_ARG;
   if (pm->precision < FFTPIM_F64 || pm->precision > FFTPIM_F32_FARBF16X3) return FFTPIM_ERR_INVALID_ARG;
   if (pm->value_type != FFTPIM_REAL && pm->value_type != FFTPIM_COMPLEX) return FFTPIM_ERR_INVALID_ARG;
@@ -752,13 +836,13 @@ int build_tables(fftpim_plan_s* p, hipStream_t st) {
   dfree(p, dimg);
   dfree(p, dph);
 
-  // far-zone table G^p_far at the offsets between observer and source grids
+  // far-zone table G^p_far at the offsets between observer and source grids,
+  // evaluated on the device in FP64 (Sec. 3.2)
   std::vector<cd> ft;
   int nf[3] = {p->fg.n[0], p->fg.n[1], p->fg.n[2]};
-  if (p->lat.dims == 2 && !p->lat.npsp()) {
-    // the Floquet series of Eq. (pgf_2) needs up to ~1e5 terms per entry at
-    // the smallest z offsets: evaluated on the device
+  {
     FarTableArgs ta{};
+    ta.dims = p->lat.dims;
     for (int c = 0; c < 3; ++c) {
       ta.nf[c] = nf[c];
       ta.delta[c] = p->fg.h[c];
@@ -772,15 +856,17 @@ int build_tables(fftpim_plan_s* p, hipStream_t st) {
     const int64_t total = static_cast<int64_t>(2 * nf[0] - 1) * (2 * nf[1] - 1) * (2 * nf[2] - 1);
     cplx<double>* dt = nullptr;
     CHK(dalloc(p, &dt, static_cast<size_t>(total)));
-    launch_far_table_pgf2(ta, dt, st);
+    if (p->lat.dims == 2 && !p->lat.npsp())
+      launch_far_table_pgf2(ta, dt, st);
+    else
+      CHK(launch_far_table(ta, p->lat.npsp(), dt, st));
     std::vector<cplx<double>> ht(static_cast<size_t>(total));
     HIPCHK(hipMemcpyAsync(ht.data(), dt, total * sizeof(cplx<double>), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipGetLastError());
     dfree(p, dt);
     ft.resize(static_cast<size_t>(total));
     for (int64_t i = 0; i < total; ++i) ft[i] = cd(ht[i].x, ht[i].y);
-  } else {
-    far_table(p->lat, id, nf, p->fg.h, ft);
   }
   std::vector<cplx<R>> ftr(ft.size());
   for (size_t i = 0; i < ft.size(); ++i) {
@@ -805,7 +891,7 @@ int build_sym(fftpim_plan_s* p, const std::vector<int32_t>& start, const double*
               const CorrArgs& ca, hipStream_t st) {
   const int nbx = p->nb[0], nby = p->nb[1], nbz = p->nb[2];
   const int64_t nboxes = static_cast<int64_t>(nbx) * nby * nbz;
-  const int rc = p->prm.corr_radius;
+  const CorrRegion reg = corr_region(p);
   std::vector<int32_t> ebox, ebox_of_box(nboxes, -1);
   int max_box = 0;
   for (int64_t b = 0; b < nboxes; ++b) {
@@ -869,11 +955,12 @@ int build_sym(fftpim_plan_s* p, const std::vector<int32_t>& start, const double*
       zoff += zround(g.cum);
     };
     open_group();
-    for (int cx = std::max(0, bx - rc); cx <= std::min(nbx - 1, bx + rc); ++cx)
-      for (int cy = std::max(0, by - rc); cy <= std::min(nby - 1, by + rc); ++cy)
-        for (int cz = std::max(0, bz - rc); cz <= std::min(nbz - 1, bz + rc); ++cz) {
+    for (int cx = std::max(0, bx - reg.reach[0]); cx <= std::min(nbx - 1, bx + reg.reach[0]); ++cx)
+      for (int cy = std::max(0, by - reg.reach[1]); cy <= std::min(nby - 1, by + reg.reach[1]); ++cy)
+        for (int cz = std::max(0, bz - reg.reach[2]); cz <= std::min(nbz - 1, bz + reg.reach[2]); ++cz) {
           const int64_t Bp = (static_cast<int64_t>(cx) * nby + cy) * nbz + cz;
           if (Bp < B || ebox_of_box[Bp] < 0) continue;
+          if (reg.ball && !ball_close(reg.bw, reg.br2, bx - cx, by - cy, bz - cz)) continue;
           const int kp = ebox_of_box[Bp];
           const int n0 = start[Bp], nj = start[Bp + 1] - n0;
           const int64_t j = static_cast<int64_t>(po.size());
@@ -1129,10 +1216,15 @@ int build_tiles(fftpim_plan_s* p, const std::vector<int32_t>& start, const std::
 
 int build_correction(fftpim_plan_s* p, const std::vector<int32_t>& start, const double* pos3_dev,
                      hipStream_t st) {
-  const int q = p->ng.q, rc = p->prm.corr_radius, id = p->prm.n_images;
+  const int q = p->ng.q, id = p->prm.n_images;
+  const CorrRegion reg = corr_region(p);
+  const int rc = std::max(reg.reach[0], std::max(reg.reach[1], reg.reach[2]));
   const int dims = p->lat.dims;
   const int A = 2 * id + 1;
   CorrArgs ca{};
+  ca.ball = reg.ball;
+  for (int c = 0; c < 3; ++c) ca.bw[c] = reg.bw[c];
+  ca.br2 = reg.br2;
   for (int c = 0; c < 3; ++c) {
     ca.nb[c] = p->nb[c];
     ca.nint[c] = p->ng.nint[c];
@@ -1173,6 +1265,7 @@ int build_correction(fftpim_plan_s* p, const std::vector<int32_t>& start, const 
   int32_t* dent[3];
   for (int c = 0; c < 3; ++c) {
     const int nint = p->ng.nint[c];
+    const int rcc = reg.reach[c];
     std::vector<int32_t> off(nint + 2, 0), ent;
     for (int S = 0; S <= nint; ++S) {
       off[S] = static_cast<int32_t>(ent.size());
@@ -1180,8 +1273,8 @@ int build_correction(fftpim_plan_s* p, const std::vector<int32_t>& start, const 
         int mask = 0;
         if (ca.per[c]) {
           for (int i = -id; i <= id; ++i)
-            if (std::abs(S - b - i * nint) <= rc) mask |= 1 << (i + id);
-        } else if (std::abs(S - b) <= rc) {
+            if (std::abs(S - b - i * nint) <= rcc) mask |= 1 << (i + id);
+        } else if (std::abs(S - b) <= rcc) {
           mask = 1;
         }
         if (mask) ent.push_back(b | (mask << 16));
@@ -1247,12 +1340,11 @@ int build_correction(fftpim_plan_s* p, const std::vector<int32_t>& start, const 
   HIPCHK(hipStreamSynchronize(st));
   HIPCHK(hipGetLastError());
   dfree(p, dcount);
-  dfree(p, dg0);
-  dfree(p, dph);
-  for (int c = 0; c < 3; ++c) {
-    dfree(p, doff[c]);
-    dfree(p, dent[c]);
-  }
+  // the traversal arrays (per-axis candidate lists, image phases, G0 table)
+  // stay with the plan: the position gradient walks the same pairs
+  p->grad_ca = ca;
+  p->grad_ca.images_only = 0;
+  p->g0tab = dg0;
   if (p->tile) CHK(build_tiles(p, start, rowptr, st));
   return FFTPIM_OK;
 }
@@ -1310,6 +1402,14 @@ int build_plan(fftpim_plan_s* p, int64_t N, const double* src_dev, hipStream_t s
     g.lo[c] = lo[c];
     p->M[c] = 2 * g.n[c];
     p->nb[c] = g.nint[c] + 1;
+  }
+  if (pm.corr_ball > 0.0) {
+    // every pair of boxes with overlapping stencils (offsets up to q on each
+    // axis) must be corrected: the near table's zeroed entries reach them
+    const CorrRegion reg = corr_region(p);
+    if (!ball_close(reg.bw, reg.br2, g.q, g.q, g.q)) return FFTPIM_ERR_INVALID_ARG;
+    for (int c = 0; c < 3; ++c)
+      if (reg.reach[c] > kMaxCorrRadius) return FFTPIM_ERR_INVALID_ARG;
   }
   // far grids (Sec. 3.2, Eq. (grid)): n - q - 1 cells on every axis
   GridGeom& f = p->fg;
@@ -1442,7 +1542,7 @@ int build_plan(fftpim_plan_s* p, int64_t N, const double* src_dev, hipStream_t s
   }
   CHK(build_correction(p, start, dpos, st));
   plan_log("correction operator", t0);
-  dfree(p, dpos);
+  p->pos3 = dpos;  // kept for the exact terms of the position gradient
 
   // workspace
   const int P = planes_for(p, pm.nrhs_max);
@@ -1657,6 +1757,18 @@ int fftpim_apply_pair_noalloc(fftpim_plan_t plan, const void* q_dev, void* u_dev
                       : run_apply_pair<double>(plan, pb, q_dev, u_dev, v_dev, w_dev, nrhs, st);
     plan->timing = timing;
     return s;
+  });
+}
+
+int fftpim_grad_positions(fftpim_plan_t plan, const void* q_dev, const void* g_dev, int nrhs, double* grad_dev,
+                          fftpim_stream_t stream) {
+  return guarded([&]() -> int {
+    if (!plan || !q_dev || !g_dev || !grad_dev) return FFTPIM_ERR_INVALID_ARG;
+    if (nrhs < 1 || nrhs > plan->prm.nrhs_max) return FFTPIM_ERR_INVALID_ARG;
+    if (plan->g0tab == nullptr || plan->pos3 == nullptr) return FFTPIM_ERR_UNSUPPORTED;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (plan->prm.precision != FFTPIM_F64) return run_grad<float>(plan, q_dev, g_dev, nrhs, grad_dev, st);
+    return run_grad<double>(plan, q_dev, g_dev, nrhs, grad_dev, st);
   });
 }
 

@@ -46,6 +46,40 @@ __host__ __device__ inline cplx<R> cscale(cplx<R> a, R s) {
   return cmake<R>(a.x * s, a.y * s);
 }
 
+// FP64 complex helpers for plan-time device code
+__host__ __device__ inline cplx<double> cexp_d(cplx<double> z) {
+  double sn, cs;
+  sincos(z.y, &sn, &cs);
+  const double e = exp(z.x);
+  return cmake<double>(e * cs, e * sn);
+}
+
+__host__ __device__ inline cplx<double> cdiv_d(cplx<double> a, cplx<double> b) {
+  const double d = 1.0 / (b.x * b.x + b.y * b.y);
+  return cmake<double>((a.x * b.x + a.y * b.y) * d, (a.y * b.x - a.x * b.y) * d);
+}
+
+// square root with Im <= 0 (and Re >= 0 on the real axis), computed without
+// cancellation from the principal root
+__host__ __device__ inline cplx<double> csqrt_im_nonpos_d(cplx<double> w) {
+  const double a = hypot(w.x, w.y);
+  if (a == 0.0) return cmake<double>(0.0, 0.0);
+  double re, im;
+  if (w.x >= 0.0) {
+    re = sqrt(0.5 * (a + w.x));
+    im = w.y / (2.0 * re);
+  } else {
+    im = copysign(sqrt(0.5 * (a - w.x)), w.y);
+    re = w.y / (2.0 * im);
+  }
+  if (im > 0.0) {
+    re = -re;
+    im = -im;
+  }
+  return cmake<double>(re, im);
+}
+
+
 // Geometry of one uniform grid with an interpolation halo (Sec. 3.2, Eq. (grid)):
 // node l on axis c sits at origin[c] + l h[c]; a point uses the q+1 nodes
 // s..s+q.  Cells (boxes) are indexed by s in [0, nint].
@@ -156,6 +190,36 @@ struct SymDev {
   int64_t *in_ptr = nullptr, *in_base = nullptr;
 };
 
+// Geometry of the near-zone correction (Sec. 3.3 Step 4, Eq. (er)) as the
+// fill, the tile builder and the position gradient traverse it.
+struct CorrArgs {
+  int nb[3], nint[3], per[3];
+  int rc, id;
+  int R, W;            // g0 table covers offsets [-R, R]^3, W = 2R + 1
+  int64_t N;
+  double L[3];
+  double k0, k0_im;
+  int nimg_axis;       // 2 id + 1
+  const double* phase;    // device image phases (re, im), index (gx * A + gy) * A + gz, image g - id
+  const double* phase_adj;  // conj(phase of image -i) at the index of image i (the C^H values)
+  // per-axis candidate source boxes of an observer box S: entries
+  // lent[c][loff[c][S] .. loff[c][S+1]) = b | (mask << 16), bit g of mask
+  // marking image g - id (g = 0 only on non-periodic axes) as close
+  const int32_t* loff[3];
+  const int32_t* lent[3];
+  int images_only;     // 1: drop the image-0 term (it is stored as symmetric blocks)
+  // ball-shaped correction region: an offset d (boxes, image shift included)
+  // is close when sum_c (d_c bw_c)^2 <= br2 (cube when ball == 0)
+  int ball;
+  double bw[3], br2;
+};
+
+// The ball test of the correction region, shared by host and device code.
+__host__ __device__ inline bool ball_close(const double bw[3], double br2, int dx, int dy, int dz) {
+  const double x = dx * bw[0], y = dy * bw[1], z = dz * bw[2];
+  return x * x + y * y + z * z <= br2;
+}
+
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
@@ -255,6 +319,13 @@ struct fftpim_plan_s {
   void* val = nullptr;            // double or complex double
   void* val_adj = nullptr;        // Helmholtz only: values of C^H on the same pattern
   int64_t nnz = 0;
+  // position gradient: the correction traversal of the fill (all images),
+  // the G0 table at node offsets, the sorted positions [3][N], and a [N][3]
+  // accumulator made on the first gradient call
+  fftpim::CorrArgs grad_ca{};
+  void* g0tab = nullptr;
+  double* pos3 = nullptr;
+  double* grad_acc = nullptr;
 
   // workspace
   int nplanes_max = 0;

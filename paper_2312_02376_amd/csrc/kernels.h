@@ -44,24 +44,6 @@ struct NearTableArgs {
   const double* phase;   // device [nimg][2] image phases
 };
 
-struct CorrArgs {
-  int nb[3], nint[3], per[3];
-  int rc, id;
-  int R, W;            // g0 table covers offsets [-R, R]^3, W = 2R + 1
-  int64_t N;
-  double L[3];
-  double k0, k0_im;
-  int nimg_axis;       // 2 id + 1
-  const double* phase;    // device image phases (re, im), index (gx * A + gy) * A + gz, image g - id
-  const double* phase_adj;  // conj(phase of image -i) at the index of image i (the C^H values)
-  // per-axis candidate source boxes of an observer box S: entries
-  // lent[c][loff[c][S] .. loff[c][S+1]) = b | (mask << 16), bit g of mask
-  // marking image g - id (g = 0 only on non-periodic axes) as close
-  const int32_t* loff[3];
-  const int32_t* lent[3];
-  int images_only;     // 1: drop the image-0 term (it is stored as symmetric blocks)
-};
-
 // In-cell correction stored once per unordered pair of non-empty near-grid
 // boxes ("ebox" = index into the list of non-empty boxes); see SymGroup.
 struct SymArgs {
@@ -88,8 +70,10 @@ struct SymArgs {
                                  //     sender's partials (senders in box order)
 };
 
-// Far-zone table on the device (2D-periodic kernels with k0 or a phase shift).
+// Far-zone table on the device: launch_far_table_pgf2 for 2D-periodic kernels
+// with k0 or a phase shift, launch_far_table for every other class.
 struct FarTableArgs {
+  int dims;         // periodic axes
   int nf[3];        // far grid nodes per axis
   double delta[3];  // far grid spacing
   double L[3];
@@ -98,6 +82,7 @@ struct FarTableArgs {
   int id;           // near-zone images per periodic axis
 };
 void launch_far_table_pgf2(const FarTableArgs& a, void* table, hipStream_t st);
+int launch_far_table(const FarTableArgs& a, bool npsp, void* table, hipStream_t st);
 
 struct FarArgs {
   int nf[3], nint[3], nb[3];
@@ -108,6 +93,18 @@ struct FarArgs {
 template <typename R>
 void launch_pack(const void* qu, void* qint, const int32_t* perm, int64_t N, int nrhs, int P, bool real_in,
                  bool use_perm, hipStream_t st);
+
+// Position gradient (kernels_grad.hip): differentiated interpolation of a
+// grid field F, out[m][c] += sum_p Re(conj(coef[m][p]) dF/dr_c(r_m)); and the
+// correction entries differentiated on the fly (q, g packed planes).
+template <typename R>
+int launch_interp_grad(int q, const GridArgs& g, const double h[3], const int32_t* s3, const double* u3, int64_t N,
+                       const void* grid, int P, const void* coef, double* out, hipStream_t st);
+int launch_corr_grad(int q, bool cplx_vals, const CorrArgs& a, const int32_t* s3, const double* u3, const double h[3],
+                     const double* pos3, const int32_t* box_start, const void* g0tab, int P, const void* qint,
+                     const void* gint, bool single, double* out, hipStream_t st);
+// [N][3] doubles from plan order to the caller's order (use_perm) or copied.
+void launch_unpermute3(const double* in, const int32_t* perm, int64_t N, bool use_perm, double* out, hipStream_t st);
 // Up to three part buffers summed elementwise in a fixed order (null = absent).
 template <typename R>
 struct PartPtrs {

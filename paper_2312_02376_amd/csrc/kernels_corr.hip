@@ -2,8 +2,9 @@
 // images kept (end of Sec. 3.3).
 //
 // For an observer m and a source n, the image i (|i_c| <= i_d on periodic
-// axes) is close when the Chebyshev distance between m's near-grid box and
-// the image box s_n + i * nint is at most r_c.  The stored entry is
+// axes) is close when the box offset d = s_m - s_n - i * nint lies in the
+// correction region: the cube max_c |d_c| <= r_c, or the ball
+// sum_c (d_c h_c / h_max)^2 <= r^2 of Eq. (er).  The stored entry is
 //     C[m, n] = sum_{close i} phi_i X_i(m, n),
 //     X_i(m, n) = G0(r_m - r_n - R_i) - G_grid,i(m, n)      (G0 term dropped
 //                                                            for n = m, i = 0)
@@ -25,6 +26,35 @@ __device__ inline void axis_range(const int32_t* __restrict__ off, int S, int& l
   hi = off[S + 1];
 }
 
+// Whether image (imx, imy, imz) of the candidate source box (bx, by, bz) is
+// close to the observer box S, given that it is close axis by axis (the
+// per-axis masks hold the cube region): the image-0 term is left out when
+// only images are stored, and the ball region also tests the whole offset.
+__device__ inline bool image_close(const CorrArgs& a, const int S[3], int bx, int by, int bz, int imx, int imy,
+                                   int imz) {
+  if (a.images_only && imx == 0 && imy == 0 && imz == 0) return false;
+  return !a.ball || ball_close(a.bw, a.br2, S[0] - bx - imx * a.nint[0], S[1] - by - imy * a.nint[1],
+                               S[2] - bz - imz * a.nint[2]);
+}
+
+// Whether any image of the candidate source box is close (the per-axis masks
+// mx, my, mz: bit g marks image g - id on that axis as close axis by axis).
+__device__ inline bool any_close(const CorrArgs& a, const int S[3], int bx, int by, int bz, int mx, int my, int mz) {
+  const int A = a.nimg_axis;
+  for (int gx = 0; gx < A; ++gx) {
+    if (!((mx >> gx) & 1)) continue;
+    for (int gy = 0; gy < A; ++gy) {
+      if (!((my >> gy) & 1)) continue;
+      for (int gz = 0; gz < A; ++gz) {
+        if (!((mz >> gz) & 1)) continue;
+        if (image_close(a, S, bx, by, bz, gx - a.id * a.per[0], gy - a.id * a.per[1], gz - a.id * a.per[2]))
+          return true;
+      }
+    }
+  }
+  return false;
+}
+
 __global__ void k_corr_count(CorrArgs a, const int32_t* __restrict__ s3, const int32_t* __restrict__ box_start,
                              int64_t* __restrict__ rowcount) {
   const int32_t *loff0 = a.loff[0], *loff1 = a.loff[1], *loff2 = a.loff[2];
@@ -32,19 +62,20 @@ __global__ void k_corr_count(CorrArgs a, const int32_t* __restrict__ s3, const i
   int64_t m = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (m >= a.N) return;
   int x0, x1, y0, y1, z0, z1;
-  axis_range(loff0, s3[m], x0, x1);
-  axis_range(loff1, s3[a.N + m], y0, y1);
-  axis_range(loff2, s3[2 * a.N + m], z0, z1);
+  const int S[3] = {s3[m], s3[a.N + m], s3[2 * a.N + m]};
+  axis_range(loff0, S[0], x0, x1);
+  axis_range(loff1, S[1], y0, y1);
+  axis_range(loff2, S[2], z0, z1);
   int64_t cnt = 0;
-  const int z0b = a.per[0] ? 1 << a.id : 1, z1b = a.per[1] ? 1 << a.id : 1, z2b = a.per[2] ? 1 << a.id : 1;
   for (int ix = x0; ix < x1; ++ix) {
     int bx = lent0[ix] & 0xffff;
     for (int iy = y0; iy < y1; ++iy) {
       int by = lent1[iy] & 0xffff;
       for (int iz = z0; iz < z1; ++iz) {
         int bz = lent2[iz] & 0xffff;
-        if (a.images_only && (lent0[ix] >> 16) == z0b && (lent1[iy] >> 16) == z1b && (lent2[iz] >> 16) == z2b)
-          continue;  // only the image-0 term is close: it lives in the symmetric blocks
+        // no close image left (e.g. only the image-0 term, which lives in the
+        // symmetric blocks, or none inside the ball)
+        if (!any_close(a, S, bx, by, bz, lent0[ix] >> 16, lent1[iy] >> 16, lent2[iz] >> 16)) continue;
         int64_t b = (static_cast<int64_t>(bx) * a.nb[1] + by) * a.nb[2] + bz;
         cnt += box_start[b + 1] - box_start[b];
       }
@@ -78,14 +109,13 @@ __global__ void __launch_bounds__(64) k_corr_fill(
   double* valr = static_cast<double*>(val_v);
   cplx<double>* valc = static_cast<cplx<double>*>(val_v);
   cplx<double>* vadj = static_cast<cplx<double>*>(vadj_v);
-  const int z0b = a.per[0] ? 1 << a.id : 1, z1b = a.per[1] ? 1 << a.id : 1, z2b = a.per[2] ? 1 << a.id : 1;
   for (int ix = lo[0]; ix < hi[0]; ++ix) {
     const int bx = lent0[ix] & 0xffff, mx = lent0[ix] >> 16;
     for (int iy = lo[1]; iy < hi[1]; ++iy) {
       const int by = lent1[iy] & 0xffff, my = lent1[iy] >> 16;
       for (int iz = lo[2]; iz < hi[2]; ++iz) {
         const int bz = lent2[iz] & 0xffff, mz = lent2[iz] >> 16;
-        if (a.images_only && mx == z0b && my == z1b && mz == z2b) continue;
+        if (!any_close(a, S, bx, by, bz, mx, my, mz)) continue;
         const int64_t b = (static_cast<int64_t>(bx) * a.nb[1] + by) * a.nb[2] + bz;
         const int n0 = box_start[b], n1 = box_start[b + 1];
         for (int n = n0; n < n1; ++n) {
@@ -109,7 +139,7 @@ __global__ void __launch_bounds__(64) k_corr_fill(
               for (int gz = 0; gz < A; ++gz) {
                 if (!((mz >> gz) & 1)) continue;
                 const int imz = gz - a.id * a.per[2];
-                if (a.images_only && imx == 0 && imy == 0 && imz == 0) continue;
+                if (!image_close(a, S, bx, by, bz, imx, imy, imz)) continue;
                 const int D[3] = {S[0] - bx - imx * a.nint[0], S[1] - by - imy * a.nint[1],
                                   S[2] - bz - imz * a.nint[2]};
                 // exact part

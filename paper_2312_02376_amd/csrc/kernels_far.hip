@@ -536,38 +536,6 @@ __global__ void k_far_reduce(const cplx<R>* __restrict__ part, cplx<R>* __restri
 
 constexpr int kTableThreads = 256;
 
-__device__ inline cplx<double> cexp_d(cplx<double> z) {
-  double sn, cs;
-  sincos(z.y, &sn, &cs);
-  const double e = exp(z.x);
-  return cmake<double>(e * cs, e * sn);
-}
-
-__device__ inline cplx<double> cdiv_d(cplx<double> a, cplx<double> b) {
-  const double d = 1.0 / (b.x * b.x + b.y * b.y);
-  return cmake<double>((a.x * b.x + a.y * b.y) * d, (a.y * b.x - a.x * b.y) * d);
-}
-
-// square root with Im <= 0 (and Re >= 0 on the real axis), computed without
-// cancellation from the principal root
-__device__ inline cplx<double> csqrt_im_nonpos_d(cplx<double> w) {
-  const double a = hypot(w.x, w.y);
-  if (a == 0.0) return cmake<double>(0.0, 0.0);
-  double re, im;
-  if (w.x >= 0.0) {
-    re = sqrt(0.5 * (a + w.x));
-    im = w.y / (2.0 * re);
-  } else {
-    im = copysign(sqrt(0.5 * (a - w.x)), w.y);
-    re = w.y / (2.0 * im);
-  }
-  if (im > 0.0) {
-    re = -re;
-    im = -im;
-  }
-  return cmake<double>(re, im);
-}
-
 // CW: complex wavenumbers (a lossy k0 or a complex phase shift); the real
 // instantiation keeps the propagating / evanescent split in real arithmetic.
 template <bool CW>

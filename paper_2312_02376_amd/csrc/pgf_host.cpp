@@ -1,10 +1,11 @@
-// Host FP64 evaluation of the periodic Green's function G^p (Sec. 2) for the
-// far-zone kernel table (Sec. 3.2: the table of G^p_far at the offsets between
-// the shifted observer and source grids, evaluated with the rapidly converging
-// series of Eq. (pgf) and Eq. (lgf)).
+// Host FP64 evaluation of the periodic Green's function G^p (Sec. 2) with the
+// rapidly converging series of Eq. (pgf) and Eq. (lgf) (valid away from the
+// periodic axes / planes), the Rayleigh-Wood checks of a plan and the self
+// coefficient lim_{r->0}[G^p - G0].  The far-zone table itself is evaluated on
+// the device (kernels_table.hip, kernels_far.hip) with the same series; this
+// evaluator is the library's reference for them and is exposed through
+// fftpim_eval_pgf.
 //
-// The far-grid offsets never vanish on any axis (the two grids are shifted by
-// half a cell), so the series always have a non-vanishing transverse distance.
 // Wavenumbers may be complex (a lossy k0, a complex phase shift; Sec. 2): the
 // series are then their analytic continuation, with every square root taken
 // with Im <= 0.
@@ -12,8 +13,6 @@
 
 #include <algorithm>
 #include <cmath>
-#include <system_error>
-#include <thread>
 #include <vector>
 
 namespace fftpim {
@@ -544,71 +543,6 @@ cd pgf_self(const Lattice& lat) {
     out += acc / (4.0 * kPi * L[0]);
   }
   return out;
-}
-
-void far_table(const Lattice& lat, int i_d, const int nf[3], const double delta[3],
-               std::vector<cd>& table) {
-  const int sx = 2 * nf[0] - 1, sy = 2 * nf[1] - 1, sz = 2 * nf[2] - 1;
-  const int64_t total = static_cast<int64_t>(sx) * sy * sz;
-  table.assign(total, cd(0.0, 0.0));
-  const unsigned nthreads = std::max(1u, std::min(64u, std::thread::hardware_concurrency()));
-  const bool spectral1 = lat.dims == 1 && !lat.npsp();
-  auto offset = [&](int64_t e, double r[3]) {
-    int dz = static_cast<int>(e % sz);
-    int dy = static_cast<int>((e / sz) % sy);
-    int dx = static_cast<int>(e / (static_cast<int64_t>(sz) * sy));
-    r[0] = (dx - (nf[0] - 1) - 0.5) * delta[0];
-    r[1] = (dy - (nf[1] - 1) - 0.5) * delta[1];
-    r[2] = (dz - (nf[2] - 1) - 0.5) * delta[2];
-  };
-  auto work = [&](unsigned t) {
-    if (!spectral1) {
-      for (int64_t e = t; e < total; e += nthreads) {
-        double r[3];
-        offset(e, r);
-        table[e] = pgf(lat, r) - g_near(lat, r, i_d);
-      }
-      return;
-    }
-    // Eq. (pgf_1) per transverse offset (y, z): the K0 factors of the Floquet
-    // terms depend on rho only and serve every x offset.  The series with the
-    // unreduced x equals G^p including its Bloch factor.
-    std::vector<cd> kx, kk;
-    for (int64_t yz = t; yz < static_cast<int64_t>(sy) * sz; yz += nthreads) {
-      double r[3];
-      offset(yz, r);
-      const double rho = std::hypot(r[1], r[2]);
-      const double Lx = lat.L[0];
-      const double kreach = kDecay / rho + std::abs(lat.k0) + std::abs(lat.kt[0]);
-      const int mmax = static_cast<int>(std::ceil(kreach * Lx / (2.0 * kPi))) + 1;
-      kx.resize(2 * mmax + 1);
-      kk.resize(2 * mmax + 1);
-      for (int m = -mmax; m <= mmax; ++m) {
-        kx[m + mmax] = lat.kt[0] + 2.0 * kPi * m / Lx;
-        const cd krho = csqrt_im_nonpos(lat.k0 * lat.k0 - kx[m + mmax] * kx[m + mmax]);
-        kk[m + mmax] = bessel_k0c(cd(0.0, 1.0) * krho * rho);
-      }
-      for (int dx = 0; dx < sx; ++dx) {
-        const int64_t e = static_cast<int64_t>(dx) * sy * sz + yz;
-        offset(e, r);
-        cd sum = 0.0;
-        for (int m = -mmax; m <= mmax; ++m) sum += std::exp(cd(0.0, -1.0) * kx[m + mmax] * r[0]) * kk[m + mmax];
-        table[e] = sum / (2.0 * kPi * Lx) - g_near(lat, r, i_d);
-      }
-    }
-  };
-  std::vector<std::thread> pool;
-  pool.reserve(nthreads);
-  unsigned started = 0;
-  for (; started < nthreads; ++started) {
-    try {
-      pool.emplace_back(work, started);
-    } catch (const std::system_error&) {
-      break;  // no more host threads: the calling thread takes the rest
-    }
-  }
-  for (unsigned t = started; t < nthreads; ++t) work(t);
-  for (auto& th : pool) th.join();
 }
 
 }  // namespace fftpim

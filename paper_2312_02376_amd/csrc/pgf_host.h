@@ -1,5 +1,6 @@
-// Host FP64 periodic Green's function (Sec. 2, Eq. (pgf) and Eq. (lgf)) used to
-// tabulate the far-zone kernel of Sec. 3.2.
+// Host FP64 periodic Green's function (Sec. 2, Eq. (pgf) and Eq. (lgf)): the
+// library's own evaluator of G^p (exposed through fftpim_eval_pgf), the
+// Rayleigh-Wood checks of a plan, and the self coefficient of Eq. (5).
 #pragma once
 
 #include <complex>
@@ -45,9 +46,4 @@ cd g_near(const Lattice& lat, const double r[3], int i_d);
 // Nonzero when this evaluator does not cover the problem class.
 int check_supported(const Lattice& lat);
 bool wood_anomaly(const Lattice& lat);
-// G^p_far at the offsets (d - 1/2) * delta, d_c in [-(nf_c - 1), nf_c - 1],
-// x slowest; table size (2 nf_x - 1)(2 nf_y - 1)(2 nf_z - 1).
-void far_table(const Lattice& lat, int i_d, const int nf[3], const double delta[3],
-               std::vector<cd>& table);
-
 }  // namespace fftpim

@@ -29,7 +29,7 @@ EXPORTS = (
     "fftpim_default_params", "fftpim_plan", "fftpim_apply", "fftpim_apply_adjoint",
     "fftpim_apply_pair", "fftpim_apply_parts", "fftpim_get_permutation", "fftpim_plan_info", "fftpim_last_status",
     "fftpim_destroy", "fftpim_error_string", "fftpim_eval_pgf", "fftpim_stage_times", "fftpim_eval_pgf_self",
-    "fftpim_apply_pair_noalloc",
+    "fftpim_apply_pair_noalloc", "fftpim_grad_positions",
 )
 STAGES = ("pack", "near_spread", "near_fft", "near_interp", "near_corr", "far", "unpack")
 
@@ -52,7 +52,7 @@ class Params(ctypes.Structure):
                 ("far_n", ctypes.c_int * 3), ("far_order", ctypes.c_int), ("n_images", ctypes.c_int),
                 ("precision", ctypes.c_int), ("value_type", ctypes.c_int), ("self_mode", ctypes.c_int),
                 ("order_io", ctypes.c_int), ("nrhs_max", ctypes.c_int), ("corr_layout", ctypes.c_int),
-                ("max_bytes", ctypes.c_size_t)]
+                ("max_bytes", ctypes.c_size_t), ("corr_ball", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):
@@ -85,6 +85,7 @@ def lib():
         L.fftpim_apply_adjoint.argtypes = [vp, vp, vp, ci, vp]
         L.fftpim_apply_pair.argtypes = [vp, vp, vp, vp, vp, ci, vp]
         L.fftpim_apply_pair_noalloc.argtypes = [vp, vp, vp, vp, vp, ci, vp]
+        L.fftpim_grad_positions.argtypes = [vp, vp, vp, ci, vp, vp]
         L.fftpim_apply_parts.argtypes = [vp, ci, ci, vp, vp, ci, vp]
         L.fftpim_get_permutation.argtypes = [vp, ci, vp]
         L.fftpim_plan_info.argtypes = [vp, ctypes.POINTER(Info)]
@@ -173,7 +174,7 @@ class Plan:
     def __init__(self, positions, periodic_dims, L, k0=0.0, kt=(0.0, 0.0, 0.0), near_n=(16, 16, 16),
                  near_order=4, corr_radius=6, far_n=(16, 16, 16), far_order=7, n_images=1, precision="f64",
                  value_type="complex", order="user", nrhs_max=1, box=None, self_mode="images",
-                 corr_layout="auto", max_bytes=0, stream=None):
+                 corr_layout="auto", max_bytes=0, corr_ball=0.0, stream=None):
         import torch
         if not (isinstance(positions, torch.Tensor) and positions.is_cuda and positions.dtype == torch.float64):
             raise TypeError("positions must be a CUDA float64 tensor of shape (N, 3)")
@@ -196,6 +197,7 @@ class Plan:
         pm.nrhs_max = int(nrhs_max)
         pm.corr_layout = {"auto": 0, "csr": 1, "sym": 2, "tile": 3}[corr_layout]
         pm.max_bytes = int(max_bytes)
+        pm.corr_ball = float(corr_ball)
         self.params = pm
         self.precision = precision
         self.value_type = value_type
@@ -282,6 +284,28 @@ class Plan:
                                                _stream_handle(stream)), "fftpim_apply_pair_noalloc")
         return (out_u[0], out_w[0]) if sq else (out_u, out_w)
 
+    def grad_positions(self, q, g, out=None, stream=None):
+        """dL/dr (N, 3) float64 for L = Re sum conj(g) (A q) (real values:
+        sum g (A q)), q and g of shape (nrhs, N) or (N,)."""
+        import torch
+        q2 = self._in(q)
+        g2 = self._in(g)
+        if g2.shape != q2.shape:
+            raise ValueError("q and g must have the same shape")
+        if out is None:
+            out = torch.empty((self.N, 3), dtype=torch.float64, device=self.device)
+        elif (out.dtype != torch.float64 or out.device != self.device or tuple(out.shape) != (self.N, 3)
+              or not out.is_contiguous()):
+            raise ValueError("out must be a contiguous float64 (N, 3) tensor on the plan's device")
+        _check(lib().fftpim_grad_positions(self._h, ctypes.c_void_p(q2.data_ptr()), ctypes.c_void_p(g2.data_ptr()),
+                                           q2.shape[0], ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)),
+               "fftpim_grad_positions")
+        return out
+
+    def _in(self, x):
+        x2, _, _ = self._io(x, None)
+        return x2
+
     def apply_parts(self, q, parts, adjoint=False, out=None, stream=None):
         q2, out, sq = self._io(q, out)
         _check(lib().fftpim_apply_parts(self._h, int(parts), 1 if adjoint else 0, ctypes.c_void_p(q2.data_ptr()),
@@ -332,17 +356,26 @@ def _autograd_function():
         """u = A q with dL/dq = A^H dL/du: the backward pass is the library's
         conjugate-transpose apply (for a real loss of complex u, PyTorch's
         gradient convention makes the gradient of q exactly A^H times the
-        gradient of u; for real static kernels A^H = A^T).  Gradients with
-        respect to positions are not provided."""
+        gradient of u; for real static kernels A^H = A^T).  When positions
+        are given and require a gradient, the backward pass also returns
+        dL/dr from fftpim_grad_positions (the plan must have been made from
+        those positions)."""
 
         @staticmethod
-        def forward(ctx, q, plan):
+        def forward(ctx, q, positions, plan):
             ctx.plan = plan
+            ctx.save_for_backward(q)
             return plan.apply(q)
 
         @staticmethod
         def backward(ctx, gu):
-            return ctx.plan.adjoint(gu.contiguous()), None
+            (q,) = ctx.saved_tensors
+            gu = gu.contiguous()
+            gq = ctx.plan.adjoint(gu) if ctx.needs_input_grad[0] else None
+            gpos = None
+            if ctx.needs_input_grad[1]:
+                gpos = ctx.plan.grad_positions(q.detach().contiguous(), gu)
+            return gq, gpos, None
 
     return FFTPIMFunction
 
@@ -350,9 +383,11 @@ def _autograd_function():
 _FN = None
 
 
-def apply_autograd(plan, q):
-    """Differentiable u = A q (amplitudes only) for a Plan."""
+def apply_autograd(plan, q, positions=None):
+    """Differentiable u = A q for a Plan: gradients with respect to the
+    amplitudes q and, when `positions` (the tensor the plan was made from)
+    requires a gradient, with respect to the positions."""
     global _FN
     if _FN is None:
         _FN = _autograd_function()
-    return _FN.apply(q, plan)
+    return _FN.apply(q, positions, plan)

@@ -37,7 +37,7 @@ def coulomb_1k():
           "columns: index, u", [np.arange(1000), u.real])
 
 
-def helmholtz_100k(nrows=16):
+def helmholtz_100k(nrows=256):
     src, q64 = W.helmholtz_surface_100k()
     q = q64.astype(np.complex128)
     v = W.gaussian_complex(1, len(src), 102)[0].astype(np.complex128)
@@ -53,7 +53,7 @@ def helmholtz_100k(nrows=16):
           [rows, u.real, u.imag, w.real, w.imag])
 
 
-def coulomb_1m(nrows=6):
+def coulomb_1m(nrows=128):
     src, q = W.coulomb_cube_1m_batched()
     lat = P.Lattice(3, [1.0, 1.0, 1.0])
     rows = np.sort(np.random.default_rng(11).choice(len(src), nrows, replace=False))

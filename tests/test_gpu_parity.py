@@ -66,14 +66,15 @@ def _points(kind, N, seed):
     raise ValueError(kind)
 
 
-def _setup(name, N=257, seed=31, precision="f64", nrhs=None, corr_layout="auto", self_mode="images"):
+def _setup(name, N=257, seed=31, precision="f64", nrhs=None, corr_layout="auto", self_mode="images",
+           corr_ball=0.0):
     latkw, kind, nrhs0, vt, nn, q, rc, nf, qf = CASES[name]
     nrhs = nrhs0 if nrhs is None else nrhs
     lat = P.Lattice(latkw["dims"], latkw["L"], latkw.get("k0", 0.0), latkw.get("kt", [0, 0, 0]))
     src = _points(kind, N, seed)
     if kind == "cube":
         src = src * np.asarray((latkw["L"] + [1, 1, 1])[:3])
-    ref = S.FFTPIM(lat, S.Params(nn, q, rc, nf, qf, 1), src, self_mode=self_mode)
+    ref = S.FFTPIM(lat, S.Params(nn, q, rc, nf, qf, 1, corr_ball=corr_ball), src, self_mode=self_mode)
     rng = np.random.default_rng(seed + 1)
     if vt == "real":
         qv = rng.standard_normal((nrhs, N))
@@ -85,7 +86,7 @@ def _setup(name, N=257, seed=31, precision="f64", nrhs=None, corr_layout="auto",
     plan = fp.Plan(pos, latkw["dims"], latkw["L"], k0=latkw.get("k0", 0.0), kt=latkw.get("kt", [0, 0, 0]),
                    near_n=nn, near_order=q, corr_radius=rc, far_n=nf, far_order=qf, n_images=1,
                    precision=precision, value_type=vt, nrhs_max=max(4, nrhs), corr_layout=corr_layout,
-                   self_mode=self_mode)
+                   self_mode=self_mode, corr_ball=corr_ball)
     return lat, ref, plan, qv
 
 
@@ -447,3 +448,37 @@ def test_self_exclude(name):
     cs = _fftpim().eval_pgf_self(lat.dims, lat.L[:lat.dims], lat.k0, lat.kt[:lat.dims])
     np.testing.assert_allclose(d, cs * qv if plan.value_type == "complex" else cs.real * qv,
                                rtol=1e-9, atol=1e-12 * np.abs(u).max())
+
+
+@pytest.mark.parametrize("name,layout,nrhs", [
+    ("npsp3_real", "sym", None), ("npsp3_real", "csr", None), ("npsp3_real", "tile", 19),
+    ("helm2_bloch", "sym", None), ("helm2_bloch", "csr", None), ("helm1_bloch", "auto", None),
+    ("npsp2_real", "auto", None), ("helm3_cphase", "csr", None),
+])
+def test_ball_region(name, layout, nrhs):
+    # the ball correction region of Eq. (er) (radius in units of the largest
+    # near-grid spacing; anisotropic spacings in the slab and surface cases)
+    print("case", name, layout, flush=True)
+    lat, ref, plan, qv = _setup(name, corr_layout=layout, nrhs=nrhs, corr_ball=7.0)
+    qd = _to_dev(plan, qv)
+    for adjoint in (False, True):
+        got = plan.apply_parts(qd, PARTS["near_corr"], adjoint=adjoint).cpu().numpy()
+        want = (ref.adjoint if adjoint else ref.apply)(qv, parts=("near_corr",))
+        assert rel(got, want) < 1e-11, adjoint
+        got = plan.apply_parts(qd, 7, adjoint=adjoint).cpu().numpy()
+        want = (ref.adjoint if adjoint else ref.apply)(qv)
+        assert rel(got, want) < 1e-11, adjoint
+    up, wp = plan.apply_pair(qd, qd)
+    want_w = ref.adjoint(qv)
+    if lat.npsp:
+        want_w = want_w - want_w.mean(axis=-1, keepdims=True)
+    assert rel(up.cpu().numpy(), ref.apply(qv)) < 1e-11
+    assert rel(wp.cpu().numpy(), want_w) < 1e-11
+
+
+def test_ball_region_rejects_too_small_radius():
+    fp = _fftpim()
+    src = W.uniform_cube(100, 2)
+    with pytest.raises(fp.FFTPIMError):
+        fp.Plan(torch.tensor(src, device="cuda"), 3, [1, 1, 1], near_n=(16, 16, 16), near_order=4,
+                far_n=(10, 10, 10), far_order=5, corr_ball=6.0)   # 4 sqrt(3) = 6.93 needed

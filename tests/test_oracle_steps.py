@@ -9,6 +9,7 @@ import pytest
 from oracle import pgf as P
 from oracle import steps as S
 from oracle.psp import psp_forward
+from paper_2312_02376_amd import workloads as W
 
 
 @pytest.mark.parametrize("q", [1, 2, 3, 4, 5, 7])
@@ -131,3 +132,69 @@ def test_method_accuracy_against_direct_pair_sum():
         errs.append(np.linalg.norm(u - ref) / np.linalg.norm(ref))
     assert errs[1] < errs[0] < 1e-3
     assert errs[1] < 1e-4
+
+
+def test_ball_region_membership_and_limits():
+    # the ball region of Eq. (er) over box offsets: exactly the offsets with
+    # sum_c (d_c h_c / h_max)^2 <= R^2 (anisotropic spacings), contained in
+    # the cube of the same reach, and the whole cube when R covers its corner
+    lat = P.Lattice(2, [1.0, 1.0])
+    rng = np.random.default_rng(9)
+    src = rng.random((40, 3)) * np.array([1.0, 1.0, 0.37])
+    m = S.FFTPIM(lat, S.Params((16, 16, 16), 2, 3, (6, 6, 6), 2, 1, corr_ball=4.5), src)
+    w = m.h / m.h.max()
+    assert w.min() < 0.5  # the z spacing is the smallest
+    d = np.stack(np.meshgrid(*[np.arange(-14, 15)] * 3, indexing="ij"), axis=-1).reshape(-1, 3)
+    inside = m._close(d)
+    brute = np.array([(x * w[0]) ** 2 + (y * w[1]) ** 2 + (z * w[2]) ** 2 <= 4.5 ** 2 for x, y, z in d])
+    assert np.array_equal(inside, brute)
+    assert inside[np.all(d == 0, axis=1)].all()
+    # along z the ball reaches further (in boxes) than along x
+    assert m._close(np.array([[0, 0, int(4.5 / w[2])]]))[0] and not m._close(np.array([[5, 0, 0]]))[0]
+
+
+@pytest.mark.parametrize("dims", [2, 3])
+def test_full_ball_correction_gives_direct_near_sum(dims):
+    # a ball large enough to hold every (m, n, i) triple: the near zone is the
+    # direct near-image sum, as for the cube
+    k = 3.0
+    lat = P.Lattice(dims, [1, 1, 1], k0=k, kt=[0.4, -0.7, 0.2][:dims])
+    n, q = 8, 2
+    nint = n - q
+    m, rng = _small(lat, n=n, q=q, rc=2 * nint + 2, N=30, seed=dims + 7)
+    m.prm.corr_ball = float(np.sqrt(3.0) * (2 * nint + 2))
+    qv = (rng.standard_normal(30) + 1j * rng.standard_normal(30))[None, :]
+    rows = np.arange(30)
+    got = (m.near_grid_part(qv, rows) + m.near_corr_part(qv, rows))[0]
+    d = m.obs[:, None, :] - m.src[None, :, :]
+    G = P.g_near(d, lat, 1)
+    np.fill_diagonal(G, 0.0)
+    rngs = [range(-1, 2) if c < dims else range(0, 1) for c in range(3)]
+    s_img = 0.0
+    for ix in rngs[0]:
+        for iy in rngs[1]:
+            for iz in rngs[2]:
+                if ix == iy == iz == 0:
+                    continue
+                R = np.array([ix, iy, iz]) * lat.L
+                s_img += np.exp(-1j * lat.kt @ R) * P.g0(-R, lat.k0)
+    want = G @ qv[0] + s_img * qv[0]
+    np.testing.assert_allclose(got, want, rtol=1e-11, atol=1e-12 * np.abs(want).max())
+
+
+def test_ball_region_accuracy_improves_with_radius():
+    # the method error against the direct pair sum falls as the ball grows
+    k = 2 * np.pi
+    lat = P.Lattice(2, [1.0, 1.0], k0=k, kt=[0.3 * k, 0.1 * k])
+    rng = np.random.default_rng(21)
+    src = W.smooth_closed_surface(600, 4)
+    q = rng.standard_normal(600) + 1j * rng.standard_normal(600)
+    rows = np.arange(0, 600, 25)
+    exact = psp_forward(lat, src, q, obs_index=rows, workers=1)
+    errs = []
+    m = S.FFTPIM(lat, S.Params((32, 32, 16), 4, 4, (24, 24, 16), 7, 1, corr_ball=4.0), src)
+    for R in (4.0, 6.0, 10.0):
+        m.prm.corr_ball = R
+        u = m.apply(q, rows=rows)
+        errs.append(np.linalg.norm(u - exact) / np.linalg.norm(exact))
+    assert errs[0] > 4 * errs[1] > 16 * errs[2], errs
