@@ -108,7 +108,9 @@ typedef struct {
  * near grid and n - q - 1 cells otherwise.  Orders are Lagrange degrees
  * (q + 1 nodes per axis). */
 typedef struct {
-  int near_n[3];     /* near grid nodes per axis (2*near_n must be a power of 2) */
+  int near_n[3];     /* near grid nodes per axis (any size from near_order + 2 to
+                        2048; the zero-padded transforms use the smallest power
+                        of two >= 2 near_n - 1, reported as near_fft) */
   int near_order;    /* near projection/interpolation degree */
   int corr_radius;   /* error-correction radius in near-grid boxes (Chebyshev) */
   int far_n[3];      /* far grid nodes per axis */
@@ -131,7 +133,20 @@ typedef struct {
                         grid spacings), corr_radius then unused.  The ball
                         must hold every offset with max_c |d_c| <= near_order
                         (overlapping stencils), else INVALID_ARG. */
+  int far_sum;       /* far grid sum of Eq. (8), u^g = K_far q_g: FFTPIM_FAR_AUTO,
+                        FFTPIM_FAR_DIRECT or FFTPIM_FAR_FFT (see below) */
 } fftpim_params_t;
+
+/* Evaluation of the far grid sum of Eq. (8).  K_far is shift invariant
+ * (Sec. 3.2: one table value per node offset between the observer and source
+ * grids), so the sum is a 3D discrete convolution.  DIRECT forms it term by
+ * term from the table (or on matrix cores for at least eight planes; the
+ * BF16 precisions always take this path).  FFT zero-pads the far grid to the
+ * smallest power of two >= 2 far_n - 1 per axis and convolves with the
+ * table's spectrum, O(N_g log N_g) instead of O(N_g^2): the path for large
+ * far grids, as wave problems of several wavelengths per period need.  AUTO
+ * takes FFT from 8192 far grid nodes up, DIRECT below. */
+enum { FFTPIM_FAR_AUTO = 0, FFTPIM_FAR_DIRECT = 1, FFTPIM_FAR_FFT = 2 };
 
 /* Storage of the near-zone correction of Eq. (er): one CSR row per observer;
  * or (SYM) the in-cell part once per unordered pair of near-grid boxes (the
@@ -159,10 +174,12 @@ typedef struct {
   int64_t device_bytes;       /* device memory held by the plan */
   int nplanes_max;            /* complex grid planes for nrhs_max */
   double plan_seconds;        /* wall time of fftpim_plan */
+  int far_fft[3];             /* far-sum transform lengths (0: direct far sum) */
 } fftpim_info_t;
 
 /* Fill *params with defaults for the problem (order 4 near, order 7 far,
- * i_d = 1, F64, complex values, images kept, user order, nrhs_max 1). */
+ * i_d = 1, F64, complex values, images kept, user order, nrhs_max 1,
+ * automatic far sum). */
 int fftpim_default_params(const fftpim_problem_t* problem, fftpim_params_t* params);
 
 /* Build a plan (Sec. 3.2 and 3.3 preprocessing: grids, interpolation

@@ -42,7 +42,14 @@ constexpr int kSpreadCsrPlanes = 4;
     if (s_ != FFTPIM_OK) return s_; \
   } while (0)
 
-bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+// AUTO far sum: the FFT convolution from this many far grid nodes up
+constexpr int64_t kFarFftMinNodes = 8192;
+// smallest transform length (a power of two) holding m points
+int fft_length(int m) {
+  int M = 1;
+  while (M < m) M *= 2;
+  return M;
+}
 int ilog2(int v) {
   int l = 0;
   while ((1 << l) < v) ++l;
@@ -186,23 +193,29 @@ FftPassDesc pass_desc(int M, int n_in, int n_out, bool contig, int64_t nouter, i
   return d;
 }
 
+// Zero-padded (aperiodic) 3D convolution of a grid [n0][n1][n2][P] with a
+// kernel given by its spectrum hat ([M0][M1][M2], scaled by 1/(M0 M1 M2)):
+// pruned forward passes z, y, then x with the spectrum multiply fused
+// (conjugated for the adjoint), pruned inverse passes y, z.  Reads in, uses
+// bufA ([n0][n1][M2][P]) and bufB ([n0][M1][M2][P]), writes out (may be in).
 template <typename R>
-void near_convolution(fftpim_plan_s* p, const WorkSet& ws, int P, bool adjoint, hipStream_t st) {
+void grid_convolution(const int n[3], const int M[3], void* const tw[3], const void* hat, const void* in,
+                      void* bufA, void* bufB, void* out, int P, bool adjoint, hipStream_t st) {
   // grids are [x][y][z][P]: a pass along one axis sees outer x line x columns,
   // the columns being the axes after it together with the planes
-  const int nx = p->ng.n[0], ny = p->ng.n[1], nz = p->ng.n[2];
-  const int Mx = p->M[0], My = p->M[1], Mz = p->M[2];
+  const int nx = n[0], ny = n[1], nz = n[2];
+  const int Mx = M[0], My = M[1], Mz = M[2];
   const size_t es = sizeof(cplx<R>);
   const int64_t xy = static_cast<int64_t>(nx) * ny;
-  // z: grid0 [nx*ny][nz][P] -> bufA [nx*ny][Mz][P]
+  // z: in [nx*ny][nz][P] -> bufA [nx*ny][Mz][P]
   FftPassDesc dz = P == 1 ? pass_desc(Mz, nz, Mz, true, xy, 1, 1, nz, 1, Mz, es)
                           : pass_desc(Mz, nz, Mz, false, xy, P, P, static_cast<int64_t>(nz) * P, P,
                                       static_cast<int64_t>(Mz) * P, es);
-  launch_fft_pass<R>(0, ws.grid0, ws.bufA, dz, p->twiddle[2], nullptr, false, st);
+  launch_fft_pass<R>(0, in, bufA, dz, tw[2], nullptr, false, st);
   // y: bufA [nx][ny][Mz*P] -> bufB [nx][My][Mz*P]
   const int64_t zc = static_cast<int64_t>(Mz) * P;
   FftPassDesc dy = pass_desc(My, ny, My, false, nx, zc, zc, ny * zc, zc, My * zc, es);
-  launch_fft_pass<R>(0, ws.bufA, ws.bufB, dy, p->twiddle[1], nullptr, false, st);
+  launch_fft_pass<R>(0, bufA, bufB, dy, tw[1], nullptr, false, st);
   // x: in place on bufB [nx][My*Mz*P], fused spectrum multiply (one spectrum
   // value per (y, z) serves all planes)
   const int64_t cols = My * zc;
@@ -210,15 +223,21 @@ void near_convolution(fftpim_plan_s* p, const WorkSet& ws, int P, bool adjoint, 
   dx.spec_line = static_cast<int64_t>(My) * Mz;
   dx.spec_col = 1;
   dx.spec_div = P;
-  launch_fft_pass<R>(2, ws.bufB, ws.bufB, dx, p->twiddle[0], p->near_hat, adjoint, st);
+  launch_fft_pass<R>(2, bufB, bufB, dx, tw[0], hat, adjoint, st);
   // inverse y: bufB [nx][My][Mz*P] -> bufA [nx][ny][Mz*P]
   FftPassDesc iy = pass_desc(My, My, ny, false, nx, zc, zc, My * zc, zc, ny * zc, es);
-  launch_fft_pass<R>(1, ws.bufB, ws.bufA, iy, p->twiddle[1], nullptr, false, st);
-  // inverse z: bufA [nx*ny][Mz][P] -> grid0 [nx*ny][nz][P]
+  launch_fft_pass<R>(1, bufB, bufA, iy, tw[1], nullptr, false, st);
+  // inverse z: bufA [nx*ny][Mz][P] -> out [nx*ny][nz][P]
   FftPassDesc iz = P == 1 ? pass_desc(Mz, Mz, nz, true, xy, 1, 1, Mz, 1, nz, es)
                           : pass_desc(Mz, Mz, nz, false, xy, P, P, static_cast<int64_t>(Mz) * P, P,
                                       static_cast<int64_t>(nz) * P, es);
-  launch_fft_pass<R>(1, ws.bufA, ws.grid0, iz, p->twiddle[2], nullptr, false, st);
+  launch_fft_pass<R>(1, bufA, out, iz, tw[2], nullptr, false, st);
+}
+
+// Near Step 2 (Sec. 3.3): in place on the work set's near grid.
+template <typename R>
+void near_convolution(fftpim_plan_s* p, const WorkSet& ws, int P, bool adjoint, hipStream_t st) {
+  grid_convolution<R>(p->ng.n, p->M, p->twiddle, p->near_hat, ws.grid0, ws.bufA, ws.bufB, ws.grid0, P, adjoint, st);
 }
 
 SymArgs sym_args(const fftpim_plan_s* p) {
@@ -349,6 +368,11 @@ int far_field(fftpim_plan_s* p, const WorkSet& ws, bool adjoint, const void* in,
   const double* fw_in = adjoint ? p->fo_w : p->fs_w;
   CHK(launch_far_moments<R>(qf, fa, fbs, fpm, fw_in, N, in, P, ws.far_mom, sf));
   CHK(launch_far_gather<R>(qf, fa, ws.far_mom, P, ws.far_q, sf));
+  if (p->far_fft) {
+    grid_convolution<R>(p->fg.n, p->Mf, p->ftwiddle, p->far_hat, ws.far_q, ws.far_bufA, ws.far_bufB, ws.far_u, P,
+                        adjoint, sf);
+    return FFTPIM_OK;
+  }
   launch_far_apply<R>(fa, p->far_table, ws.far_q, ws.far_u, ws.far_part, P, adjoint,
                       p->prm.precision == FFTPIM_F32_FARBF16 ? 1 : (p->prm.precision == FFTPIM_F32_FARBF16X3 ? 2 : 0),
                       sf);
@@ -494,7 +518,7 @@ int run_apply(fftpim_plan_s* p, int parts, bool adjoint, const void* in, void* o
 
 // Byte sizes of the arrays of one near-grid + far-zone work set (for the
 // plan's largest plane count), in WorkSet field order.
-constexpr int kWorkArrays = 7;
+constexpr int kWorkArrays = 9;
 void work_set_sizes(const fftpim_plan_s* p, size_t sz[kWorkArrays]) {
   const size_t P = static_cast<size_t>(p->nplanes_max);
   const size_t es = cbytes(p);
@@ -511,11 +535,14 @@ void work_set_sizes(const fftpim_plan_s* p, size_t sz[kWorkArrays]) {
   sz[3] = fboxes * K1 * K1 * K1 * P * es;                                // far_mom
   sz[4] = Ngf * P * es;                                                  // far_q
   sz[5] = Ngf * P * es;                                                  // far_u
-  sz[6] = max_splits * Ngf * P * es;                                     // far_part
+  sz[6] = p->far_fft ? 0 : max_splits * Ngf * P * es;                    // far_part
+  sz[7] = p->far_fft ? static_cast<size_t>(f.n[0]) * f.n[1] * p->Mf[2] * P * es : 0;   // far_bufA
+  sz[8] = p->far_fft ? static_cast<size_t>(f.n[0]) * p->Mf[1] * p->Mf[2] * P * es : 0;  // far_bufB
 }
 
 void** work_set_slots(WorkSet& ws, int k) {
-  void** slots[kWorkArrays] = {&ws.grid0, &ws.bufA, &ws.bufB, &ws.far_mom, &ws.far_q, &ws.far_u, &ws.far_part};
+  void** slots[kWorkArrays] = {&ws.grid0, &ws.bufA, &ws.bufB,     &ws.far_mom, &ws.far_q,
+                               &ws.far_u, &ws.far_part, &ws.far_bufA, &ws.far_bufB};
   return slots[k];
 }
 
@@ -739,8 +766,7 @@ int validate(const fftpim_problem_t* pr, const fftpim_params_t* pm) {
   if (pm->near_order < 1 || pm->near_order > kMaxNearOrder) return FFTPIM_ERR_INVALID_ARG;
   if (pm->far_order < 1 || pm->far_order > kMaxFarOrder) return FFTPIM_ERR_INVALID_ARG;
   for (int c = 0; c < 3; ++c) {
-    if (pm->near_n[c] < pm->near_order + 2 || !is_pow2(2 * pm->near_n[c]) || pm->near_n[c] > 2048)
-      return FFTPIM_ERR_INVALID_ARG;
+    if (pm->near_n[c] < pm->near_order + 2 || pm->near_n[c] > 2048) return FFTPIM_ERR_INVALID_ARG;
     if (pm->far_n[c] < pm->far_order + 2 || pm->far_n[c] > 512) return FFTPIM_ERR_INVALID_ARG;
   }
   if (!std::isfinite(pm->corr_ball) || pm->corr_ball < 0.0 || pm->corr_ball > kMaxCorrRadius)
@@ -748,6 +774,10 @@ int validate(const fftpim_problem_t* pr, const fftpim_params_t* pm) {
   if (pm->corr_ball == 0.0 && (pm->corr_radius < pm->near_order || pm->corr_radius > kMaxCorrRadius))
     return FFTPIM_ERR_INVALID_ARG;
   if (pm->n_images < 0 || pm->n_images > 2) return FFTPIM_ERR_INVALID_ARG;
+  if (pm->far_sum < FFTPIM_FAR_AUTO || pm->far_sum > FFTPIM_FAR_FFT) return FFTPIM_ERR_INVALID_ARG;
+  if (pm->far_sum == FFTPIM_FAR_FFT &&
+      (pm->precision == FFTPIM_F32_FARBF16 || pm->precision == FFTPIM_F32_FARBF16X3))
+    return FFTPIM_ERR_INVALID_ARG;
   if (pm->precision < FFTPIM_F64 || pm->precision > FFTPIM_F32_FARBF16X3) return FFTPIM_ERR_INVALID_ARG;
   if (pm->value_type != FFTPIM_REAL && pm->value_type != FFTPIM_COMPLEX) return FFTPIM_ERR_INVALID_ARG;
   if (pm->self_mode != FFTPIM_SELF_IMAGES && pm->self_mode != FFTPIM_SELF_EXCLUDE) return FFTPIM_ERR_INVALID_ARG;
@@ -860,6 +890,46 @@ int build_tables(fftpim_plan_s* p, hipStream_t st) {
       launch_far_table_pgf2(ta, dt, st);
     else
       CHK(launch_far_table(ta, p->lat.npsp(), dt, st));
+    if (p->far_fft) {
+      // the table as one period of a circulant, its FP64 spectrum scaled by
+      // 1/(Mfx Mfy Mfz) and stored in the working precision
+      const int Mx = p->Mf[0], My = p->Mf[1], Mz = p->Mf[2];
+      const int64_t mt = static_cast<int64_t>(Mx) * My * Mz;
+      cplx<double>* C = nullptr;
+      CHK(dalloc(p, &C, static_cast<size_t>(mt)));
+      launch_far_circulant(dt, nf, p->Mf, C, st);
+      cplx<double>* tw64[3];
+      for (int c = 0; c < 3; ++c) CHK(upload(p, &tw64[c], twiddles<double>(p->Mf[c])));
+      const size_t es = sizeof(cplx<double>);
+      FftPassDesc dz = pass_desc(Mz, Mz, Mz, true, static_cast<int64_t>(Mx) * My, 1, 1, Mz, 1, Mz, es);
+      launch_fft_pass<double>(0, C, C, dz, tw64[2], nullptr, false, st);
+      FftPassDesc dy = pass_desc(My, My, My, false, Mx, Mz, Mz, static_cast<int64_t>(My) * Mz, Mz,
+                                 static_cast<int64_t>(My) * Mz, es);
+      launch_fft_pass<double>(0, C, C, dy, tw64[1], nullptr, false, st);
+      const int64_t cols = static_cast<int64_t>(My) * Mz;
+      FftPassDesc dx = pass_desc(Mx, Mx, Mx, false, 1, cols, cols, Mx * cols, cols, Mx * cols, es);
+      launch_fft_pass<double>(0, C, C, dx, tw64[0], nullptr, false, st);
+      cplx<R>* fh = nullptr;
+      CHK(dalloc(p, &fh, static_cast<size_t>(mt)));
+      launch_scale_convert<R>(C, fh, mt, 1.0 / static_cast<double>(mt), st);
+      HIPCHK(hipStreamSynchronize(st));
+      HIPCHK(hipGetLastError());
+      // a non-finite table value (a series that failed) poisons the spectrum
+      std::vector<cplx<double>> probe(static_cast<size_t>(total));
+      HIPCHK(hipMemcpy(probe.data(), dt, total * sizeof(cplx<double>), hipMemcpyDeviceToHost));
+      for (const auto& v : probe)
+        if (!std::isfinite(v.x) || !std::isfinite(v.y)) return FFTPIM_ERR_UNSUPPORTED;
+      dfree(p, C);
+      dfree(p, dt);
+      for (int c = 0; c < 3; ++c) dfree(p, tw64[c]);
+      p->far_hat = fh;
+      for (int c = 0; c < 3; ++c) {
+        cplx<R>* tw = nullptr;
+        CHK(upload(p, &tw, twiddles<R>(p->Mf[c])));
+        p->ftwiddle[c] = tw;
+      }
+      return FFTPIM_OK;
+    }
     std::vector<cplx<double>> ht(static_cast<size_t>(total));
     HIPCHK(hipMemcpyAsync(ht.data(), dt, total * sizeof(cplx<double>), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -1400,7 +1470,8 @@ int build_plan(fftpim_plan_s* p, int64_t N, const double* src_dev, hipStream_t s
     g.h[c] = (hi[c] - lo[c]) / g.nint[c];
     g.origin[c] = lo[c] - 0.5 * (g.q - 1) * g.h[c];
     g.lo[c] = lo[c];
-    p->M[c] = 2 * g.n[c];
+    // the zero-padded (aperiodic) convolution needs M >= 2 n - 1 points
+    p->M[c] = fft_length(2 * g.n[c] - 1);
     p->nb[c] = g.nint[c] + 1;
   }
   if (pm.corr_ball > 0.0) {
@@ -1422,6 +1493,13 @@ int build_plan(fftpim_plan_s* p, int64_t N, const double* src_dev, hipStream_t s
     f.origin[c] = lo[c] - 0.5 * (f.q - 1) * f.h[c];
     f.lo[c] = lo[c];
     p->fnb[c] = f.nint[c] + 1;
+  }
+  // far grid sum: direct (term by term or matrix cores) or FFT convolution
+  {
+    const int64_t ngf = static_cast<int64_t>(f.n[0]) * f.n[1] * f.n[2];
+    const bool bf16 = pm.precision == FFTPIM_F32_FARBF16 || pm.precision == FFTPIM_F32_FARBF16X3;
+    p->far_fft = pm.far_sum == FFTPIM_FAR_FFT || (pm.far_sum == FFTPIM_FAR_AUTO && !bf16 && ngf >= kFarFftMinNodes);
+    for (int c = 0; c < 3; ++c) p->Mf[c] = p->far_fft ? fft_length(2 * f.n[c] - 1) : 0;
   }
   // near stencils and the box sort
   std::vector<int32_t> s(3 * N);
@@ -1803,6 +1881,7 @@ int fftpim_plan_info(fftpim_plan_t plan, fftpim_info_t* info) {
       r.far_n[c] = plan->fg.n[c];
       r.far_cells[c] = plan->fg.nint[c];
       r.far_h[c] = plan->fg.h[c];
+      r.far_fft[c] = plan->Mf[c];
     }
     r.corr_nnz = plan->nnz + plan->sym_nvals;
     r.corr_sym_values = plan->sym_nvals;

@@ -220,6 +220,87 @@ __host__ __device__ inline bool ball_close(const double bw[3], double br2, int d
   return x * x + y * y + z * z <= br2;
 }
 
+// The G0 table at near-grid node offsets ([W]^3 complex FP64) as the
+// correction fill and gradient kernels read it: from global memory, or
+// staged once per workgroup in LDS (real parts only for real kernels) when
+// it fits kTabLdsBytes.
+constexpr size_t kTabLdsBytes = 64 * 1024;
+inline size_t tab_lds_bytes(int W, bool cplx) {
+  return static_cast<size_t>(W) * W * W * (cplx ? 16 : 8);
+}
+
+#ifdef __HIPCC__
+// Per-axis candidate source boxes of an observer box: entries (b | mask << 16)
+// where bit (i + id) of mask marks image i_c as close.
+__device__ inline void axis_range(const int32_t* __restrict__ off, int S, int& lo, int& hi) {
+  lo = off[S];
+  hi = off[S + 1];
+}
+
+// Whether image (imx, imy, imz) of the candidate source box (bx, by, bz) is
+// close to the observer box S, given that it is close axis by axis (the
+// per-axis masks hold the cube region): the image-0 term is left out when
+// only images are stored, and the ball region also tests the whole offset.
+__device__ inline bool image_close(const CorrArgs& a, const int S[3], int bx, int by, int bz, int imx, int imy,
+                                   int imz) {
+  if (a.images_only && imx == 0 && imy == 0 && imz == 0) return false;
+  return !a.ball || ball_close(a.bw, a.br2, S[0] - bx - imx * a.nint[0], S[1] - by - imy * a.nint[1],
+                               S[2] - bz - imz * a.nint[2]);
+}
+
+// Whether any image of the candidate source box is close (the per-axis masks
+// mx, my, mz: bit g marks image g - id on that axis as close axis by axis).
+__device__ inline bool any_close(const CorrArgs& a, const int S[3], int bx, int by, int bz, int mx, int my, int mz) {
+  const int A = a.nimg_axis;
+  for (int gx = 0; gx < A; ++gx) {
+    if (!((mx >> gx) & 1)) continue;
+    for (int gy = 0; gy < A; ++gy) {
+      if (!((my >> gy) & 1)) continue;
+      for (int gz = 0; gz < A; ++gz) {
+        if (!((mz >> gz) & 1)) continue;
+        if (image_close(a, S, bx, by, bz, gx - a.id * a.per[0], gy - a.id * a.per[1], gz - a.id * a.per[2]))
+          return true;
+      }
+    }
+  }
+  return false;
+}
+
+template <bool CPLX>
+__device__ inline void tab_stage(const cplx<double>* __restrict__ g, double* lt, int64_t n) {
+  for (int64_t t = threadIdx.x; t < n; t += blockDim.x) {
+    const cplx<double> v = g[t];
+    if (CPLX) {
+      lt[2 * t] = v.x;
+      lt[2 * t + 1] = v.y;
+    } else {
+      lt[t] = v.x;
+    }
+  }
+  __syncthreads();
+}
+
+template <bool CPLX, bool LT>
+__device__ inline void tab_get(const cplx<double>* __restrict__ g, const double* lt, int64_t i, double& x,
+                               double& y) {
+  if constexpr (LT) {
+    if constexpr (CPLX) {
+      typedef double d2_t __attribute__((ext_vector_type(2)));
+      const d2_t v = reinterpret_cast<const d2_t*>(lt)[i];
+      x = v.x;
+      y = v.y;
+    } else {
+      x = lt[i];
+      y = 0.0;
+    }
+  } else {
+    const cplx<double> t = g[i];
+    x = t.x;
+    y = CPLX ? t.y : 0.0;
+  }
+}
+#endif
+
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
@@ -235,7 +316,9 @@ struct WorkSet {
   void* far_mom = nullptr;   // [far boxes][(qf+1)^3][planes] box moments
   void* far_q = nullptr;     // [Ngf][planes] far source grid
   void* far_u = nullptr;     // [Ngf][planes] far observer grid
-  void* far_part = nullptr;  // [splits][Ngf][planes] partial grid sums
+  void* far_part = nullptr;  // [splits][Ngf][planes] partial grid sums (direct far sum)
+  void* far_bufA = nullptr;  // [nfx][nfy][Mfz][planes] after the z pass (FFT far sum)
+  void* far_bufB = nullptr;  // [nfx][Mfy][Mfz][planes] after the y pass (FFT far sum)
 };
 
 // Arrays of the fused forward + adjoint pair beyond the plan's own workspace:
@@ -287,7 +370,11 @@ struct fftpim_plan_s {
   // tables
   void* near_hat = nullptr;       // [Mx][My][Mz] complex R, scaled by 1/(Mx My Mz)
   void* twiddle[3] = {nullptr, nullptr, nullptr};  // per axis, M/2 complex R
-  void* far_table = nullptr;      // [(2nf-1)^3] complex R
+  void* far_table = nullptr;      // [(2nf-1)^3] complex R (direct far sum)
+  bool far_fft = false;           // far grid sum as a zero-padded FFT convolution
+  int Mf[3] = {0, 0, 0};          // its transform lengths
+  void* far_hat = nullptr;        // [Mfx][Mfy][Mfz] complex R, scaled by 1/(Mfx Mfy Mfz)
+  void* ftwiddle[3] = {nullptr, nullptr, nullptr};
 
   // in-cell correction as symmetric box-pair blocks (when sym is set), the
   // CSR below then holds only the close-image part

@@ -83,6 +83,10 @@ struct FarTableArgs {
 };
 void launch_far_table_pgf2(const FarTableArgs& a, void* table, hipStream_t st);
 int launch_far_table(const FarTableArgs& a, bool npsp, void* table, hipStream_t st);
+// The far table ([2nf-1]^3 offsets, FP64) laid out as one period of the
+// circulant of length Mf >= 2 nf - 1 per axis (offset d at index d mod Mf,
+// zero where no offset lands) for the FFT far sum.
+void launch_far_circulant(const void* table, const int nf[3], const int Mf[3], void* out, hipStream_t st);
 
 struct FarArgs {
   int nf[3], nint[3], nb[3];

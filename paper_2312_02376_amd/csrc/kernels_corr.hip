@@ -19,41 +19,6 @@
 
 namespace fftpim {
 
-// Per-axis candidate source boxes of an observer box: entries (b | mask << 16)
-// where bit (i + id) of mask marks image i_c as close.
-__device__ inline void axis_range(const int32_t* __restrict__ off, int S, int& lo, int& hi) {
-  lo = off[S];
-  hi = off[S + 1];
-}
-
-// Whether image (imx, imy, imz) of the candidate source box (bx, by, bz) is
-// close to the observer box S, given that it is close axis by axis (the
-// per-axis masks hold the cube region): the image-0 term is left out when
-// only images are stored, and the ball region also tests the whole offset.
-__device__ inline bool image_close(const CorrArgs& a, const int S[3], int bx, int by, int bz, int imx, int imy,
-                                   int imz) {
-  if (a.images_only && imx == 0 && imy == 0 && imz == 0) return false;
-  return !a.ball || ball_close(a.bw, a.br2, S[0] - bx - imx * a.nint[0], S[1] - by - imy * a.nint[1],
-                               S[2] - bz - imz * a.nint[2]);
-}
-
-// Whether any image of the candidate source box is close (the per-axis masks
-// mx, my, mz: bit g marks image g - id on that axis as close axis by axis).
-__device__ inline bool any_close(const CorrArgs& a, const int S[3], int bx, int by, int bz, int mx, int my, int mz) {
-  const int A = a.nimg_axis;
-  for (int gx = 0; gx < A; ++gx) {
-    if (!((mx >> gx) & 1)) continue;
-    for (int gy = 0; gy < A; ++gy) {
-      if (!((my >> gy) & 1)) continue;
-      for (int gz = 0; gz < A; ++gz) {
-        if (!((mz >> gz) & 1)) continue;
-        if (image_close(a, S, bx, by, bz, gx - a.id * a.per[0], gy - a.id * a.per[1], gz - a.id * a.per[2]))
-          return true;
-      }
-    }
-  }
-  return false;
-}
 
 __global__ void k_corr_count(CorrArgs a, const int32_t* __restrict__ s3, const int32_t* __restrict__ box_start,
                              int64_t* __restrict__ rowcount) {
@@ -84,14 +49,16 @@ __global__ void k_corr_count(CorrArgs a, const int32_t* __restrict__ s3, const i
   rowcount[m] = cnt;
 }
 
-template <int Q, bool CPLX, bool ADJ>
-__global__ void __launch_bounds__(64) k_corr_fill(
+template <int Q, bool CPLX, bool ADJ, bool LT>
+__global__ void __launch_bounds__(256) k_corr_fill(
     CorrArgs a, const int32_t* __restrict__ s3, const double* __restrict__ u3, const double* __restrict__ pos3,
     const int32_t* __restrict__ box_start, const cplx<double>* __restrict__ g0tab,
     const int64_t* __restrict__ rowptr, int32_t* __restrict__ col, void* __restrict__ val_v,
     void* __restrict__ vadj_v) {
   const int32_t *loff0 = a.loff[0], *loff1 = a.loff[1], *loff2 = a.loff[2];
   const int32_t *lent0 = a.lent[0], *lent1 = a.lent[1], *lent2 = a.lent[2];
+  extern __shared__ double lt[];
+  if (LT) tab_stage<CPLX>(g0tab, lt, static_cast<int64_t>(a.W) * a.W * a.W);
   int64_t m = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (m >= a.N) return;
   const int64_t N = a.N;
@@ -166,13 +133,14 @@ __global__ void __launch_bounds__(64) k_corr_fill(
                   const int64_t rowx = static_cast<int64_t>(D[0] + dx + R) * W;
                   for (int dy = -Q; dy <= Q; ++dy) {
                     const double cxy = cx * C[1][dy + Q];
-                    const cplx<double>* g = g0tab + (rowx + D[1] + dy + R) * W + (D[2] + R);
+                    const int64_t toff = (rowx + D[1] + dy + R) * W + (D[2] + R);
                     double sr = 0.0, si = 0.0;
 #pragma unroll
                     for (int dz = -Q; dz <= Q; ++dz) {
-                      const cplx<double> t = g[dz];
-                      sr += C[2][dz + Q] * t.x;
-                      if (CPLX) si += C[2][dz + Q] * t.y;
+                      double tx, ty;
+                      tab_get<CPLX, LT>(g0tab, lt, toff + dz, tx, ty);
+                      sr += C[2][dz + Q] * tx;
+                      if (CPLX) si += C[2][dz + Q] * ty;
                     }
                     gr += cxy * sr;
                     gi += cxy * si;
@@ -530,11 +498,22 @@ template <int Q>
 static void fill_q(bool cplx_vals, bool adj, const CorrArgs& a, const int32_t* s3, const double* u3,
                    const double* pos3, const int32_t* box_start, const void* g0tab, const int64_t* rowptr,
                    int32_t* col, void* val, void* val_adj, hipStream_t st) {
-  unsigned nb = static_cast<unsigned>((a.N + 63) / 64);
+  // the table in LDS when it fits (blocks of 256 rows), else read from
+  // global memory (blocks of 64)
+  const size_t lds = tab_lds_bytes(a.W, cplx_vals);
+  const bool lt = lds <= kTabLdsBytes;
+  const unsigned bs = lt ? 256 : 64;
+  unsigned nb = static_cast<unsigned>((a.N + bs - 1) / bs);
   const cplx<double>* g = static_cast<const cplx<double>*>(g0tab);
-#define FFTPIM_FILL(C, J)                                                                                  \
-  hipLaunchKernelGGL((k_corr_fill<Q, C, J>), dim3(nb), dim3(64), 0, st, a, s3, u3, pos3, box_start, g,     \
-                     rowptr, col, val, val_adj)
+#define FFTPIM_FILL(C, J)                                                                                     \
+  do {                                                                                                        \
+    if (lt)                                                                                                   \
+      hipLaunchKernelGGL((k_corr_fill<Q, C, J, true>), dim3(nb), dim3(bs), lds, st, a, s3, u3, pos3,         \
+                         box_start, g, rowptr, col, val, val_adj);                                            \
+    else                                                                                                      \
+      hipLaunchKernelGGL((k_corr_fill<Q, C, J, false>), dim3(nb), dim3(bs), 0, st, a, s3, u3, pos3,          \
+                         box_start, g, rowptr, col, val, val_adj);                                            \
+  } while (0)
   if (!cplx_vals)
     FFTPIM_FILL(false, false);
   else if (adj)

@@ -98,21 +98,71 @@ __global__ void __launch_bounds__(256) k_interp_grad(GridArgs g, const double h0
   out[3 * m + 2] += gz;
 }
 
-// The correction part of the gradient, one thread per point k (plan order).
-// CPLX: complex correction values (a Helmholtz kernel or a phase shift).
-template <int Q, bool CPLX>
-__global__ void __launch_bounds__(64) k_corr_grad(CorrArgs a, const int32_t* __restrict__ s3,
-                                                  const double* __restrict__ u3, const double h0, const double h1,
-                                                  const double h2, const double* __restrict__ pos3,
-                                                  const int32_t* __restrict__ box_start,
-                                                  const cplx<double>* __restrict__ g0tab, int P,
-                                                  const void* __restrict__ q_v, const void* __restrict__ g_v,
-                                                  int single, double* __restrict__ out) {
-  const int32_t *loff0 = a.loff[0], *loff1 = a.loff[1], *loff2 = a.loff[2];
-  const int32_t *lent0 = a.lent[0], *lent1 = a.lent[1], *lent2 = a.lent[2];
-  const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (k >= a.N) return;
+// Wave-level inclusive prefix sum and total of an int, and sum of a double.
+__device__ inline int wave_incl_scan(int v, int lane) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Orders one wavefront's LDS writes before its later reads (and reads before
+// later writes): the lanes of a wave run in lockstep, so a compiler and
+// memory fence at workgroup scope is all that is needed.
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+constexpr int kGradWaves = 4;             // wavefronts per workgroup
+constexpr int kGradBPL = 2;               // candidate source boxes per lane per chunk
+constexpr int kGradCH = 64 * kGradBPL;    // candidate boxes per chunk
+constexpr int kGradPPW = 8;               // observer points per wavefront
+constexpr int kGradListInts = 3 * kGradCH + 1;  // per-wave LDS list (prefix, first point, candidate)
+constexpr int kGradWDoubles = 6 * 16;           // per-wave LDS weights of k: w[3][Q+1], dw[3][Q+1], Q < 16
+
+inline size_t grad_list_bytes() {
+  return static_cast<size_t>(kGradWaves) * (kGradListInts * sizeof(int) + kGradWDoubles * sizeof(double));
+}
+
+// The correction part of the gradient.  One wavefront per point k (plan
+// order; kGradPPW points in turn); its candidate source boxes (the product
+// of the three per-axis lists) are taken kGradCH at a time: every lane
+// counts the points of kGradBPL boxes, a wave prefix sum lays the chunk's
+// pairs out, and the pairs are then processed 64 at a time, one per lane
+// (lane t finds its box by binary search over the prefix), so the lanes stay
+// busy whatever the box occupancy.  The G0 table is read from LDS when LT.
+template <int Q, bool CPLX, bool LT>
+__global__ void __launch_bounds__(64 * kGradWaves) k_corr_grad(
+    CorrArgs a, const int32_t* __restrict__ s3, const double* __restrict__ u3, const double h0, const double h1,
+    const double h2, const double* __restrict__ pos3, const int32_t* __restrict__ box_start,
+    const cplx<double>* __restrict__ g0tab, int P, const void* __restrict__ q_v, const void* __restrict__ g_v,
+    int single, double* __restrict__ out) {
+  extern __shared__ __align__(16) double lt[];
+  const int64_t tabn = static_cast<int64_t>(a.W) * a.W * a.W;
+  if (LT) tab_stage<CPLX>(g0tab, lt, tabn);
+  double* wlds = lt + (LT ? tabn * (CPLX ? 2 : 1) : 0);
+  int* lists = reinterpret_cast<int*>(wlds + kGradWaves * kGradWDoubles);
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+  const int lane = static_cast<int>(threadIdx.x) & 63;
+  // the weights of k and their derivatives (the same for every lane) live in
+  // LDS, read as broadcasts, to keep registers for the per-pair arrays
+  double* wk = wlds + wave * kGradWDoubles;  // [3][Q + 1]
+  double* dk = wk + 3 * (Q + 1);             // [3][Q + 1]
+  int* pre = lists + wave * kGradListInts;  // [kGradCH + 1] pair offsets of the chunk's boxes
+  int* cn0 = pre + kGradCH + 1;             // [kGradCH] first point of each box
+  int* ccd = cn0 + kGradCH;                 // [kGradCH] candidate index of each box
   const int64_t N = a.N;
+  const int A = a.nimg_axis, W = a.W, R = a.R;
   // amplitudes: complex planes of FP64 (single = 0) or FP32 (single = 1)
   auto ampl = [&](const void* v, int64_t pt, int p, double& re, double& im) {
     if (single) {
@@ -125,47 +175,98 @@ __global__ void __launch_bounds__(64) k_corr_grad(CorrArgs a, const int32_t* __r
       im = x.y;
     }
   };
-  const int S[3] = {s3[k], s3[N + k], s3[2 * N + k]};
-  double wk[3][Q + 1], dk[3][Q + 1];
-  lagrange_with_deriv<Q>(u3[k], wk[0], dk[0]);
-  lagrange_with_deriv<Q>(u3[N + k], wk[1], dk[1]);
-  lagrange_with_deriv<Q>(u3[2 * N + k], wk[2], dk[2]);
-  const double hh[3] = {h0, h1, h2};
-  for (int c = 0; c < 3; ++c)
-    for (int t = 0; t <= Q; ++t) dk[c][t] /= hh[c];
-  const double rk[3] = {pos3[k], pos3[N + k], pos3[2 * N + k]};
-  int lo[3], hi[3];
-  lo[0] = loff0[S[0]];
-  hi[0] = loff0[S[0] + 1];
-  lo[1] = loff1[S[1]];
-  hi[1] = loff1[S[1] + 1];
-  lo[2] = loff2[S[2]];
-  hi[2] = loff2[S[2] + 1];
-  const int A = a.nimg_axis, W = a.W, R = a.R;
-  double gx = 0.0, gy = 0.0, gz = 0.0;
-  for (int ix = lo[0]; ix < hi[0]; ++ix) {
-    const int bx = lent0[ix] & 0xffff, mx = lent0[ix] >> 16;
-    for (int iy = lo[1]; iy < hi[1]; ++iy) {
-      const int by = lent1[iy] & 0xffff, my = lent1[iy] >> 16;
-      for (int iz = lo[2]; iz < hi[2]; ++iz) {
-        const int bz = lent2[iz] & 0xffff, mz = lent2[iz] >> 16;
-        const int64_t b = (static_cast<int64_t>(bx) * a.nb[1] + by) * a.nb[2] + bz;
-        const int n0 = box_start[b], n1 = box_start[b + 1];
-        for (int n = n0; n < n1; ++n) {
+  for (int pp = 0; pp < kGradPPW; ++pp) {
+    const int64_t k = (static_cast<int64_t>(blockIdx.x) * kGradWaves + wave) * kGradPPW + pp;
+    if (k >= N) break;
+    const int S[3] = {s3[k], s3[N + k], s3[2 * N + k]};
+    if (lane < 3) {
+      double w[Q + 1], dw[Q + 1];
+      lagrange_with_deriv<Q>(u3[lane * N + k], w, dw);
+      const double hc = lane == 0 ? h0 : (lane == 1 ? h1 : h2);
+#pragma unroll
+      for (int t = 0; t <= Q; ++t) {
+        wk[lane * (Q + 1) + t] = w[t];
+        dk[lane * (Q + 1) + t] = dw[t] / hc;
+      }
+    }
+    wave_lds_sync();
+    const double rk[3] = {pos3[k], pos3[N + k], pos3[2 * N + k]};
+    int lo[3], hi[3];
+    axis_range(a.loff[0], S[0], lo[0], hi[0]);
+    axis_range(a.loff[1], S[1], lo[1], hi[1]);
+    axis_range(a.loff[2], S[2], lo[2], hi[2]);
+    const int Ly = hi[1] - lo[1], Lz = hi[2] - lo[2];
+    const int ncand = (hi[0] - lo[0]) * Ly * Lz;
+    double gx = 0.0, gy = 0.0, gz = 0.0;
+    for (int c0 = 0; c0 < ncand; c0 += kGradCH) {
+      int cnt[kGradBPL], n0[kGradBPL];
+      int sum = 0;
+#pragma unroll
+      for (int i = 0; i < kGradBPL; ++i) {
+        const int c = c0 + lane * kGradBPL + i;
+        cnt[i] = 0;
+        n0[i] = 0;
+        if (c < ncand) {
+          const int ex = a.lent[0][lo[0] + c / (Ly * Lz)], ey = a.lent[1][lo[1] + (c / Lz) % Ly],
+                    ez = a.lent[2][lo[2] + c % Lz];
+          const int bx = ex & 0xffff, by = ey & 0xffff, bz = ez & 0xffff;
+          if (any_close(a, S, bx, by, bz, ex >> 16, ey >> 16, ez >> 16)) {
+            const int64_t b = (static_cast<int64_t>(bx) * a.nb[1] + by) * a.nb[2] + bz;
+            n0[i] = box_start[b];
+            cnt[i] = box_start[b + 1] - n0[i];
+          }
+        }
+        sum += cnt[i];
+      }
+      const int incl = wave_incl_scan(sum, lane);
+      const int tot = __shfl(incl, 63, 64);
+      int run = incl - sum;
+#pragma unroll
+      for (int i = 0; i < kGradBPL; ++i) {
+        pre[lane * kGradBPL + i] = run;
+        cn0[lane * kGradBPL + i] = n0[i];
+        ccd[lane * kGradBPL + i] = c0 + lane * kGradBPL + i;
+        run += cnt[i];
+      }
+      if (lane == 0) pre[kGradCH] = tot;
+      wave_lds_sync();
+      for (int t0 = 0; t0 < tot; t0 += 64) {
+        const int t = t0 + lane;
+        if (t < tot) {
+          // the box holding pair t: the largest i with pre[i] <= t (it has
+          // at least one point since pre[i + 1] > t)
+          int ilo = 0, ihi = kGradCH - 1;
+          while (ilo < ihi) {
+            const int mid = (ilo + ihi + 1) >> 1;
+            if (pre[mid] <= t) ilo = mid;
+            else ihi = mid - 1;
+          }
+          const int n = cn0[ilo] + (t - pre[ilo]);
+          const int c = ccd[ilo];
+          const int ex = a.lent[0][lo[0] + c / (Ly * Lz)], ey = a.lent[1][lo[1] + (c / Lz) % Ly],
+                    ez = a.lent[2][lo[2] + c % Lz];
+          const int bx = ex & 0xffff, by = ey & 0xffff, bz = ez & 0xffff;
+          const int mx = ex >> 16, my = ey >> 16, mz = ez >> 16;
           double wn[3][Q + 1];
-          for (int c = 0; c < 3; ++c) lagrange_all<Q, double>(u3[c * N + n], wn[c]);
+#pragma unroll
+          for (int cc = 0; cc < 3; ++cc) lagrange_all<Q, double>(u3[cc * N + n], wn[cc]);
           // correlations C_c(d) = sum_a w_a(k) w_{a-d}(n) and their
-          // derivatives along axis c (weights of k differentiated)
+          // derivatives along axis c (weights of k differentiated); every
+          // loop over these small arrays is unrolled so they stay in registers
           double C[3][2 * Q + 1], Cd[3][2 * Q + 1];
-          for (int c = 0; c < 3; ++c)
+#pragma unroll
+          for (int cc = 0; cc < 3; ++cc)
+#pragma unroll
             for (int d = -Q; d <= Q; ++d) {
-              double s = 0.0, sd = 0.0;
-              for (int aa = max(0, d); aa <= min(Q, Q + d); ++aa) {
-                s += wk[c][aa] * wn[c][aa - d];
-                sd += dk[c][aa] * wn[c][aa - d];
+              double sw = 0.0, sd = 0.0;
+#pragma unroll
+              for (int aa = 0; aa <= Q; ++aa) {
+                if (aa - d < 0 || aa - d > Q) continue;
+                sw += wk[cc * (Q + 1) + aa] * wn[cc][aa - d];
+                sd += dk[cc * (Q + 1) + aa] * wn[cc][aa - d];
               }
-              C[c][d + Q] = s;
-              Cd[c][d + Q] = sd;
+              C[cc][d + Q] = sw;
+              Cd[cc][d + Q] = sd;
             }
           // the pair's amplitude products over the planes:
           // s1 = sum_p conj(g_k) q_n (observer side), s2 = sum_p conj(g_n) q_k (source side)
@@ -191,13 +292,11 @@ __global__ void __launch_bounds__(64) k_corr_grad(CorrArgs a, const int32_t* __r
               for (int gzi = 0; gzi < A; ++gzi) {
                 if (!((mz >> gzi) & 1)) continue;
                 const int imz = gzi - a.id * a.per[2];
-                if (a.ball && !ball_close(a.bw, a.br2, S[0] - bx - imx * a.nint[0], S[1] - by - imy * a.nint[1],
-                                          S[2] - bz - imz * a.nint[2]))
-                  continue;
+                if (!image_close(a, S, bx, by, bz, imx, imy, imz)) continue;
                 const int D[3] = {S[0] - bx - imx * a.nint[0], S[1] - by - imy * a.nint[1],
                                   S[2] - bz - imz * a.nint[2]};
                 // exact part: grad G0(d), d = r_k - r_n - R_j (dropped for the self pair)
-                double ex[3][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+                double ex3[3][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
                 if (!(n == k && imx == 0 && imy == 0 && imz == 0)) {
                   const double d0 = rk[0] - rn[0] - imx * a.L[0];
                   const double d1 = rk[1] - rn[1] - imy * a.L[1];
@@ -211,29 +310,36 @@ __global__ void __launch_bounds__(64) k_corr_grad(CorrArgs a, const int32_t* __r
                   const double fr = a.k0_im - 1.0 / r, fi = -a.k0;  // -j k0 - 1/r
                   const double dgr = g0r * fr - g0i * fi, dgi = g0r * fi + g0i * fr;
                   const double dd[3] = {d0, d1, d2};
-                  for (int c = 0; c < 3; ++c) {
-                    ex[c][0] = dgr * dd[c] / r;
-                    ex[c][1] = CPLX ? dgi * dd[c] / r : 0.0;
+#pragma unroll
+                  for (int cc = 0; cc < 3; ++cc) {
+                    ex3[cc][0] = dgr * dd[cc] / r;
+                    ex3[cc][1] = CPLX ? dgi * dd[cc] / r : 0.0;
                   }
                 }
                 // grid part: three components of sum_d C C C G0tab(D + d),
                 // one factor differentiated
                 double pyr = 0.0, pyi = 0.0, pzr = 0.0, pzi = 0.0;
                 double gridx_r = 0.0, gridx_i = 0.0;
+                // x stays a loop (bounding the loads in flight, hence the
+                // registers); its two weights are picked by selects, not by
+                // a run-time index, so C and Cd stay in registers
+#pragma nounroll
                 for (int ddx = -Q; ddx <= Q; ++ddx) {
                   const int64_t rowx = static_cast<int64_t>(D[0] + ddx + R) * W;
                   double ar = 0.0, ai = 0.0, ayr = 0.0, ayi = 0.0, azr = 0.0, azi = 0.0;
+#pragma unroll
                   for (int ddy = -Q; ddy <= Q; ++ddy) {
-                    const cplx<double>* tab = g0tab + (rowx + D[1] + ddy + R) * W + (D[2] + R);
+                    const int64_t toff = (rowx + D[1] + ddy + R) * W + (D[2] + R);
                     double sr = 0.0, si = 0.0, sdr = 0.0, sdi = 0.0;
 #pragma unroll
                     for (int ddz = -Q; ddz <= Q; ++ddz) {
-                      const cplx<double> t = tab[ddz];
-                      sr += C[2][ddz + Q] * t.x;
-                      sdr += Cd[2][ddz + Q] * t.x;
+                      double tx, ty;
+                      tab_get<CPLX, LT>(g0tab, lt, toff + ddz, tx, ty);
+                      sr += C[2][ddz + Q] * tx;
+                      sdr += Cd[2][ddz + Q] * tx;
                       if (CPLX) {
-                        si += C[2][ddz + Q] * t.y;
-                        sdi += Cd[2][ddz + Q] * t.y;
+                        si += C[2][ddz + Q] * ty;
+                        sdi += Cd[2][ddz + Q] * ty;
                       }
                     }
                     const double cy = C[1][ddy + Q], cdy = Cd[1][ddy + Q];
@@ -244,7 +350,12 @@ __global__ void __launch_bounds__(64) k_corr_grad(CorrArgs a, const int32_t* __r
                     azr += cy * sdr;
                     azi += cy * sdi;
                   }
-                  const double cx = C[0][ddx + Q], cdx = Cd[0][ddx + Q];
+                  double cx = 0.0, cdx = 0.0;
+#pragma unroll
+                  for (int t = 0; t <= 2 * Q; ++t) {
+                    cx = (t == ddx + Q) ? C[0][t] : cx;
+                    cdx = (t == ddx + Q) ? Cd[0][t] : cdx;
+                  }
                   gridx_r += cdx * ar;
                   gridx_i += cdx * ai;
                   pyr += cx * ayr;
@@ -252,8 +363,8 @@ __global__ void __launch_bounds__(64) k_corr_grad(CorrArgs a, const int32_t* __r
                   pzr += cx * azr;
                   pzi += cx * azi;
                 }
-                const double xr_[3] = {ex[0][0] - gridx_r, ex[1][0] - pyr, ex[2][0] - pzr};
-                const double xi_[3] = {ex[0][1] - gridx_i, ex[1][1] - pyi, ex[2][1] - pzi};
+                const double xr_[3] = {ex3[0][0] - gridx_r, ex3[1][0] - pyr, ex3[2][0] - pzr};
+                const double xi_[3] = {ex3[0][1] - gridx_i, ex3[1][1] - pyi, ex3[2][1] - pzi};
                 // phases of image j and of image -j
                 const int pidx = (gxi * A + gyi) * A + gzi;
                 const int nidx = ((a.per[0] ? A - 1 - gxi : gxi) * A + (a.per[1] ? A - 1 - gyi : gyi)) * A +
@@ -277,11 +388,18 @@ __global__ void __launch_bounds__(64) k_corr_grad(CorrArgs a, const int32_t* __r
           }
         }
       }
+      wave_lds_sync();
     }
+    gx = wave_sum(gx);
+    gy = wave_sum(gy);
+    gz = wave_sum(gz);
+    if (lane == 0) {
+      out[3 * k] += gx;
+      out[3 * k + 1] += gy;
+      out[3 * k + 2] += gz;
+    }
+    wave_lds_sync();
   }
-  out[3 * k] += gx;
-  out[3 * k + 1] += gy;
-  out[3 * k + 2] += gz;
 }
 
 __global__ void k_unpermute3(const double* __restrict__ in, const int32_t* __restrict__ perm, int64_t N, int use_perm,
@@ -325,16 +443,26 @@ int launch_interp_grad(int q, const GridArgs& g, const double h[3], const int32_
 int launch_corr_grad(int q, bool cplx_vals, const CorrArgs& a, const int32_t* s3, const double* u3, const double h[3],
                      const double* pos3, const int32_t* box_start, const void* g0tab, int P, const void* qint,
                      const void* gint, bool single, double* out, hipStream_t st) {
-  const dim3 gr(static_cast<unsigned>((a.N + 63) / 64));
-  const cplx<double>* tab = static_cast<const cplx<double>*>(g0tab);
-#define FFTPIM_CG(QV)                                                                                           \
-  do {                                                                                                          \
-    if (cplx_vals)                                                                                              \
-      hipLaunchKernelGGL((k_corr_grad<QV, true>), gr, dim3(64), 0, st, a, s3, u3, h[0], h[1], h[2], pos3,        \
-                         box_start, tab, P, qint, gint, single ? 1 : 0, out);                                   \
-    else                                                                                                        \
-      hipLaunchKernelGGL((k_corr_grad<QV, false>), gr, dim3(64), 0, st, a, s3, u3, h[0], h[1], h[2], pos3,       \
-                         box_start, tab, P, qint, gint, single ? 1 : 0, out);                                   \
+  // the table in LDS beside the wave lists when both fit, else read from
+  // global memory
+  const size_t tab = tab_lds_bytes(a.W, cplx_vals);
+  const bool lt = tab + grad_list_bytes() <= kTabLdsBytes;
+  const size_t lds = (lt ? tab : 0) + grad_list_bytes();
+  const int64_t per_block = static_cast<int64_t>(kGradWaves) * kGradPPW;
+  const dim3 gr(static_cast<unsigned>((a.N + per_block - 1) / per_block));
+  const cplx<double>* tab_d = static_cast<const cplx<double>*>(g0tab);
+#define FFTPIM_CG1(QV, CV, LV)                                                                                  \
+  hipLaunchKernelGGL((k_corr_grad<QV, CV, LV>), gr, dim3(64 * kGradWaves), lds, st, a, s3, u3, h[0], h[1], h[2], \
+                     pos3, box_start, tab_d, P, qint, gint, single ? 1 : 0, out)
+#define FFTPIM_CG(QV)                                  \
+  do {                                                 \
+    if (cplx_vals) {                                   \
+      if (lt) FFTPIM_CG1(QV, true, true);              \
+      else FFTPIM_CG1(QV, true, false);                \
+    } else {                                           \
+      if (lt) FFTPIM_CG1(QV, false, true);             \
+      else FFTPIM_CG1(QV, false, false);               \
+    }                                                  \
   } while (0)
   switch (q) {
     case 1: FFTPIM_CG(1); break;
@@ -348,6 +476,7 @@ int launch_corr_grad(int q, bool cplx_vals, const CorrArgs& a, const int32_t* s3
     default: return FFTPIM_ERR_UNSUPPORTED;
   }
 #undef FFTPIM_CG
+#undef FFTPIM_CG1
   return FFTPIM_OK;
 }
 

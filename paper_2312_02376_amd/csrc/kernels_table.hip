@@ -375,4 +375,27 @@ int launch_far_table(const FarTableArgs& a, bool npsp, void* table, hipStream_t 
   return FFTPIM_OK;
 }
 
+__global__ void k_far_circulant(const cplx<double>* __restrict__ table, int nf0, int nf1, int nf2, int M0, int M1,
+                                int M2, cplx<double>* __restrict__ out) {
+  const int64_t total = static_cast<int64_t>(M0) * M1 * M2;
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int i2 = static_cast<int>(idx % M2);
+  const int i1 = static_cast<int>((idx / M2) % M1);
+  const int i0 = static_cast<int>(idx / (static_cast<int64_t>(M1) * M2));
+  // index i holds offset i (i < nf) or i - M (the negative offsets)
+  const int e0 = i0 < nf0 ? i0 : i0 - M0, e1 = i1 < nf1 ? i1 : i1 - M1, e2 = i2 < nf2 ? i2 : i2 - M2;
+  cplx<double> v = cmake<double>(0.0, 0.0);
+  if (e0 > -nf0 && e1 > -nf1 && e2 > -nf2)
+    v = table[((static_cast<int64_t>(e0 + nf0 - 1) * (2 * nf1 - 1)) + e1 + nf1 - 1) * (2 * nf2 - 1) + e2 + nf2 - 1];
+  out[idx] = v;
+}
+
+void launch_far_circulant(const void* table, const int nf[3], const int Mf[3], void* out, hipStream_t st) {
+  const int64_t total = static_cast<int64_t>(Mf[0]) * Mf[1] * Mf[2];
+  hipLaunchKernelGGL(k_far_circulant, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0, st,
+                     static_cast<const cplx<double>*>(table), nf[0], nf[1], nf[2], Mf[0], Mf[1], Mf[2],
+                     static_cast<cplx<double>*>(out));
+}
+
 }  // namespace fftpim

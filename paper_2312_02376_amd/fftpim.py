@@ -52,7 +52,7 @@ class Params(ctypes.Structure):
                 ("far_n", ctypes.c_int * 3), ("far_order", ctypes.c_int), ("n_images", ctypes.c_int),
                 ("precision", ctypes.c_int), ("value_type", ctypes.c_int), ("self_mode", ctypes.c_int),
                 ("order_io", ctypes.c_int), ("nrhs_max", ctypes.c_int), ("corr_layout", ctypes.c_int),
-                ("max_bytes", ctypes.c_size_t), ("corr_ball", ctypes.c_double)]
+                ("max_bytes", ctypes.c_size_t), ("corr_ball", ctypes.c_double), ("far_sum", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -64,7 +64,7 @@ class Info(ctypes.Structure):
                 ("corr_tile_values", ctypes.c_int64),
                 ("corr_value_bytes", ctypes.c_int), ("corr_layout_used", ctypes.c_int),
                 ("device_bytes", ctypes.c_int64), ("nplanes_max", ctypes.c_int),
-                ("plan_seconds", ctypes.c_double)]
+                ("plan_seconds", ctypes.c_double), ("far_fft", ctypes.c_int * 3)]
 
 
 _lib = None
@@ -168,13 +168,14 @@ class Plan:
     The remaining arguments map one-to-one onto fftpim_problem_t and
     fftpim_params_t (include/fftpim.h); precision is "f64", "f32",
     "f32_farbf16" (FP32 with a bfloat16-input far grid sum) or
-    "f32_farbf16x3" (the same with split three-product bfloat16 terms).
+    "f32_farbf16x3" (the same with split three-product bfloat16 terms);
+    far_sum is "auto", "direct" or "fft" (the far grid sum of Eq. (8)).
     """
 
     def __init__(self, positions, periodic_dims, L, k0=0.0, kt=(0.0, 0.0, 0.0), near_n=(16, 16, 16),
                  near_order=4, corr_radius=6, far_n=(16, 16, 16), far_order=7, n_images=1, precision="f64",
                  value_type="complex", order="user", nrhs_max=1, box=None, self_mode="images",
-                 corr_layout="auto", max_bytes=0, corr_ball=0.0, stream=None):
+                 corr_layout="auto", max_bytes=0, corr_ball=0.0, far_sum="auto", stream=None):
         import torch
         if not (isinstance(positions, torch.Tensor) and positions.is_cuda and positions.dtype == torch.float64):
             raise TypeError("positions must be a CUDA float64 tensor of shape (N, 3)")
@@ -198,6 +199,7 @@ class Plan:
         pm.corr_layout = {"auto": 0, "csr": 1, "sym": 2, "tile": 3}[corr_layout]
         pm.max_bytes = int(max_bytes)
         pm.corr_ball = float(corr_ball)
+        pm.far_sum = {"auto": 0, "direct": 1, "fft": 2}[far_sum]
         self.params = pm
         self.precision = precision
         self.value_type = value_type

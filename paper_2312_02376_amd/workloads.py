@@ -163,3 +163,9 @@ def dynamic_cube(n, seed, D=100.0):
     rng = np.random.default_rng(seed)
     pos = 0.5 + rng.random((n, 3)) * D
     return pos, gaussian_complex(1, n, seed)[0]
+
+
+def dynamic_cube_k0(n, D=100.0):
+    """Free-space wavenumber of the dynamic runs of Sec. 4.2: the mean point
+    spacing D / n^(1/3) is a twentieth of the wavelength."""
+    return 2.0 * np.pi / (20.0 * D / n ** (1.0 / 3.0))

@@ -4,7 +4,7 @@ Every value is computed by the FP64 direct-sum oracle (oracle.psp) on the
 seeded inputs of paper_2312_02376_amd.workloads; nothing here touches the GPU
 library.  Run from the repository root:
 
-    python tests/golden/make_golden.py [coulomb_1k] [helmholtz_100k] [coulomb_1m]
+    python tests/golden/make_golden.py [coulomb_1k] [helmholtz_100k] [coulomb_1m] [dynamic_cube_20k]
 """
 import os
 import sys
@@ -64,7 +64,27 @@ def coulomb_1m(nrows=128):
           "(workloads.coulomb_cube_1m_batched);\nexact u at sampled rows.\ncolumns: row, rhs, u", cols)
 
 
+def dynamic_cube_20k(nrows=32):
+    # Sec. 4.2 (Fig. complex_real): a 100^3 cube of points in a 3D-periodic
+    # cell of period 101, k0 chosen so that the mean spacing is lambda/20,
+    # phase wavenumbers 0.01 - 0.01j on every axis; the static (NPSP)
+    # counterpart uses neutral real strengths on the same points
+    src, q = W.dynamic_cube(20000, 8)
+    k0 = W.dynamic_cube_k0(len(src))
+    lat = P.Lattice(3, [101.0] * 3, k0, [0.01 - 0.01j] * 3)
+    rows = np.sort(np.random.default_rng(13).choice(len(src), nrows, replace=False))
+    u = psp_forward(lat, src, q.astype(np.complex128), obs_index=rows, workers=host_workers())
+    qs = W.gaussian_neutral(1, len(src), 8)[0]
+    us = psp_forward(P.Lattice(3, [101.0] * 3), src, qs, obs_index=rows, workers=host_workers())
+    _save("dynamic_cube_20k_rows.txt",
+          "3D-periodic cell of period 101, 20000 points uniform in a centred 100^3 cube (workloads.dynamic_cube(20000, 8));\n"
+          "dynamic: k0 = workloads.dynamic_cube_k0(20000), kt = (0.01 - 0.01j)(1, 1, 1), strengths of dynamic_cube;\n"
+          "static: k0 = 0, kt = 0, strengths workloads.gaussian_neutral(1, 20000, 8).\n"
+          "exact u at sampled rows. columns: row, Re u_dyn, Im u_dyn, u_static",
+          [rows, u.real, u.imag, us.real])
+
+
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["coulomb_1k", "helmholtz_100k", "coulomb_1m"]
+    which = sys.argv[1:] or ["coulomb_1k", "helmholtz_100k", "coulomb_1m", "dynamic_cube_20k"]
     for w in which:
         globals()[w]()

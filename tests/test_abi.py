@@ -58,10 +58,12 @@ CUBE = dict(periodic_dims=3, L=[1.0, 1.0, 1.0])
 
 @pytest.mark.parametrize("kw,code", [
     (dict(near_order=0), 1), (dict(near_order=9), 1), (dict(far_order=10), 1),
-    (dict(near_n=(12, 16, 16)), 1),          # 2n must be a power of two
+    (dict(near_n=(5, 16, 16)), 1),           # at least near_order + 2 nodes
+    (dict(near_n=(16, 2049, 16)), 1),        # at most 2048 nodes
     (dict(corr_radius=2), 1),                 # r_c >= q is required
     (dict(n_images=3), 1), (dict(precision=5), 1), (dict(nrhs_max=0), 1),
-    (dict(self_mode=2), 1),
+    (dict(self_mode=2), 1), (dict(far_sum=3), 1),
+    (dict(far_sum=2, precision=2), 1),       # the BF16 far modes are direct sums
 ])
 def test_parameter_validation(kw, code):
     assert _plan_status(CUBE, **kw) == code

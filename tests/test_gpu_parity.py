@@ -46,6 +46,11 @@ CASES = {
                     (16, 16, 8), 4, 4, (10, 10, 8), 5),
     "phase1_cstatic": (dict(dims=1, L=[1.0], k0=0.0, kt=[0.9 - 0.4j]), "rod", 1, "complex", (16, 8, 8), 3, 3,
                        (10, 8, 8), 4),
+    # near grids that are not powers of two (Sec. 4.2, Table near-zone:
+    # 17^3 upwards); the transforms pad to the next power of two >= 2n - 1
+    "npsp3_odd": (dict(dims=3, L=[1, 1, 1]), "cube", 3, "real", (17, 17, 17), 4, 5, (10, 10, 10), 5),
+    "helm2_odd": (dict(dims=2, L=[1, 1], k0=TWO_PI, kt=[0.3 * TWO_PI, 0.1 * TWO_PI]), "surface", 2, "complex",
+                  (20, 24, 11), 4, 4, (10, 10, 8), 5),
 }
 
 
@@ -67,7 +72,7 @@ def _points(kind, N, seed):
 
 
 def _setup(name, N=257, seed=31, precision="f64", nrhs=None, corr_layout="auto", self_mode="images",
-           corr_ball=0.0):
+           corr_ball=0.0, far_sum="auto"):
     latkw, kind, nrhs0, vt, nn, q, rc, nf, qf = CASES[name]
     nrhs = nrhs0 if nrhs is None else nrhs
     lat = P.Lattice(latkw["dims"], latkw["L"], latkw.get("k0", 0.0), latkw.get("kt", [0, 0, 0]))
@@ -86,7 +91,7 @@ def _setup(name, N=257, seed=31, precision="f64", nrhs=None, corr_layout="auto",
     plan = fp.Plan(pos, latkw["dims"], latkw["L"], k0=latkw.get("k0", 0.0), kt=latkw.get("kt", [0, 0, 0]),
                    near_n=nn, near_order=q, corr_radius=rc, far_n=nf, far_order=qf, n_images=1,
                    precision=precision, value_type=vt, nrhs_max=max(4, nrhs), corr_layout=corr_layout,
-                   self_mode=self_mode, corr_ball=corr_ball)
+                   self_mode=self_mode, corr_ball=corr_ball, far_sum=far_sum)
     return lat, ref, plan, qv
 
 
@@ -127,6 +132,33 @@ def test_full_apply_and_adjoint(name):
         # only the zero-mean part of A^H v is defined for the neutral static case
         want = want - want.mean(axis=-1, keepdims=True)
     assert rel(w, want) < 1e-11
+
+
+@pytest.mark.parametrize("name", ["npsp3_real", "helm2_bloch", "helm1_bloch", "coax_dyn", "helm3_cphase", "npsp1_real",
+                                  "npsp2_real", "helm2_odd"])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_far_sum_by_fft(name, precision):
+    # the far grid sum of Eq. (8) as a zero-padded FFT convolution: the far
+    # part against the oracle's term-by-term sum, forward and adjoint, and
+    # against the library's direct sum on the same plan parameters
+    print("case", name, precision, flush=True)
+    lat, ref, plan, qv = _setup(name, precision=precision, far_sum="fft")
+    _, _, plan_d, _ = _setup(name, precision=precision, far_sum="direct")
+    info = plan.info()
+    nf = CASES[name][7]
+    assert all(m >= 2 * n - 1 and (m & (m - 1)) == 0 for m, n in zip(info["far_fft"], nf)), info["far_fft"]
+    assert plan_d.info()["far_fft"] == [0, 0, 0]
+    qd = _to_dev(plan, qv)
+    tol = 1e-11 if precision == "f64" else 2e-5
+    for adjoint in (False, True):
+        got = plan.apply_parts(qd, PARTS["far"], adjoint=adjoint).cpu().numpy()
+        direct = plan_d.apply_parts(qd, PARTS["far"], adjoint=adjoint).cpu().numpy()
+        want = (ref.adjoint if adjoint else ref.apply)(qv, parts=("far",))
+        e, ed = rel(got, want), rel(got, direct)
+        print("  adjoint", adjoint, "vs oracle %.2e vs direct %.2e" % (e, ed), flush=True)
+        assert e < tol and ed < tol
+    plan.close()
+    plan_d.close()
 
 
 @pytest.mark.parametrize("name", ["npsp3_real", "helm2_bloch"])
