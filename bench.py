@@ -237,7 +237,9 @@ def main():
     ap.add_argument("--oracle-rows", type=int, default=24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="helmholtz_100k",
-                    choices=["helmholtz_100k"] + sorted(SECONDARY))
+                    choices=["helmholtz_100k", "multicell_48"] + sorted(SECONDARY))
+    ap.add_argument("--target", type=float, default=1e-4, help="error target of the multi-cell parameter choice")
+    ap.add_argument("--lanes", type=int, default=4, help="streams of the multi-cell batch")
     ap.add_argument("--no-batched", action="store_true", help="skip the nested 1M-point batched record")
     ap.add_argument("--no-forces", action="store_true", help="skip the nested 2M-point position-gradient record")
     ap.add_argument("--no-separate", action="store_true",
@@ -263,6 +265,9 @@ def main():
         print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 3}))
         return
 
+    if args.workload == "multicell_48":
+        print(json.dumps(multicell_record(args)), flush=True)
+        return
     if args.workload != "helmholtz_100k":
         run_secondary(args, args.workload)
         return
@@ -408,6 +413,101 @@ def main():
     if not args.no_forces:
         result["forces"] = forces_record(args)
     print(json.dumps(result), flush=True)
+
+
+def multicell_record(args):
+    """48 independent cells (N log-uniform in [5e3, 5e5], 5.9M points in all;
+    1D, 2D and 3D periodicity; static and Helmholtz; Gaussian blobs; complex
+    strengths): parameters per cell from fftpim_autotune for the error target
+    in FP32 (FP64 correction), one step = one fftpim_batch_apply over all
+    cells; also timed as one lane (cells in turn) and as separate applies."""
+    import numpy as np
+    import torch
+
+    from paper_2312_02376_amd import fftpim as fp
+    from paper_2312_02376_amd import workloads as W
+    fp.lib()
+    dev = torch.device("cuda:0")
+    cells = W.multi_cell(48, 4)
+    plans, ins, tune_s, plan_s, preds, infos = [], [], 0.0, 0.0, [], []
+    for c, cell in enumerate(cells):
+        pos = torch.tensor(cell["pos"], device=dev)
+        t0 = time.perf_counter()
+        kw, rep = fp.autotune(pos, cell["dims"], cell["L"], args.target, k0=cell["k0"], kt=cell["kt"],
+                              precision="f32")
+        t1 = time.perf_counter()
+        plan = fp.Plan(pos, cell["dims"], cell["L"], k0=cell["k0"], kt=cell["kt"], order="plan", **kw)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        tune_s += t1 - t0
+        plan_s += t2 - t1
+        perm = plan.permutation().long()
+        ins.append(torch.tensor(cell["q"], dtype=torch.complex64, device=dev)[perm].contiguous())
+        plans.append(plan)
+        preds.append(rep)
+        inf = plan.info()
+        infos.append(dict(N=len(cell["q"]), dims=cell["dims"], k0=cell["k0"], near_n=list(kw["near_n"]),
+                          q=kw["near_order"], corr_ball=round(kw["corr_ball"], 2), far_n=list(kw["far_n"]),
+                          far_order=kw["far_order"], corr_nnz=inf["corr_nnz"],
+                          predicted_rel_err=rep["predicted_rel_err"]))
+        print("cell %d N %d dims %d k0 %.2f tuned in %.2fs planned in %.2fs" %
+              (c, len(cell["q"]), cell["dims"], cell["k0"], t1 - t0, t2 - t1), flush=True)
+    outs = [torch.empty_like(x) for x in ins]
+    Ntot = sum(len(c["q"]) for c in cells)
+
+    def timed(fn, steps, warm):
+        for _ in range(warm):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps
+
+    steps = max(3, args.steps // 4)
+    batch = fp.Batch(plans, lanes=args.lanes)
+    ms = timed(lambda: batch.apply(ins, outs), steps, 1)
+    one = fp.Batch(plans, lanes=1)
+    ms_one = timed(lambda: one.apply(ins, outs), steps, 1)
+    ms_sep = timed(lambda: [p.apply(x, out=o) for p, x, o in zip(plans, ins, outs)], steps, 1)
+    batch.apply(ins, outs)
+    torch.cuda.synchronize()
+    # accuracy on the stored exact rows (plan order: the row's position in
+    # the plan's permutation)
+    errs = []
+    gpath = os.path.join(ROOT, "tests", "golden", "multi_cell_48_rows.txt")
+    if os.path.exists(gpath):
+        g = np.loadtxt(gpath)
+        for c, plan in enumerate(plans):
+            sel = g[:, 0] == c
+            rows = g[sel, 1].astype(np.int64)
+            inv = torch.empty_like(plan.permutation().long())
+            perm = plan.permutation().long()
+            inv[perm] = torch.arange(len(perm), device=dev)
+            u = outs[c][inv[torch.tensor(rows, device=dev)]].cpu().numpy()
+            ex = g[sel, 2] + 1j * g[sel, 3]
+            errs.append(float(np.linalg.norm(u - ex) / np.linalg.norm(ex)))
+    for p in plans:
+        if p.last_status() != 0:
+            raise RuntimeError("device-reported error in the multi-cell batch")
+    rec = {"metric": "observer points/s per multi-cell apply", "value": Ntot / (ms * 1e-3),
+           "unit": "observer points/s", "n_gpus": 1, "steps": steps, "warmup": 1, "ms_per_step": ms,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32 (FP64 correction)",
+           "data": "synthetic",
+           "config": {"workload": "48 independent cells, N log-uniform in [5e3, 5e5] (%d points), mixed 1D/2D/3D "
+                                  "periodicity, static and Helmholtz, Gaussian blobs, complex strengths" % Ntot,
+                      "target_rel_err": args.target, "lanes": args.lanes},
+           "ms_one_lane": ms_one, "ms_separate_applies": ms_sep, "tune_seconds": tune_s, "plan_seconds": plan_s,
+           "max_predicted_rel_err": max(r["predicted_rel_err"] for r in preds),
+           "rel_err_vs_oracle_rows": {"max": max(errs), "median": float(np.median(errs)), "cells": len(errs),
+                                      "rows_per_cell": 4} if errs else None,
+           "cells": infos}
+    batch.close()
+    one.close()
+    for p in plans:
+        p.close()
+    return rec
 
 
 def forces_record(args):

@@ -316,6 +316,62 @@ int fftpim_eval_pgf(const fftpim_problem_t* problem, int64_t n, const double* r_
  * WOOD_ANOMALY. */
 int fftpim_eval_pgf_self(const fftpim_problem_t* problem, double* out);
 
+/* ---- Many independent cells -------------------------------------------
+ * Sec. 4.2 runs 1D, 2D and 3D periodicities, static and dynamic, with one
+ * implementation; a workload of many such cells of uneven size is served by
+ * a parameter choice per cell and a batch apply. */
+
+typedef struct {
+  double predicted_rel_err;    /* error model value of the chosen parameters */
+  double predicted_ms;         /* cost model value of one apply, milliseconds */
+  int64_t predicted_corr_nnz;  /* correction pairs the choice implies (sampled) */
+  int candidates;              /* parameter sets the search scored */
+} fftpim_tune_report_t;
+
+/* Chooses the method parameters of Sec. 3.2-3.3 for a problem and its n
+ * points (device [n][3], FP64) so that the predicted relative L2 error of
+ * the potential stays below target_rel_err at the least predicted apply
+ * time for nrhs right-hand sides in the given precision.  The error model
+ * bounds the near zone by the interpolation error outside the correction
+ * ball of Eq. (er) (decaying with the ball radius, floored by (k0 h)^(q+1)
+ * for a wave kernel) and the far zone by the interpolation error of G_far of
+ * Eq. (4) on the far grids of Eq. (grid) (set by the far spacing relative
+ * to the period and to the wavelength); its constants come from measured
+ * errors with a margin.  The cost model is fitted to measured per-part
+ * times.  params: in, value_type, self_mode, order_io, nrhs_max, corr_layout
+ * and max_bytes are kept (fill it with fftpim_default_params first); out,
+ * near_n, near_order, corr_ball (the ball region; corr_radius its ceiling),
+ * far_n, far_order, n_images = 1, precision and far_sum = AUTO are set.
+ * report may be NULL.  Reads the points to the host; allocates no device
+ * memory.  Errors: INVALID_ARG (also an FP32 precision with a target below
+ * 5e-6), OUT_OF_CELL, UNSUPPORTED (no parameter set reaches the target
+ * within the grid limits), DEVICE. */
+int fftpim_autotune(const fftpim_problem_t* problem, int64_t n, const double* xyz_dev,
+                    double target_rel_err, int precision, int nrhs, fftpim_params_t* params,
+                    fftpim_tune_report_t* report);
+
+typedef struct fftpim_batch_s* fftpim_batch_t;
+
+/* Groups ncells plans (not owned: they must outlive the batch and must not
+ * be applied elsewhere while a batch apply runs) to be applied together.
+ * The cells are ranked by a predicted cost and dealt, largest first, to the
+ * least-loaded of nlanes (1..16) streams; each lane applies its cells in
+ * turn while every cell still runs its near, correction and far parts on its
+ * plan's own concurrent streams, so small and large cells fill the GPU
+ * together.  use_graph is reserved and must be 0 (1 returns
+ * FFTPIM_ERR_UNSUPPORTED: recording a batch apply as one HIP graph is
+ * switched off). */
+int fftpim_batch_create(fftpim_batch_t* batch, const fftpim_plan_t* plans, int ncells, int nlanes,
+                        int use_graph);
+
+/* in[c], out[c], nrhs[c]: the arguments of fftpim_apply for cell c (of
+ * fftpim_apply_adjoint when adjoint = 1).  Enqueued on stream, which waits
+ * for every cell; no host synchronisation. */
+int fftpim_batch_apply(fftpim_batch_t batch, const void* const* in, void* const* out,
+                       const int* nrhs, int adjoint, fftpim_stream_t stream);
+
+int fftpim_batch_destroy(fftpim_batch_t batch);
+
 #ifdef __cplusplus
 }
 #endif

@@ -30,6 +30,7 @@ SOURCES = [
     ("kernels_table.hip", []),
     ("kernels_grad.hip", []),
     ("api.cpp", ["-x", "hip"]),
+    ("multi.cpp", ["-x", "hip"]),
     ("pgf_host.cpp", []),
 ]
 

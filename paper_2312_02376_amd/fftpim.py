@@ -29,7 +29,8 @@ EXPORTS = (
     "fftpim_default_params", "fftpim_plan", "fftpim_apply", "fftpim_apply_adjoint",
     "fftpim_apply_pair", "fftpim_apply_parts", "fftpim_get_permutation", "fftpim_plan_info", "fftpim_last_status",
     "fftpim_destroy", "fftpim_error_string", "fftpim_eval_pgf", "fftpim_stage_times", "fftpim_eval_pgf_self",
-    "fftpim_apply_pair_noalloc", "fftpim_grad_positions",
+    "fftpim_apply_pair_noalloc", "fftpim_grad_positions", "fftpim_autotune", "fftpim_batch_create",
+    "fftpim_batch_apply", "fftpim_batch_destroy",
 )
 STAGES = ("pack", "near_spread", "near_fft", "near_interp", "near_corr", "far", "unpack")
 
@@ -67,6 +68,11 @@ class Info(ctypes.Structure):
                 ("plan_seconds", ctypes.c_double), ("far_fft", ctypes.c_int * 3)]
 
 
+class TuneReport(ctypes.Structure):
+    _fields_ = [("predicted_rel_err", ctypes.c_double), ("predicted_ms", ctypes.c_double),
+                ("predicted_corr_nnz", ctypes.c_int64), ("candidates", ctypes.c_int)]
+
+
 _lib = None
 
 
@@ -96,6 +102,11 @@ def lib():
         L.fftpim_eval_pgf.argtypes = [ctypes.POINTER(Problem), i64, vp, vp]
         L.fftpim_stage_times.argtypes = [vp, ci, vp, vp]
         L.fftpim_eval_pgf_self.argtypes = [ctypes.POINTER(Problem), vp]
+        L.fftpim_autotune.argtypes = [ctypes.POINTER(Problem), i64, vp, ctypes.c_double, ci, ci,
+                                      ctypes.POINTER(Params), ctypes.POINTER(TuneReport)]
+        L.fftpim_batch_create.argtypes = [ctypes.POINTER(vp), vp, ci, ci, ci]
+        L.fftpim_batch_apply.argtypes = [vp, vp, vp, vp, ci, vp]
+        L.fftpim_batch_destroy.argtypes = [vp]
         for name in EXPORTS:
             if name != "fftpim_error_string":
                 getattr(L, name).restype = ci
@@ -393,3 +404,74 @@ def apply_autograd(plan, q, positions=None):
     if _FN is None:
         _FN = _autograd_function()
     return _FN.apply(q, positions, plan)
+
+
+_PRECISIONS = {"f64": F64, "f32": F32, "f32_farbf16": F32_FARBF16, "f32_farbf16x3": F32_FARBF16X3}
+
+
+def autotune(positions, periodic_dims, L, target, k0=0.0, kt=(0.0, 0.0, 0.0), precision="f64", nrhs=1,
+             value_type="complex", box=None):
+    """fftpim_autotune: the cost-model parameter choice for a target relative
+    error.  Returns (kwargs for Plan, report dict)."""
+    import torch
+    if not (isinstance(positions, torch.Tensor) and positions.is_cuda and positions.dtype == torch.float64):
+        raise TypeError("positions must be a CUDA float64 tensor of shape (N, 3)")
+    pos = positions.contiguous()
+    pr = make_problem(periodic_dims, L, k0, kt, box)
+    pm = Params()
+    _check(lib().fftpim_default_params(ctypes.byref(pr), ctypes.byref(pm)), "fftpim_default_params")
+    pm.value_type = {"real": REAL, "complex": COMPLEX}[value_type]
+    rep = TuneReport()
+    _check(lib().fftpim_autotune(ctypes.byref(pr), int(pos.shape[0]), ctypes.c_void_p(pos.data_ptr()), float(target),
+                                 _PRECISIONS[precision], int(nrhs), ctypes.byref(pm), ctypes.byref(rep)),
+           "fftpim_autotune")
+    kw = dict(near_n=tuple(pm.near_n), near_order=pm.near_order, corr_radius=pm.corr_radius,
+              corr_ball=pm.corr_ball, far_n=tuple(pm.far_n), far_order=pm.far_order, n_images=pm.n_images,
+              precision=precision, value_type=value_type, nrhs_max=max(1, pm.nrhs_max))
+    report = {f: getattr(rep, f) for f, _ in TuneReport._fields_}
+    return kw, report
+
+
+class Batch:
+    """fftpim_batch_*: several plans applied together (the plans are not
+    owned and must outlive the batch)."""
+
+    def __init__(self, plans, lanes=4, graph=False):
+        self.plans = list(plans)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p._h for p in self.plans])
+        h = ctypes.c_void_p()
+        _check(lib().fftpim_batch_create(ctypes.byref(h), arr, len(self.plans), int(lanes), 1 if graph else 0),
+               "fftpim_batch_create")
+        self._h = h
+
+    def apply(self, xs, outs=None, adjoint=False, stream=None):
+        import torch
+        if len(xs) != len(self.plans):
+            raise ValueError("one input per cell")
+        ins, os_, nr = [], [], []
+        made = []
+        for c, (pl, x) in enumerate(zip(self.plans, xs)):
+            x2, out, squeeze = pl._io(x, None if outs is None else outs[c])
+            made.append((x2, out, squeeze))
+            ins.append(x2.data_ptr())
+            os_.append(out.data_ptr())
+            nr.append(int(x2.shape[0]))
+        n = len(self.plans)
+        ia = (ctypes.c_void_p * n)(*ins)
+        oa = (ctypes.c_void_p * n)(*os_)
+        ra = (ctypes.c_int * n)(*nr)
+        _check(lib().fftpim_batch_apply(self._h, ia, oa, ra, 1 if adjoint else 0, _stream_handle(stream)),
+               "fftpim_batch_apply")
+        self._keep = made  # inputs stay alive until the caller synchronises
+        return [o.reshape(-1) if sq else o for (_, o, sq) in made]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().fftpim_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -169,3 +169,40 @@ def dynamic_cube_k0(n, D=100.0):
     """Free-space wavenumber of the dynamic runs of Sec. 4.2: the mean point
     spacing D / n^(1/3) is a twentieth of the wavelength."""
     return 2.0 * np.pi / (20.0 * D / n ** (1.0 / 3.0))
+
+
+def multi_cell(ncells, seed, n_lo=5000, n_hi=500000, nblobs=8, sigma=0.05):
+    """Independent cells of uneven size: N log-uniform in [n_lo, n_hi],
+    periodic dimension 1, 2 or 3 (period 1), static or Helmholtz with
+    k0 L uniform in [pi/2, 4 pi] (phase wavenumbers 0), redrawn within 0.05
+    of 2 pi sqrt(j), j = 1..4, where the lattice sums have Rayleigh-Wood
+    anomalies for a zero phase shift; points in Gaussian blobs of width
+    sigma, wrapped on periodic axes and clipped to [0, 1] on the others;
+    complex N(0,1) strengths, mean removed on static cells.
+
+    Returns a list of dicts: dims, L, k0, kt, pos [N][3], q [N] complex128."""
+    rng = np.random.default_rng(seed)
+    cells = []
+    for _ in range(ncells):
+        n = int(round(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi)))))
+        dims = int(rng.integers(1, 4))
+        static = bool(rng.integers(0, 2))
+        k0 = 0.0
+        if not static:
+            while True:
+                k0 = rng.uniform(0.5 * np.pi, 4 * np.pi)
+                x = k0 / (2 * np.pi)
+                if all(abs(x - np.sqrt(j)) > 0.05 for j in range(1, 5)):
+                    break
+        centres = rng.random((nblobs, 3))
+        which = rng.integers(0, nblobs, n)
+        pos = centres[which] + sigma * rng.standard_normal((n, 3))
+        pos[:, :dims] = np.mod(pos[:, :dims], 1.0)
+        # a wrapped coordinate can round up to exactly 1.0
+        pos[:, :dims] = np.where(pos[:, :dims] >= 1.0, 0.0, pos[:, :dims])
+        pos[:, dims:] = np.clip(pos[:, dims:], 0.0, 1.0)
+        q = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+        if static:
+            q -= q.mean()
+        cells.append(dict(dims=dims, L=[1.0] * dims, k0=k0, kt=[0.0] * dims, pos=pos, q=q))
+    return cells

@@ -5,6 +5,7 @@ seeded inputs of paper_2312_02376_amd.workloads; nothing here touches the GPU
 library.  Run from the repository root:
 
     python tests/golden/make_golden.py [coulomb_1k] [helmholtz_100k] [coulomb_1m] [dynamic_cube_20k]
+        [multi_cell_small] [multi_cell_48]
 """
 import os
 import sys
@@ -84,7 +85,49 @@ def dynamic_cube_20k(nrows=32):
           [rows, u.real, u.imag, us.real])
 
 
+def multi_cell_48(nrows=4):
+    # the 48-cell workload of the benchmark (workloads.multi_cell(48, 4)):
+    # N log-uniform in [5e3, 5e5], mixed periodicity, static and Helmholtz
+    cells = W.multi_cell(48, 4)
+    cols = [[], [], [], []]
+    for c, cell in enumerate(cells):
+        lat = P.Lattice(cell["dims"], cell["L"], cell["k0"], cell["kt"])
+        n = len(cell["q"])
+        rows = np.sort(np.random.default_rng(200 + c).choice(n, nrows, replace=False))
+        u = psp_forward(lat, cell["pos"], cell["q"], obs_index=rows, workers=host_workers())
+        cols[0].append(np.full(nrows, c))
+        cols[1].append(rows)
+        cols[2].append(u.real)
+        cols[3].append(u.imag)
+        print("cell", c, "done", flush=True)
+    _save("multi_cell_48_rows.txt",
+          "48 independent cells, workloads.multi_cell(48, 4);\n"
+          "exact u = A q at sampled rows of each cell.\ncolumns: cell, row, Re u, Im u",
+          [np.concatenate(x) for x in cols])
+
+
+def multi_cell_small(nrows=16):
+    # eight independent cells of uneven size (workloads.multi_cell(8, 21,
+    # 2000, 12000)): mixed periodicity, static and Helmholtz
+    cells = W.multi_cell(8, 21, 2000, 12000)
+    cols = [[], [], [], []]
+    for c, cell in enumerate(cells):
+        lat = P.Lattice(cell["dims"], cell["L"], cell["k0"], cell["kt"])
+        n = len(cell["q"])
+        rows = np.sort(np.random.default_rng(100 + c).choice(n, nrows, replace=False))
+        u = psp_forward(lat, cell["pos"], cell["q"], obs_index=rows, workers=host_workers())
+        cols[0].append(np.full(nrows, c))
+        cols[1].append(rows)
+        cols[2].append(u.real)
+        cols[3].append(u.imag)
+    _save("multi_cell_small_rows.txt",
+          "eight independent cells, workloads.multi_cell(8, 21, 2000, 12000);\n"
+          "exact u = A q at sampled rows of each cell.\ncolumns: cell, row, Re u, Im u",
+          [np.concatenate(x) for x in cols])
+
+
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["coulomb_1k", "helmholtz_100k", "coulomb_1m", "dynamic_cube_20k"]
+    which = sys.argv[1:] or ["coulomb_1k", "helmholtz_100k", "coulomb_1m", "dynamic_cube_20k", "multi_cell_small",
+                             "multi_cell_48"]
     for w in which:
         globals()[w]()

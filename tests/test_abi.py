@@ -165,3 +165,26 @@ def test_self_evaluator_matches_oracle(dims, L, k0, kt):
     got = fp.eval_pgf_self(dims, L, k0, kt)
     want = P.pgf_self(P.Lattice(dims, L, k0, kt))
     assert abs(got - want) <= 2e-12 * abs(want), (got, want)
+
+
+def test_autotune_and_batch_argument_checks():
+    # every check here fails before the library reads the (dummy) points
+    L = fp.lib()
+    pr = fp.make_problem(3, [1.0, 1.0, 1.0])
+    pm = fp.Params()
+    assert L.fftpim_default_params(ctypes.byref(pr), ctypes.byref(pm)) == 0
+    rep = fp.TuneReport()
+    dummy = ctypes.c_void_p(0x1000)
+    tune = L.fftpim_autotune
+    assert tune(None, 10, dummy, 1e-4, 0, 1, ctypes.byref(pm), ctypes.byref(rep)) == 1
+    assert tune(ctypes.byref(pr), 0, dummy, 1e-4, 0, 1, ctypes.byref(pm), ctypes.byref(rep)) == 1
+    assert tune(ctypes.byref(pr), 10, dummy, 0.0, 0, 1, ctypes.byref(pm), ctypes.byref(rep)) == 1
+    assert tune(ctypes.byref(pr), 10, dummy, 1e-7, 1, 1, ctypes.byref(pm), ctypes.byref(rep)) == 1  # FP32 floor
+    assert tune(ctypes.byref(pr), 10, dummy, 1e-4, 0, 0, ctypes.byref(pm), ctypes.byref(rep)) == 1
+    h = ctypes.c_void_p()
+    plans = (ctypes.c_void_p * 2)(None, None)
+    assert L.fftpim_batch_create(ctypes.byref(h), plans, 2, 4, 0) == 1      # null plans
+    assert L.fftpim_batch_create(ctypes.byref(h), plans, 0, 4, 0) == 1      # no cells
+    assert L.fftpim_batch_create(ctypes.byref(h), plans, 2, 17, 0) == 1     # lanes 1..16
+    assert L.fftpim_batch_apply(None, None, None, None, 0, None) == 1
+    assert L.fftpim_batch_destroy(None) == 1
