@@ -19,8 +19,9 @@
 // Cost model (milliseconds of one apply on one MI355X, fitted to measured
 // per-part times): near grid a0 + a1 N (q+1)^3 P + a2 M log2(M) P over the
 // padded transform size M; correction c0 + c1 nnz (1 + (P - 1)/4); far zone
-// f0 + a1 2 N (qf+1)^3 P + the grid sum (Ngf^2 P direct, or the FFT term
-// from 8192 nodes up).  The parts run concurrently, so the sum ranks
+// f0 + a1 (2 N + Ngf) (qf+1)^3 P (projection, box moments to nodes,
+// interpolation) + the grid sum (Ngf^2 P direct, or the FFT term from 8192
+// nodes up).  The parts run concurrently, so the sum ranks
 // candidates conservatively.
 #include <hip/hip_runtime.h>
 
@@ -48,6 +49,7 @@ constexpr double kCostGrid0 = 0.11, kCostGridPt = 1.26e-8, kCostFft = 5.6e-10;
 constexpr double kCostCorr0 = 0.06, kCostCorrNnz = 3.6e-9;
 constexpr double kCostFar0 = 0.10, kCostFarDirect = 2.0e-9;
 constexpr int64_t kFarFftNodes = 8192;
+constexpr double kFarMomentBytes = 8.0e9;
 
 int fft_len(int m) {
   int M = 1;
@@ -237,10 +239,12 @@ int tune(const fftpim_problem_t* pr, int64_t N, const double* xyz_dev, double ta
           ngf *= nf[c];
           Mf *= fft_len(2 * nf[c] - 1);
         }
-        if (!ok) break;
+        // the far box moments hold (qf+1)^3 values per box and plane
+        if (!ok || ngf * std::pow(qf + 1, 3) * P * 16.0 > kFarMomentBytes) break;
         ++candidates;
         const double sum_ms = ngf >= kFarFftNodes ? kCostFft * Mf * std::log2(Mf) * P : kCostFarDirect * ngf * ngf * P;
-        const double ms = kCostFar0 + 2.0 * kCostGridPt * static_cast<double>(N) * std::pow(qf + 1, 3) * P + sum_ms;
+        const double taps = std::pow(qf + 1, 3);
+        const double ms = kCostFar0 + kCostGridPt * (2.0 * static_cast<double>(N) + ngf) * taps * P + sum_ms;
         if (ms < bf.ms) {
           bf.q = qf;
           for (int c = 0; c < 3; ++c) bf.n[c] = nf[c];
