@@ -187,8 +187,17 @@ int fftpim_default_params(const fftpim_problem_t* problem, fftpim_params_t* para
  * Eq. (pgf)/(lgf), the FFT of the zero-padded near-zone table, and the
  * error-correction operator of Eq. (er)).
  *   src_xyz_dev: device double [n_src][3]; copied, may be freed afterwards.
- *   obs_xyz_dev: must be NULL (observers coincide with sources, Sec. 2);
- *                separate observer sets return FFTPIM_ERR_UNIMPLEMENTED.
+ *   obs_xyz_dev: NULL: the observers are the sources (Sec. 2; n_obs 0 or
+ *                n_src).  Otherwise device double [n_obs][3], a separate
+ *                observer set, copied: u is evaluated there (Eq. (1) with r_m
+ *                the observers; the target region D of Sec. 3.2 bounds both
+ *                sets, observers on periodic axes lie in [0, L) too).  The
+ *                correction is then held as a CSR per direction (observer
+ *                rows, and source rows for A^H); params.self_mode must be
+ *                FFTPIM_SELF_IMAGES and corr_layout AUTO or CSR; an observer
+ *                exactly on a source keeps only the grid part of that pair
+ *                (the reading of the n = m term); fftpim_apply_pair(_noalloc)
+ *                and fftpim_grad_positions return FFTPIM_ERR_UNSUPPORTED.
  *   stream:      stream for the plan's device work; the call synchronizes it.
  * On success *plan owns all device memory it needs; free with fftpim_destroy.
  * Errors: INVALID_ARG, OUT_OF_CELL, WOOD_ANOMALY, UNSUPPORTED, NO_MEMORY,

@@ -335,6 +335,17 @@ void resolve_timers(fftpim_plan_s* p) {
 template <typename R>
 void correction_zone(fftpim_plan_s* p, bool adjoint, const void* in, int P, void* out, hipStream_t sc) {
   const int64_t N = p->N;
+  if (p->sep) {
+    // separate observers: observer rows forward, source rows (C^H) for the
+    // conjugate transpose
+    if (adjoint)
+      launch_corr_spmv<R>(p->complex_kernel, p->rowptr_a, p->col_a, p->val_a, N, p->corr_order_a, p->corr_slots_a,
+                          in, P, out, false, sc);
+    else
+      launch_corr_spmv<R>(p->complex_kernel, p->rowptr, p->col, p->val, p->No, p->corr_order, p->corr_slots, in, P,
+                          out, false, sc);
+    return;
+  }
   const void* v = (adjoint && p->nonhermitian) ? p->val_adj : p->val;
   if (p->tile) {
     // real correction values: the operator is symmetric, so the conjugate
@@ -360,7 +371,7 @@ void correction_zone(fftpim_plan_s* p, bool adjoint, const void* in, int P, void
 // for the adjoint) and the grid sum with K (K^H); the result is in ws.far_u.
 template <typename R>
 int far_field(fftpim_plan_s* p, const WorkSet& ws, bool adjoint, const void* in, int P, hipStream_t sf) {
-  const int64_t N = p->N;
+  const int64_t N = adjoint ? p->No : p->N;  // points projected: observers for the adjoint
   const FarArgs fa = far_args(p);
   const int qf = p->fg.q;
   const int32_t* fbs = adjoint ? p->fbox_start_o : p->fbox_start_s;
@@ -382,7 +393,7 @@ int far_field(fftpim_plan_s* p, const WorkSet& ws, bool adjoint, const void* in,
 template <typename R>
 int far_zone(fftpim_plan_s* p, const WorkSet& ws, bool adjoint, const void* in, int P, void* out,
              hipStream_t sf) {
-  const int64_t N = p->N;
+  const int64_t N = adjoint ? p->N : p->No;  // points interpolated: observers forward
   const FarArgs fa = far_args(p);
   const int qf = p->fg.q;
   const int32_t* fs_out = adjoint ? p->fs_s : p->fo_s;
@@ -406,9 +417,13 @@ int near_field(fftpim_plan_s* p, const WorkSet& ws, bool adjoint, const void* in
   const GridArgs ga = grid_args(p->ng);
   {
     StageTimer t(p, sn, FFTPIM_STAGE_NEAR_SPREAD);
+    // the projected points: sources forward, observers for the adjoint
+    // (the same set unless the plan has separate observers)
     if (p->wt_row != nullptr)
       launch_spread_csr<R>(p->wt_row, p->wt_idx, p->wt_val, static_cast<int64_t>(p->ng.n[0]) * p->ng.n[1] * p->ng.n[2],
                            in, P, ws.grid0, sn);
+    else if (adjoint)
+      CHK(launch_spread_near<R>(p->ng.q, ga, p->box_start_o, p->near_s_o, p->near_w_o, p->No, in, P, ws.grid0, sn));
     else
       CHK(launch_spread_near<R>(p->ng.q, ga, p->box_start, p->near_s, p->near_w, p->N, in, P, ws.grid0, sn));
   }
@@ -426,7 +441,10 @@ int near_grid_zone(fftpim_plan_s* p, const WorkSet& ws, bool adjoint, const void
   CHK(near_field<R>(p, ws, adjoint, in, P, sn));
   {
     StageTimer t(p, sn, FFTPIM_STAGE_NEAR_INTERP);
-    CHK(launch_interp<R>(p->ng.q, ga, p->near_s, p->near_w, p->N, ws.grid0, P, out, false, sn));
+    if (adjoint)
+      CHK(launch_interp<R>(p->ng.q, ga, p->near_s, p->near_w, p->N, ws.grid0, P, out, false, sn));
+    else
+      CHK(launch_interp<R>(p->ng.q, ga, p->near_s_o, p->near_w_o, p->No, ws.grid0, P, out, false, sn));
   }
   return FFTPIM_OK;
 }
@@ -446,7 +464,12 @@ DiagTerm self_term(const fftpim_plan_s* p, const void* packed_in, bool adjoint) 
 template <typename R>
 int run_apply(fftpim_plan_s* p, int parts, bool adjoint, const void* in, void* out, int nrhs, hipStream_t st,
               bool finalize) {
-  const int64_t N = p->N;
+  // the input lives on the sources (observers for the adjoint), the output
+  // on the observers (sources); one set unless the plan has separate observers
+  const int64_t N = adjoint ? p->No : p->N;
+  const int64_t Nout = adjoint ? p->N : p->No;
+  const int32_t* perm_in = adjoint ? p->perm_o : p->perm;
+  const int32_t* perm_out = adjoint ? p->perm : p->perm_o;
   const int P = planes_for(p, nrhs);
   const bool real_io = p->prm.value_type == FFTPIM_REAL;
   const bool use_perm = p->prm.order_io == FFTPIM_ORDER_USER;
@@ -454,7 +477,7 @@ int run_apply(fftpim_plan_s* p, int parts, bool adjoint, const void* in, void* o
   if (p->timing && p->ev_used > 4096) resolve_timers(p);
   {
     StageTimer t(p, st, FFTPIM_STAGE_PACK);
-    launch_pack<R>(in, p->q_int, p->perm, N, nrhs, P, real_io, use_perm, st);
+    launch_pack<R>(in, p->q_int, perm_in, N, nrhs, P, real_io, use_perm, st);
     if (finalize && !adjoint && p->lat.npsp()) {
       launch_plane_sums<R>(p->q_int, nullptr, nullptr, N, P, p->sums_work, p->sums, st);
       launch_check_neutral(p->sums, P, p->prm.precision != FFTPIM_F64 ? 1e-5 : 1e-10, p->status_dev, st);
@@ -504,13 +527,13 @@ int run_apply(fftpim_plan_s* p, int parts, bool adjoint, const void* in, void* o
   const double* mean = nullptr;
   if (finalize && adjoint && p->lat.npsp()) {
     // only the zero-mean part of A^H v is defined for the neutral static case
-    launch_plane_sums<R>(un, uc, uf, N, P, p->sums_work, p->sums, st, diag);
-    launch_mean_from_sums(p->sums, P, N, p->sums + 4 * p->nplanes_max, st);
+    launch_plane_sums<R>(un, uc, uf, Nout, P, p->sums_work, p->sums, st, diag);
+    launch_mean_from_sums(p->sums, P, Nout, p->sums + 4 * p->nplanes_max, st);
     mean = p->sums + 4 * p->nplanes_max;
   }
   {
     StageTimer t(p, st, FFTPIM_STAGE_UNPACK);
-    launch_unpack<R>(un, uc, uf, out, p->perm, N, nrhs, P, real_io, use_perm, mean, st, diag);
+    launch_unpack<R>(un, uc, uf, out, perm_out, Nout, nrhs, P, real_io, use_perm, mean, st, diag);
   }
   if (hipPeekAtLastError() != hipSuccess) return FFTPIM_ERR_DEVICE;
   return FFTPIM_OK;
@@ -1284,8 +1307,10 @@ int build_tiles(fftpim_plan_s* p, const std::vector<int32_t>& start, const std::
   return FFTPIM_OK;
 }
 
+// start: the source box sort; start_o, pos3_o: the observers' when they are
+// a separate set (nullptr otherwise).
 int build_correction(fftpim_plan_s* p, const std::vector<int32_t>& start, const double* pos3_dev,
-                     hipStream_t st) {
+                     const std::vector<int32_t>* start_o, const double* pos3_o, hipStream_t st) {
   const int q = p->ng.q, id = p->prm.n_images;
   const CorrRegion reg = corr_region(p);
   const int rc = std::max(reg.reach[0], std::max(reg.reach[1], reg.reach[2]));
@@ -1306,6 +1331,7 @@ int build_correction(fftpim_plan_s* p, const std::vector<int32_t>& start, const 
   ca.R = rc + q;
   ca.W = 2 * ca.R + 1;
   ca.N = p->N;
+  ca.Nc = p->N;
   ca.k0 = p->lat.k0.real();
   ca.k0_im = p->lat.k0.imag();
   ca.nimg_axis = A;
@@ -1374,42 +1400,93 @@ int build_correction(fftpim_plan_s* p, const std::vector<int32_t>& start, const 
   cplx<double>* dg0 = nullptr;
   CHK(upload(p, &dg0, g0t));
   if (p->sym) CHK(build_sym(p, start, pos3_dev, dg0, ca, st));
-  // count, scan, fill
-  int64_t* dcount = nullptr;
-  CHK(dalloc(p, &dcount, p->N));
-  CHK(launch_corr_count(ca, p->near_s, p->box_start, dcount, st));
-  std::vector<int64_t> rowptr(p->N + 1, 0);
-  HIPCHK(hipMemcpyAsync(rowptr.data() + 1, dcount, p->N * sizeof(int64_t), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  for (int64_t m = 0; m < p->N; ++m) rowptr[m + 1] += rowptr[m];
-  p->nnz = rowptr[p->N];
-  if (std::getenv("FFTPIM_LOG"))
-    std::fprintf(stderr, "fftpim plan: correction nnz %lld\n", static_cast<long long>(p->nnz));
-  CHK(upload(p, &p->rowptr, rowptr));
-  {
-    std::vector<int32_t> order;
-    build_row_order(start, p->nb, p->N, order);
-    p->corr_slots = static_cast<int64_t>(order.size());
-    CHK(upload(p, &p->corr_order, order));
-  }
-  CHK(dalloc(p, &p->col, p->nnz));
+  // count, scan, fill one CSR: rows are one point set (stencils s3r,
+  // weights u3r, positions posr, box sort rstart), columns the other
   const bool cv = p->complex_kernel;
   const size_t vb = cv ? 16 : 8;
-  {
-    unsigned char* v = nullptr;
-    CHK(dalloc(p, &v, p->nnz * vb));
-    p->val = v;
-    if (p->nonhermitian) {
-      unsigned char* va = nullptr;
-      CHK(dalloc(p, &va, p->nnz * vb));
-      p->val_adj = va;
+  struct Csr {
+    int64_t* rowptr = nullptr;
+    int32_t* col = nullptr;
+    void* val = nullptr;
+    void* val_adj = nullptr;
+    int32_t* order = nullptr;
+    int64_t slots = 0, nnz = 0;
+    std::vector<int64_t> host_rowptr;
+  };
+  auto build_csr = [&](CorrArgs a, int64_t nr, const int32_t* s3r, const double* u3r, const double* posr,
+                       const std::vector<int32_t>& rstart, int64_t nc, const double* u3c, const double* posc,
+                       const int32_t* cstart, bool with_adj, Csr& out) -> int {
+    a.N = nr;
+    a.Nc = nc;
+    int64_t* dcount = nullptr;
+    CHK(dalloc(p, &dcount, nr));
+    CHK(launch_corr_count(a, s3r, cstart, dcount, st));
+    std::vector<int64_t>& rowptr = out.host_rowptr;
+    rowptr.assign(nr + 1, 0);
+    HIPCHK(hipMemcpyAsync(rowptr.data() + 1, dcount, nr * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int64_t m = 0; m < nr; ++m) rowptr[m + 1] += rowptr[m];
+    out.nnz = rowptr[nr];
+    if (std::getenv("FFTPIM_LOG"))
+      std::fprintf(stderr, "fftpim plan: correction nnz %lld\n", static_cast<long long>(out.nnz));
+    CHK(upload(p, &out.rowptr, rowptr));
+    {
+      std::vector<int32_t> order;
+      build_row_order(rstart, p->nb, nr, order);
+      out.slots = static_cast<int64_t>(order.size());
+      CHK(upload(p, &out.order, order));
     }
+    CHK(dalloc(p, &out.col, out.nnz));
+    unsigned char* v = nullptr;
+    CHK(dalloc(p, &v, out.nnz * vb));
+    out.val = v;
+    if (with_adj) {
+      unsigned char* va = nullptr;
+      CHK(dalloc(p, &va, out.nnz * vb));
+      out.val_adj = va;
+    }
+    CHK(launch_corr_fill(q, cv, with_adj, a, s3r, u3r, posr, u3c, posc, cstart, dg0, out.rowptr, out.col, out.val,
+                         out.val_adj, st));
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipGetLastError());
+    dfree(p, dcount);
+    return FFTPIM_OK;
+  };
+  Csr fwd;
+  if (!p->sep) {
+    CHK(build_csr(ca, p->N, p->near_s, p->near_u, pos3_dev, start, p->N, p->near_u, pos3_dev, p->box_start,
+                  p->nonhermitian, fwd));
+  } else {
+    // rows are observers; the conjugate transpose gets its own CSR with
+    // source rows: C^H(n, m) = conj(C(m, n)) is the conjugate-transpose
+    // value of the fill with the roles swapped (the region and G0 are
+    // symmetric under swapping the points and reversing the image), and for
+    // a real symmetric kernel simply the swapped fill's value
+    CHK(build_csr(ca, p->No, p->near_s_o, p->near_u_o, pos3_o, *start_o, p->N, p->near_u, pos3_dev, p->box_start,
+                  false, fwd));
+    Csr adj;
+    CHK(build_csr(ca, p->N, p->near_s, p->near_u, pos3_dev, start, p->No, p->near_u_o, pos3_o, p->box_start_o,
+                  p->nonhermitian, adj));
+    p->rowptr_a = adj.rowptr;
+    p->col_a = adj.col;
+    if (p->nonhermitian) {
+      p->val_a = adj.val_adj;
+      dfree(p, adj.val);
+    } else {
+      p->val_a = adj.val;
+    }
+    p->corr_order_a = adj.order;
+    p->corr_slots_a = adj.slots;
+    p->nnz_a = adj.nnz;
   }
-  CHK(launch_corr_fill(q, cv, p->nonhermitian, ca, p->near_s, p->near_u, pos3_dev, p->box_start, dg0, p->rowptr,
-                       p->col, p->val, p->val_adj, st));
-  HIPCHK(hipStreamSynchronize(st));
-  HIPCHK(hipGetLastError());
-  dfree(p, dcount);
+  p->rowptr = fwd.rowptr;
+  p->col = fwd.col;
+  p->val = fwd.val;
+  p->val_adj = fwd.val_adj;
+  p->corr_order = fwd.order;
+  p->corr_slots = fwd.slots;
+  p->nnz = fwd.nnz;
+  const std::vector<int64_t>& rowptr = fwd.host_rowptr;
   // the traversal arrays (per-axis candidate lists, image phases, G0 table)
   // stay with the plan: the position gradient walks the same pairs
   p->grad_ca = ca;
@@ -1427,26 +1504,35 @@ void plan_log(const char* what, std::chrono::steady_clock::time_point t0) {
   std::fflush(stderr);
 }
 
-int build_plan(fftpim_plan_s* p, int64_t N, const double* src_dev, hipStream_t st) {
+int build_plan(fftpim_plan_s* p, int64_t N, const double* src_dev, int64_t No, const double* obs_dev,
+               hipStream_t st) {
   const auto t0 = std::chrono::steady_clock::now();
   const fftpim_problem_t& pr = p->problem;
   const fftpim_params_t& pm = p->prm;
   const int dims = pr.periodic_dims;
+  const bool sep = obs_dev != nullptr;
+  p->sep = sep;
+  p->No = sep ? No : N;
   // positions to host
-  std::vector<double> xyz(static_cast<size_t>(N) * 3);
+  std::vector<double> xyz(static_cast<size_t>(N) * 3), xyz_o;
   HIPCHK(hipMemcpyAsync(xyz.data(), src_dev, xyz.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  if (sep) {
+    xyz_o.resize(static_cast<size_t>(No) * 3);
+    HIPCHK(hipMemcpyAsync(xyz_o.data(), obs_dev, xyz_o.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  }
   HIPCHK(hipStreamSynchronize(st));
   // target region D (Sec. 3.2): the cell on periodic axes; the given box or
-  // the bounding box elsewhere
+  // the bounding box of sources and observers elsewhere
   double lo[3], hi[3];
   for (int c = 0; c < 3; ++c) {
     double mn = INFINITY, mx = -INFINITY;
-    for (int64_t i = 0; i < N; ++i) {
-      double v = xyz[3 * i + c];
-      if (!std::isfinite(v)) return FFTPIM_ERR_INVALID_ARG;
-      mn = std::min(mn, v);
-      mx = std::max(mx, v);
-    }
+    for (const std::vector<double>* X : {&xyz, &xyz_o})
+      for (size_t i = 0; i < X->size() / 3; ++i) {
+        const double v = (*X)[3 * i + c];
+        if (!std::isfinite(v)) return FFTPIM_ERR_INVALID_ARG;
+        mn = std::min(mn, v);
+        mx = std::max(mx, v);
+      }
     if (c < dims) {
       if (mn < 0.0 || mx >= pr.L[c]) return FFTPIM_ERR_OUT_OF_CELL;
       lo[c] = 0.0;
@@ -1501,40 +1587,68 @@ int build_plan(fftpim_plan_s* p, int64_t N, const double* src_dev, hipStream_t s
     p->far_fft = pm.far_sum == FFTPIM_FAR_FFT || (pm.far_sum == FFTPIM_FAR_AUTO && !bf16 && ngf >= kFarFftMinNodes);
     for (int c = 0; c < 3; ++c) p->Mf[c] = p->far_fft ? fft_length(2 * f.n[c] - 1) : 0;
   }
-  // near stencils and the box sort
-  std::vector<int32_t> s(3 * N);
-  std::vector<double> u(3 * N);
-  std::vector<int64_t> key(N);
-  for (int64_t i = 0; i < N; ++i) {
-    for (int c = 0; c < 3; ++c) stencil(xyz[3 * i + c], g.origin[c], g.h[c], g.q, g.n[c], s[3 * i + c], u[3 * i + c]);
-    key[i] = (static_cast<int64_t>(s[3 * i]) * p->nb[1] + s[3 * i + 1]) * p->nb[2] + s[3 * i + 2];
-  }
+  // near stencils and the box sort of one point set (Sec. 3.3), with its
+  // stencils on one far grid (Sec. 3.2, Eq. (grid)): the source grid, or the
+  // observer grid shifted by -h/2
+  struct SetGeom {
+    int64_t n = 0;
+    std::vector<int32_t> order, start, s_sorted, f_s, forder, fstart;
+    std::vector<double> u_sorted, pos_sorted, f_u;
+    int fmax = 0;
+  };
   const int64_t nboxes = static_cast<int64_t>(p->nb[0]) * p->nb[1] * p->nb[2];
-  std::vector<int32_t> order, start;
-  counting_sort(key, nboxes, order, start);
-  std::vector<int32_t> s_sorted(3 * N), fs_s(3 * N), fo_s(3 * N);
-  std::vector<double> u_sorted(3 * N), pos_sorted(3 * N), fs_u(3 * N), fo_u(3 * N);
-  std::vector<int64_t> fkey_s(N), fkey_o(N);
-  for (int64_t j = 0; j < N; ++j) {
-    const int64_t i = order[j];
-    for (int c = 0; c < 3; ++c) {
-      s_sorted[c * N + j] = s[3 * i + c];
-      u_sorted[c * N + j] = u[3 * i + c];
-      pos_sorted[c * N + j] = xyz[3 * i + c];
-      stencil(xyz[3 * i + c], f.origin[c], f.h[c], f.q, f.n[c], fs_s[c * N + j], fs_u[c * N + j]);
-      stencil(xyz[3 * i + c], f.origin[c] - 0.5 * f.h[c], f.h[c], f.q, f.n[c], fo_s[c * N + j], fo_u[c * N + j]);
-    }
-    fkey_s[j] = (static_cast<int64_t>(fs_s[j]) * p->fnb[1] + fs_s[N + j]) * p->fnb[2] + fs_s[2 * N + j];
-    fkey_o[j] = (static_cast<int64_t>(fo_s[j]) * p->fnb[1] + fo_s[N + j]) * p->fnb[2] + fo_s[2 * N + j];
-  }
   const int64_t fboxes = static_cast<int64_t>(p->fnb[0]) * p->fnb[1] * p->fnb[2];
-  std::vector<int32_t> forder_s, fstart_s, forder_o, fstart_o;
-  counting_sort(fkey_s, fboxes, forder_s, fstart_s);
-  counting_sort(fkey_o, fboxes, forder_o, fstart_o);
-  for (int64_t k = 0; k < fboxes; ++k) {
-    p->fmax_box_s = std::max(p->fmax_box_s, fstart_s[k + 1] - fstart_s[k]);
-    p->fmax_box_o = std::max(p->fmax_box_o, fstart_o[k + 1] - fstart_o[k]);
-  }
+  auto near_geom = [&](const std::vector<double>& X, SetGeom& G) {
+    const int64_t n = static_cast<int64_t>(X.size() / 3);
+    G.n = n;
+    std::vector<int32_t> sv(3 * n);
+    std::vector<double> uv(3 * n);
+    std::vector<int64_t> key(n);
+    for (int64_t i = 0; i < n; ++i) {
+      for (int c = 0; c < 3; ++c) stencil(X[3 * i + c], g.origin[c], g.h[c], g.q, g.n[c], sv[3 * i + c], uv[3 * i + c]);
+      key[i] = (static_cast<int64_t>(sv[3 * i]) * p->nb[1] + sv[3 * i + 1]) * p->nb[2] + sv[3 * i + 2];
+    }
+    counting_sort(key, nboxes, G.order, G.start);
+    G.s_sorted.resize(3 * n);
+    G.u_sorted.resize(3 * n);
+    G.pos_sorted.resize(3 * n);
+    for (int64_t j = 0; j < n; ++j) {
+      const int64_t i = G.order[j];
+      for (int c = 0; c < 3; ++c) {
+        G.s_sorted[c * n + j] = sv[3 * i + c];
+        G.u_sorted[c * n + j] = uv[3 * i + c];
+        G.pos_sorted[c * n + j] = X[3 * i + c];
+      }
+    }
+  };
+  auto far_geom = [&](SetGeom& G, double shift, std::vector<int32_t>& fs, std::vector<double>& fu,
+                      std::vector<int32_t>& forder, std::vector<int32_t>& fstart, int& fmax) {
+    const int64_t n = G.n;
+    fs.resize(3 * n);
+    fu.resize(3 * n);
+    std::vector<int64_t> fkey(n);
+    for (int64_t j = 0; j < n; ++j) {
+      for (int c = 0; c < 3; ++c)
+        stencil(G.pos_sorted[c * n + j], f.origin[c] + shift * f.h[c], f.h[c], f.q, f.n[c], fs[c * n + j], fu[c * n + j]);
+      fkey[j] = (static_cast<int64_t>(fs[j]) * p->fnb[1] + fs[n + j]) * p->fnb[2] + fs[2 * n + j];
+    }
+    counting_sort(fkey, fboxes, forder, fstart);
+    fmax = 0;
+    for (int64_t k = 0; k < fboxes; ++k) fmax = std::max(fmax, fstart[k + 1] - fstart[k]);
+  };
+  SetGeom gs, go;
+  near_geom(xyz, gs);
+  if (sep) near_geom(xyz_o, go);
+  SetGeom& gobs = sep ? go : gs;
+  std::vector<int32_t> fs_s, fo_s, forder_s, fstart_s, forder_o, fstart_o;
+  std::vector<double> fs_u, fo_u;
+  far_geom(gs, 0.0, fs_s, fs_u, forder_s, fstart_s, p->fmax_box_s);
+  far_geom(gobs, -0.5, fo_s, fo_u, forder_o, fstart_o, p->fmax_box_o);
+  const std::vector<int32_t>& order = gs.order;
+  const std::vector<int32_t>& start = gs.start;
+  const std::vector<int32_t>& s_sorted = gs.s_sorted;
+  const std::vector<double>& u_sorted = gs.u_sorted;
+  const std::vector<double>& pos_sorted = gs.pos_sorted;
 
   CHK(upload(p, &p->perm, order));
   CHK(upload(p, &p->near_s, s_sorted));
@@ -1546,7 +1660,25 @@ int build_plan(fftpim_plan_s* p, int64_t N, const double* src_dev, hipStream_t s
   CHK(upload(p, &p->fo_u, fo_u));
   const std::vector<double> w_near = weights_soa(u_sorted, N, g.q);
   CHK(upload(p, &p->near_w, w_near));
-  if (planes_for(p, pm.nrhs_max) <= kSpreadCsrPlanes) {
+  double* dpos_o = nullptr;
+  if (sep) {
+    CHK(upload(p, &p->perm_o, go.order));
+    CHK(upload(p, &p->near_s_o, go.s_sorted));
+    CHK(upload(p, &p->near_u_o, go.u_sorted));
+    CHK(upload(p, &p->box_start_o, go.start));
+    CHK(upload(p, &p->near_w_o, weights_soa(go.u_sorted, No, g.q)));
+    CHK(upload(p, &dpos_o, go.pos_sorted));
+  } else {
+    p->perm_o = p->perm;
+    p->near_s_o = p->near_s;
+    p->near_u_o = p->near_u;
+    p->near_w_o = p->near_w;
+    p->box_start_o = p->box_start;
+  }
+  // the node-major projection weights serve sources only: with separate
+  // observers the conjugate transpose projects observers, so both use the
+  // box-tiled gather
+  if (!sep && planes_for(p, pm.nrhs_max) <= kSpreadCsrPlanes) {
     // W^T by grid node (Step 1 of Sec. 3.3 as a sparse product): entries of a
     // node in increasing point order, weight = product of the 1D weights
     const int K1 = g.q + 1;
@@ -1576,7 +1708,7 @@ int build_plan(fftpim_plan_s* p, int64_t N, const double* src_dev, hipStream_t s
     CHK(upload(p, &p->wt_val, wval));
   }
   CHK(upload(p, &p->fs_w, weights_soa(fs_u, N, f.q)));
-  CHK(upload(p, &p->fo_w, weights_soa(fo_u, N, f.q)));
+  CHK(upload(p, &p->fo_w, weights_soa(fo_u, p->No, f.q)));
   CHK(upload(p, &p->fperm_s, forder_s));
   CHK(upload(p, &p->fbox_start_s, fstart_s));
   CHK(upload(p, &p->fperm_o, forder_o));
@@ -1605,7 +1737,11 @@ int build_plan(fftpim_plan_s* p, int64_t N, const double* src_dev, hipStream_t s
     // box's amplitudes and row sums
     const bool fits = static_cast<int64_t>(max_box) * Pm <= 2048 && g.q <= 7;
     const bool dense = static_cast<double>(N) >= 3.0 * static_cast<double>(std::max<int64_t>(nonempty, 1));
-    if (pm.corr_layout == FFTPIM_CORR_SYM) {
+    if (sep) {
+      // the box-pair blocks and the dense tiles rely on the correction being
+      // symmetric in observer and source: separate observers use the CSR
+      if (pm.corr_layout != FFTPIM_CORR_AUTO && pm.corr_layout != FFTPIM_CORR_CSR) return FFTPIM_ERR_UNSUPPORTED;
+    } else if (pm.corr_layout == FFTPIM_CORR_SYM) {
       if (!fits) return FFTPIM_ERR_INVALID_ARG;
       p->sym = true;
     } else if (pm.corr_layout == FFTPIM_CORR_TILE) {
@@ -1618,22 +1754,25 @@ int build_plan(fftpim_plan_s* p, int64_t N, const double* src_dev, hipStream_t s
       p->sym = !p->tile && fits && dense && Pm <= 4;
     }
   }
-  CHK(build_correction(p, start, dpos, st));
+  CHK(build_correction(p, start, dpos, sep ? &go.start : nullptr, dpos_o, st));
   plan_log("correction operator", t0);
   p->pos3 = dpos;  // kept for the exact terms of the position gradient
+  if (dpos_o) dfree(p, dpos_o);
 
   // workspace
   const int P = planes_for(p, pm.nrhs_max);
   p->nplanes_max = P;
   const size_t es = cbytes(p);
+  // packed inputs and the three parts hold either point set
+  const size_t Nmax = static_cast<size_t>(std::max(N, p->No));
   unsigned char* b = nullptr;
-  CHK(dalloc(p, &b, static_cast<size_t>(N) * P * es));
+  CHK(dalloc(p, &b, Nmax * P * es));
   p->q_int = b;
-  CHK(dalloc(p, &b, static_cast<size_t>(N) * P * es));
+  CHK(dalloc(p, &b, Nmax * P * es));
   p->u_int = b;
-  CHK(dalloc(p, &b, static_cast<size_t>(N) * P * es));
+  CHK(dalloc(p, &b, Nmax * P * es));
   p->u_corr = b;
-  CHK(dalloc(p, &b, static_cast<size_t>(N) * P * es));
+  CHK(dalloc(p, &b, Nmax * P * es));
   p->u_far = b;
   HIPCHK(hipStreamCreateWithFlags(&p->s_corr, hipStreamNonBlocking));
   HIPCHK(hipStreamCreateWithFlags(&p->s_far, hipStreamNonBlocking));
@@ -1652,7 +1791,7 @@ int build_plan(fftpim_plan_s* p, int64_t N, const double* src_dev, hipStream_t s
     p->sym_zpart = b;
   }
   CHK(dalloc(p, &p->sums, static_cast<size_t>(6) * P));
-  CHK(dalloc(p, &p->sums_work, static_cast<size_t>(plane_sums_chunks(N)) * P * 4));
+  CHK(dalloc(p, &p->sums_work, static_cast<size_t>(plane_sums_chunks(static_cast<int64_t>(Nmax))) * P * 4));
   CHK(dalloc(p, &p->status_dev, 1));
   HIPCHK(hipMemsetAsync(p->status_dev, 0, sizeof(int), st));
   HIPCHK(hipStreamSynchronize(st));
@@ -1754,8 +1893,13 @@ int fftpim_plan(fftpim_plan_t* plan, const fftpim_problem_t* problem, const fftp
     if (!plan || !problem || !params || !src_xyz_dev) return FFTPIM_ERR_INVALID_ARG;
     *plan = nullptr;
     if (n_src < 1 || n_src > (int64_t{1} << 30)) return FFTPIM_ERR_INVALID_ARG;
-    if (obs_xyz_dev != nullptr) return FFTPIM_ERR_UNIMPLEMENTED;
-    if (n_obs != n_src && n_obs != 0) return FFTPIM_ERR_INVALID_ARG;
+    if (obs_xyz_dev != nullptr) {
+      // separate observers: the self term of Eq. (5) has no meaning
+      if (n_obs < 1 || n_obs > (int64_t{1} << 30)) return FFTPIM_ERR_INVALID_ARG;
+      if (params->self_mode != FFTPIM_SELF_IMAGES) return FFTPIM_ERR_INVALID_ARG;
+    } else if (n_obs != n_src && n_obs != 0) {
+      return FFTPIM_ERR_INVALID_ARG;
+    }
     CHK(validate(problem, params));
     const Lattice lat = lattice_of(*problem);
     if (params->value_type == FFTPIM_REAL && !lat.npsp()) return FFTPIM_ERR_INVALID_ARG;
@@ -1774,7 +1918,7 @@ int fftpim_plan(fftpim_plan_t* plan, const fftpim_problem_t* problem, const fftp
     if (params->self_mode == FFTPIM_SELF_EXCLUDE) p->self_coef = pgf_self(lat);
     hipStream_t st = static_cast<hipStream_t>(stream);
     // an exception inside the build still frees the partly built plan
-    int s = guarded([&]() -> int { return build_plan(p, n_src, src_xyz_dev, st); });
+    int s = guarded([&]() -> int { return build_plan(p, n_src, src_xyz_dev, n_obs, obs_xyz_dev, st); });
     if (s != FFTPIM_OK) {
       fftpim_destroy(p);
       return s;
@@ -1809,6 +1953,7 @@ int fftpim_apply_pair(fftpim_plan_t plan, const void* q_dev, void* u_dev, const 
   return guarded([&]() -> int {
     if (!plan || !q_dev || !u_dev || !v_dev || !w_dev) return FFTPIM_ERR_INVALID_ARG;
     if (nrhs < 1 || nrhs > plan->prm.nrhs_max) return FFTPIM_ERR_INVALID_ARG;
+    if (plan->sep) return FFTPIM_ERR_UNSUPPORTED;
     hipStream_t st = static_cast<hipStream_t>(stream);
     CHK(ensure_pair_buffers(plan));
     if (plan->prm.precision != FFTPIM_F64)
@@ -1822,6 +1967,7 @@ int fftpim_apply_pair_noalloc(fftpim_plan_t plan, const void* q_dev, void* u_dev
   return guarded([&]() -> int {
     if (!plan || !q_dev || !u_dev || !v_dev || !w_dev) return FFTPIM_ERR_INVALID_ARG;
     if (nrhs < 1 || nrhs > plan->prm.nrhs_max) return FFTPIM_ERR_INVALID_ARG;
+    if (plan->sep) return FFTPIM_ERR_UNSUPPORTED;
     if (pair_buffer_bytes(plan) > kScratchBytes) return FFTPIM_ERR_SCRATCH_LIMIT;
     void* base = nullptr;
     CHK(scratch_address(plan->device, &base));
@@ -1843,7 +1989,7 @@ int fftpim_grad_positions(fftpim_plan_t plan, const void* q_dev, const void* g_d
   return guarded([&]() -> int {
     if (!plan || !q_dev || !g_dev || !grad_dev) return FFTPIM_ERR_INVALID_ARG;
     if (nrhs < 1 || nrhs > plan->prm.nrhs_max) return FFTPIM_ERR_INVALID_ARG;
-    if (plan->g0tab == nullptr || plan->pos3 == nullptr) return FFTPIM_ERR_UNSUPPORTED;
+    if (plan->g0tab == nullptr || plan->pos3 == nullptr || plan->sep) return FFTPIM_ERR_UNSUPPORTED;
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (plan->prm.precision != FFTPIM_F64) return run_grad<float>(plan, q_dev, g_dev, nrhs, grad_dev, st);
     return run_grad<double>(plan, q_dev, g_dev, nrhs, grad_dev, st);
@@ -1860,7 +2006,10 @@ int fftpim_apply_parts(fftpim_plan_t plan, int parts, int adjoint, const void* q
 int fftpim_get_permutation(fftpim_plan_t plan, int which, int32_t* perm_dev) {
   return guarded([&]() -> int {
     if (!plan || !perm_dev || (which != 0 && which != 1)) return FFTPIM_ERR_INVALID_ARG;
-    HIPCHK(hipMemcpy(perm_dev, plan->perm, plan->N * sizeof(int32_t), hipMemcpyDeviceToDevice));
+    if (which == 1)
+      HIPCHK(hipMemcpy(perm_dev, plan->perm_o, plan->No * sizeof(int32_t), hipMemcpyDeviceToDevice));
+    else
+      HIPCHK(hipMemcpy(perm_dev, plan->perm, plan->N * sizeof(int32_t), hipMemcpyDeviceToDevice));
     return FFTPIM_OK;
   });
 }
@@ -1870,7 +2019,7 @@ int fftpim_plan_info(fftpim_plan_t plan, fftpim_info_t* info) {
     if (!plan || !info) return FFTPIM_ERR_INVALID_ARG;
     fftpim_info_t r{};
     r.n_src = plan->N;
-    r.n_obs = plan->N;
+    r.n_obs = plan->No;
     for (int c = 0; c < 3; ++c) {
       r.near_n[c] = plan->ng.n[c];
       r.near_fft[c] = plan->M[c];
@@ -1883,9 +2032,9 @@ int fftpim_plan_info(fftpim_plan_t plan, fftpim_info_t* info) {
       r.far_h[c] = plan->fg.h[c];
       r.far_fft[c] = plan->Mf[c];
     }
-    r.corr_nnz = plan->nnz + plan->sym_nvals;
+    r.corr_nnz = plan->nnz + plan->nnz_a + plan->sym_nvals;
     r.corr_sym_values = plan->sym_nvals;
-    r.corr_csr_nnz = plan->tile ? 0 : plan->nnz;
+    r.corr_csr_nnz = plan->tile ? 0 : plan->nnz + plan->nnz_a;
     r.corr_tile_values = plan->tile_nvals;
     r.corr_value_bytes = plan->complex_kernel ? 16 : 8;
     r.corr_layout_used = plan->tile ? FFTPIM_CORR_TILE : (plan->sym ? FFTPIM_CORR_SYM : FFTPIM_CORR_CSR);

@@ -196,7 +196,8 @@ struct CorrArgs {
   int nb[3], nint[3], per[3];
   int rc, id;
   int R, W;            // g0 table covers offsets [-R, R]^3, W = 2R + 1
-  int64_t N;
+  int64_t N;           // row points (observers)
+  int64_t Nc;          // column points (sources; = N when the sets coincide)
   double L[3];
   double k0, k0_im;
   int nimg_axis;       // 2 id + 1
@@ -335,7 +336,24 @@ struct fftpim_plan_s {
   fftpim::Lattice lat;
   fftpim_problem_t problem;
   fftpim_params_t prm;
-  int64_t N = 0;
+  int64_t N = 0;               // sources
+  // separate observers (otherwise the observer arrays below alias the
+  // source arrays and No = N)
+  bool sep = false;
+  int64_t No = 0;
+  int32_t* perm_o = nullptr;      // observer plan position -> caller index
+  int32_t* near_s_o = nullptr;    // observer near stencils, weights, box sort
+  double* near_u_o = nullptr;
+  double* near_w_o = nullptr;
+  int32_t* box_start_o = nullptr;
+  // conjugate-transpose correction with separate observers: CSR with source
+  // rows and observer columns holding C^H
+  int64_t* rowptr_a = nullptr;
+  int32_t* col_a = nullptr;
+  void* val_a = nullptr;
+  int32_t* corr_order_a = nullptr;
+  int64_t corr_slots_a = 0;
+  int64_t nnz_a = 0;
   int device = 0;              // HIP device current when the plan was made
   bool complex_kernel = true;  // G0 or the phases are complex
   bool nonhermitian = false;   // k0 != 0 or a complex phase shift: C^H needs its own values

@@ -165,9 +165,11 @@ void launch_scale_convert(const void* in, void* out, int64_t n, double s, hipStr
 // correction
 int launch_corr_count(const CorrArgs& a, const int32_t* s3, const int32_t* box_start, int64_t* rowcount,
                       hipStream_t st);
+// rows: s3/u3/pos3 ([3][a.N]); columns: u3c/pos3c ([3][a.Nc]) and box_start
 int launch_corr_fill(int q, bool cplx_vals, bool adj, const CorrArgs& a, const int32_t* s3, const double* u3,
-                     const double* pos3, const int32_t* box_start, const void* g0tab, const int64_t* rowptr,
-                     int32_t* col, void* val, void* val_adj, hipStream_t st);
+                     const double* pos3, const double* u3c, const double* pos3c, const int32_t* box_start,
+                     const void* g0tab, const int64_t* rowptr, int32_t* col, void* val, void* val_adj,
+                     hipStream_t st);
 // Dense row tiles of real correction values (see kernels_corr.hip).
 void launch_tile_fill(const int32_t* tile_rows, int64_t nslots, const int64_t* rowptr, const int32_t* col,
                       const double* val, const int64_t* coff, const int32_t* cols, const int64_t* voff, double* tv,

@@ -49,19 +49,23 @@ __global__ void k_corr_count(CorrArgs a, const int32_t* __restrict__ s3, const i
   rowcount[m] = cnt;
 }
 
+// Rows are the points of s3/u3/pos3 ([3][N]), columns those of
+// box_start/u3c/pos3c ([3][Nc]); the two sets coincide unless the plan has
+// separate observers.  A pair at zero distance (the self pair, or an
+// observer placed on a source) keeps only its grid part.
 template <int Q, bool CPLX, bool ADJ, bool LT>
 __global__ void __launch_bounds__(256) k_corr_fill(
     CorrArgs a, const int32_t* __restrict__ s3, const double* __restrict__ u3, const double* __restrict__ pos3,
-    const int32_t* __restrict__ box_start, const cplx<double>* __restrict__ g0tab,
-    const int64_t* __restrict__ rowptr, int32_t* __restrict__ col, void* __restrict__ val_v,
-    void* __restrict__ vadj_v) {
+    const double* __restrict__ u3c, const double* __restrict__ pos3c, const int32_t* __restrict__ box_start,
+    const cplx<double>* __restrict__ g0tab, const int64_t* __restrict__ rowptr, int32_t* __restrict__ col,
+    void* __restrict__ val_v, void* __restrict__ vadj_v) {
   const int32_t *loff0 = a.loff[0], *loff1 = a.loff[1], *loff2 = a.loff[2];
   const int32_t *lent0 = a.lent[0], *lent1 = a.lent[1], *lent2 = a.lent[2];
   extern __shared__ double lt[];
   if (LT) tab_stage<CPLX>(g0tab, lt, static_cast<int64_t>(a.W) * a.W * a.W);
   int64_t m = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (m >= a.N) return;
-  const int64_t N = a.N;
+  const int64_t N = a.N, Nc = a.Nc;
   const int S[3] = {s3[m], s3[N + m], s3[2 * N + m]};
   double wm[3][Q + 1];
   for (int c = 0; c < 3; ++c) lagrange_all<Q, double>(u3[c * N + m], wm[c]);
@@ -87,7 +91,7 @@ __global__ void __launch_bounds__(256) k_corr_fill(
         const int n0 = box_start[b], n1 = box_start[b + 1];
         for (int n = n0; n < n1; ++n) {
           double wn[3][Q + 1];
-          for (int c = 0; c < 3; ++c) lagrange_all<Q, double>(u3[c * N + n], wn[c]);
+          for (int c = 0; c < 3; ++c) lagrange_all<Q, double>(u3c[c * Nc + n], wn[c]);
           double C[3][2 * Q + 1];
           for (int c = 0; c < 3; ++c)
             for (int d = -Q; d <= Q; ++d) {
@@ -95,7 +99,7 @@ __global__ void __launch_bounds__(256) k_corr_fill(
               for (int aa = max(0, d); aa <= min(Q, Q + d); ++aa) s += wm[c][aa] * wn[c][aa - d];
               C[c][d + Q] = s;
             }
-          const double rn[3] = {pos3[n], pos3[N + n], pos3[2 * N + n]};
+          const double rn[3] = {pos3c[n], pos3c[Nc + n], pos3c[2 * Nc + n]};
           double fr = 0.0, fi = 0.0, ar = 0.0, ai = 0.0;
           for (int gx = 0; gx < A; ++gx) {
             if (!((mx >> gx) & 1)) continue;
@@ -111,11 +115,11 @@ __global__ void __launch_bounds__(256) k_corr_fill(
                                   S[2] - bz - imz * a.nint[2]};
                 // exact part
                 double er = 0.0, ei = 0.0;
-                if (!(n == m && imx == 0 && imy == 0 && imz == 0)) {
-                  double dx = rm[0] - rn[0] - imx * a.L[0];
-                  double dy = rm[1] - rn[1] - imy * a.L[1];
-                  double dz = rm[2] - rn[2] - imz * a.L[2];
-                  double r = sqrt(dx * dx + dy * dy + dz * dz);
+                const double ddx = rm[0] - rn[0] - imx * a.L[0];
+                const double ddy = rm[1] - rn[1] - imy * a.L[1];
+                const double ddz = rm[2] - rn[2] - imz * a.L[2];
+                const double r = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
+                if (r > 0.0) {
                   double inv = (a.k0_im != 0.0 ? exp(a.k0_im * r) : 1.0) / (4.0 * M_PI * r);
                   if (CPLX) {
                     double s, c;
@@ -496,8 +500,8 @@ int launch_corr_count(const CorrArgs& a, const int32_t* s3, const int32_t* box_s
 
 template <int Q>
 static void fill_q(bool cplx_vals, bool adj, const CorrArgs& a, const int32_t* s3, const double* u3,
-                   const double* pos3, const int32_t* box_start, const void* g0tab, const int64_t* rowptr,
-                   int32_t* col, void* val, void* val_adj, hipStream_t st) {
+                   const double* pos3, const double* u3c, const double* pos3c, const int32_t* box_start,
+                   const void* g0tab, const int64_t* rowptr, int32_t* col, void* val, void* val_adj, hipStream_t st) {
   // the table in LDS when it fits (blocks of 256 rows), else read from
   // global memory (blocks of 64)
   const size_t lds = tab_lds_bytes(a.W, cplx_vals);
@@ -508,11 +512,11 @@ static void fill_q(bool cplx_vals, bool adj, const CorrArgs& a, const int32_t* s
 #define FFTPIM_FILL(C, J)                                                                                     \
   do {                                                                                                        \
     if (lt)                                                                                                   \
-      hipLaunchKernelGGL((k_corr_fill<Q, C, J, true>), dim3(nb), dim3(bs), lds, st, a, s3, u3, pos3,         \
-                         box_start, g, rowptr, col, val, val_adj);                                            \
+      hipLaunchKernelGGL((k_corr_fill<Q, C, J, true>), dim3(nb), dim3(bs), lds, st, a, s3, u3, pos3, u3c,    \
+                         pos3c, box_start, g, rowptr, col, val, val_adj);                                     \
     else                                                                                                      \
-      hipLaunchKernelGGL((k_corr_fill<Q, C, J, false>), dim3(nb), dim3(bs), 0, st, a, s3, u3, pos3,          \
-                         box_start, g, rowptr, col, val, val_adj);                                            \
+      hipLaunchKernelGGL((k_corr_fill<Q, C, J, false>), dim3(nb), dim3(bs), 0, st, a, s3, u3, pos3, u3c,     \
+                         pos3c, box_start, g, rowptr, col, val, val_adj);                                     \
   } while (0)
   if (!cplx_vals)
     FFTPIM_FILL(false, false);
@@ -524,17 +528,18 @@ static void fill_q(bool cplx_vals, bool adj, const CorrArgs& a, const int32_t* s
 }
 
 int launch_corr_fill(int q, bool cplx_vals, bool adj, const CorrArgs& a, const int32_t* s3, const double* u3,
-                     const double* pos3, const int32_t* box_start, const void* g0tab, const int64_t* rowptr,
-                     int32_t* col, void* val, void* val_adj, hipStream_t st) {
+                     const double* pos3, const double* u3c, const double* pos3c, const int32_t* box_start,
+                     const void* g0tab, const int64_t* rowptr, int32_t* col, void* val, void* val_adj,
+                     hipStream_t st) {
   switch (q) {
-    case 1: fill_q<1>(cplx_vals, adj, a, s3, u3, pos3, box_start, g0tab, rowptr, col, val, val_adj, st); break;
-    case 2: fill_q<2>(cplx_vals, adj, a, s3, u3, pos3, box_start, g0tab, rowptr, col, val, val_adj, st); break;
-    case 3: fill_q<3>(cplx_vals, adj, a, s3, u3, pos3, box_start, g0tab, rowptr, col, val, val_adj, st); break;
-    case 4: fill_q<4>(cplx_vals, adj, a, s3, u3, pos3, box_start, g0tab, rowptr, col, val, val_adj, st); break;
-    case 5: fill_q<5>(cplx_vals, adj, a, s3, u3, pos3, box_start, g0tab, rowptr, col, val, val_adj, st); break;
-    case 6: fill_q<6>(cplx_vals, adj, a, s3, u3, pos3, box_start, g0tab, rowptr, col, val, val_adj, st); break;
-    case 7: fill_q<7>(cplx_vals, adj, a, s3, u3, pos3, box_start, g0tab, rowptr, col, val, val_adj, st); break;
-    case 8: fill_q<8>(cplx_vals, adj, a, s3, u3, pos3, box_start, g0tab, rowptr, col, val, val_adj, st); break;
+    case 1: fill_q<1>(cplx_vals, adj, a, s3, u3, pos3, u3c, pos3c, box_start, g0tab, rowptr, col, val, val_adj, st); break;
+    case 2: fill_q<2>(cplx_vals, adj, a, s3, u3, pos3, u3c, pos3c, box_start, g0tab, rowptr, col, val, val_adj, st); break;
+    case 3: fill_q<3>(cplx_vals, adj, a, s3, u3, pos3, u3c, pos3c, box_start, g0tab, rowptr, col, val, val_adj, st); break;
+    case 4: fill_q<4>(cplx_vals, adj, a, s3, u3, pos3, u3c, pos3c, box_start, g0tab, rowptr, col, val, val_adj, st); break;
+    case 5: fill_q<5>(cplx_vals, adj, a, s3, u3, pos3, u3c, pos3c, box_start, g0tab, rowptr, col, val, val_adj, st); break;
+    case 6: fill_q<6>(cplx_vals, adj, a, s3, u3, pos3, u3c, pos3c, box_start, g0tab, rowptr, col, val, val_adj, st); break;
+    case 7: fill_q<7>(cplx_vals, adj, a, s3, u3, pos3, u3c, pos3c, box_start, g0tab, rowptr, col, val, val_adj, st); break;
+    case 8: fill_q<8>(cplx_vals, adj, a, s3, u3, pos3, u3c, pos3c, box_start, g0tab, rowptr, col, val, val_adj, st); break;
     default: return FFTPIM_ERR_UNSUPPORTED;
   }
   return FFTPIM_OK;

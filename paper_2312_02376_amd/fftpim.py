@@ -186,12 +186,18 @@ class Plan:
     def __init__(self, positions, periodic_dims, L, k0=0.0, kt=(0.0, 0.0, 0.0), near_n=(16, 16, 16),
                  near_order=4, corr_radius=6, far_n=(16, 16, 16), far_order=7, n_images=1, precision="f64",
                  value_type="complex", order="user", nrhs_max=1, box=None, self_mode="images",
-                 corr_layout="auto", max_bytes=0, corr_ball=0.0, far_sum="auto", stream=None):
+                 corr_layout="auto", max_bytes=0, corr_ball=0.0, far_sum="auto", observers=None, stream=None):
         import torch
         if not (isinstance(positions, torch.Tensor) and positions.is_cuda and positions.dtype == torch.float64):
             raise TypeError("positions must be a CUDA float64 tensor of shape (N, 3)")
         pos = positions.contiguous()
         self.N = int(pos.shape[0])
+        obs = None
+        if observers is not None:
+            if not (isinstance(observers, torch.Tensor) and observers.is_cuda and observers.dtype == torch.float64):
+                raise TypeError("observers must be a CUDA float64 tensor of shape (M, 3)")
+            obs = observers.contiguous()
+        self.M = self.N if obs is None else int(obs.shape[0])
         self.problem = make_problem(periodic_dims, L, k0, kt, box)
         pm = Params()
         for c in range(3):
@@ -221,20 +227,25 @@ class Plan:
         self.device = pos.device
         h = ctypes.c_void_p()
         _check(lib().fftpim_plan(ctypes.byref(h), ctypes.byref(self.problem), ctypes.byref(pm), self.N,
-                                 ctypes.c_void_p(pos.data_ptr()), 0, None, _stream_handle(stream)), "fftpim_plan")
+                                 ctypes.c_void_p(pos.data_ptr()), 0 if obs is None else self.M,
+                                 None if obs is None else ctypes.c_void_p(obs.data_ptr()), _stream_handle(stream)),
+               "fftpim_plan")
         self._h = h
 
-    def _io(self, x, out):
+    def _io(self, x, out, adjoint=False):
+        """Checks an input of the sources (observers when adjoint) and an
+        output of the observers (sources when adjoint)."""
         import torch
+        n_in, n_out = (self.M, self.N) if adjoint else (self.N, self.M)
         if not isinstance(x, torch.Tensor) or x.dtype != self.dtype or x.device != self.device:
             raise TypeError("expected a %s tensor on %s" % (self.dtype, self.device))
         squeeze = x.dim() == 1
         x2 = x.reshape(1, -1) if squeeze else x
-        if x2.shape[1] != self.N:
-            raise ValueError("expected %d points, got %d" % (self.N, x2.shape[1]))
+        if x2.shape[1] != n_in:
+            raise ValueError("expected %d points, got %d" % (n_in, x2.shape[1]))
         x2 = x2.contiguous()
         if out is None:
-            out = torch.empty_like(x2)
+            out = torch.empty((x2.shape[0], n_out), dtype=x2.dtype, device=x2.device)
         else:
             # the library writes nrhs x N elements through out's pointer:
             # accept only a tensor that holds exactly that, densely
@@ -243,8 +254,10 @@ class Plan:
             if out.device != self.device:
                 raise ValueError("out is on %s, the plan on %s" % (out.device, self.device))
             o2 = out.reshape(1, -1) if (squeeze and out.dim() == 1) else out
-            if tuple(o2.shape) != tuple(x2.shape):
-                raise ValueError("out has shape %s, expected %s" % (tuple(out.shape), tuple(x.shape)))
+            want = (x2.shape[0], n_out)
+            if tuple(o2.shape) != want:
+                raise ValueError("out has shape %s, expected %s" % (tuple(out.shape),
+                                                                   (n_out,) if squeeze else want))
             if not out.is_contiguous():
                 raise ValueError("out must be contiguous")
             if _overlap(out, x2):
@@ -261,7 +274,7 @@ class Plan:
 
     def adjoint(self, v, out=None, stream=None):
         """w = A^H v (mean removed for the neutral static case)."""
-        v2, out, sq = self._io(v, out)
+        v2, out, sq = self._io(v, out, adjoint=True)
         _check(lib().fftpim_apply_adjoint(self._h, ctypes.c_void_p(v2.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                           v2.shape[0], _stream_handle(stream)), "fftpim_apply_adjoint")
         return out[0] if sq else out
@@ -320,16 +333,20 @@ class Plan:
         return x2
 
     def apply_parts(self, q, parts, adjoint=False, out=None, stream=None):
-        q2, out, sq = self._io(q, out)
+        q2, out, sq = self._io(q, out, adjoint=adjoint)
         _check(lib().fftpim_apply_parts(self._h, int(parts), 1 if adjoint else 0, ctypes.c_void_p(q2.data_ptr()),
                                         ctypes.c_void_p(out.data_ptr()), q2.shape[0], _stream_handle(stream)),
                "fftpim_apply_parts")
         return out[0] if sq else out
 
-    def permutation(self):
+    def permutation(self, observers=False):
+        """Plan-order position -> caller index, of the sources or (with
+        observers=True) of the observers."""
         import torch
-        perm = torch.empty(self.N, dtype=torch.int32, device=self.device)
-        _check(lib().fftpim_get_permutation(self._h, 0, ctypes.c_void_p(perm.data_ptr())), "fftpim_get_permutation")
+        n = self.M if observers else self.N
+        perm = torch.empty(n, dtype=torch.int32, device=self.device)
+        _check(lib().fftpim_get_permutation(self._h, 1 if observers else 0, ctypes.c_void_p(perm.data_ptr())),
+               "fftpim_get_permutation")
         return perm
 
     def info(self):

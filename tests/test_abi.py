@@ -188,3 +188,21 @@ def test_autotune_and_batch_argument_checks():
     assert L.fftpim_batch_create(ctypes.byref(h), plans, 2, 17, 0) == 1     # lanes 1..16
     assert L.fftpim_batch_apply(None, None, None, None, 0, None) == 1
     assert L.fftpim_batch_destroy(None) == 1
+
+
+def test_separate_observer_argument_checks():
+    # both fail before the library reads the (dummy) points
+    L = fp.lib()
+    pr = fp.make_problem(3, [1.0, 1.0, 1.0])
+    pm = fp.Params()
+    assert L.fftpim_default_params(ctypes.byref(pr), ctypes.byref(pm)) == 0
+    h = ctypes.c_void_p()
+    dummy = ctypes.c_void_p(0x1000)
+    # an observer array needs n_obs >= 1
+    assert L.fftpim_plan(ctypes.byref(h), ctypes.byref(pr), ctypes.byref(pm), 10, dummy, 0, dummy, None) == 1
+    # the exclude-self mode has no meaning for separate observers
+    pm.self_mode = 1
+    assert L.fftpim_plan(ctypes.byref(h), ctypes.byref(pr), ctypes.byref(pm), 10, dummy, 5, dummy, None) == 1
+    # without an observer array n_obs is 0 or n_src
+    pm.self_mode = 0
+    assert L.fftpim_plan(ctypes.byref(h), ctypes.byref(pr), ctypes.byref(pm), 10, dummy, 5, None, None) == 1

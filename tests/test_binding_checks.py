@@ -10,9 +10,10 @@ torch = pytest.importorskip("torch")
 from paper_2312_02376_amd import fftpim as fp  # noqa: E402
 
 
-def _stub(N=7, dtype=torch.complex128):
+def _stub(N=7, dtype=torch.complex128, M=None):
     p = fp.Plan.__new__(fp.Plan)
     p.N = N
+    p.M = N if M is None else M
     p.dtype = dtype
     p.device = torch.device("cpu")
     p._h = None
@@ -67,3 +68,18 @@ def test_pair_outputs_may_not_overlap():
         p.apply_pair(q, v, out_u=buf[0:2], out_w=buf[1:3])
     with pytest.raises(ValueError):
         p.apply_pair(q, v, out_u=v.clone(), out_w=q)
+
+
+def test_separate_observer_shapes():
+    # 7 sources, 5 observers: apply takes 7 and gives 5, the adjoint the reverse
+    p = _stub(7, M=5)
+    x2, out, sq = p._io(torch.zeros(2, 7, dtype=torch.complex128), None)
+    assert out.shape == (2, 5)
+    x2, out, sq = p._io(torch.zeros(2, 5, dtype=torch.complex128), None, adjoint=True)
+    assert out.shape == (2, 7)
+    with pytest.raises(ValueError):
+        p._io(torch.zeros(2, 5, dtype=torch.complex128), None)
+    with pytest.raises(ValueError):
+        p._io(torch.zeros(2, 7, dtype=torch.complex128), torch.zeros(2, 7, dtype=torch.complex128))
+    x2, out, sq = p._io(torch.zeros(7, dtype=torch.complex128), torch.zeros(5, dtype=torch.complex128))
+    assert sq and out.shape == (1, 5)
