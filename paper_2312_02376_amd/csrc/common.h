@@ -267,6 +267,110 @@ __device__ inline bool any_close(const CorrArgs& a, const int S[3], int bx, int 
   return false;
 }
 
+// Wave-level inclusive prefix sum and total of an int, and sum of a double.
+__device__ inline int wave_incl_scan(int v, int lane) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Orders one wavefront's LDS writes before its later reads (and reads before
+// later writes): the lanes of a wave run in lockstep, so a compiler and
+// memory fence at workgroup scope is all that is needed.
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+constexpr int kPairBPL = 2;                    // candidate boxes per lane per chunk
+constexpr int kPairCH = 64 * kPairBPL;         // candidate boxes per chunk
+constexpr int kPairListInts = 3 * kPairCH + 1;  // per-wave LDS lists (prefix, first point, candidate)
+
+// The close pairs of one row point, enumerated by one wavefront: the row's
+// box S has per-axis candidate lists [lo, hi) of column boxes; their product
+// is taken kPairCH candidates at a time, every lane counting the points of
+// kPairBPL boxes (zero for boxes with no close image), a wave prefix sum
+// laying the chunk's pairs out, and the pairs are then handed out 64 at a
+// time, one per lane (lane t finds its box by binary search over the
+// prefix).  Pairs come in candidate order (x, then y, then z box), points in
+// order within a box: body(t, n, bx, by, bz, mx, my, mz) runs on the lanes
+// that hold pair t of the row (t counted from 0 over the whole row), n being
+// the column point and m* the per-axis image masks.  lists: kPairListInts
+// ints of LDS owned by the wave.
+template <typename F>
+__device__ inline void wave_pairs(const CorrArgs& a, const int S[3], const int lo[3], const int hi[3],
+                                  const int32_t* __restrict__ box_start, int* lists, int lane, F&& body) {
+  int* pre = lists;              // [kPairCH + 1] pair offsets of the chunk's boxes
+  int* cn0 = pre + kPairCH + 1;  // [kPairCH] first point of each box
+  int* ccd = cn0 + kPairCH;      // [kPairCH] candidate index of each box
+  const int Ly = hi[1] - lo[1], Lz = hi[2] - lo[2];
+  const int ncand = (hi[0] - lo[0]) * Ly * Lz;
+  int64_t tbase = 0;
+  for (int c0 = 0; c0 < ncand; c0 += kPairCH) {
+    int cnt[kPairBPL], n0[kPairBPL];
+    int sum = 0;
+#pragma unroll
+    for (int i = 0; i < kPairBPL; ++i) {
+      const int c = c0 + lane * kPairBPL + i;
+      cnt[i] = 0;
+      n0[i] = 0;
+      if (c < ncand) {
+        const int ex = a.lent[0][lo[0] + c / (Ly * Lz)], ey = a.lent[1][lo[1] + (c / Lz) % Ly],
+                  ez = a.lent[2][lo[2] + c % Lz];
+        const int bx = ex & 0xffff, by = ey & 0xffff, bz = ez & 0xffff;
+        if (any_close(a, S, bx, by, bz, ex >> 16, ey >> 16, ez >> 16)) {
+          const int64_t b = (static_cast<int64_t>(bx) * a.nb[1] + by) * a.nb[2] + bz;
+          n0[i] = box_start[b];
+          cnt[i] = box_start[b + 1] - n0[i];
+        }
+      }
+      sum += cnt[i];
+    }
+    const int incl = wave_incl_scan(sum, lane);
+    const int tot = __shfl(incl, 63, 64);
+    int run = incl - sum;
+#pragma unroll
+    for (int i = 0; i < kPairBPL; ++i) {
+      pre[lane * kPairBPL + i] = run;
+      cn0[lane * kPairBPL + i] = n0[i];
+      ccd[lane * kPairBPL + i] = c0 + lane * kPairBPL + i;
+      run += cnt[i];
+    }
+    if (lane == 0) pre[kPairCH] = tot;
+    wave_lds_sync();
+    for (int t0 = 0; t0 < tot; t0 += 64) {
+      const int t = t0 + lane;
+      if (t < tot) {
+        // the box holding pair t: the largest i with pre[i] <= t (it has at
+        // least one point since pre[i + 1] > t)
+        int ilo = 0, ihi = kPairCH - 1;
+        while (ilo < ihi) {
+          const int mid = (ilo + ihi + 1) >> 1;
+          if (pre[mid] <= t) ilo = mid;
+          else ihi = mid - 1;
+        }
+        const int n = cn0[ilo] + (t - pre[ilo]);
+        const int c = ccd[ilo];
+        const int ex = a.lent[0][lo[0] + c / (Ly * Lz)], ey = a.lent[1][lo[1] + (c / Lz) % Ly],
+                  ez = a.lent[2][lo[2] + c % Lz];
+        body(tbase + t, n, ex & 0xffff, ey & 0xffff, ez & 0xffff, ex >> 16, ey >> 16, ez >> 16);
+      }
+    }
+    tbase += tot;
+    wave_lds_sync();
+  }
+}
+
 template <bool CPLX>
 __device__ inline void tab_stage(const cplx<double>* __restrict__ g, double* lt, int64_t n) {
   for (int64_t t = threadIdx.x; t < n; t += blockDim.x) {

@@ -49,136 +49,151 @@ __global__ void k_corr_count(CorrArgs a, const int32_t* __restrict__ s3, const i
   rowcount[m] = cnt;
 }
 
-// Rows are the points of s3/u3/pos3 ([3][N]), columns those of
-// box_start/u3c/pos3c ([3][Nc]); the two sets coincide unless the plan has
-// separate observers.  A pair at zero distance (the self pair, or an
-// observer placed on a source) keeps only its grid part.
+// The correction values of Eq. (er): for each close triple (m, n, i),
+// phi_i [G0(r_m - r_n - R_i) - sum_ab w_a(r_m) w_b(r_n) G0tab(a - b + D_i)],
+// the double sum taken through 1D weight correlations.  Rows are the points
+// of s3/u3/pos3 ([3][N]), columns those of box_start/u3c/pos3c ([3][Nc]);
+// the two sets coincide unless the plan has separate observers.  A pair at
+// zero distance (the self pair, or an observer placed on a source) keeps
+// only its grid part.  One wavefront per row (kFillRPW rows in turn):
+// wave_pairs hands the row's close pairs to the lanes 64 at a time in the
+// order the count kernel and the row pointers assume, so entry t of row m
+// goes to rowptr[m] + t.  ADJ also writes the values of C^H on the same
+// pattern.  The G0 table is read from LDS when LT.
+constexpr int kFillWaves = 4, kFillRPW = 8;
+
+inline size_t fill_list_bytes() { return static_cast<size_t>(kFillWaves) * kPairListInts * sizeof(int); }
+
 template <int Q, bool CPLX, bool ADJ, bool LT>
-__global__ void __launch_bounds__(256) k_corr_fill(
+__global__ void __launch_bounds__(64 * kFillWaves) k_corr_fill_wave(
     CorrArgs a, const int32_t* __restrict__ s3, const double* __restrict__ u3, const double* __restrict__ pos3,
     const double* __restrict__ u3c, const double* __restrict__ pos3c, const int32_t* __restrict__ box_start,
     const cplx<double>* __restrict__ g0tab, const int64_t* __restrict__ rowptr, int32_t* __restrict__ col,
     void* __restrict__ val_v, void* __restrict__ vadj_v) {
-  const int32_t *loff0 = a.loff[0], *loff1 = a.loff[1], *loff2 = a.loff[2];
-  const int32_t *lent0 = a.lent[0], *lent1 = a.lent[1], *lent2 = a.lent[2];
-  extern __shared__ double lt[];
-  if (LT) tab_stage<CPLX>(g0tab, lt, static_cast<int64_t>(a.W) * a.W * a.W);
-  int64_t m = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (m >= a.N) return;
+  extern __shared__ __align__(16) double lt[];
+  const int64_t tabn = static_cast<int64_t>(a.W) * a.W * a.W;
+  if (LT) tab_stage<CPLX>(g0tab, lt, tabn);
+  int* lists = reinterpret_cast<int*>(lt + (LT ? tabn * (CPLX ? 2 : 1) : 0));
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+  const int lane = static_cast<int>(threadIdx.x) & 63;
+  int* wl = lists + wave * kPairListInts;
   const int64_t N = a.N, Nc = a.Nc;
-  const int S[3] = {s3[m], s3[N + m], s3[2 * N + m]};
-  double wm[3][Q + 1];
-  for (int c = 0; c < 3; ++c) lagrange_all<Q, double>(u3[c * N + m], wm[c]);
-  const double rm[3] = {pos3[m], pos3[N + m], pos3[2 * N + m]};
-  int lo[3], hi[3];
-  axis_range(loff0, S[0], lo[0], hi[0]);
-  axis_range(loff1, S[1], lo[1], hi[1]);
-  axis_range(loff2, S[2], lo[2], hi[2]);
-  const int A = a.nimg_axis;
-  const int W = a.W, R = a.R;
-  int64_t j = rowptr[m];
+  const int A = a.nimg_axis, W = a.W, R = a.R;
   double* valr = static_cast<double*>(val_v);
   cplx<double>* valc = static_cast<cplx<double>*>(val_v);
   cplx<double>* vadj = static_cast<cplx<double>*>(vadj_v);
-  for (int ix = lo[0]; ix < hi[0]; ++ix) {
-    const int bx = lent0[ix] & 0xffff, mx = lent0[ix] >> 16;
-    for (int iy = lo[1]; iy < hi[1]; ++iy) {
-      const int by = lent1[iy] & 0xffff, my = lent1[iy] >> 16;
-      for (int iz = lo[2]; iz < hi[2]; ++iz) {
-        const int bz = lent2[iz] & 0xffff, mz = lent2[iz] >> 16;
-        if (!any_close(a, S, bx, by, bz, mx, my, mz)) continue;
-        const int64_t b = (static_cast<int64_t>(bx) * a.nb[1] + by) * a.nb[2] + bz;
-        const int n0 = box_start[b], n1 = box_start[b + 1];
-        for (int n = n0; n < n1; ++n) {
-          double wn[3][Q + 1];
-          for (int c = 0; c < 3; ++c) lagrange_all<Q, double>(u3c[c * Nc + n], wn[c]);
-          double C[3][2 * Q + 1];
-          for (int c = 0; c < 3; ++c)
-            for (int d = -Q; d <= Q; ++d) {
-              double s = 0.0;
-              for (int aa = max(0, d); aa <= min(Q, Q + d); ++aa) s += wm[c][aa] * wn[c][aa - d];
-              C[c][d + Q] = s;
-            }
-          const double rn[3] = {pos3c[n], pos3c[Nc + n], pos3c[2 * Nc + n]};
-          double fr = 0.0, fi = 0.0, ar = 0.0, ai = 0.0;
-          for (int gx = 0; gx < A; ++gx) {
-            if (!((mx >> gx) & 1)) continue;
-            const int imx = gx - a.id * a.per[0];
-            for (int gy = 0; gy < A; ++gy) {
-              if (!((my >> gy) & 1)) continue;
-              const int imy = gy - a.id * a.per[1];
-              for (int gz = 0; gz < A; ++gz) {
-                if (!((mz >> gz) & 1)) continue;
-                const int imz = gz - a.id * a.per[2];
-                if (!image_close(a, S, bx, by, bz, imx, imy, imz)) continue;
-                const int D[3] = {S[0] - bx - imx * a.nint[0], S[1] - by - imy * a.nint[1],
-                                  S[2] - bz - imz * a.nint[2]};
-                // exact part
-                double er = 0.0, ei = 0.0;
-                const double ddx = rm[0] - rn[0] - imx * a.L[0];
-                const double ddy = rm[1] - rn[1] - imy * a.L[1];
-                const double ddz = rm[2] - rn[2] - imz * a.L[2];
-                const double r = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
-                if (r > 0.0) {
-                  double inv = (a.k0_im != 0.0 ? exp(a.k0_im * r) : 1.0) / (4.0 * M_PI * r);
-                  if (CPLX) {
-                    double s, c;
-                    sincos(a.k0 * r, &s, &c);
-                    er = c * inv;
-                    ei = -s * inv;
-                  } else {
-                    er = inv;
-                  }
-                }
-                // grid part
-                double gr = 0.0, gi = 0.0;
-                for (int dx = -Q; dx <= Q; ++dx) {
-                  const double cx = C[0][dx + Q];
-                  const int64_t rowx = static_cast<int64_t>(D[0] + dx + R) * W;
-                  for (int dy = -Q; dy <= Q; ++dy) {
-                    const double cxy = cx * C[1][dy + Q];
-                    const int64_t toff = (rowx + D[1] + dy + R) * W + (D[2] + R);
-                    double sr = 0.0, si = 0.0;
+  for (int rr = 0; rr < kFillRPW; ++rr) {
+    const int64_t m = (static_cast<int64_t>(blockIdx.x) * kFillWaves + wave) * kFillRPW + rr;
+    if (m >= N) break;
+    const int S[3] = {s3[m], s3[N + m], s3[2 * N + m]};
+    double wm[3][Q + 1];
 #pragma unroll
-                    for (int dz = -Q; dz <= Q; ++dz) {
-                      double tx, ty;
-                      tab_get<CPLX, LT>(g0tab, lt, toff + dz, tx, ty);
-                      sr += C[2][dz + Q] * tx;
-                      if (CPLX) si += C[2][dz + Q] * ty;
-                    }
-                    gr += cxy * sr;
-                    gi += cxy * si;
-                  }
-                }
-                const double xr = er - gr, xi = ei - gi;
-                if (CPLX) {
-                  const int pidx = (gx * A + gy) * A + gz;
-                  const double pr = a.phase[2 * pidx], pi = a.phase[2 * pidx + 1];
-                  fr += pr * xr - pi * xi;
-                  fi += pr * xi + pi * xr;
-                  if (ADJ) {
-                    // entry (m, n) of C^H: psi_i conj(X), psi_i = conj(phase_{-i})
-                    const double qr = a.phase_adj[2 * pidx], qi = a.phase_adj[2 * pidx + 1];
-                    ar += qr * xr + qi * xi;
-                    ai += qi * xr - qr * xi;
-                  }
-                } else {
-                  fr += xr;
-                }
+    for (int c = 0; c < 3; ++c) lagrange_all<Q, double>(u3[c * N + m], wm[c]);
+    const double rm[3] = {pos3[m], pos3[N + m], pos3[2 * N + m]};
+    int lo[3], hi[3];
+    axis_range(a.loff[0], S[0], lo[0], hi[0]);
+    axis_range(a.loff[1], S[1], lo[1], hi[1]);
+    axis_range(a.loff[2], S[2], lo[2], hi[2]);
+    const int64_t j0 = rowptr[m];
+    wave_pairs(a, S, lo, hi, box_start, wl, lane, [&](int64_t t, int n, int bx, int by, int bz, int mx, int my, int mz) {
+      double wn[3][Q + 1];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) lagrange_all<Q, double>(u3c[c * Nc + n], wn[c]);
+      double C[3][2 * Q + 1];
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int d = -Q; d <= Q; ++d) {
+          double sw = 0.0;
+#pragma unroll
+          for (int aa = 0; aa <= Q; ++aa) {
+            if (aa - d < 0 || aa - d > Q) continue;
+            sw += wm[c][aa] * wn[c][aa - d];
+          }
+          C[c][d + Q] = sw;
+        }
+      const double rn[3] = {pos3c[n], pos3c[Nc + n], pos3c[2 * Nc + n]};
+      double fr = 0.0, fi = 0.0, ar = 0.0, ai = 0.0;
+      for (int gx = 0; gx < A; ++gx) {
+        if (!((mx >> gx) & 1)) continue;
+        const int imx = gx - a.id * a.per[0];
+        for (int gy = 0; gy < A; ++gy) {
+          if (!((my >> gy) & 1)) continue;
+          const int imy = gy - a.id * a.per[1];
+          for (int gz = 0; gz < A; ++gz) {
+            if (!((mz >> gz) & 1)) continue;
+            const int imz = gz - a.id * a.per[2];
+            if (!image_close(a, S, bx, by, bz, imx, imy, imz)) continue;
+            const int D[3] = {S[0] - bx - imx * a.nint[0], S[1] - by - imy * a.nint[1], S[2] - bz - imz * a.nint[2]};
+            // exact part (a pair at zero distance keeps only its grid part)
+            double er = 0.0, ei = 0.0;
+            const double ddx = rm[0] - rn[0] - imx * a.L[0];
+            const double ddy = rm[1] - rn[1] - imy * a.L[1];
+            const double ddz = rm[2] - rn[2] - imz * a.L[2];
+            const double r = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
+            if (r > 0.0) {
+              const double inv = (a.k0_im != 0.0 ? exp(a.k0_im * r) : 1.0) / (4.0 * M_PI * r);
+              if (CPLX) {
+                double sn, cs;
+                sincos(a.k0 * r, &sn, &cs);
+                er = cs * inv;
+                ei = -sn * inv;
+              } else {
+                er = inv;
               }
             }
+            // grid part: x stays a loop (bounding the registers), its weight
+            // picked by selects so C stays in registers
+            double gr = 0.0, gi = 0.0;
+#pragma nounroll
+            for (int dx = -Q; dx <= Q; ++dx) {
+              double cx = 0.0;
+#pragma unroll
+              for (int u = 0; u <= 2 * Q; ++u) cx = (u == dx + Q) ? C[0][u] : cx;
+              const int64_t rowx = static_cast<int64_t>(D[0] + dx + R) * W;
+#pragma unroll
+              for (int dy = -Q; dy <= Q; ++dy) {
+                const double cxy = cx * C[1][dy + Q];
+                const int64_t toff = (rowx + D[1] + dy + R) * W + (D[2] + R);
+                double sr = 0.0, si = 0.0;
+#pragma unroll
+                for (int dz = -Q; dz <= Q; ++dz) {
+                  double tx, ty;
+                  tab_get<CPLX, LT>(g0tab, lt, toff + dz, tx, ty);
+                  sr += C[2][dz + Q] * tx;
+                  if (CPLX) si += C[2][dz + Q] * ty;
+                }
+                gr += cxy * sr;
+                gi += cxy * si;
+              }
+            }
+            const double xr = er - gr, xi = ei - gi;
+            if (CPLX) {
+              const int pidx = (gx * A + gy) * A + gz;
+              const double pr = a.phase[2 * pidx], pi = a.phase[2 * pidx + 1];
+              fr += pr * xr - pi * xi;
+              fi += pr * xi + pi * xr;
+              if (ADJ) {
+                // entry (m, n) of C^H: psi_i conj(X), psi_i = conj(phase_{-i})
+                const double qr = a.phase_adj[2 * pidx], qi = a.phase_adj[2 * pidx + 1];
+                ar += qr * xr + qi * xi;
+                ai += qi * xr - qr * xi;
+              }
+            } else {
+              fr += xr;
+            }
           }
-          col[j] = n;
-          if (CPLX) {
-            valc[j] = cmake<double>(fr, fi);
-            if (ADJ) vadj[j] = cmake<double>(ar, ai);
-          } else {
-            valr[j] = fr;
-          }
-          ++j;
         }
       }
-    }
+      const int64_t j = j0 + t;
+      col[j] = n;
+      if (CPLX) {
+        valc[j] = cmake<double>(fr, fi);
+        if (ADJ) vadj[j] = cmake<double>(ar, ai);
+      } else {
+        valr[j] = fr;
+      }
+    });
   }
 }
 
@@ -502,21 +517,22 @@ template <int Q>
 static void fill_q(bool cplx_vals, bool adj, const CorrArgs& a, const int32_t* s3, const double* u3,
                    const double* pos3, const double* u3c, const double* pos3c, const int32_t* box_start,
                    const void* g0tab, const int64_t* rowptr, int32_t* col, void* val, void* val_adj, hipStream_t st) {
-  // the table in LDS when it fits (blocks of 256 rows), else read from
-  // global memory (blocks of 64)
-  const size_t lds = tab_lds_bytes(a.W, cplx_vals);
-  const bool lt = lds <= kTabLdsBytes;
-  const unsigned bs = lt ? 256 : 64;
-  unsigned nb = static_cast<unsigned>((a.N + bs - 1) / bs);
+  // one wavefront per row (kFillRPW rows each), the table in LDS beside
+  // the wave lists when both fit, else read from global memory
+  const size_t tab = tab_lds_bytes(a.W, cplx_vals);
+  const bool lt = tab + fill_list_bytes() <= kTabLdsBytes;
+  const size_t lds = (lt ? tab : 0) + fill_list_bytes();
+  const int64_t per_block = static_cast<int64_t>(kFillWaves) * kFillRPW;
+  const unsigned nb = static_cast<unsigned>((a.N + per_block - 1) / per_block);
   const cplx<double>* g = static_cast<const cplx<double>*>(g0tab);
 #define FFTPIM_FILL(C, J)                                                                                     \
   do {                                                                                                        \
     if (lt)                                                                                                   \
-      hipLaunchKernelGGL((k_corr_fill<Q, C, J, true>), dim3(nb), dim3(bs), lds, st, a, s3, u3, pos3, u3c,    \
-                         pos3c, box_start, g, rowptr, col, val, val_adj);                                     \
+      hipLaunchKernelGGL((k_corr_fill_wave<Q, C, J, true>), dim3(nb), dim3(64 * kFillWaves), lds, st, a, s3,  \
+                         u3, pos3, u3c, pos3c, box_start, g, rowptr, col, val, val_adj);                      \
     else                                                                                                      \
-      hipLaunchKernelGGL((k_corr_fill<Q, C, J, false>), dim3(nb), dim3(bs), 0, st, a, s3, u3, pos3, u3c,     \
-                         pos3c, box_start, g, rowptr, col, val, val_adj);                                     \
+      hipLaunchKernelGGL((k_corr_fill_wave<Q, C, J, false>), dim3(nb), dim3(64 * kFillWaves), lds, st, a, s3, \
+                         u3, pos3, u3c, pos3c, box_start, g, rowptr, col, val, val_adj);                      \
   } while (0)
   if (!cplx_vals)
     FFTPIM_FILL(false, false);

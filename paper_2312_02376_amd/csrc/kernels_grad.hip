@@ -98,36 +98,9 @@ __global__ void __launch_bounds__(256) k_interp_grad(GridArgs g, const double h0
   out[3 * m + 2] += gz;
 }
 
-// Wave-level inclusive prefix sum and total of an int, and sum of a double.
-__device__ inline int wave_incl_scan(int v, int lane) {
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int t = __shfl_up(v, o, 64);
-    if (lane >= o) v += t;
-  }
-  return v;
-}
-
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-// Orders one wavefront's LDS writes before its later reads (and reads before
-// later writes): the lanes of a wave run in lockstep, so a compiler and
-// memory fence at workgroup scope is all that is needed.
-__device__ inline void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
-
 constexpr int kGradWaves = 4;             // wavefronts per workgroup
-constexpr int kGradBPL = 2;               // candidate source boxes per lane per chunk
-constexpr int kGradCH = 64 * kGradBPL;    // candidate boxes per chunk
 constexpr int kGradPPW = 8;               // observer points per wavefront
-constexpr int kGradListInts = 3 * kGradCH + 1;  // per-wave LDS list (prefix, first point, candidate)
+constexpr int kGradListInts = kPairListInts;
 constexpr int kGradWDoubles = 6 * 16;           // per-wave LDS weights of k: w[3][Q+1], dw[3][Q+1], Q < 16
 
 inline size_t grad_list_bytes() {
@@ -135,12 +108,9 @@ inline size_t grad_list_bytes() {
 }
 
 // The correction part of the gradient.  One wavefront per point k (plan
-// order; kGradPPW points in turn); its candidate source boxes (the product
-// of the three per-axis lists) are taken kGradCH at a time: every lane
-// counts the points of kGradBPL boxes, a wave prefix sum lays the chunk's
-// pairs out, and the pairs are then processed 64 at a time, one per lane
-// (lane t finds its box by binary search over the prefix), so the lanes stay
-// busy whatever the box occupancy.  The G0 table is read from LDS when LT.
+// order; kGradPPW points in turn); wave_pairs hands its close pairs to the
+// lanes 64 at a time, so the lanes stay busy whatever the box occupancy.
+// The G0 table is read from LDS when LT.
 template <int Q, bool CPLX, bool LT>
 __global__ void __launch_bounds__(64 * kGradWaves) k_corr_grad(
     CorrArgs a, const int32_t* __restrict__ s3, const double* __restrict__ u3, const double h0, const double h1,
@@ -158,9 +128,7 @@ __global__ void __launch_bounds__(64 * kGradWaves) k_corr_grad(
   // LDS, read as broadcasts, to keep registers for the per-pair arrays
   double* wk = wlds + wave * kGradWDoubles;  // [3][Q + 1]
   double* dk = wk + 3 * (Q + 1);             // [3][Q + 1]
-  int* pre = lists + wave * kGradListInts;  // [kGradCH + 1] pair offsets of the chunk's boxes
-  int* cn0 = pre + kGradCH + 1;             // [kGradCH] first point of each box
-  int* ccd = cn0 + kGradCH;                 // [kGradCH] candidate index of each box
+  int* pre = lists + wave * kGradListInts;  // the wave's pair-enumeration lists
   const int64_t N = a.N;
   const int A = a.nimg_axis, W = a.W, R = a.R;
   // amplitudes: complex planes of FP64 (single = 0) or FP32 (single = 1)
@@ -195,58 +163,8 @@ __global__ void __launch_bounds__(64 * kGradWaves) k_corr_grad(
     axis_range(a.loff[0], S[0], lo[0], hi[0]);
     axis_range(a.loff[1], S[1], lo[1], hi[1]);
     axis_range(a.loff[2], S[2], lo[2], hi[2]);
-    const int Ly = hi[1] - lo[1], Lz = hi[2] - lo[2];
-    const int ncand = (hi[0] - lo[0]) * Ly * Lz;
     double gx = 0.0, gy = 0.0, gz = 0.0;
-    for (int c0 = 0; c0 < ncand; c0 += kGradCH) {
-      int cnt[kGradBPL], n0[kGradBPL];
-      int sum = 0;
-#pragma unroll
-      for (int i = 0; i < kGradBPL; ++i) {
-        const int c = c0 + lane * kGradBPL + i;
-        cnt[i] = 0;
-        n0[i] = 0;
-        if (c < ncand) {
-          const int ex = a.lent[0][lo[0] + c / (Ly * Lz)], ey = a.lent[1][lo[1] + (c / Lz) % Ly],
-                    ez = a.lent[2][lo[2] + c % Lz];
-          const int bx = ex & 0xffff, by = ey & 0xffff, bz = ez & 0xffff;
-          if (any_close(a, S, bx, by, bz, ex >> 16, ey >> 16, ez >> 16)) {
-            const int64_t b = (static_cast<int64_t>(bx) * a.nb[1] + by) * a.nb[2] + bz;
-            n0[i] = box_start[b];
-            cnt[i] = box_start[b + 1] - n0[i];
-          }
-        }
-        sum += cnt[i];
-      }
-      const int incl = wave_incl_scan(sum, lane);
-      const int tot = __shfl(incl, 63, 64);
-      int run = incl - sum;
-#pragma unroll
-      for (int i = 0; i < kGradBPL; ++i) {
-        pre[lane * kGradBPL + i] = run;
-        cn0[lane * kGradBPL + i] = n0[i];
-        ccd[lane * kGradBPL + i] = c0 + lane * kGradBPL + i;
-        run += cnt[i];
-      }
-      if (lane == 0) pre[kGradCH] = tot;
-      wave_lds_sync();
-      for (int t0 = 0; t0 < tot; t0 += 64) {
-        const int t = t0 + lane;
-        if (t < tot) {
-          // the box holding pair t: the largest i with pre[i] <= t (it has
-          // at least one point since pre[i + 1] > t)
-          int ilo = 0, ihi = kGradCH - 1;
-          while (ilo < ihi) {
-            const int mid = (ilo + ihi + 1) >> 1;
-            if (pre[mid] <= t) ilo = mid;
-            else ihi = mid - 1;
-          }
-          const int n = cn0[ilo] + (t - pre[ilo]);
-          const int c = ccd[ilo];
-          const int ex = a.lent[0][lo[0] + c / (Ly * Lz)], ey = a.lent[1][lo[1] + (c / Lz) % Ly],
-                    ez = a.lent[2][lo[2] + c % Lz];
-          const int bx = ex & 0xffff, by = ey & 0xffff, bz = ez & 0xffff;
-          const int mx = ex >> 16, my = ey >> 16, mz = ez >> 16;
+    wave_pairs(a, S, lo, hi, box_start, pre, lane, [&](int64_t, int n, int bx, int by, int bz, int mx, int my, int mz) {
           double wn[3][Q + 1];
 #pragma unroll
           for (int cc = 0; cc < 3; ++cc) lagrange_all<Q, double>(u3[cc * N + n], wn[cc]);
@@ -386,10 +304,7 @@ __global__ void __launch_bounds__(64 * kGradWaves) k_corr_grad(
               }
             }
           }
-        }
-      }
-      wave_lds_sync();
-    }
+    });
     gx = wave_sum(gx);
     gy = wave_sum(gy);
     gz = wave_sum(gz);
