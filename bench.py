@@ -424,7 +424,8 @@ def dynamic_cube_record(args):
     (k0 from a mean spacing of lambda/20, a period of about five wavelengths,
     phase wavenumbers 0.01 - 0.01j) and static (neutral real strengths), each
     at the relative errors 1e-3 and 1e-5 with parameters from
-    fftpim_autotune; FP64, one step = one fftpim_apply."""
+    fftpim_autotune; FP64, one step = one fftpim_apply.  The 1e-3 results
+    are compared with the 1e-5 ones."""
     import numpy as np
     import torch
 
@@ -436,10 +437,8 @@ def dynamic_cube_record(args):
     src, qd = W.dynamic_cube(N, 9)
     qs = W.gaussian_neutral(1, N, 9)[0]
     k0 = W.dynamic_cube_k0(N)
-    gpath = os.path.join(ROOT, "tests", "golden", "dynamic_cube_1m_rows.txt")
-    gold = np.loadtxt(gpath) if os.path.exists(gpath) else None
     pos = torch.tensor(src, device=dev)
-    out = {}
+    out, results = {}, {}
     for case in ("dynamic", "static"):
         for target in (1e-3, 1e-5):
             kw_p = dict(k0=k0, kt=[0.01 - 0.01j] * 3) if case == "dynamic" else {}
@@ -455,12 +454,7 @@ def dynamic_cube_record(args):
             u = torch.empty_like(x)
             ms, med = time_steps(lambda: plan.apply(x, out=u), max(3, args.steps // 4), 1)
             plan.apply(x, out=u)
-            err = None
-            if gold is not None:
-                rows = gold[:, 0].astype(np.int64)
-                want = gold[:, 1] + 1j * gold[:, 2] if case == "dynamic" else gold[:, 3]
-                got = u.cpu().numpy()[rows]
-                err = float(np.linalg.norm(got - want) / np.linalg.norm(want))
+            results[(case, target)] = u.cpu().numpy()
             if plan.last_status() != 0:
                 raise RuntimeError("device-reported error in the dynamic-cube apply")
             inf = plan.info()
@@ -468,8 +462,7 @@ def dynamic_cube_record(args):
                 "ms_per_apply": ms, "ms_median": med, "plan_seconds": t2 - t1, "tune_seconds": t1 - t0,
                 "near_n": list(kw["near_n"]), "near_order": kw["near_order"], "corr_ball": round(kw["corr_ball"], 2),
                 "far_n": list(kw["far_n"]), "far_order": kw["far_order"], "far_fft": inf["far_fft"],
-                "corr_nnz": inf["corr_nnz"], "predicted_rel_err": rep["predicted_rel_err"],
-                "rel_err_vs_oracle_rows": err}
+                "corr_nnz": inf["corr_nnz"], "predicted_rel_err": rep["predicted_rel_err"]}
             print(case, target, json.dumps(out["%s_%g" % (case, target)]), flush=True)
             plan.close()
             del x, u
@@ -478,7 +471,13 @@ def dynamic_cube_record(args):
            "period 101 (about 5 wavelengths), FP64", "k0": k0, "results": out,
            "dynamic_over_static": {"1e-3": out["dynamic_0.001"]["ms_per_apply"] / out["static_0.001"]["ms_per_apply"],
                                    "1e-5": out["dynamic_1e-05"]["ms_per_apply"] / out["static_1e-05"]["ms_per_apply"]},
-           "oracle_rows": 0 if gold is None else int(gold.shape[0])}
+           # the exact sum at 10^6 points is out of the oracle's reach (its
+           # Ewald sums at this k0 L take hours per row set); the 1e-3
+           # results are checked against the 1e-5 ones instead, and both
+           # parameter rules against the exact sum at 20,000 points in
+           # the tests
+           "rel_diff_1e-3_vs_1e-5": {c: float(np.linalg.norm(results[(c, 1e-3)] - results[(c, 1e-5)]) /
+                                              np.linalg.norm(results[(c, 1e-5)])) for c in ("dynamic", "static")}}
     return rec
 
 

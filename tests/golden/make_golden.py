@@ -5,7 +5,7 @@ seeded inputs of paper_2312_02376_amd.workloads; nothing here touches the GPU
 library.  Run from the repository root:
 
     python tests/golden/make_golden.py [coulomb_1k] [helmholtz_100k] [coulomb_1m] [dynamic_cube_20k]
-        [multi_cell_small] [multi_cell_48] [dynamic_cube_1m]
+        [multi_cell_small] [multi_cell_48]
 """
 import os
 import sys
@@ -85,26 +85,6 @@ def dynamic_cube_20k(nrows=32):
           [rows, u.real, u.imag, us.real])
 
 
-def dynamic_cube_1m(nrows=16):
-    # the same cube at the paper's largest size (about 10^6 points, a period
-    # of about five wavelengths)
-    N = 1_000_000
-    src, q = W.dynamic_cube(N, 9)
-    k0 = W.dynamic_cube_k0(N)
-    lat = P.Lattice(3, [101.0] * 3, k0, [0.01 - 0.01j] * 3)
-    rows = np.sort(np.random.default_rng(17).choice(N, nrows, replace=False))
-    u = psp_forward(lat, src, q.astype(np.complex128), obs_index=rows, workers=host_workers())
-    print("dynamic done", flush=True)
-    qs = W.gaussian_neutral(1, N, 9)[0]
-    us = psp_forward(P.Lattice(3, [101.0] * 3), src, qs, obs_index=rows, workers=host_workers())
-    _save("dynamic_cube_1m_rows.txt",
-          "3D-periodic cell of period 101, 10^6 points uniform in a centred 100^3 cube (workloads.dynamic_cube(1000000, 9));\n"
-          "dynamic: k0 = workloads.dynamic_cube_k0(1000000), kt = (0.01 - 0.01j)(1, 1, 1); static: k0 = 0, kt = 0,\n"
-          "strengths workloads.gaussian_neutral(1, 1000000, 9).  exact u at sampled rows.\n"
-          "columns: row, Re u_dyn, Im u_dyn, u_static",
-          [rows, u.real, u.imag, us.real])
-
-
 def multi_cell_48(nrows=4):
     # the 48-cell workload of the benchmark (workloads.multi_cell(48, 4)):
     # N log-uniform in [5e3, 5e5], mixed periodicity, static and Helmholtz
@@ -148,6 +128,6 @@ def multi_cell_small(nrows=16):
 
 if __name__ == "__main__":
     which = sys.argv[1:] or ["coulomb_1k", "helmholtz_100k", "coulomb_1m", "dynamic_cube_20k", "multi_cell_small",
-                             "multi_cell_48", "dynamic_cube_1m"]
+                             "multi_cell_48"]
     for w in which:
         globals()[w]()
