@@ -206,13 +206,16 @@ int tune(const fftpim_problem_t* pr, int64_t N, const double* xyz_dev, double ta
         for (int c = 0; c < d.dims; ++c)
           if (rb * hmx > 0.45 * d.ext[c]) fits = false;
         if (!fits) continue;
-        ++candidates;
-        const int64_t nnz = estimate_nnz(xyz, N, sample, d, nint, h, rb);
         double M = 1.0;
         for (int c = 0; c < 3; ++c) M *= fft_len(2 * n[c] - 1);
-        const double ms = kCostGrid0 + kCostGridPt * static_cast<double>(N) * std::pow(q + 1, 3) * P +
-                          kCostFft * M * std::log2(M) * P + kCostCorr0 +
-                          kCostCorrNnz * static_cast<double>(nnz) * (1.0 + 0.25 * (P - 1));
+        const double grid_ms = kCostGrid0 + kCostGridPt * static_cast<double>(N) * std::pow(q + 1, 3) * P +
+                               kCostFft * M * std::log2(M) * P + kCostCorr0;
+        // the sampled pair count is the costly part of a candidate: skip it
+        // when the grid steps alone already cost more than the best so far
+        if (grid_ms >= bn.ms) continue;
+        ++candidates;
+        const int64_t nnz = estimate_nnz(xyz, N, sample, d, nint, h, rb);
+        const double ms = grid_ms + kCostCorrNnz * static_cast<double>(nnz) * (1.0 + 0.25 * (P - 1));
         if (ms < bn.ms) {
           bn.q = q;
           for (int c = 0; c < 3; ++c) bn.n[c] = n[c];
