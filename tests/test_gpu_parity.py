@@ -71,15 +71,54 @@ def _points(kind, N, seed):
     raise ValueError(kind)
 
 
+class _CachedRef:
+    """The oracle of one case with its results kept: several tests compare
+    different library paths (layouts, precisions, the fused pair) with the
+    same oracle products, which are computed once per test session."""
+
+    def __init__(self, ref):
+        self._ref = ref
+        self._memo = {}
+
+    def __getattr__(self, k):
+        return getattr(self._ref, k)
+
+    def _call(self, kind, x, rows, parts):
+        x = np.asarray(x)
+        key = (kind, None if rows is None else np.asarray(rows).tobytes(), tuple(parts), x.shape, x.tobytes())
+        if key not in self._memo:
+            fn = self._ref.apply if kind == "apply" else self._ref.adjoint
+            self._memo[key] = fn(x, rows=rows, parts=parts)
+        return np.array(self._memo[key], copy=True)
+
+    def apply(self, q, rows=None, parts=("near_grid", "near_corr", "far")):
+        return self._call("apply", q, rows, parts)
+
+    def adjoint(self, v, rows=None, parts=("near_grid", "near_corr", "far")):
+        return self._call("adjoint", v, rows, parts)
+
+
+_REFS = {}
+
+
+def _oracle(name, N, seed, corr_ball, self_mode):
+    key = (name, N, seed, corr_ball, self_mode)
+    if key not in _REFS:
+        latkw, kind, nrhs0, vt, nn, q, rc, nf, qf = CASES[name]
+        lat = P.Lattice(latkw["dims"], latkw["L"], latkw.get("k0", 0.0), latkw.get("kt", [0, 0, 0]))
+        src = _points(kind, N, seed)
+        if kind == "cube":
+            src = src * np.asarray((latkw["L"] + [1, 1, 1])[:3])
+        _REFS[key] = (lat, src, _CachedRef(S.FFTPIM(lat, S.Params(nn, q, rc, nf, qf, 1, corr_ball=corr_ball), src,
+                                                    self_mode=self_mode)))
+    return _REFS[key]
+
+
 def _setup(name, N=257, seed=31, precision="f64", nrhs=None, corr_layout="auto", self_mode="images",
            corr_ball=0.0, far_sum="auto"):
     latkw, kind, nrhs0, vt, nn, q, rc, nf, qf = CASES[name]
     nrhs = nrhs0 if nrhs is None else nrhs
-    lat = P.Lattice(latkw["dims"], latkw["L"], latkw.get("k0", 0.0), latkw.get("kt", [0, 0, 0]))
-    src = _points(kind, N, seed)
-    if kind == "cube":
-        src = src * np.asarray((latkw["L"] + [1, 1, 1])[:3])
-    ref = S.FFTPIM(lat, S.Params(nn, q, rc, nf, qf, 1, corr_ball=corr_ball), src, self_mode=self_mode)
+    lat, src, ref = _oracle(name, N, seed, corr_ball, self_mode)
     rng = np.random.default_rng(seed + 1)
     if vt == "real":
         qv = rng.standard_normal((nrhs, N))
