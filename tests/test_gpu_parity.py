@@ -443,13 +443,15 @@ def test_far_bf16_modes(name):
 def test_fp32_register_fft_lengths(near_n):
     # FP32 strided passes run the register transform (line lengths 64, 128
     # and 512 here; 16, 32 and 256 are covered by the other FP32 tests), FP64
-    # the LDS-stage kernel that the stage tests pin to the oracle: the near
-    # grid parts must agree to FP32 rounding, forward and adjoint, with one
-    # plane and with batched planes
+    # the LDS-stage kernel: with one plane both near grid parts are compared
+    # with the oracle's, and with batched planes FP32 with FP64, forward and
+    # adjoint, to FP32 rounding
     fp = _fftpim()
     rng = np.random.default_rng(53)
     N = 1500
-    pos = torch.tensor(rng.random((N, 3)), dtype=torch.float64, device="cuda")
+    src = rng.random((N, 3))
+    pos = torch.tensor(src, dtype=torch.float64, device="cuda")
+    ref = S.FFTPIM(P.Lattice(3, [1.0, 1.0, 1.0], 3.0, [0.4, 0.2, 0.1]), S.Params(near_n, 3, 3, (8, 8, 8), 3, 1), src)
     for nrhs in (1, 12):
         plans = [fp.Plan(pos, 3, [1.0, 1.0, 1.0], k0=3.0, kt=[0.4, 0.2, 0.1], near_n=near_n, near_order=3,
                          corr_radius=3, far_n=(8, 8, 8), far_order=3, precision=prec, nrhs_max=nrhs)
@@ -458,6 +460,11 @@ def test_fp32_register_fft_lengths(near_n):
         for adjoint in (False, True):
             u64 = plans[0].apply_parts(_to_dev(plans[0], q), 1, adjoint=adjoint).cpu().numpy()
             u32 = plans[1].apply_parts(_to_dev(plans[1], q), 1, adjoint=adjoint).cpu().numpy()
+            if nrhs == 1:
+                want = (ref.adjoint if adjoint else ref.apply)(q, parts=("near_grid",))
+                e64, e32 = rel(u64, want), rel(u32, want)
+                print(near_n, adjoint, "near grid vs oracle: fp64 %.2e fp32 %.2e" % (e64, e32), flush=True)
+                assert e64 < 1e-11 and e32 < 2e-5, (near_n, adjoint, e64, e32)
             err = rel(u32, u64)
             print(near_n, nrhs, adjoint, "fp32 vs fp64 near grid rel %.2e" % err, flush=True)
             assert err < 2e-5, (near_n, nrhs, adjoint, err)
