@@ -5,7 +5,9 @@ seeded inputs of paper_2312_02376_amd.workloads; nothing here touches the GPU
 library.  Run from the repository root:
 
     python tests/golden/make_golden.py [coulomb_1k] [helmholtz_100k] [coulomb_1m] [dynamic_cube_20k]
-        [multi_cell_small] [multi_cell_48]
+        [multi_cell_small] [multi_cell_48] [forces_2m]
+
+forces_2m is not in the default list: it takes about half an hour on 8 cores.
 """
 import os
 import sys
@@ -15,6 +17,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
 
+from oracle import grad as OG  # noqa: E402
 from oracle import pgf as P  # noqa: E402
 from oracle.psp import host_workers, psp_adjoint, psp_forward  # noqa: E402
 from paper_2312_02376_amd import workloads as W  # noqa: E402
@@ -124,6 +127,29 @@ def multi_cell_small(nrows=16):
           "eight independent cells, workloads.multi_cell(8, 21, 2000, 12000);\n"
           "exact u = A q at sampled rows of each cell.\ncolumns: cell, row, Re u, Im u",
           [np.concatenate(x) for x in cols])
+
+
+def _forces_row(args):
+    src, q, k = args
+    return OG.psp_grad(P.Lattice(3, [1.0, 1.0, 1.0]), src, q, q, [k])[0]
+
+
+def forces_2m(nrows=8):
+    # the 2M-point 3D-periodic Coulomb cell of the forces record: 2M uniform
+    # points (seed 5), one neutral Gaussian right-hand side (seed 5, drawn in
+    # float32 as the record does); dL/dr_k of L = q . (A q) at sampled rows
+    import multiprocessing as mp
+    N = 2_000_000
+    src = W.uniform_cube(N, 5)
+    q = W.gaussian_neutral(1, N, 5, np.float32)[0].astype(np.float64)
+    rows = np.sort(np.random.default_rng(13).choice(N, nrows, replace=False))
+    with mp.get_context("fork").Pool(min(nrows, host_workers())) as pool:
+        g = np.array(pool.map(_forces_row, [(src, q, int(k)) for k in rows]))
+    _save("forces_cube_2m_rows.txt",
+          "3D-periodic Coulomb, unit cube, 2M uniform points (workloads.uniform_cube(2000000, 5)), one neutral\n"
+          "Gaussian right-hand side q (workloads.gaussian_neutral(1, N, 5, float32)); exact dL/dr_k of\n"
+          "L = q . (A q) at sampled rows (oracle.grad.psp_grad).\ncolumns: row, dL/dx, dL/dy, dL/dz",
+          [rows, g[:, 0], g[:, 1], g[:, 2]])
 
 
 if __name__ == "__main__":
