@@ -216,7 +216,8 @@ __global__ void k_mean_from_sums(const double* __restrict__ sums, int P, double 
 // box-sorted point list.  Points are staged through LDS in chunks together
 // with their 1D Lagrange weights and amplitudes; each thread then sums the
 // staged points that cover its node, always in the same order (no atomics,
-// bitwise reproducible).
+// bitwise reproducible).  Used below 16 planes, where the few multiply-adds
+// per point leave the broadcast reads cheaper than per-lane point lists.
 constexpr int kSpreadTX = 4, kSpreadTY = 8, kSpreadTZ = 8, kSpreadChunk = 256;
 
 template <typename R, int Q, int PB>
@@ -310,6 +311,139 @@ __global__ void __launch_bounds__(256) k_spread_near(
 #pragma unroll
     for (int pp = 0; pp < PB; ++pp)
       if (p0 + pp < P) grid[node * P + p0 + pp] = cmake<R>(ax[pp], ay[pp]);
+  }
+}
+
+// The same projection for many planes, each thread summing only the points
+// that cover its own nodes.  In the gather above every staged point passes
+// through all lanes of a wavefront while its stencil covers few of their
+// nodes, so most multiply-add slots are idle.  Here a block owns a tile of
+// TX x TY x TZ nodes with one wavefront per x layer; a thread owns two
+// z-adjacent nodes (gz, gz + 1).  The boxes are walked one x slab at a time:
+// the block stages the slab's points of the tile's y/z influence region
+// (1D weights, z box, PB amplitude planes) in LDS, and each thread of a
+// layer that the slab covers walks only its own runs - the boxes y in
+// [gy - Q, gy] and z in [gz - Q, gz + 1] - so its multiply-adds are useful;
+// the lanes of a wavefront differ only in how many points they hold.  Every
+// node sums its points in a fixed order (slab, run, point): no atomics,
+// bitwise reproducible.
+constexpr int kOwnTX = 4, kOwnTY = 8, kOwnTZ = 16;
+
+template <typename R>
+struct OwnCfg {
+  static constexpr int PB = sizeof(R) == 4 ? 16 : 8;    // planes per pass
+  static constexpr int CH = sizeof(R) == 4 ? 192 : 160;  // staged points per chunk
+};
+
+template <typename R, int Q>
+__global__ void __launch_bounds__(256) k_spread_own(
+    GridArgs g, const int32_t* __restrict__ box_start, const int32_t* __restrict__ s3,
+    const double* __restrict__ w3, int64_t N, const cplx<R>* __restrict__ qint, int P,
+    cplx<R>* __restrict__ grid) {
+  constexpr int TX = kOwnTX, TY = kOwnTY, TZ = kOwnTZ, PB = OwnCfg<R>::PB, CH = OwnCfg<R>::CH;
+  static_assert(TY * (TZ / 2) == 64 && TX * 64 == 256, "one wavefront per x layer of the tile");
+  constexpr int NRY = TY + Q, NBZ = TZ + Q;  // y runs and z boxes of a slab's region
+  constexpr int QS = PB + 2;                 // padded plane stride of a staged point (LDS banks)
+  __shared__ int bs[NRY][NBZ + 1];           // global start of each box of the slab's runs
+  __shared__ int rs[NRY + 1];                // slab-local start of each run
+  __shared__ R sw[CH][3][Q + 1];
+  __shared__ int sbz[CH];
+  __shared__ cplx<R> sq[CH][QS];
+  const int nty = (g.n[1] + TY - 1) / TY, ntz = (g.n[2] + TZ - 1) / TZ;
+  const int tile = blockIdx.x;
+  const int tz = tile % ntz, ty = (tile / ntz) % nty, tx = tile / (ntz * nty);
+  const int gx0 = tx * TX, gy0 = ty * TY, gz0 = tz * TZ;
+  const int tid = threadIdx.x;
+  const int gx = gx0 + tid / 64, gy = gy0 + (tid / (TZ / 2)) % TY, gz = gz0 + 2 * (tid % (TZ / 2));
+  const bool valid = gx < g.n[0] && gy < g.n[1] && gz < g.n[2];
+  const int p0 = blockIdx.y * PB;
+  const int by0 = max(0, gy0 - Q), by1 = min(g.nint[1], gy0 + TY - 1);
+  const int bz0 = max(0, gz0 - Q), bz1 = min(g.nint[2], gz0 + TZ - 1);
+  const int nry = max(0, by1 - by0 + 1), nbz = max(0, bz1 - bz0 + 1);
+  // this thread's runs (slab-independent): y boxes [ly0, ly1], z boxes [lz0, lz1)
+  const int ly0 = max(by0, gy - Q) - by0, ly1 = valid ? min(by1, gy) - by0 : -1;
+  const int lz0 = max(bz0, gz - Q) - bz0, lz1 = max(lz0, min(bz1, gz + 1) - bz0 + 1);
+  R a0x[PB], a0y[PB], a1x[PB], a1y[PB];
+#pragma unroll
+  for (int pp = 0; pp < PB; ++pp) a0x[pp] = a0y[pp] = a1x[pp] = a1y[pp] = R(0);
+  const int bxa = max(0, gx0 - Q), bxb = min(g.nint[0], gx0 + TX - 1);
+  for (int bx = bxa; bx <= bxb; ++bx) {
+    __syncthreads();  // the previous slab's LDS is no longer read
+    for (int i = tid; i < nry * (nbz + 1); i += 256) {
+      const int iy = i / (nbz + 1), iz = i % (nbz + 1);
+      bs[iy][iz] = box_start[(static_cast<int64_t>(bx) * g.nb[1] + by0 + iy) * g.nb[2] + bz0 + iz];
+    }
+    __syncthreads();
+    if (tid == 0) {
+      rs[0] = 0;
+      for (int iy = 0; iy < nry; ++iy) rs[iy + 1] = rs[iy] + (bs[iy][nbz] - bs[iy][0]);
+    }
+    __syncthreads();
+    const int total = rs[nry];
+    const int kx = gx - bx;  // x weight index; the slab covers this layer when 0 <= kx <= Q
+    const bool mine = valid && kx >= 0 && kx <= Q;
+    for (int c0 = 0; c0 < total; c0 += CH) {
+      const int c1 = min(total, c0 + CH);
+      if (c0 > 0) __syncthreads();
+      for (int k = c0 + tid; k < c1; k += 256) {
+        int lo = 0, hi = nry - 1;  // run with rs[lo] <= k < rs[lo + 1]
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (rs[mid] <= k) lo = mid; else hi = mid - 1;
+        }
+        const int64_t j = bs[lo][0] + (k - rs[lo]);
+        const int s = k - c0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+          for (int a = 0; a <= Q; ++a) sw[s][c][a] = static_cast<R>(w3[(c * (Q + 1) + a) * N + j]);
+        sbz[s] = s3[2 * N + j] - bz0;
+#pragma unroll
+        for (int pp = 0; pp < PB; ++pp)
+          sq[s][pp] = (p0 + pp < P) ? qint[j * P + p0 + pp] : cmake<R>(R(0), R(0));
+      }
+      __syncthreads();
+      if (!mine) continue;
+      // walk this thread's runs clipped to [c0, c1) as one flat loop, so
+      // that a lane with an empty run does not wait for the others
+      int iy = ly0, k = 0, e = 0, ky = 0;
+      for (;;) {
+        while (k >= e && iy <= ly1) {
+          const int base = rs[iy] - bs[iy][0];
+          k = max(c0, base + bs[iy][lz0]);
+          e = min(c1, base + bs[iy][lz1]);
+          ky = gy - (by0 + iy);
+          ++iy;
+        }
+        if (k >= e) break;
+        const int s = k - c0;
+        const int kz0 = gz - bz0 - sbz[s];  // in [-1, Q]
+        const R wxy = sw[s][0][kx] * sw[s][1][ky];
+        const R wz0 = kz0 >= 0 ? sw[s][2][max(kz0, 0)] : R(0);
+        const R wz1 = kz0 + 1 <= Q ? sw[s][2][min(kz0 + 1, Q)] : R(0);
+        const R w0 = wxy * wz0, w1 = wxy * wz1;
+#pragma unroll
+        for (int pp = 0; pp < PB; ++pp) {
+          const cplx<R> v = sq[s][pp];
+          a0x[pp] += w0 * v.x;
+          a0y[pp] += w0 * v.y;
+          a1x[pp] += w1 * v.x;
+          a1y[pp] += w1 * v.y;
+        }
+        ++k;
+      }
+    }
+  }
+  if (valid) {
+    const int64_t node = (static_cast<int64_t>(gx) * g.n[1] + gy) * g.n[2] + gz;
+#pragma unroll
+    for (int pp = 0; pp < PB; ++pp)
+      if (p0 + pp < P) grid[node * P + p0 + pp] = cmake<R>(a0x[pp], a0y[pp]);
+    if (gz + 1 < g.n[2]) {
+#pragma unroll
+      for (int pp = 0; pp < PB; ++pp)
+        if (p0 + pp < P) grid[(node + 1) * P + p0 + pp] = cmake<R>(a1x[pp], a1y[pp]);
+    }
   }
 }
 
@@ -990,23 +1124,26 @@ void launch_mean_from_sums(const double* sums, int P, int64_t N, double* mean, h
 template <typename R, int Q>
 static void spread_q(const GridArgs& g, const int32_t* box_start, const int32_t* s3, const double* u3,
                      int64_t N, const void* qint, int P, void* grid, hipStream_t st) {
+  if (P >= 16) {
+    // many planes: the own-list form
+    const unsigned otiles = static_cast<unsigned>(((g.n[0] + kOwnTX - 1) / kOwnTX) *
+                                                  ((g.n[1] + kOwnTY - 1) / kOwnTY) *
+                                                  ((g.n[2] + kOwnTZ - 1) / kOwnTZ));
+    dim3 gr(otiles, (P + OwnCfg<R>::PB - 1) / OwnCfg<R>::PB);
+    hipLaunchKernelGGL((k_spread_own<R, Q>), gr, dim3(256), 0, st, g, box_start, s3, u3, N,
+                       static_cast<const cplx<R>*>(qint), P, static_cast<cplx<R>*>(grid));
+    return;
+  }
   const unsigned tiles = static_cast<unsigned>(((g.n[0] + kSpreadTX - 1) / kSpreadTX) *
                                                ((g.n[1] + kSpreadTY - 1) / kSpreadTY) *
                                                ((g.n[2] + kSpreadTZ - 1) / kSpreadTZ));
-  // with many planes a tile takes up to 32 at once, so every staged point is
-  // read once per 32 planes rather than once per 8
 #define FFTPIM_SPREAD_PB(PBV)                                                                              \
   do {                                                                                                     \
     dim3 gr(tiles, (P + PBV - 1) / PBV);                                                                   \
     hipLaunchKernelGGL((k_spread_near<R, Q, PBV>), gr, dim3(256), 0, st, g, box_start, s3, u3, N,          \
                        static_cast<const cplx<R>*>(qint), P, static_cast<cplx<R>*>(grid));                 \
   } while (0)
-  if (P >= 32)
-    FFTPIM_SPREAD_PB(32);
-  else if (P >= 16)
-    FFTPIM_SPREAD_PB(16);
-  else
-    FFTPIM_PB_DISPATCH(P, FFTPIM_SPREAD_PB(PB));
+  FFTPIM_PB_DISPATCH(P, FFTPIM_SPREAD_PB(PB));
 #undef FFTPIM_SPREAD_PB
 }
 

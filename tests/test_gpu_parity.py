@@ -293,6 +293,27 @@ def test_many_right_hand_sides(name, nrhs, precision):
             assert rel(got, want) < tol and elem(got, want) < 5 * tol, (part, adjoint, elem(got, want))
 
 
+@pytest.mark.parametrize("name,nrhs", [("npsp3_odd", 37), ("helm2_odd", 21), ("npsp1_real", 33), ("helm1_bloch", 16),
+                                       ("phase3_static", 23), ("npsp2_real", 64)])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_many_planes_near_grid(name, nrhs, precision):
+    # 16 or more planes: the projection runs in its own-list form (each
+    # thread sums the points covering its two nodes); grids that are not
+    # multiples of its tile, 1D and 2D cells, and plane counts that leave
+    # a partial last pass
+    print("case", name, nrhs, precision, flush=True)
+    lat, ref, plan, qv = _setup(name, N=311, seed=71, precision=precision, nrhs=nrhs)
+    qd = _to_dev(plan, qv)
+    tol = 1e-11 if precision == "f64" else 2e-5
+    for adjoint in (False, True):
+        got = plan.apply_parts(qd, PARTS["near_grid"], adjoint=adjoint).cpu().numpy()
+        want = (ref.adjoint if adjoint else ref.apply)(qv, parts=("near_grid",))
+        e, em = rel(got, want), elem(got, want)
+        print("  adjoint", adjoint, "rel %.2e max elem %.2e" % (e, em), flush=True)
+        assert e < tol and em < 5 * tol, (name, adjoint, e, em)
+    plan.close()
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_symmetric_block_layout(name):
     # the in-cell correction stored once per box pair (+ a close-image CSR)
