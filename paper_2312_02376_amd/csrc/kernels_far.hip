@@ -478,13 +478,135 @@ __global__ void __launch_bounds__(256) k_far_interp_box(FarArgs f, const int32_t
   }
 }
 
+// The same interpolation on FP64 matrix cores.  With W[m][(a, b, c)] =
+// wx_m[a] wy_m[b] wz_m[c] shared by all points of the box, it is the dense
+// product U[points][columns] = W[points][nodes] G[nodes][columns], the 2P
+// real columns being the interleaved real and imaginary parts of the planes
+// (W is real).  A wavefront owns RT 16-point row tiles and CT 16-column
+// tiles and walks the nodes as (a, b) pairs with four z nodes per 16x16x4
+// step (z padded to a multiple of four with zero weights).  Lane l supplies
+// W[point l % 16][z node 4 h + l / 16] and G[that node][column l % 16];
+// accumulation is FP64, as in the vector form above.
+constexpr int kFimRT = 2, kFimCT = 4;
+constexpr int kFimPts = 4 * 16 * kFimRT;  // points per block
+
+template <typename R, int QF>
+__global__ void __launch_bounds__(256) k_far_interp_mfma(FarArgs f, const int32_t* __restrict__ fbox_start,
+                                                         const int32_t* __restrict__ fperm,
+                                                         const int32_t* __restrict__ s3, const double* __restrict__ w3,
+                                                         int64_t N, const cplx<R>* __restrict__ grid, int P,
+                                                         cplx<R>* __restrict__ u, int accumulate) {
+  constexpr int K1 = QF + 1, K = K1 * K1 * K1, H = (K1 + 3) / 4;
+  constexpr int RT = kFimRT, CT = kFimCT;
+  extern __shared__ unsigned char lds_raw[];
+  double* sw = reinterpret_cast<double*>(lds_raw);           // [kFimPts][3][K1]
+  int* sperm = reinterpret_cast<int*>(sw + kFimPts * 3 * K1);  // [kFimPts]
+  cplx<R>* sg = reinterpret_cast<cplx<R>*>(sperm + kFimPts);  // [K][P]
+  const int64_t b = blockIdx.x;
+  const int jb = fbox_start[b] + blockIdx.y * kFimPts;
+  const int je = min(fbox_start[b + 1], jb + kFimPts);
+  if (jb >= je) return;  // the whole block leaves together
+  const int np = je - jb;
+  const int m0 = fperm[fbox_start[b]];
+  const int sx = s3[m0], sy = s3[N + m0], sz = s3[2 * N + m0];
+  for (int t = threadIdx.x; t < K * P; t += blockDim.x) {
+    const int k = t / P, p = t - k * P;
+    const int a = k / (K1 * K1), bb = (k / K1) % K1, c = k % K1;
+    const int64_t node = (static_cast<int64_t>(sx + a) * f.nf[1] + (sy + bb)) * f.nf[2] + (sz + c);
+    sg[t] = grid[node * P + p];
+  }
+  for (int t = threadIdx.x; t < np; t += blockDim.x) {
+    const int m = fperm[jb + t];
+    sperm[t] = m;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int a = 0; a < K1; ++a) sw[(t * 3 + c) * K1 + a] = w3[(c * K1 + a) * N + m];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int kk = lane >> 4, li = lane & 15;
+  const int twoP = 2 * P;
+  const R* sgr = reinterpret_cast<const R*>(sg);
+  // this lane's point in each row tile (A operand) and its z weights
+  int pt[RT];
+  double wzs[RT][H];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    pt[rt] = (wave * RT + rt) * 16 + li;
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+      const int c = 4 * h + kk;
+      wzs[rt][h] = (pt[rt] < np && c < K1) ? sw[(pt[rt] * 3 + 2) * K1 + c] : 0.0;
+    }
+    if (pt[rt] >= np) pt[rt] = 0;  // zero weights above; any staged point's x, y weights do
+  }
+  for (int pc = 0; pc < twoP; pc += 16 * CT) {
+    mfma_d4 acc[RT][CT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = mfma_d4{0.0, 0.0, 0.0, 0.0};
+    for (int a = 0; a < K1; ++a)
+      for (int bb = 0; bb < K1; ++bb) {
+        double wxy[RT];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) wxy[rt] = sw[(pt[rt] * 3 + 0) * K1 + a] * sw[(pt[rt] * 3 + 1) * K1 + bb];
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+          const int c = 4 * h + kk;
+          const int node = (a * K1 + bb) * K1 + (c < K1 ? c : 0);
+          double bv[CT];
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct) {
+            const int col = pc + ct * 16 + li;
+            bv[ct] = (c < K1 && col < twoP) ? static_cast<double>(sgr[node * twoP + col]) : 0.0;
+          }
+#pragma unroll
+          for (int rt = 0; rt < RT; ++rt) {
+            const double av = wxy[rt] * wzs[rt][h];
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+              if (pc + ct * 16 < twoP) acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[ct], acc[rt][ct], 0, 0, 0);
+          }
+        }
+      }
+    // element r of lane l: row 4 r + l / 16, column l % 16
+    R* ur = reinterpret_cast<R*>(u);
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        const int col = pc + ct * 16 + li;
+        if (col >= twoP) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = (wave * RT + rt) * 16 + 4 * r + kk;
+          if (row < np) {
+            R* o = ur + static_cast<int64_t>(sperm[row]) * twoP + col;
+            const R v = static_cast<R>(acc[rt][ct][r]);
+            *o = accumulate ? *o + v : v;
+          }
+        }
+      }
+  }
+}
+
 template <typename R, int QF>
 static bool far_interp_box_q(const FarArgs& f, const int32_t* fbox_start, const int32_t* fperm, int max_box,
                              const int32_t* s3, const double* w3, int64_t N, const void* grid, int P, void* u,
                              bool acc, hipStream_t st) {
   constexpr int K = (QF + 1) * (QF + 1) * (QF + 1);
   const size_t lds = static_cast<size_t>(K) * P * sizeof(cplx<R>);
-  if (P < 8 || lds > 128 * 1024) return false;
+  if (P < 8) return false;
+  const size_t lds_m = lds + static_cast<size_t>(kFimPts) * (3 * (QF + 1) * sizeof(double) + sizeof(int));
+  if (lds_m <= 128 * 1024) {
+    dim3 gm(static_cast<unsigned>(f.nboxes), static_cast<unsigned>((max_box + kFimPts - 1) / kFimPts));
+    hipLaunchKernelGGL((k_far_interp_mfma<R, QF>), gm, dim3(256), lds_m, st, f, fbox_start, fperm, s3, w3, N,
+                       static_cast<const cplx<R>*>(grid), P, static_cast<cplx<R>*>(u), acc ? 1 : 0);
+    return true;
+  }
+  if (lds > 128 * 1024) return false;
   dim3 gr(static_cast<unsigned>(f.nboxes), static_cast<unsigned>((max_box + kFarInterpChunk - 1) / kFarInterpChunk));
 #define FFTPIM_FIB(LPV)                                                                                    \
   hipLaunchKernelGGL((k_far_interp_box<R, QF, LPV>), gr, dim3(256), lds, st, f, fbox_start, fperm, s3, w3, N, \
