@@ -97,6 +97,104 @@ __global__ void __launch_bounds__(128) k_far_moments(const int32_t* __restrict__
   }
 }
 
+// The same moments on FP64 matrix cores for batched planes: per box,
+// M[nodes][columns] = W^T[nodes][points] Q[points][columns] (the 2P real
+// columns are the interleaved real and imaginary parts of the planes), a
+// dense product reduced over the box's points four at a time with 16x16x4
+// FP64 MFMA steps.  Node tiles of 16 nodes are dealt to the four wavefronts
+// (at most four each, so (qf+1)^3 <= 256); a block covers 32 columns (two
+// 16-column tiles: the accumulators stay within two wavefronts per SIMD) and
+// all of its box's points, staged through LDS in chunks with their 1D weights.
+// Lane l supplies W[point 4 s + l / 16][node l % 16 of the tile] and
+// Q[point 4 s + l / 16][column l % 16]; FP64 accumulator element r of lane
+// l holds node 4 r + l / 16 and column l % 16.
+constexpr int kMomMfmaChunk = 64, kMomMfmaCols = 32;
+typedef double mom_d4 __attribute__((ext_vector_type(4)));
+
+template <typename R, int QF>
+__global__ void __launch_bounds__(256) k_far_moments_mfma(const int32_t* __restrict__ fbox_start,
+                                                          const int32_t* __restrict__ fperm,
+                                                          const double* __restrict__ w3, int64_t N,
+                                                          const cplx<R>* __restrict__ qint, int P,
+                                                          cplx<R>* __restrict__ mom) {
+  constexpr int K1 = QF + 1, K = K1 * K1 * K1, NT = (K + 15) / 16, TW = (NT + 3) / 4, CH = kMomMfmaChunk;
+  constexpr int NC = kMomMfmaCols, CT = NC / 16;
+  static_assert(TW <= 4, "at most four node tiles per wavefront");
+  __shared__ double sw[CH][3][K1];
+  __shared__ R sq[CH][NC + 1];  // this block's real columns, padded
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int kk = lane >> 4, li = lane & 15;
+  const int64_t b = blockIdx.x;
+  const int col0 = blockIdx.y * NC;  // first real column of this block
+  const int twoP = 2 * P;
+  const R* qr = reinterpret_cast<const R*>(qint);
+  // this lane's node (A operand row) in each of its tiles
+  int na[TW], nb_[TW], nc[TW];
+  bool nv[TW];
+#pragma unroll
+  for (int i = 0; i < TW; ++i) {
+    const int k = (wave + 4 * i) * 16 + li;
+    nv[i] = (wave + 4 * i) < NT && k < K;
+    const int kc = nv[i] ? k : 0;
+    na[i] = kc / (K1 * K1);
+    nb_[i] = (kc / K1) % K1;
+    nc[i] = kc % K1;
+  }
+  mom_d4 acc[TW][CT];
+#pragma unroll
+  for (int i = 0; i < TW; ++i)
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) acc[i][ct] = mom_d4{0.0, 0.0, 0.0, 0.0};
+  const int j0 = fbox_start[b], j1 = fbox_start[b + 1];
+  for (int base = j0; base < j1; base += CH) {
+    const int cnt = min(CH, j1 - base);
+    __syncthreads();
+    for (int i = t; i < CH; i += 256) {
+      const bool ok = i < cnt;
+      const int n = ok ? fperm[base + i] : 0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int a = 0; a < K1; ++a) sw[i][c][a] = ok ? w3[(c * K1 + a) * N + n] : 0.0;
+    }
+    for (int e = t; e < CH * NC; e += 256) {
+      const int i = e / NC, c = e % NC;
+      const bool ok = i < cnt && col0 + c < twoP;
+      sq[i][c] = ok ? qr[static_cast<int64_t>(fperm[base + i]) * twoP + col0 + c] : R(0);
+    }
+    __syncthreads();
+    for (int s = 0; s < cnt; s += 4) {
+      const int i = s + kk;  // this lane's point (zero weights past cnt)
+      double bv[CT];
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) bv[ct] = static_cast<double>(sq[i][ct * 16 + li]);
+#pragma unroll
+      for (int it = 0; it < TW; ++it) {
+        if (wave + 4 * it >= NT) break;
+        const double av = nv[it] ? sw[i][0][na[it]] * sw[i][1][nb_[it]] * sw[i][2][nc[it]] : 0.0;
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+          if (col0 + ct * 16 < twoP) acc[it][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[ct], acc[it][ct], 0, 0, 0);
+      }
+    }
+  }
+  R* mr = reinterpret_cast<R*>(mom);
+#pragma unroll
+  for (int it = 0; it < TW; ++it) {
+    if (wave + 4 * it >= NT) break;
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      const int col = col0 + ct * 16 + li;
+      if (col >= twoP) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int k = (wave + 4 * it) * 16 + 4 * r + kk;
+        if (k < K) mr[(b * K + k) * twoP + col] = static_cast<R>(acc[it][ct][r]);
+      }
+    }
+  }
+}
+
 template <typename R, int QF>
 __global__ void k_far_gather(FarArgs f, const cplx<R>* __restrict__ mom, int P, cplx<R>* __restrict__ grid) {
   constexpr int K1 = QF + 1;
@@ -784,6 +882,15 @@ static void moments_q(const FarArgs& f, const int32_t* fbox_start, const int32_t
     hipLaunchKernelGGL((k_far_moments<R, QF, PBV>), gr, dim3(bs), 0, st, fbox_start, fperm, u3, N,          \
                        static_cast<const cplx<R>*>(qint), P, static_cast<cplx<R>*>(mom));                   \
   } while (0)
+  if constexpr (K1 <= 6) {
+    if (P >= 8) {
+      // batched planes: the matrix-core form
+      dim3 gm(static_cast<unsigned>(f.nboxes), (2 * P + kMomMfmaCols - 1) / kMomMfmaCols);
+      hipLaunchKernelGGL((k_far_moments_mfma<R, QF>), gm, dim3(256), 0, st, fbox_start, fperm, u3, N,
+                         static_cast<const cplx<R>*>(qint), P, static_cast<cplx<R>*>(mom));
+      return;
+    }
+  }
   // accumulators: (qf+1) z nodes x PB planes per thread
   if (P >= 4 && K1 <= 6)
     FFTPIM_MOM(4);
