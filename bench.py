@@ -181,12 +181,23 @@ def run_secondary(args, key):
         acc = float(np.linalg.norm(got - gold) / np.linalg.norm(gold))
     print("stages (ms per launch): " + ", ".join(
         "%s %.4f" % (k, t / c) for k, (t, c) in stages.items() if c), file=sys.stderr, flush=True)
+    alone = None
+    if args.isolated_parts:
+        # each part of the forward apply on its own (no concurrent streams):
+        # the launch times a kernel takes without sharing the GPU
+        alone = {}
+        for bit, part in ((1, "near_grid"), (2, "near_corr"), (4, "far")):
+            plan.apply_parts(qd, bit, out=u)
+            st = staged_pass(plan, lambda: plan.apply_parts(qd, bit, out=u), args.steps)
+            alone[part] = {k: t / c for k, (t, c) in st.items() if c and k not in ("pack", "unpack")}
+        print("stages alone (ms per launch): %s" % json.dumps(alone), file=sys.stderr, flush=True)
     print(json.dumps({"workload": wl["name"], "value": N * nrhs / (ms * 1e-3), "unit": "observer points/s",
                       "ms_per_step": ms, "steps": args.steps, "N": N, "nrhs": nrhs, "dtype": wl["precision"],
                       "corr_nnz": info["corr_nnz"], "corr_layout_used": info["corr_layout_used"],
                       "corr_tile_values": info["corr_tile_values"], "plan_seconds": plan_s,
                       "rel_l2_vs_oracle_rows": acc,
-                      "stages_ms": {k: t / c for k, (t, c) in stages.items() if c}}), flush=True)
+                      "stages_ms": {k: t / c for k, (t, c) in stages.items() if c},
+                      "stages_alone_ms": alone}), flush=True)
     plan.close()
 
 
@@ -241,6 +252,8 @@ def main():
     ap.add_argument("--target", type=float, default=1e-4, help="error target of the multi-cell parameter choice")
     ap.add_argument("--lanes", type=int, default=4, help="streams of the multi-cell batch")
     ap.add_argument("--no-batched", action="store_true", help="skip the nested 1M-point batched record")
+    ap.add_argument("--isolated-parts", action="store_true",
+                    help="secondary workloads: also time each part of the apply on its own")
     ap.add_argument("--no-forces", action="store_true", help="skip the nested 2M-point position-gradient record")
     ap.add_argument("--no-separate", action="store_true",
                     help="skip the timing of the step made of two single calls")

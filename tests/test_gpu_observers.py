@@ -99,6 +99,34 @@ def test_parts_and_adjoint_match_oracle(name):
     plan.close()
 
 
+@pytest.mark.parametrize("name", ["npsp3_real", "helm2_bloch"])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_many_planes_near_grid(name, precision):
+    # 16 or more planes: projection and interpolation run in their tiled
+    # forms, each over its own point set (sources or observers)
+    latkw, box, vt, nn, q, rc, nf, qf = CASES[name]
+    lat = P.Lattice(latkw["dims"], latkw["L"], latkw.get("k0", 0.0), latkw.get("kt", [0, 0, 0]))
+    rng = np.random.default_rng(15)
+    src = rng.random((301, 3)) * np.asarray(box)
+    obs = rng.random((173, 3)) * np.asarray(box)
+    nrhs = 40 if vt == "real" else 21
+    plan = _fp().Plan(torch.tensor(src, device="cuda"), latkw["dims"], latkw["L"], k0=latkw.get("k0", 0.0),
+                      kt=latkw.get("kt", [0, 0, 0]), near_n=nn, near_order=q, corr_radius=rc, far_n=nf, far_order=qf,
+                      value_type=vt, observers=torch.tensor(obs, device="cuda"), nrhs_max=nrhs, precision=precision)
+    ref = S.FFTPIM(lat, S.Params(nn, q, rc, nf, qf, 1), src, obs=obs)
+    tol = 1e-11 if precision == "f64" else 2e-5
+    for adjoint, n in ((False, len(src)), (True, len(obs))):
+        x = rng.standard_normal((nrhs, n))
+        if vt == "complex":
+            x = x + 1j * rng.standard_normal((nrhs, n))
+        got = plan.apply_parts(_dev(plan, x), PARTS["near_grid"], adjoint=adjoint).cpu().numpy()
+        want = (ref.adjoint if adjoint else ref.apply)(x, parts=("near_grid",))
+        e = rel(got, want)
+        print(name, precision, "adjoint", adjoint, "rel %.2e" % e, flush=True)
+        assert e < tol, (name, precision, adjoint, e)
+    plan.close()
+
+
 def test_accuracy_at_separate_observers():
     # 2D-periodic Helmholtz with a phase shift: the library at separate
     # observers against the exact sum of Eq. (1)
