@@ -635,6 +635,35 @@ def forces_record(args):
     return rec
 
 
+def near_kernels_alone(plan, info, wl, qd, u, N, nrhs, steps):
+    """The projection, FFT convolution and interpolation of one forward apply
+    with no concurrent streams: launch time (HIP events) and algorithmic
+    bytes of each, against the 8 TB/s HBM peak.  Bytes: the projection and
+    the interpolation read every point's 1D weights (3 (q+1) doubles), its
+    box (3 ints) and its P planes once and write (read) every grid node's P
+    planes once; the FFT counts each of its five pruned passes reading its
+    input and writing its output once, plus the spectrum."""
+    P = (nrhs + 1) // 2 if wl["value_type"] == "real" else nrhs
+    eb = 8 if wl["precision"] != "f64" else 16  # bytes of one complex plane value
+    n0, n1, n2 = info["near_n"]
+    M0, M1, M2 = info["near_fft"]
+    q = wl["near_order"]
+    pts = N * (3 * (q + 1) * 8 + 12 + P * eb)
+    grid = n0 * n1 * n2 * P * eb
+    fft = P * eb * (2 * (n0 * n1 * n2 + n0 * n1 * M2) + 2 * (n0 * n1 * M2 + n0 * M1 * M2) + 2 * n0 * M1 * M2) \
+        + M0 * M1 * M2 * eb
+    plan.apply_parts(qd, 1, out=u)
+    st = staged_pass(plan, lambda: plan.apply_parts(qd, 1, out=u), steps)
+    out = {}
+    for name, stage, nbytes in (("projection", "near_spread", pts + grid), ("fft_convolution", "near_fft", fft),
+                                ("interpolation", "near_interp", pts + grid)):
+        t, c = st[stage]
+        ms = t / max(c, 1)
+        out[name] = {"ms": ms, "algorithmic_GB": nbytes / 1e9, "GB_s": nbytes / (ms * 1e-3) / 1e9,
+                     "frac_hbm_peak": nbytes / (ms * 1e-3) / 8e12}
+    return out
+
+
 def batched_record(args):
     """The 1M-point, 64-right-hand-side Coulomb cell (FP32 bulk, FP64
     correction), one step = fftpim_apply_pair over all right-hand sides, and
@@ -702,6 +731,7 @@ def batched_record(args):
                                "unit": "TFLOP/s", "frac": flops / launch_s / 1e12 / 78.6, "traffic": None,
                                "flops_per_launch": flops, "avg_launch_ms": launch_s * 1e3,
                                "hbm_GBps_stored_values": tbytes / launch_s / 1e9}
+            rec["near_kernels_alone"] = near_kernels_alone(plan, info, wl, qd, u, N, nrhs, steps)
         out[key] = rec
         plan.close()
         del qd, vd, u, w
