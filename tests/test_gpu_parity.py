@@ -469,6 +469,68 @@ def test_far_bf16_modes(name):
         assert e["bf16x3"] < e["bf16"] / 20 and e["bf16x3"] < 2.0 ** 8 * e["fp32"], e
 
 
+def _bf16(x):
+    """float32 values rounded to bfloat16 (nearest, ties to even, on the upper
+    half of the binary32 encoding), returned as float64."""
+    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _bf16_product(K, Q, split):
+    """Q @ K.T with both operands taken through bfloat16 (float32 first), the
+    products exact and summed in float64; split: the three-product form
+    lo.hi + hi.lo + hi.hi with hi = bf16(x), lo = bf16(x - hi)."""
+    K32, Q32 = K.astype(np.float32), Q.astype(np.float32)
+    Kh, Qh = _bf16(K32), _bf16(Q32)
+    if not split:
+        return Qh @ Kh.T
+    Kl = _bf16((K32.astype(np.float64) - Kh).astype(np.float32))
+    Ql = _bf16((Q32.astype(np.float64) - Qh).astype(np.float32))
+    return Ql @ Kh.T + Qh @ Kl.T + Qh @ Kh.T
+
+
+@pytest.mark.parametrize("name", ["npsp3_real", "npsp2_real"])
+def test_far_bf16_modes_match_host_emulation(name):
+    # the far part of both bfloat16 modes against a host emulation of the
+    # same rounding: the oracle's far grid amplitudes and kernel table taken
+    # to float32 and then to bfloat16 (or split into two bfloat16 parts),
+    # their products summed in float64, and the oracle's interpolation.  The
+    # library differs from the emulation only by float32 accumulation and by
+    # the float32 rounding of its grid amplitudes (which can move a value
+    # across a bfloat16 rounding boundary): the difference must stay within
+    # four times the float32 mode's own far-part error, and for plain
+    # bfloat16 under a hundredth of the mode's departure from the unrounded
+    # far part (the split mode's departure is only about ten times the
+    # float32 error)
+    _, ref32, plan32, qv32 = _setup(name, N=400, seed=47, nrhs=19, precision="f32")
+    e32 = {}
+    for adjoint in (False, True):
+        got = plan32.apply_parts(_to_dev(plan32, qv32), PARTS["far"], adjoint=adjoint).cpu().numpy()
+        e32[adjoint] = rel(got, (ref32.adjoint if adjoint else ref32.apply)(qv32, parts=("far",)).real)
+    plan32.close()
+    for prec, split in (("f32_farbf16", False), ("f32_farbf16x3", True)):
+        lat, ref, plan, qv = _setup(name, N=400, seed=47, nrhs=19, precision=prec)
+        qd = _to_dev(plan, qv)
+        K = ref._far_matrix().real  # static lattices: a real far kernel
+        for adjoint in (False, True):
+            if adjoint:
+                Qg = S._spread(ref.fst_obs, qv, ref.Ngf).real
+                emu = S._interp(ref.fst_src, _bf16_product(K.T, Qg, split), np.arange(ref.src.shape[0]))
+            else:
+                Qg = S._spread(ref.fst_src, qv, ref.Ngf).real
+                emu = S._interp(ref.fst_obs, _bf16_product(K, Qg, split), np.arange(ref.obs.shape[0]))
+            exact = (ref.adjoint if adjoint else ref.apply)(qv, parts=("far",)).real
+            got = plan.apply_parts(qd, PARTS["far"], adjoint=adjoint).cpu().numpy()
+            d_lib, d_mode = rel(got, emu), rel(emu, exact)
+            print(name, prec, "adjoint", adjoint, "library vs emulation %.2e, emulation vs unrounded %.2e, "
+                  "float32 mode %.2e" % (d_lib, d_mode, e32[adjoint]), flush=True)
+            assert d_lib < 4 * e32[adjoint], (name, prec, adjoint, d_lib, e32[adjoint])
+            if not split:
+                assert d_lib < 0.01 * d_mode, (name, prec, adjoint, d_lib, d_mode)
+        plan.close()
+
+
 @pytest.mark.parametrize("near_n", [(32, 32, 32), (64, 64, 32), (256, 16, 16)])
 def test_fp32_register_fft_lengths(near_n):
     # FP32 strided passes run the register transform (line lengths 64, 128
