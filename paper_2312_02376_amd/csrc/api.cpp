@@ -420,8 +420,8 @@ int near_field(fftpim_plan_s* p, const WorkSet& ws, bool adjoint, const void* in
     // the projected points: sources forward, observers for the adjoint
     // (the same set unless the plan has separate observers)
     if (p->wt_row != nullptr)
-      launch_spread_csr<R>(p->wt_row, p->wt_idx, p->wt_val, static_cast<int64_t>(p->ng.n[0]) * p->ng.n[1] * p->ng.n[2],
-                           in, P, ws.grid0, sn);
+      launch_spread_csr<R>(p->wt_node, p->wt_nnodes, p->wt_row, p->wt_idx, p->wt_val,
+                           static_cast<int64_t>(p->ng.n[0]) * p->ng.n[1] * p->ng.n[2], in, P, ws.grid0, sn);
     else if (adjoint)
       CHK(launch_spread_near<R>(p->ng.q, ga, p->box_start_o, p->near_s_o, p->near_w_o, p->No, in, P, ws.grid0, sn));
     else
@@ -1703,7 +1703,18 @@ int build_plan(fftpim_plan_s* p, int64_t N, const double* src_dev, int64_t No, c
             widx[k] = static_cast<int32_t>(m);
             wval[k] = w_near[a * N + m] * w_near[(K1 + b) * N + m] * w_near[(2 * K1 + c) * N + m];
           }
-    CHK(upload(p, &p->wt_row, wrow));
+    // only the nodes with entries are visited (the grid is zeroed first):
+    // clustered points leave most of a fine grid empty
+    std::vector<int64_t> wnode, wrow_c;
+    for (int64_t k = 0; k < n3; ++k)
+      if (wrow[k + 1] > wrow[k]) {
+        wnode.push_back(k);
+        wrow_c.push_back(wrow[k]);
+      }
+    wrow_c.push_back(wrow[n3]);
+    p->wt_nnodes = static_cast<int64_t>(wnode.size());
+    if (p->wt_nnodes > 0) CHK(upload(p, &p->wt_node, wnode));
+    CHK(upload(p, &p->wt_row, wrow_c));
     CHK(upload(p, &p->wt_idx, widx));
     CHK(upload(p, &p->wt_val, wval));
   }

@@ -510,7 +510,10 @@ struct fftpim_plan_s {
   // correction (FP64 values)
   int64_t* rowptr = nullptr;
   double* sums_work = nullptr;     // scratch of the plane sums
-  // node-major transposed near weights (plans with at most kSpreadCsrPlanes planes)
+  // node-major transposed near weights (plans with at most kSpreadCsrPlanes
+  // planes), over the nodes that have entries (wt_node) only
+  int64_t* wt_node = nullptr;
+  int64_t wt_nnodes = 0;
   int64_t* wt_row = nullptr;
   int32_t* wt_idx = nullptr;
   double* wt_val = nullptr;

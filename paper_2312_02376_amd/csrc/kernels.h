@@ -147,8 +147,8 @@ void launch_check_neutral(const double* sums, int P, double tol, int* status, hi
 void launch_mean_from_sums(const double* sums, int P, int64_t N, double* mean, hipStream_t st);
 // Projection through the node-major weight CSR (few planes).
 template <typename R>
-void launch_spread_csr(const int64_t* wrow, const int32_t* widx, const double* wval, int64_t n3, const void* qint,
-                       int P, void* grid, hipStream_t st);
+void launch_spread_csr(const int64_t* wnode, int64_t nnodes, const int64_t* wrow, const int32_t* widx,
+                       const double* wval, int64_t n3, const void* qint, int P, void* grid, hipStream_t st);
 template <typename R>
 int launch_spread_near(int q, const GridArgs& g, const int32_t* box_start, const int32_t* s3, const double* u3,
                        int64_t N, const void* qint, int P, void* grid, hipStream_t st);

@@ -448,18 +448,21 @@ __global__ void __launch_bounds__(256) k_spread_own(
 }
 
 // Projection from a node-major weight list (few planes): the transposed
-// interpolation weights W^T as CSR by grid node, entries in increasing point
-// order, built at plan time.  16 lanes per node add its entries and combine
-// them by a fixed shuffle order; nodes without entries are written as zero.
+// interpolation weights W^T as CSR over the grid nodes that have entries, in
+// increasing point order, built at plan time.  16 lanes per listed node add
+// its entries and combine them by a fixed shuffle order; the grid is zeroed
+// first, so empty nodes cost nothing here.
 template <typename R>
-__global__ void __launch_bounds__(256) k_spread_csr(const int64_t* __restrict__ wrow, const int32_t* __restrict__ widx,
-                                                    const double* __restrict__ wval, int64_t n3,
+__global__ void __launch_bounds__(256) k_spread_csr(const int64_t* __restrict__ wnode, int64_t nnodes,
+                                                    const int64_t* __restrict__ wrow, const int32_t* __restrict__ widx,
+                                                    const double* __restrict__ wval,
                                                     const cplx<R>* __restrict__ qint, int P,
                                                     cplx<R>* __restrict__ grid) {
-  const int64_t node = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 4;
+  const int64_t i = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 4;
   const int sl = threadIdx.x & 15;
-  if (node >= n3) return;  // all 16 lanes of a node leave together
-  const int64_t j0 = wrow[node], j1 = wrow[node + 1];
+  if (i >= nnodes) return;  // all 16 lanes of a node leave together
+  const int64_t node = wnode[i];
+  const int64_t j0 = wrow[i], j1 = wrow[i + 1];
   for (int p = 0; p < P; ++p) {
     double ar = 0.0, ai = 0.0;
     for (int64_t j = j0 + sl; j < j1; j += 16) {
@@ -474,6 +477,13 @@ __global__ void __launch_bounds__(256) k_spread_csr(const int64_t* __restrict__ 
     }
     if (sl == 0) grid[node * P + p] = cmake<R>(static_cast<R>(ar), static_cast<R>(ai));
   }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_zero_grid(cplx<R>* __restrict__ grid, int64_t n) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; k < n; k += stride)
+    grid[k] = cmake<R>(R(0), R(0));
 }
 
 // ---------------------------------------------------------------------------
@@ -1148,10 +1158,15 @@ static void spread_q(const GridArgs& g, const int32_t* box_start, const int32_t*
 }
 
 template <typename R>
-void launch_spread_csr(const int64_t* wrow, const int32_t* widx, const double* wval, int64_t n3, const void* qint,
-                       int P, void* grid, hipStream_t st) {
-  hipLaunchKernelGGL((k_spread_csr<R>), dim3(blocks_for(n3 * 16, kPointBlock)), dim3(kPointBlock), 0, st, wrow, widx,
-                     wval, n3, static_cast<const cplx<R>*>(qint), P, static_cast<cplx<R>*>(grid));
+void launch_spread_csr(const int64_t* wnode, int64_t nnodes, const int64_t* wrow, const int32_t* widx,
+                       const double* wval, int64_t n3, const void* qint, int P, void* grid, hipStream_t st) {
+  const int64_t nz = n3 * P;
+  hipLaunchKernelGGL((k_zero_grid<R>), dim3(static_cast<unsigned>(std::min<int64_t>(blocks_for(nz, 256), 65536))),
+                     dim3(256), 0, st, static_cast<cplx<R>*>(grid), nz);
+  if (nnodes > 0)
+    hipLaunchKernelGGL((k_spread_csr<R>), dim3(blocks_for(nnodes * 16, kPointBlock)), dim3(kPointBlock), 0, st,
+                       wnode, nnodes, wrow, widx, wval, static_cast<const cplx<R>*>(qint), P,
+                       static_cast<cplx<R>*>(grid));
 }
 
 template <typename R>
@@ -1314,8 +1329,8 @@ void launch_scale_convert(const void* in, void* out, int64_t n, double s, hipStr
                                  int, int, bool, bool, const double*, hipStream_t, DiagTerm);            \
   template void launch_plane_sums<R>(const void*, const void*, const void*, int64_t, int, double*, double*, \
                                      hipStream_t, DiagTerm);                                             \
-  template void launch_spread_csr<R>(const int64_t*, const int32_t*, const double*, int64_t, const void*, int, \
-                                     void*, hipStream_t);                                                \
+  template void launch_spread_csr<R>(const int64_t*, int64_t, const int64_t*, const int32_t*, const double*, \
+                                     int64_t, const void*, int, void*, hipStream_t);                                                \
   template int launch_spread_near<R>(int, const GridArgs&, const int32_t*, const int32_t*, const double*, \
                                      int64_t, const void*, int, void*, hipStream_t);                     \
   template int launch_interp<R>(int, const GridArgs&, const int32_t*, const double*, int64_t,            \
