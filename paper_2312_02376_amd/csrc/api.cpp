@@ -1703,18 +1703,28 @@ int build_plan(fftpim_plan_s* p, int64_t N, const double* src_dev, int64_t No, c
             widx[k] = static_cast<int32_t>(m);
             wval[k] = w_near[a * N + m] * w_near[(K1 + b) * N + m] * w_near[(2 * K1 + c) * N + m];
           }
-    // only the nodes with entries are visited (the grid is zeroed first):
-    // clustered points leave most of a fine grid empty
-    std::vector<int64_t> wnode, wrow_c;
-    for (int64_t k = 0; k < n3; ++k)
-      if (wrow[k + 1] > wrow[k]) {
-        wnode.push_back(k);
-        wrow_c.push_back(wrow[k]);
-      }
-    wrow_c.push_back(wrow[n3]);
-    p->wt_nnodes = static_cast<int64_t>(wnode.size());
-    if (p->wt_nnodes > 0) CHK(upload(p, &p->wt_node, wnode));
-    CHK(upload(p, &p->wt_row, wrow_c));
+    // clustered points leave most of a fine grid empty: then only the nodes
+    // with entries are listed and visited (the grid is zeroed first);
+    // otherwise every node is visited and writes its own value
+    int64_t filled = 0;
+    for (int64_t k = 0; k < n3; ++k) filled += wrow[k + 1] > wrow[k] ? 1 : 0;
+    if (filled > 0 && 2 * filled < n3) {
+      std::vector<int64_t> wnode, wrow_c;
+      wnode.reserve(static_cast<size_t>(filled));
+      wrow_c.reserve(static_cast<size_t>(filled) + 1);
+      for (int64_t k = 0; k < n3; ++k)
+        if (wrow[k + 1] > wrow[k]) {
+          wnode.push_back(k);
+          wrow_c.push_back(wrow[k]);
+        }
+      wrow_c.push_back(wrow[n3]);
+      p->wt_nnodes = filled;
+      CHK(upload(p, &p->wt_node, wnode));
+      CHK(upload(p, &p->wt_row, wrow_c));
+    } else {
+      p->wt_nnodes = n3;
+      CHK(upload(p, &p->wt_row, wrow));
+    }
     CHK(upload(p, &p->wt_idx, widx));
     CHK(upload(p, &p->wt_val, wval));
   }

@@ -448,10 +448,11 @@ __global__ void __launch_bounds__(256) k_spread_own(
 }
 
 // Projection from a node-major weight list (few planes): the transposed
-// interpolation weights W^T as CSR over the grid nodes that have entries, in
-// increasing point order, built at plan time.  16 lanes per listed node add
-// its entries and combine them by a fixed shuffle order; the grid is zeroed
-// first, so empty nodes cost nothing here.
+// interpolation weights W^T as CSR by grid node, entries in increasing point
+// order, built at plan time.  16 lanes per node add its entries and combine
+// them by a fixed shuffle order.  With a node list (wnode, for grids mostly
+// empty) only the listed nodes are visited and the grid is zeroed first;
+// without one every node is visited and empty nodes write zero.
 template <typename R>
 __global__ void __launch_bounds__(256) k_spread_csr(const int64_t* __restrict__ wnode, int64_t nnodes,
                                                     const int64_t* __restrict__ wrow, const int32_t* __restrict__ widx,
@@ -461,7 +462,7 @@ __global__ void __launch_bounds__(256) k_spread_csr(const int64_t* __restrict__ 
   const int64_t i = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 4;
   const int sl = threadIdx.x & 15;
   if (i >= nnodes) return;  // all 16 lanes of a node leave together
-  const int64_t node = wnode[i];
+  const int64_t node = wnode != nullptr ? wnode[i] : i;
   const int64_t j0 = wrow[i], j1 = wrow[i + 1];
   for (int p = 0; p < P; ++p) {
     double ar = 0.0, ai = 0.0;
@@ -1160,9 +1161,11 @@ static void spread_q(const GridArgs& g, const int32_t* box_start, const int32_t*
 template <typename R>
 void launch_spread_csr(const int64_t* wnode, int64_t nnodes, const int64_t* wrow, const int32_t* widx,
                        const double* wval, int64_t n3, const void* qint, int P, void* grid, hipStream_t st) {
-  const int64_t nz = n3 * P;
-  hipLaunchKernelGGL((k_zero_grid<R>), dim3(static_cast<unsigned>(std::min<int64_t>(blocks_for(nz, 256), 65536))),
-                     dim3(256), 0, st, static_cast<cplx<R>*>(grid), nz);
+  if (wnode != nullptr) {
+    const int64_t nz = n3 * P;
+    hipLaunchKernelGGL((k_zero_grid<R>), dim3(static_cast<unsigned>(std::min<int64_t>(blocks_for(nz, 256), 65536))),
+                       dim3(256), 0, st, static_cast<cplx<R>*>(grid), nz);
+  }
   if (nnodes > 0)
     hipLaunchKernelGGL((k_spread_csr<R>), dim3(blocks_for(nnodes * 16, kPointBlock)), dim3(kPointBlock), 0, st,
                        wnode, nnodes, wrow, widx, wval, static_cast<const cplx<R>*>(qint), P,
