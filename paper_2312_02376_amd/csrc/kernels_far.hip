@@ -581,10 +581,10 @@ __global__ void __launch_bounds__(256) k_far_interp_box(FarArgs f, const int32_t
 // product U[points][columns] = W[points][nodes] G[nodes][columns], the 2P
 // real columns being the interleaved real and imaginary parts of the planes
 // (W is real).  A wavefront owns RT 16-point row tiles and CT 16-column
-// tiles and walks the nodes as (a, b) pairs with four z nodes per 16x16x4
-// step (z padded to a multiple of four with zero weights).  Lane l supplies
-// W[point l % 16][z node 4 h + l / 16] and G[that node][column l % 16];
-// accumulation is FP64, as in the vector form above.
+// tiles and walks the (qf+1)^3 nodes four at a time in their linear order
+// (a, b, c) (one 16x16x4 step each, the last one padded with zero weights).
+// Lane l supplies W[point l % 16][node 4 s + l / 16] and G[that node][column
+// l % 16]; accumulation is FP64, as in the vector form above.
 constexpr int kFimRT = 2, kFimCT = 4;
 constexpr int kFimPts = 4 * 16 * kFimRT;  // points per block
 
@@ -594,7 +594,7 @@ __global__ void __launch_bounds__(256) k_far_interp_mfma(FarArgs f, const int32_
                                                          const int32_t* __restrict__ s3, const double* __restrict__ w3,
                                                          int64_t N, const cplx<R>* __restrict__ grid, int P,
                                                          cplx<R>* __restrict__ u, int accumulate) {
-  constexpr int K1 = QF + 1, K = K1 * K1 * K1, H = (K1 + 3) / 4;
+  constexpr int K1 = QF + 1, K = K1 * K1 * K1, NS = (K + 3) / 4;
   constexpr int RT = kFimRT, CT = kFimCT;
   extern __shared__ unsigned char lds_raw[];
   double* sw = reinterpret_cast<double*>(lds_raw);           // [kFimPts][3][K1]
@@ -626,18 +626,14 @@ __global__ void __launch_bounds__(256) k_far_interp_mfma(FarArgs f, const int32_
   const int kk = lane >> 4, li = lane & 15;
   const int twoP = 2 * P;
   const R* sgr = reinterpret_cast<const R*>(sg);
-  // this lane's point in each row tile (A operand) and its z weights
+  // this lane's point in each row tile (A operand)
   int pt[RT];
-  double wzs[RT][H];
+  bool pv[RT];
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt) {
     pt[rt] = (wave * RT + rt) * 16 + li;
-#pragma unroll
-    for (int h = 0; h < H; ++h) {
-      const int c = 4 * h + kk;
-      wzs[rt][h] = (pt[rt] < np && c < K1) ? sw[(pt[rt] * 3 + 2) * K1 + c] : 0.0;
-    }
-    if (pt[rt] >= np) pt[rt] = 0;  // zero weights above; any staged point's x, y weights do
+    pv[rt] = pt[rt] < np;
+    if (!pv[rt]) pt[rt] = 0;  // its weights are replaced by zero below
   }
   for (int pc = 0; pc < twoP; pc += 16 * CT) {
     mfma_d4 acc[RT][CT];
@@ -645,30 +641,26 @@ __global__ void __launch_bounds__(256) k_far_interp_mfma(FarArgs f, const int32_
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = mfma_d4{0.0, 0.0, 0.0, 0.0};
-    for (int a = 0; a < K1; ++a)
-      for (int bb = 0; bb < K1; ++bb) {
-        double wxy[RT];
+    for (int st = 0; st < NS; ++st) {
+      const int node = 4 * st + kk;
+      const bool nv = node < K;
+      const int nd = nv ? node : 0;
+      const int a = nd / (K1 * K1), bb = (nd / K1) % K1, c = nd % K1;
+      double bv[CT];
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt) wxy[rt] = sw[(pt[rt] * 3 + 0) * K1 + a] * sw[(pt[rt] * 3 + 1) * K1 + bb];
-#pragma unroll
-        for (int h = 0; h < H; ++h) {
-          const int c = 4 * h + kk;
-          const int node = (a * K1 + bb) * K1 + (c < K1 ? c : 0);
-          double bv[CT];
-#pragma unroll
-          for (int ct = 0; ct < CT; ++ct) {
-            const int col = pc + ct * 16 + li;
-            bv[ct] = (c < K1 && col < twoP) ? static_cast<double>(sgr[node * twoP + col]) : 0.0;
-          }
-#pragma unroll
-          for (int rt = 0; rt < RT; ++rt) {
-            const double av = wxy[rt] * wzs[rt][h];
-#pragma unroll
-            for (int ct = 0; ct < CT; ++ct)
-              if (pc + ct * 16 < twoP) acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[ct], acc[rt][ct], 0, 0, 0);
-          }
-        }
+      for (int ct = 0; ct < CT; ++ct) {
+        const int col = pc + ct * 16 + li;
+        bv[ct] = (nv && col < twoP) ? static_cast<double>(sgr[nd * twoP + col]) : 0.0;
       }
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        const double* w = sw + pt[rt] * 3 * K1;
+        const double av = (nv && pv[rt]) ? w[a] * w[K1 + bb] * w[2 * K1 + c] : 0.0;
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+          if (pc + ct * 16 < twoP) acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[ct], acc[rt][ct], 0, 0, 0);
+      }
+    }
     // element r of lane l: row 4 r + l / 16, column l % 16
     R* ur = reinterpret_cast<R*>(u);
 #pragma unroll
