@@ -818,8 +818,42 @@ __global__ void __launch_bounds__(256) k_fft_pass(const cplx<R>* in,
 // consecutive lines, so every global load and store is a run of T columns.
 // Natural order in and out, forward exp(-2 pi i / M), unscaled inverse, as the
 // LDS-stage kernel above.
+// cos(pi k / 16) and sin(pi k / 16), k = 0..16: the twiddles inside the
+// register transforms (lines of at most 32 values), from their Taylor series
+// at compile time, so that every butterfly's factor is an immediate and the
+// factors 1 and -i cost no multiplications
+constexpr double ct_sin(double x) {
+  double term = x, sum = x;
+  for (int n = 1; n < 24; ++n) {
+    term *= -x * x / ((2.0 * n) * (2.0 * n + 1.0));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double ct_cos(double x) {
+  double term = 1.0, sum = 1.0;
+  for (int n = 1; n < 24; ++n) {
+    term *= -x * x / ((2.0 * n - 1.0) * (2.0 * n));
+    sum += term;
+  }
+  return sum;
+}
+struct RegTwiddles {
+  double c[17], s[17];
+  constexpr RegTwiddles() : c(), s() {
+    for (int k = 0; k <= 16; ++k) {
+      c[k] = ct_cos(3.14159265358979323846 * k / 16.0);
+      s[k] = ct_sin(3.14159265358979323846 * k / 16.0);
+    }
+  }
+};
+constexpr RegTwiddles kRegTw{};
+
 template <typename R, int L>
 __device__ inline void reg_dft(cplx<R>* v, const cplx<R>* tws, int twstride, bool inverse) {
+  static_assert(L <= 32, "register lines of at most 32 values");
+  (void)tws;
+  (void)twstride;
   // bit-reversal permutation (compile-time indices)
 #pragma unroll
   for (int i = 0; i < L; ++i) {
@@ -840,10 +874,14 @@ __device__ inline void reg_dft(cplx<R>* v, const cplx<R>* tws, int twstride, boo
 #pragma unroll
       for (int j = 0; j < s; ++j) {
         cplx<R> b = v[k + j + s];
-        if (j != 0) {
-          cplx<R> w = tws[j * (L / (2 * s)) * twstride];
-          if (inverse) w.y = -w.y;
-          b = cmul(b, w);
+        // factor exp(-+ i pi e / 16) with e = 16 j / s
+        const int e = 16 * j / s;
+        if (e == 8) {
+          b = inverse ? cmake<R>(-b.y, b.x) : cmake<R>(b.y, -b.x);
+        } else if (e != 0) {
+          const R c = static_cast<R>(kRegTw.c[e]);
+          const R sn = static_cast<R>(kRegTw.s[e]);
+          b = cmul(b, cmake<R>(c, inverse ? sn : -sn));
         }
         const cplx<R> a = v[k + j];
         v[k + j] = cadd(a, b);
